@@ -1,0 +1,88 @@
+"""Seeded synthetic workloads for PC-MM (inputs only, no group arithmetic).
+
+The paper measures uniform random square matrices with element bit-widths
+t in {4, 8, 12, 16} and sizes n in {8, ..., 512} (Sec. 4.2; Appendix A).  The
+workloads below follow that recipe and add the rectangular, signed, batched and
+serving shapes of this library's benchmark set.  Everything is drawn with
+numpy's PCG64 from a fixed seed; encryption nonces and the secret key are not
+drawn here: they are derived from the same seed by the counter-based scalar
+derivation that both the library and the CPU reference implement.
+
+This module is shared by the tests, the benchmark and the CPU reference; it
+holds no curve, field or compression arithmetic.
+"""
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class PCMMShape:
+    m: int
+    n: int
+    l: int
+    bits: int          # plaintext bit-width t of A
+    signed: bool       # A entries in [-2^(t-1), 2^(t-1)) instead of [0, 2^t)
+    msg_bits: int      # plaintext bit-width of the encrypted matrix
+    seed: int
+    name: str = ""
+
+
+@dataclass
+class BatchWorkload:
+    shapes: List[PCMMShape] = field(default_factory=list)
+    seed: int = 4
+
+
+# The named workloads (sizes and seeds are fixed so every run sees the same
+# inputs).  "tiny" is the 16x16 case the CPU reference finishes in seconds.
+TINY = PCMMShape(16, 16, 16, 4, False, 4, seed=1, name="tiny16_t4")
+SIGNED128 = PCMMShape(128, 128, 128, 8, True, 8, seed=2, name="signed128_t8")
+LARGE_T2 = PCMMShape(512, 512, 512, 2, False, 4, seed=32, name="large512_t2")
+LARGE_T4 = PCMMShape(512, 512, 512, 4, False, 4, seed=34, name="large512_t4")
+SERVE_LAYER = PCMMShape(256, 1024, 8, 8, True, 8, seed=5, name="serve256x1024x8_t8")
+
+NAMED = {s.name: s for s in (TINY, SIGNED128, LARGE_T2, LARGE_T4, SERVE_LAYER)}
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def gen_plain_matrix(rng: np.random.Generator, rows: int, cols: int, bits: int,
+                     signed: bool) -> np.ndarray:
+    """Uniform t-bit plaintext matrix: int8 when signed, uint8 otherwise."""
+    if not (1 <= bits <= 8):
+        raise ValueError("bits must be in 1..8")
+    if signed:
+        lo, hi = -(1 << (bits - 1)), (1 << (bits - 1))
+        return rng.integers(lo, hi, size=(rows, cols), dtype=np.int64).astype(np.int8)
+    return rng.integers(0, 1 << bits, size=(rows, cols), dtype=np.int64).astype(np.uint8)
+
+
+def gen_messages(rng: np.random.Generator, rows: int, cols: int, bits: int) -> np.ndarray:
+    """Uniform unsigned messages of `bits` bits (the encrypted matrix B)."""
+    return rng.integers(0, 1 << bits, size=(rows, cols), dtype=np.int64).astype(np.int32)
+
+
+def make_inputs(shape: PCMMShape):
+    """(A, msg) for one PC-MM: A is m x n, msg is n x l (drawn in that order)."""
+    rng = rng_for(shape.seed)
+    A = gen_plain_matrix(rng, shape.m, shape.n, shape.bits, shape.signed)
+    msg = gen_messages(rng, shape.n, shape.l, shape.msg_bits)
+    return A, msg
+
+
+def batch_workload(count: int = 64, seed: int = 4, lo: int = 32, hi: int = 512,
+                   bit_choices=(1, 2, 4, 8), msg_bits: int = 8) -> BatchWorkload:
+    """Uneven batch: m, n, l uniform in {lo..hi}, A bit-width uniform over
+    `bit_choices` (unsigned), uniform `msg_bits`-bit messages."""
+    rng = rng_for(seed)
+    shapes = []
+    for b in range(count):
+        m, n, l = (int(x) for x in rng.integers(lo, hi + 1, size=3))
+        bits = int(rng.choice(np.asarray(bit_choices)))
+        shapes.append(PCMMShape(m, n, l, bits, False, msg_bits, seed=seed * 1000003 + b,
+                                name=f"batch{b}"))
+    return BatchWorkload(shapes=shapes, seed=seed)

@@ -1,0 +1,180 @@
+/*
+ * pcmm.h -- plaintext-ciphertext matrix multiplication (PC-MM) over unpacked
+ * EC-ElGamal ciphertexts on NIST P-256, on AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Alg. 3 of the paper, Sec. 3.3): given a plaintext m x n integer
+ * matrix A and n l EC-ElGamal ciphertexts Enc(b_kj) = (B1_kj, B2_kj), produce
+ * the m l ciphertexts Enc(c_ij) with c_ij = sum_k a_ik b_kj, i.e. in the group
+ * of points
+ *     (C1_ij, C2_ij) = (sum_k a_ik B1_kj, sum_k a_ik B2_kj).
+ * Two methods are provided: the schoolbook inner products with every product
+ * a_ik B_kj computed by the Montgomery ladder (Sec. 3.1, Alg. 1) and Cussen's
+ * compression-reconstruction (Alg. 2 inside Alg. 3).  Both give identical
+ * group elements; after pcmm_normalize the bytes are identical too.
+ *
+ * Scheme (Sec. 2.4): KeyGen picks x in [1, q-1] and H = xG; Encrypt(m) =
+ * (rG, rH + mG) with r in [1, q-1]; decryption recovers mG = C2 - x C1 (the
+ * bounded discrete logarithm that turns mG into m is not part of this API).
+ *
+ * ------------------------------------------------------------------------
+ * Conventions
+ *   Errors      every call returns a pcmm_status; 0 is success.  Arguments are
+ *               validated on the host before any work is queued; invalid
+ *               arguments queue nothing.  GPU work is asynchronous on the given
+ *               stream (a hipStream_t passed as void*; NULL = the null stream);
+ *               launch failures return PCMM_EDEVICE.
+ *   Ownership   the caller allocates and frees every buffer (device matrices,
+ *               workspaces, host arrays).  The library keeps only immutable
+ *               curve tables per device, created on first use.
+ *   Aliasing    inputs and outputs must not overlap unless a call says so.
+ *   Points      device points are structure-of-arrays 32-bit little-endian
+ *               limbs in canonical form (integers in [0, p), not Montgomery):
+ *                 affine   : 2 coordinates (x, y); infinity = (0, 0)
+ *                 jacobian : 3 coordinates (X, Y, Z); x = X/Z^2, y = Y/Z^3;
+ *                            infinity <=> Z = 0
+ *               Element e of a pcmm_mat with `npts` points per element stores
+ *               limb `w` of coordinate `c` of point `pt` at
+ *                 d[((pt * form + c) * 8 + w) * ld + e]
+ *               so each limb plane is contiguous over elements (coalesced).
+ *   Ints        plaintext matrices A are host arrays, row-major int8 (signed)
+ *               or uint8 (unsigned, same bytes read as 0..255); `bits` is the
+ *               declared bit-width t (1..8): entries must satisfy
+ *               0 <= a < 2^t (unsigned) or -2^(t-1) <= a < 2^(t-1) (signed),
+ *               else PCMM_ERANGE.  Keeping n max|a| max|b| below the message
+ *               bound of the decryptor (Sec. 2.4) is the caller's duty.
+ * ------------------------------------------------------------------------
+ */
+#ifndef PCMM_H
+#define PCMM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PCMM_OK = 0,
+    PCMM_EINVAL = -1,       /* bad shape, bit-width, form, null pointer, config */
+    PCMM_ERANGE = -2,       /* an entry of A outside its declared bit-width     */
+    PCMM_ENOMEM = -3,       /* caller workspace too small                      */
+    PCMM_EDEVICE = -4,      /* HIP runtime or launch error                     */
+    PCMM_ENOTONCURVE = -5   /* a host point is not on P-256                    */
+} pcmm_status;
+
+#define PCMM_AFFINE 2
+#define PCMM_JACOBIAN 3
+
+/* Host form of a point: big-endian affine coordinates; infinity = (0, 0). */
+typedef struct {
+    uint8_t x[32];
+    uint8_t y[32];
+} pcmm_point_be;
+
+/* A device matrix of points (see Conventions). */
+typedef struct {
+    int32_t rows, cols;  /* logical shape; element e = r * cols + c              */
+    int32_t npts;        /* points per element: 2 for ciphertexts, 1 for points  */
+    int32_t form;        /* PCMM_AFFINE or PCMM_JACOBIAN (coordinates per point) */
+    int64_t ld;          /* limb-plane stride in elements, >= rows * cols        */
+    uint32_t *d;         /* device memory, caller-owned                          */
+} pcmm_mat;
+
+/* Tuning of pcmm_cussen.  Zero fields take the library's choice.
+ *   rounds  N, compression rounds of Alg. 2 (default 4, as in the paper; 1..8)
+ *   group   columns of A per code (default 1 = Alg. 3 exactly, one column of A
+ *           per compression; g > 1 compresses row segments of g columns into
+ *           one code and builds the table of their ciphertext combinations)
+ *   k_split split of the n (inner) dimension over independent partial sums that
+ *           are then added (0 = chosen from the shape)
+ *   k_chunk columns of A whose tables are staged in LDS at once (0 = auto)  */
+typedef struct {
+    int32_t rounds;
+    int32_t group;
+    int32_t k_split;
+    int32_t k_chunk;
+} pcmm_cussen_cfg;
+
+/* Operation counts of one pcmm_cussen call, derived from its plan. */
+typedef struct {
+    int64_t level_mults;     /* sum over columns of n_N (ECSMs per ciphertext point)       */
+    int64_t level_adds;      /* sum over columns of sum_{w<N} n_w (paper's counting)        */
+    int64_t table_entries;   /* sum over columns (groups) of table entries per output column */
+    int64_t table_adds;      /* point additions executed per output column to build tables */
+    int64_t accum_adds;      /* mixed additions executed per output column (all rows)      */
+    int64_t max_entries;     /* largest table (entries) of one column (group)              */
+} pcmm_cussen_stats;
+
+/* KeyGen (Sec. 2.4): x = scalar(seed, domain 0, index 0) in [1, q-1] and the
+ * public point H = xG.  Scalars come from a counter-based derivation: with
+ * SplitMix64's output function mix(), base = mix(seed ^ (domain << 56) ^ idx),
+ * w_i = mix(base + (i + 1) * 0x9E3779B97F4A7C15) for i = 0..4,
+ * X = sum_i w_i 2^(64 i), scalar = X mod (q - 1) + 1.
+ * sk_be: 32 bytes big-endian (host).  pk: host.  Runs on the current device
+ * and returns after the result is on the host. */
+pcmm_status pcmm_keygen(uint64_t seed, uint8_t sk_be[32], pcmm_point_be *pk);
+
+/* Encrypt (Sec. 2.4): element e (row-major index of the rows x cols message
+ * matrix) gets r_e = scalar(seed, domain 1, idx0 + e) and
+ * ct_e = (r_e G, r_e H + m_e G), with m_e taken mod q (negative allowed).
+ * msg_dev: device int32, rows x cols row-major.  ct_out: rows x cols, npts 2,
+ * PCMM_AFFINE.  workspace: device scratch of pcmm_encrypt_workspace() bytes
+ * (holds the fixed-base table of H).  PCMM_ENOTONCURVE if pk is not a
+ * finite point of P-256. */
+pcmm_status pcmm_encrypt(const pcmm_point_be *pk, const int32_t *msg_dev, int32_t rows,
+                         int32_t cols, uint64_t seed, int64_t idx0, pcmm_mat *ct_out,
+                         void *workspace, size_t ws_bytes, void *stream);
+size_t pcmm_encrypt_workspace(void);
+
+/* Schoolbook PC-MM (Sec. 3.1): C_ij = sum_k a_ik B_kj, each term by the
+ * Montgomery ladder of Alg. 1 over the t bits of |a_ik| (negative a_ik act on
+ * -B_kj), accumulated by point additions.  A: host m x n.  B: device n x l
+ * ciphertexts, affine.  C: device m x l ciphertexts, PCMM_JACOBIAN (write-only;
+ * run pcmm_normalize for canonical affine bytes) or PCMM_AFFINE (normalised
+ * here through `workspace`).  workspace: pcmm_schoolbook_workspace() bytes. */
+pcmm_status pcmm_schoolbook(const int8_t *A, int32_t m, int32_t n, int32_t bits,
+                            int32_t is_signed, const pcmm_mat *B, pcmm_mat *C,
+                            void *workspace, size_t ws_bytes, void *stream);
+size_t pcmm_schoolbook_workspace(int32_t m, int32_t n, int32_t l, int32_t c_form);
+
+/* Cussen PC-MM (Alg. 3 with Alg. 2): per column (group) of A, compress the
+ * magnitudes by N rounds of sort / de-duplicate / difference, build the table
+ * of ciphertext multiples T_kj[u] = u B_kj by the reconstruction's prefix
+ * sums, then C_ij += sign(a_ik) T_kj[code_ik].  Same arguments as
+ * pcmm_schoolbook plus cfg (NULL = defaults) and a workspace of
+ * pcmm_cussen_workspace() bytes (plan, tables, partial sums).  stats may be
+ * NULL; when given it receives the plan's operation counts. */
+pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
+                        const pcmm_mat *B, pcmm_mat *C, const pcmm_cussen_cfg *cfg,
+                        void *workspace, size_t ws_bytes, pcmm_cussen_stats *stats,
+                        void *stream);
+pcmm_status pcmm_cussen_workspace(const int8_t *A, int32_t m, int32_t n, int32_t l, int32_t bits,
+                                  int32_t is_signed, int32_t c_form, const pcmm_cussen_cfg *cfg,
+                                  size_t *bytes);
+
+/* Host-only: the compression plan's operation counts for A (no GPU work). */
+pcmm_status pcmm_cussen_plan_stats(const int8_t *A, int32_t m, int32_t n, int32_t bits,
+                                   int32_t is_signed, const pcmm_cussen_cfg *cfg,
+                                   pcmm_cussen_stats *stats);
+
+/* Normalise Jacobian points to canonical affine (x, y) = (X/Z^2, Y/Z^3) with
+ * one field inversion per batch of points (Montgomery's simultaneous
+ * inversion); infinity (Z = 0) becomes (0, 0).  in: PCMM_JACOBIAN; out:
+ * PCMM_AFFINE, same rows, cols, npts.  out may alias in (same d and ld).
+ * workspace: pcmm_normalize_workspace(rows * cols, npts) bytes. */
+pcmm_status pcmm_normalize(const pcmm_mat *in, pcmm_mat *out, void *workspace, size_t ws_bytes,
+                           void *stream);
+size_t pcmm_normalize_workspace(int64_t elements, int32_t npts);
+
+/* Decryption to points (Sec. 2.4): M_e = C2_e - x C1_e (= m_e G for a valid
+ * ciphertext of m_e).  sk_be: 32 bytes big-endian, 1 <= x < q.  C: affine
+ * ciphertexts (npts 2).  M: affine, npts 1, same rows and cols. */
+pcmm_status pcmm_decrypt_to_points(const uint8_t sk_be[32], const pcmm_mat *C, pcmm_mat *M,
+                                   void *stream);
+
+const char *pcmm_strerror(pcmm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

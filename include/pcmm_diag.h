@@ -1,0 +1,54 @@
+/*
+ * pcmm_diag.h -- self-test and measurement entry points of libpcmm.
+ *
+ * These expose the device building blocks one operation at a time so that the
+ * field arithmetic, the point formulas and the ladder of Alg. 1 can be checked
+ * element by element against an independent implementation, and they measure
+ * the instruction rates that bound the PC-MM kernels (the 32 x 32 -> 64-bit
+ * multiply-add that dominates prime-field multiplication, plain 32-bit
+ * additions, the field multiplication and the mixed point addition).
+ * Conventions (errors, streams, ownership, canonical limbs) as in pcmm.h.
+ */
+#ifndef PCMM_DIAG_H
+#define PCMM_DIAG_H
+#include <stddef.h>
+#include <stdint.h>
+
+#include "pcmm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Field operations on `count` elements in [0, p).  Operands and result are
+ * structure-of-arrays: limb w of element e at x[w * count + e].
+ * op: 0 a+b, 1 a-b, 2 a*b, 3 a^2, 4 a^-1 (0 -> 0), 5 -a, 6 Montgomery
+ * round trip of a (to and from Montgomery form).  b is ignored by unary ops. */
+pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
+                            int64_t count, void *stream);
+
+/* Point operations, element-wise over count = P->rows * P->cols elements.
+ * P, Q: affine npts 1.  k: device uint32 scalars (op 3).  R: Jacobian npts 1.
+ * op: 0 P + Q by the mixed addition (P lifted to Z = 1);
+ *     1 P + Q by the general addition, both operands first given Z != 1
+ *       (Z_P = x_Q + 2, Z_Q = y_P + 3 when nonzero);
+ *     2 2P; 3 k P by Alg. 1 over the low `t` bits of k; 4 -P. */
+pcmm_status pcmm_diag_point(int32_t op, const pcmm_mat *P, const pcmm_mat *Q, const uint32_t *k,
+                            int32_t t, pcmm_mat *R, void *stream);
+
+/* Throughput probes.  kind: 0 v_mad_u64_u32 (32x32+64 -> 64-bit multiply-add),
+ * 1 v_add3_u32 (32-bit three-input add), 2 field multiplication,
+ * 3 mixed point addition, 4 v_fma_f64.  Launches `blocks` x 256 threads that
+ * each run `iters` iterations; returns the kernel time (HIP events) and the
+ * number of operations of that kind executed. */
+pcmm_status pcmm_diag_probe(int32_t kind, int64_t iters, int32_t blocks, double *seconds,
+                            double *ops);
+
+/* Device properties used for roofline figures. */
+pcmm_status pcmm_diag_device(int32_t *cus, int32_t *clock_khz, int64_t *lds_per_block,
+                             char name[64]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

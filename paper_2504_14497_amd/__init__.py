@@ -12,6 +12,6 @@ __all__ = ["workloads", "pcmm"]
 
 def __getattr__(name):
     if name == "pcmm":
-        from . import pcmm as _p
-        return _p
+        import importlib
+        return importlib.import_module(__name__ + ".pcmm")
     raise AttributeError(name)

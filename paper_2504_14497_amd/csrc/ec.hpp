@@ -1,0 +1,178 @@
+// ec.hpp -- P-256 point arithmetic on gfx950 (device side).
+//
+// Curve (Sec. 4.1): y^2 = x^3 - 3x + b over F_p, prime order q, cofactor 1.
+// Points are held in VGPRs in Montgomery form:
+//   jpt  Jacobian (X, Y, Z), x = X/Z^2, y = Y/Z^3; the identity has Z = 0;
+//   apt  affine (x, y); the identity is (0, 0) (not on the curve since b != 0).
+// Formulas are the standard Jacobian ones for a = -3 (doubling 3M + 5S,
+// mixed addition 7M + 4S, general addition 11M + 5S).  Every exceptional
+// case of the group law (Sec. 2.3) is handled:
+//   identity operands         -> select the other operand;
+//   P = -Q                    -> H = 0, r != 0: the formulas already give Z = 0;
+//   P = Q                     -> H = 0, r = 0: the formulas break down, so the
+//                                lanes that hit it take the doubling instead.
+#pragma once
+#include "fp.hpp"
+
+namespace pcmm {
+
+struct jpt {
+    fe X, Y, Z;
+};
+
+struct apt {
+    fe x, y;
+};
+
+// standard P-256 domain parameters (b, generator) in canonical hex
+constexpr fe_const CURVE_B_PLAIN =
+    c_from_hex("5ac635d8aa3a93e7b3ebbd55769886bc651d06b0cc53b0f63bce3c3e27d2604b");
+constexpr fe_const GX_PLAIN =
+    c_from_hex("6b17d1f2e12c4247f8bce6e563a440f277037d812deb33a0f4a13945d898c296");
+constexpr fe_const GY_PLAIN =
+    c_from_hex("4fe342e2fe1a7f9b8ee7eb4a7c0f9e162bce33576b315ececbb6406837bf51f5");
+// group order q, for scalar handling
+constexpr fe_const ORDER_Q =
+    c_from_hex("ffffffff00000000ffffffffffffffffbce6faada7179e84f3b9cac2fc632551");
+
+__device__ __forceinline__ jpt jpt_infinity() {
+    jpt r;
+    r.X = fe_one_mont();
+    r.Y = fe_one_mont();
+    r.Z = fe_zero();
+    return r;
+}
+
+__device__ __forceinline__ bool jpt_is_inf(const jpt &P) { return fe_is_zero(P.Z); }
+
+__device__ __forceinline__ bool apt_is_inf(const apt &P) {
+    uint32_t x = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x |= P.x.v[i] | P.y.v[i];
+    return x == 0;
+}
+
+__device__ __forceinline__ jpt jpt_from_affine(const apt &P) {
+    jpt r;
+    r.X = P.x;
+    r.Y = P.y;
+    r.Z = apt_is_inf(P) ? fe_zero() : fe_one_mont();
+    return r;
+}
+
+__device__ __forceinline__ jpt jpt_select(bool c, const jpt &a, const jpt &b) {
+    jpt r;
+    r.X = fe_select(c, a.X, b.X);
+    r.Y = fe_select(c, a.Y, b.Y);
+    r.Z = fe_select(c, a.Z, b.Z);
+    return r;
+}
+
+__device__ __forceinline__ apt apt_neg(const apt &P) {
+    apt r;
+    r.x = P.x;
+    r.y = fe_neg(P.y);  // -0 = 0 keeps the identity encoding
+    return r;
+}
+
+__device__ __forceinline__ jpt jpt_neg(const jpt &P) {
+    jpt r = P;
+    r.Y = fe_neg(P.Y);
+    return r;
+}
+
+// 2P, a = -3 (dbl-2001-b).  Z = 0 stays Z = 0.
+__device__ __forceinline__ jpt jpt_dbl(const jpt &P) {
+    fe delta = fe_sqr(P.Z);
+    fe gamma = fe_sqr(P.Y);
+    fe beta = fe_mul(P.X, gamma);
+    fe t0 = fe_sub(P.X, delta);
+    fe t1 = fe_add(P.X, delta);
+    fe alpha = fe_mul(t0, t1);
+    alpha = fe_add(fe_dbl(alpha), alpha);             // 3 (X - delta)(X + delta)
+    jpt R;
+    fe beta4 = fe_dbl(fe_dbl(beta));
+    R.X = fe_sub(fe_sqr(alpha), fe_dbl(beta4));       // alpha^2 - 8 beta
+    fe yz = fe_add(P.Y, P.Z);
+    R.Z = fe_sub(fe_sub(fe_sqr(yz), gamma), delta);   // (Y + Z)^2 - gamma - delta
+    fe g2 = fe_sqr(gamma);
+    fe g8 = fe_dbl(fe_dbl(fe_dbl(g2)));
+    R.Y = fe_sub(fe_mul(alpha, fe_sub(beta4, R.X)), g8);
+    return R;
+}
+
+// R <- 2P on the lanes where `same` holds.  The doubling runs only when some
+// lane of the wavefront needs it, and then on the whole wavefront (a uniform
+// branch) followed by a per-lane select.
+__device__ __forceinline__ jpt fix_equal_operands(bool same, const jpt &R, const jpt &P) {
+    if (__ballot(same)) {
+        jpt D = jpt_dbl(P);
+        return jpt_select(same, R, D);
+    }
+    return R;
+}
+
+// P + Q with Q affine (madd-2007-bl), complete.
+__device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
+    fe z1z1 = fe_sqr(P.Z);
+    fe u2 = fe_mul(Q.x, z1z1);
+    fe s2 = fe_mul(fe_mul(Q.y, P.Z), z1z1);
+    fe h = fe_sub(u2, P.X);
+    fe hh = fe_sqr(h);
+    fe i4 = fe_dbl(fe_dbl(hh));
+    fe j = fe_mul(h, i4);
+    fe r = fe_sub(s2, P.Y);
+    r = fe_dbl(r);
+    fe v = fe_mul(P.X, i4);
+    jpt R;
+    R.X = fe_sub(fe_sub(fe_sqr(r), j), fe_dbl(v));
+    R.Y = fe_sub(fe_mul(r, fe_sub(v, R.X)), fe_dbl(fe_mul(P.Y, j)));
+    fe zh = fe_add(P.Z, h);
+    R.Z = fe_sub(fe_sub(fe_sqr(zh), z1z1), hh);
+    bool p_inf = jpt_is_inf(P);
+    bool q_inf = apt_is_inf(Q);
+    bool same = fe_is_zero(h) && fe_is_zero(r) && !p_inf && !q_inf;
+    R = fix_equal_operands(same, R, P);
+    R = jpt_select(p_inf, R, jpt_from_affine(Q));
+    R = jpt_select(q_inf, R, P);
+    return R;
+}
+
+// P + Q, both Jacobian (add-2007-bl), complete.
+__device__ __forceinline__ jpt jpt_add(const jpt &P, const jpt &Q) {
+    fe z1z1 = fe_sqr(P.Z);
+    fe z2z2 = fe_sqr(Q.Z);
+    fe u1 = fe_mul(P.X, z2z2);
+    fe u2 = fe_mul(Q.X, z1z1);
+    fe s1 = fe_mul(fe_mul(P.Y, Q.Z), z2z2);
+    fe s2 = fe_mul(fe_mul(Q.Y, P.Z), z1z1);
+    fe h = fe_sub(u2, u1);
+    fe h2 = fe_dbl(h);
+    fe i = fe_sqr(h2);
+    fe j = fe_mul(h, i);
+    fe r = fe_dbl(fe_sub(s2, s1));
+    fe v = fe_mul(u1, i);
+    jpt R;
+    R.X = fe_sub(fe_sub(fe_sqr(r), j), fe_dbl(v));
+    R.Y = fe_sub(fe_mul(r, fe_sub(v, R.X)), fe_dbl(fe_mul(s1, j)));
+    fe zz = fe_add(P.Z, Q.Z);
+    R.Z = fe_mul(fe_sub(fe_sub(fe_sqr(zz), z1z1), z2z2), h);
+    bool p_inf = jpt_is_inf(P);
+    bool q_inf = jpt_is_inf(Q);
+    bool same = fe_is_zero(h) && fe_is_zero(r) && !p_inf && !q_inf;
+    R = fix_equal_operands(same, R, P);
+    R = jpt_select(p_inf, R, Q);
+    R = jpt_select(q_inf, R, P);
+    return R;
+}
+
+// affine (x, y) of a Jacobian point given zinv = Z^-1 (Z != 0)
+__device__ __forceinline__ apt jpt_to_affine_with(const jpt &P, const fe &zinv) {
+    fe z2 = fe_sqr(zinv);
+    apt r;
+    r.x = fe_mul(P.X, z2);
+    r.y = fe_mul(P.Y, fe_mul(z2, zinv));
+    return r;
+}
+
+}  // namespace pcmm

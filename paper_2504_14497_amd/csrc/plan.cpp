@@ -1,0 +1,220 @@
+// plan.cpp -- Alg. 2 compression of the columns of A into table-build
+// programs and row codes (host side of Cussen PC-MM).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <unordered_map>
+
+namespace pcmm {
+
+namespace {
+
+inline int16_t base_operand(int t) { return (int16_t)(-1 - t); }
+
+// Compression and reconstruction schedule of one column (Alg. 2 with N
+// rounds).  `vals` are |a_ik| >= 0.  Emits ops into `ops` (registers numbered
+// from *nreg) and returns, for every row, the operand holding |a_ik| B_t
+// (or INT16_MIN for a zero entry).
+struct column_result {
+    std::vector<int16_t> row_operand;  // per row
+    int64_t nN = 0, adds_counted = 0;
+};
+
+column_result compress_column(const std::vector<int> &vals, int N, int t, std::vector<plan_op> &ops,
+                              int *nreg, int64_t *mul_bits) {
+    const int m = (int)vals.size();
+    column_result res;
+    res.row_operand.assign(m, INT16_MIN);
+    // levels: level[w] = sorted unique nonzero values (then differenced if w < N)
+    std::vector<std::vector<int>> level(N + 1);
+    std::vector<std::vector<int>> ptr(N + 1);  // ptr[w][i]: position in level w of element i of level w-1
+    level[0] = vals;
+    for (int w = 1; w <= N; ++w) {
+        const std::vector<int> &src = level[w - 1];
+        std::vector<int> u;
+        u.reserve(src.size());
+        for (int v : src)
+            if (v != 0) u.push_back(v);
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        ptr[w].resize(src.size());
+        for (size_t i = 0; i < src.size(); ++i) {
+            if (src[i] == 0) {
+                ptr[w][i] = -1;
+            } else {
+                ptr[w][i] = (int)(std::lower_bound(u.begin(), u.end(), src[i]) - u.begin());
+            }
+        }
+        if (w != N) {
+            for (int i = (int)u.size() - 1; i >= 1; --i) u[i] -= u[i - 1];
+        }
+        level[w] = std::move(u);
+    }
+    res.nN = (int64_t)level[N].size();
+    for (int w = 1; w < N; ++w) res.adds_counted += (int64_t)level[w].size();
+    // reconstruction: operands of level N, then prefix sums down to level 1
+    std::vector<int16_t> cur(level[N].size());
+    for (size_t i = 0; i < level[N].size(); ++i) {
+        int s = level[N][i];
+        if (s == 1) {
+            cur[i] = base_operand(t);
+        } else {
+            plan_op op{};
+            op.kind = OP_MUL;
+            op.dst = (int16_t)(*nreg)++;
+            op.a = base_operand(t);
+            op.s = s;
+            int bitsn = 0;
+            while ((s >> bitsn) != 0) ++bitsn;
+            *mul_bits += bitsn;
+            ops.push_back(op);
+            cur[i] = op.dst;
+        }
+    }
+    for (int w = N - 1; w >= 1; --w) {
+        // un-sort: element i of level w takes the operand of its difference
+        std::vector<int16_t> b(level[w].size());
+        for (size_t i = 0; i < level[w].size(); ++i) b[i] = cur[ptr[w + 1][i]];
+        // prefix sums: S_0 = b_0, S_i = S_{i-1} + b_i
+        std::vector<int16_t> S(b.size());
+        for (size_t i = 0; i < b.size(); ++i) {
+            if (i == 0) {
+                S[i] = b[i];
+            } else {
+                plan_op op{};
+                op.kind = OP_ADD;
+                op.dst = (int16_t)(*nreg)++;
+                op.a = S[i - 1];
+                op.b = b[i];
+                ops.push_back(op);
+                S[i] = op.dst;
+            }
+        }
+        cur = std::move(S);
+    }
+    // un-sort level 1 back to the rows
+    for (int i = 0; i < m; ++i)
+        if (ptr[1][i] >= 0) res.row_operand[i] = cur[ptr[1][i]];
+    return res;
+}
+
+}  // namespace
+
+int build_cussen_plan(const int8_t *A, int m, int n, int bits, bool is_signed, int N, int g,
+                      cussen_plan *out) {
+    if (!out || m < 0 || n < 0 || bits < 1 || bits > 8 || N < 1 || N > 8 || g < 1 || g > 4) return -1;
+    if ((int64_t)m * n > 0 && !A) return -1;
+    if (m > 32767) return -1;
+    // validate A against the declared bit-width
+    const int lo = is_signed ? -(1 << (bits - 1)) : 0;
+    const int hi = is_signed ? (1 << (bits - 1)) - 1 : (1 << bits) - 1;
+    auto at = [&](int i, int k) -> int {
+        int8_t v = A[(int64_t)i * n + k];
+        return is_signed ? (int)v : (int)(uint8_t)v;
+    };
+    for (int i = 0; i < m; ++i)
+        for (int k = 0; k < n; ++k) {
+            int v = at(i, k);
+            if (v < lo || v > hi) return -2;
+        }
+    cussen_plan P;
+    P.m = m;
+    P.n = n;
+    P.g = g;
+    P.N = N;
+    P.ngroups = (n + g - 1) / g;
+    P.op_begin.push_back(0);
+    P.entry_begin.push_back(0);
+    P.codes.assign((size_t)P.ngroups * m, 0);
+    std::vector<int> stamp, slot;  // direct-mapped segment lookup for g <= 2
+    for (int grp = 0; grp < P.ngroups; ++grp) {
+        const int k0 = grp * g;
+        const int gg = std::min(g, n - k0);
+        int nreg = 0;
+        // per-digit tables
+        std::vector<std::vector<int16_t>> digit_operand(gg);
+        for (int t = 0; t < gg; ++t) {
+            std::vector<int> vals(m);
+            for (int i = 0; i < m; ++i) vals[i] = std::abs(at(i, k0 + t));
+            column_result cr = compress_column(vals, N, t, P.ops, &nreg, &P.table_mul_bits);
+            P.level_mults += cr.nN;
+            P.level_adds += cr.adds_counted;
+            digit_operand[t] = std::move(cr.row_operand);
+        }
+        // distinct row segments up to sign (first nonzero digit made positive);
+        // a segment is keyed by its digits, 9 bits each
+        std::vector<int16_t> entry_operands;
+        const bool direct = gg <= 2;
+        if (direct && (int)stamp.size() < (1 << (9 * gg))) {
+            stamp.assign((size_t)1 << 18, -1);
+            slot.assign((size_t)1 << 18, 0);
+        }
+        std::unordered_map<uint64_t, int> entry_of;
+        for (int i = 0; i < m; ++i) {
+            int seg[4] = {0, 0, 0, 0};
+            int first = -1;
+            for (int t = 0; t < gg; ++t) {
+                seg[t] = at(i, k0 + t);
+                if (first < 0 && seg[t] != 0) first = t;
+            }
+            if (first < 0) continue;  // code 0: all-zero segment
+            int sigma = seg[first] < 0 ? -1 : 1;
+            uint64_t key = 0;
+            for (int t = 0; t < gg; ++t) {
+                seg[t] *= sigma;
+                key |= (uint64_t)(seg[t] + 256) << (9 * t);
+            }
+            int e = -1;
+            if (direct) {
+                if (stamp[key] == grp) e = slot[key];
+            } else {
+                auto it = entry_of.find(key);
+                if (it != entry_of.end()) e = it->second;
+            }
+            if (e < 0) {
+                // entry = sum_t seg_t B_t from the digit tables
+                int16_t acc = INT16_MIN;
+                for (int t = 0; t < gg; ++t) {
+                    if (seg[t] == 0) continue;
+                    int16_t d = digit_operand[t][i];
+                    if (acc == INT16_MIN) {
+                        acc = d;  // first nonzero digit is positive
+                    } else {
+                        plan_op op{};
+                        op.kind = OP_ADD;
+                        op.dst = (int16_t)nreg++;
+                        op.a = acc;
+                        op.b = d;
+                        op.neg_b = seg[t] < 0 ? 1 : 0;
+                        P.ops.push_back(op);
+                        acc = op.dst;
+                    }
+                }
+                e = (int)entry_operands.size();
+                entry_operands.push_back(acc);
+                if (direct) {
+                    stamp[key] = grp;
+                    slot[key] = e;
+                } else {
+                    entry_of.emplace(key, e);
+                }
+            }
+            P.codes[(size_t)grp * m + i] = (int16_t)(sigma * (e + 1));
+            ++P.accum_adds;
+        }
+        if (nreg > 32000 || entry_operands.size() > 32000) return -1;
+        P.entries.insert(P.entries.end(), entry_operands.begin(), entry_operands.end());
+        P.entry_begin.push_back((int32_t)P.entries.size());
+        P.op_begin.push_back((int32_t)P.ops.size());
+        P.nregs.push_back(nreg);
+        P.max_regs = std::max(P.max_regs, nreg);
+        P.max_entries = std::max(P.max_entries, (int)entry_operands.size());
+        P.table_entries += (int64_t)entry_operands.size();
+    }
+    for (const plan_op &op : P.ops)
+        if (op.kind == OP_ADD) ++P.table_adds;
+    *out = std::move(P);
+    return 0;
+}
+
+}  // namespace pcmm

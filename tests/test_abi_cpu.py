@@ -1,0 +1,148 @@
+"""The C-ABI library loads, exports every declared entry point, and its host
+logic (argument validation, the compression plan) is right -- all without a GPU.
+
+The compression plan is pinned against the oracle's own Alg. 2: for every
+column of A the plan's level-N multiplications and counted additions must equal
+the oracle's level lengths n_N and sum_{w<N} n_w.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2504_14497_amd import pcmm, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in ("pcmm.h", "pcmm_diag.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for mt in re.finditer(r"\b(pcmm_[a-z0-9_]+)\s*\(", text):
+            names.add(mt.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = pcmm.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 16
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared <= set(pcmm.EXPORTED)
+
+
+def test_strerror_and_status_codes():
+    assert pcmm.strerror(0) == "success"
+    for code in (-1, -2, -3, -4, -5):
+        assert pcmm.strerror(code) and pcmm.strerror(code) != "unknown status"
+
+
+def _oracle_column_counts(orc, A, N):
+    muls = adds = 0
+    for k in range(A.shape[1]):
+        col = np.abs(A[:, k].astype(np.int64))
+        _, mu, ad, lens = orc.alg2_plain(col, N, 1)
+        muls += mu
+        adds += ad
+    return muls, adds
+
+
+@pytest.mark.parametrize("shape", [W.TINY, W.SIGNED128, W.PCMMShape(37, 23, 5, 3, False, 4, seed=9),
+                                   W.PCMMShape(64, 40, 3, 8, False, 8, seed=10)])
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_plan_counts_match_oracle_alg2(orc, shape, N):
+    A, _ = W.make_inputs(shape)
+    st = pcmm.cussen_plan_stats(A, shape.bits, pcmm.CussenCfg(N, 1, 0, 0))
+    muls, adds = _oracle_column_counts(orc, A, N)
+    assert st["level_mults"] == muls
+    assert st["level_adds"] == adds
+    nz = int(np.count_nonzero(A))
+    assert st["accum_adds"] == nz
+    # table entries: distinct nonzero magnitudes per column
+    distinct = sum(len(set(np.abs(A[:, k].astype(int))) - {0}) for k in range(A.shape[1]))
+    assert st["table_entries"] == distinct
+    if N == 4:
+        # prefix sums: n_w - 1 executed additions per level below N, per column
+        executed = 0
+        for k in range(A.shape[1]):
+            _, _, _, lens = orc.alg2_plain(np.abs(A[:, k].astype(np.int64)), N, 1)
+            executed += sum(max(x - 1, 0) for x in lens[1:N])
+        assert st["table_adds"] == executed
+
+
+def test_plan_groups_reduce_accumulation():
+    A, _ = W.make_inputs(W.LARGE_T2)
+    s1 = pcmm.cussen_plan_stats(A, 2, pcmm.CussenCfg(4, 1, 0, 0))
+    for g in (2, 3, 4):
+        sg = pcmm.cussen_plan_stats(A, 2, pcmm.CussenCfg(4, g, 0, 0))
+        # one code per row segment: at most ceil(n / g) accumulations per row
+        assert sg["accum_adds"] <= A.shape[0] * ((A.shape[1] + g - 1) // g)
+        assert sg["accum_adds"] < s1["accum_adds"]
+        # a segment table holds at most 3^g... distinct segments up to sign
+        assert sg["max_entries"] <= min(A.shape[0], (4 ** g))
+
+
+def test_plan_headline_counts():
+    # 512 x 512, 4-bit: every column holds all 15 nonzero values, so each
+    # column compresses to one level-N multiplication and 15 + 1 + 1 counted
+    # additions (the (512, 4) cell of the paper's addition table, 17)
+    A, _ = W.make_inputs(W.LARGE_T4)
+    st = pcmm.cussen_plan_stats(A, 4)
+    assert st["level_mults"] == 512
+    assert st["level_adds"] == 512 * 17
+    assert st["table_adds"] == 512 * 14
+    assert st["max_entries"] == 15
+
+
+def test_validation_errors():
+    A = np.array([[0, 16]], dtype=np.uint8)
+    with pytest.raises(pcmm.PCMMError) as ei:
+        pcmm.cussen_plan_stats(A, 4)
+    assert ei.value.code == -2  # PCMM_ERANGE: 16 is not a 4-bit value
+    A = np.array([[-9, 1]], dtype=np.int8)
+    with pytest.raises(pcmm.PCMMError) as ei:
+        pcmm.cussen_plan_stats(A, 4)
+    assert ei.value.code == -2  # -9 is not a signed 4-bit value
+    A = np.array([[-8, 7]], dtype=np.int8)
+    pcmm.cussen_plan_stats(A, 4)
+    with pytest.raises(pcmm.PCMMError) as ei:
+        pcmm.cussen_plan_stats(A, 9)
+    assert ei.value.code == -1
+    with pytest.raises(pcmm.PCMMError) as ei:
+        pcmm.cussen_plan_stats(A, 4, pcmm.CussenCfg(4, 5, 0, 0))  # group > 4
+    assert ei.value.code == -1
+    with pytest.raises(pcmm.PCMMError) as ei:
+        pcmm.cussen_plan_stats(A, 4, pcmm.CussenCfg(4, 1, 3, 0))  # split not a power of two
+    assert ei.value.code == -1
+
+
+def test_null_and_shape_errors_are_host_side():
+    L = pcmm.lib()
+    # schoolbook with a null B: rejected before any device work
+    rc = L.pcmm_schoolbook(None, 1, 1, 4, 0, None, None, None, 0, None)
+    assert rc == -1
+    B = pcmm.Mat(2, 3, 2, pcmm.AFFINE, 64, 0x1000)
+    C = pcmm.Mat(1, 3, 2, pcmm.JACOBIAN, 64, 0x2000)
+    A = np.zeros((1, 5), dtype=np.uint8)  # n = 5 != B.rows
+    rc = L.pcmm_schoolbook(A.ctypes.data_as(ctypes.c_void_p), 1, 5, 4, 0, ctypes.byref(B),
+                           ctypes.byref(C), None, 0, None)
+    assert rc == -1
+    C_bad = pcmm.Mat(1, 3, 1, pcmm.JACOBIAN, 64, 0x2000)  # npts must be 2
+    A = np.zeros((1, 2), dtype=np.uint8)
+    rc = L.pcmm_schoolbook(A.ctypes.data_as(ctypes.c_void_p), 1, 2, 4, 0, ctypes.byref(B),
+                           ctypes.byref(C_bad), None, 0, None)
+    assert rc == -1
+    # workspace too small
+    rc = L.pcmm_schoolbook(A.ctypes.data_as(ctypes.c_void_p), 1, 2, 4, 0, ctypes.byref(B),
+                           ctypes.byref(C), None, 0, None)
+    assert rc == -3
+    # decrypt with a zero key
+    M = pcmm.Mat(2, 3, 1, pcmm.AFFINE, 64, 0x3000)
+    rc = L.pcmm_decrypt_to_points(bytes(32), ctypes.byref(B), ctypes.byref(M), None)
+    assert rc == -1
+    assert L.pcmm_normalize_workspace(1000, 2) >= 1000 * 2 * 32

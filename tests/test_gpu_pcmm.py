@@ -1,0 +1,213 @@
+"""GPU parity of PC-MM: schoolbook (Sec. 3.1) and Cussen (Alg. 3 with Alg. 2).
+
+Every output is a unique group element, so the bar is bit-exact equality of
+the canonical affine bytes.  Small and ragged shapes are compared element by
+element with the oracle's PC-MM on oracle-made inputs; the full-size workloads
+(in the launch configuration the benchmark uses) are compared on sampled
+outputs with the oracle's closed form of Eq. (ahe_5_elgamal), with every output
+also checked between the two GPU methods, and by decryption.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import log, random_cts, sample_positions
+from paper_2504_14497_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_14497_amd import pcmm
+    pcmm.lib()
+    return pcmm
+
+
+def _upload(dev, B):
+    n, l, _ = B.shape
+    return dev.DevPoints.from_host(B.reshape(-1, 128), n, l, 2)
+
+
+def _run_both(dev, A, bits, Bd, cfg=None):
+    Cs = dev.schoolbook(A, bits, Bd).to_host()
+    Cc, st = dev.cussen(A, bits, Bd, cfg=cfg)
+    return Cs, Cc.to_host(), st
+
+
+def test_tiny_workload_vs_oracle(dev, orc):
+    sh = W.TINY
+    A, msg = W.make_inputs(sh)
+    sk, pk = orc.keygen(sh.seed)
+    B = orc.encrypt(pk, msg, sh.seed)
+    log("tiny", sh)
+    Cs, Cc, st = _run_both(dev, A, sh.bits, _upload(dev, B))
+    want = orc.pcmm_cussen(A, B)
+    assert (want == orc.pcmm_schoolbook(A, B)).all()
+    assert (Cs == want).all()
+    assert (Cc == want).all()
+    assert st["level_mults"] > 0
+
+
+RAGGED = [
+    W.PCMMShape(1, 1, 1, 4, False, 4, seed=101),
+    W.PCMMShape(3, 5, 7, 3, False, 4, seed=102),
+    W.PCMMShape(65, 33, 17, 4, False, 4, seed=103),
+    W.PCMMShape(20, 30, 10, 8, True, 8, seed=104),
+    W.PCMMShape(130, 9, 3, 2, False, 4, seed=105),
+    W.PCMMShape(7, 70, 2, 1, False, 4, seed=106),
+    W.PCMMShape(40, 12, 33, 8, False, 8, seed=107),
+]
+
+
+@pytest.mark.parametrize("sh", RAGGED, ids=lambda s: f"{s.m}x{s.n}x{s.l}_t{s.bits}{'s' if s.signed else 'u'}")
+def test_ragged_shapes_vs_oracle(dev, orc, sh):
+    A, _ = W.make_inputs(sh)
+    B = random_cts(orc, sh.n, sh.l, sh.seed)
+    log("ragged", sh)
+    Cs, Cc, _ = _run_both(dev, A, sh.bits, _upload(dev, B))
+    want = orc.pcmm_cussen(A, B)
+    assert (Cs == want).all()
+    assert (Cc == want).all()
+
+
+@pytest.mark.parametrize("group", [1, 2, 3, 4])
+@pytest.mark.parametrize("rounds", [1, 2, 4])
+def test_cussen_configurations_vs_oracle(dev, orc, group, rounds):
+    rng = np.random.default_rng(group * 10 + rounds)
+    B = random_cts(orc, 24, 6, 200)
+    want = {}
+    for name, A, bits in (("u4", rng.integers(0, 16, size=(40, 24)).astype(np.uint8), 4),
+                          ("s3", rng.integers(-4, 4, size=(40, 24)).astype(np.int8), 3)):
+        ref = orc.pcmm_cussen(A, B)
+        Bd = _upload(dev, B)
+        for split in (1, 2, 4):
+            cfg = dev.CussenCfg(rounds, group, split, 0)
+            log("cfg", name, group, rounds, split)
+            C, st = dev.cussen(A, bits, Bd, cfg=cfg)
+            assert (C.to_host() == ref).all(), (name, group, rounds, split)
+        # small LDS chunks (one group staged at a time)
+        C, _ = dev.cussen(A, bits, Bd, cfg=dev.CussenCfg(rounds, group, 2, 1))
+        assert (C.to_host() == ref).all()
+
+
+def test_exceptional_cases_vs_oracle(dev, orc):
+    # equal ciphertexts down a column (accumulator meets P = Q, tables meet
+    # P = Q through repeated differences) and opposite ones (P = -Q)
+    B = random_cts(orc, 6, 3, 300)
+    B[1] = B[0]
+    B[3] = B[0]
+    for j in range(3):
+        for h in range(2):
+            P_ = bytes(B[0, j, 64 * h:64 * h + 64])
+            B[2, j, 64 * h:64 * h + 64] = np.frombuffer(orc.pt_neg(P_), dtype=np.uint8)
+    B[5, 1] = 0  # an infinity point inside B
+    A = np.array([[1, 1, 0, 0, 0, 2], [1, 0, 1, 0, 3, 0], [3, 3, 6, 1, 0, 1], [2, 0, 2, 5, 1, 1],
+                  [1, 2, 3, 4, 5, 6], [7, 7, 7, 7, 7, 7], [-1, 1, 1, -1, 2, -2], [0, 0, 0, 0, 0, 0]],
+                 dtype=np.int8)
+    want = orc.pcmm_cussen(A, B)
+    Bd = _upload(dev, B)
+    log("exceptional")
+    Cs, Cc, _ = _run_both(dev, A, 4, Bd)
+    assert (Cs == want).all()
+    assert (Cc == want).all()
+    for g in (2, 3):
+        C, _ = dev.cussen(A, 4, Bd, cfg=dev.CussenCfg(4, g, 2, 0))
+        assert (C.to_host() == want).all()
+    assert (want[7] == 0).all()
+
+
+def test_degenerate_sizes(dev, orc):
+    B = random_cts(orc, 3, 4, 400)
+    Bd = _upload(dev, B)
+    log("degenerate")
+    # zero rows
+    C, _ = dev.cussen(np.zeros((0, 3), np.uint8), 4, Bd)
+    assert C.to_host().shape == (0, 4, 128)
+    # A = 0 -> every output is the identity
+    for method in ("schoolbook", "cussen"):
+        A = np.zeros((5, 3), np.uint8)
+        out = dev.schoolbook(A, 4, Bd) if method == "schoolbook" else dev.cussen(A, 4, Bd)[0]
+        assert (out.to_host() == 0).all()
+    # empty inner dimension
+    B0 = dev.DevPoints.empty(0, 4, 2, dev.AFFINE)
+    C, _ = dev.cussen(np.zeros((2, 0), np.uint8), 4, B0)
+    assert (C.to_host() == 0).all()
+    # the identity matrix returns B; A = e_i e_k^T picks one ciphertext
+    I = np.eye(3, dtype=np.uint8)
+    C, _ = dev.cussen(I, 1, Bd)
+    assert (C.to_host() == B).all()
+    E = np.zeros((4, 3), np.uint8)
+    E[2, 1] = 1
+    C = dev.cussen(E, 1, Bd)[0].to_host()
+    assert (C[2] == B[1]).all() and (C[[0, 1, 3]] == 0).all()
+
+
+def test_out_of_range_is_rejected(dev, orc):
+    B = random_cts(orc, 2, 2, 500)
+    Bd = _upload(dev, B)
+    with pytest.raises(dev.PCMMError) as ei:
+        dev.cussen(np.array([[16, 0]], np.uint8), 4, Bd)
+    assert ei.value.code == -2
+    with pytest.raises(dev.PCMMError) as ei:
+        dev.schoolbook(np.array([[-3, 0]], np.int8), 2, Bd)
+    assert ei.value.code == -2
+
+
+def _full_size(dev, orc, sh, cfg=None, n_samples=24, check_schoolbook=True):
+    """The benchmark's path: GPU keygen + encrypt from the seed, Cussen with the
+    default (autotuned-free) configuration, canonical affine output."""
+    import torch
+    A, msg = W.make_inputs(sh)
+    log("full size", sh.name, "keygen+encrypt")
+    sk, pk = dev.keygen(sh.seed)
+    Bd = dev.encrypt(pk, msg, sh.seed)
+    log("full size", sh.name, "cussen")
+    Cc, st = dev.cussen(A, sh.bits, Bd, cfg=cfg)
+    torch.cuda.synchronize()
+    C = Cc.to_host()
+    ii, jj = sample_positions(sh.m, sh.l, n_samples, sh.seed)
+    osk = int.from_bytes(sk, "big")
+    log("full size", sh.name, "closed form on", len(ii), "outputs")
+    want = orc.pcmm_closed_form(A, sh.l, osk, msg, sh.seed, ii, jj)
+    got = C[ii, jj]
+    assert (got == want).all()
+    # decryption of the sampled outputs gives (A.B) G
+    AB = A.astype(np.int64) @ msg.astype(np.int64)
+    p_, b_, gx, gy, q = orc.curve_params()
+    G = orc.generator()
+    M = dev.decrypt_to_points(sk, Cc).to_host()
+    for i, j in list(zip(ii, jj))[:6]:
+        assert bytes(M[i, j]) == orc.ladder_big(int(AB[i, j]) % q, G)
+    if check_schoolbook:
+        log("full size", sh.name, "schoolbook")
+        Cs = dev.schoolbook(A, sh.bits, Bd).to_host()
+        assert (Cs == C).all()
+    return st
+
+
+def test_full_size_large_t4(dev, orc):
+    st = _full_size(dev, orc, W.LARGE_T4)
+    assert st["accum_adds"] == int(np.count_nonzero(W.make_inputs(W.LARGE_T4)[0]))
+
+
+def test_full_size_large_t2(dev, orc):
+    _full_size(dev, orc, W.LARGE_T2, check_schoolbook=False)
+    _full_size(dev, orc, W.LARGE_T2, cfg=dev_cfg(3), n_samples=8, check_schoolbook=False)
+
+
+def dev_cfg(group):
+    from paper_2504_14497_amd import pcmm
+    return pcmm.CussenCfg(4, group, 0, 0)
+
+
+def test_full_size_signed128(dev, orc):
+    _full_size(dev, orc, W.SIGNED128)
+    _full_size(dev, orc, W.SIGNED128, cfg=dev_cfg(2), n_samples=8, check_schoolbook=False)
+
+
+def test_full_size_serve_layer(dev, orc):
+    # 256 x 1024 times 1024 x 8: the split-k path with the wavefront reduction
+    _full_size(dev, orc, W.SERVE_LAYER, n_samples=12, check_schoolbook=False)

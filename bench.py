@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark: PC-MM/s and point-additions/s of Cussen PC-MM on one MI355X.
+
+Workload (default): A 512 x 512 uniform unsigned 4-bit, B 512 x 512 EC-ElGamal
+ciphertexts on P-256 of uniform 4-bit messages (seeded, synthetic).  One step
+is one complete PC-MM by Cussen's method (Alg. 3 with Alg. 2, N = 4 rounds,
+one column of A per compression): the host compression plan, its upload, the
+table build with batched inversion, the gather-and-add accumulation and the
+affine normalisation of C, with A on the host and B already resident in HBM.
+The schoolbook method (Sec. 3.1) runs on the same inputs for the speedup.
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PC-MM/s + point-adds/s at 512x512 4-bit; Cussen vs schoolbook, batched vs single"
+
+# MI355X figures used for the roofline (the path is bound by 32-bit VALU work):
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s; the
+# 32x32 -> 64-bit multiply-add issues at full rate on gfx950 (measured by the
+# probe in the diagnostics), so the INT32 multiply-add peak is the same figure.
+PEAK_INT32_MAD = 256 * 64 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic 32x32 multiply-adds of the textbook 8 x 32-bit field operations:
+# a product is 64, a square 36 (the 28 cross products counted once); the P-256
+# Montgomery reduction needs none (its digits of p are 0, 1 and 2^32 - 1)
+MADS_MUL, MADS_SQR = 64, 36
+MADS_MIXED_ADD = 7 * MADS_MUL + 4 * MADS_SQR        # 592 (madd-2007-bl, 7M + 4S)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fp.hpp", "ec.hpp", "common.hpp", "k_cussen.hip"):
+        with open(os.path.join(ROOT, "paper_2504_14497_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload):
+    """HBM bytes per launch of the accumulation kernel from the committed
+    counter summary, or None if missing or taken on different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"accumulate_{workload}_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(sh, A, target_seconds, threads):
+    """The CPU oracle's Cussen PC-MM on a bounded sample of output columns.
+
+    The sample's ciphertexts are encrypted by the oracle itself (same seed and
+    nonce indices as the full matrix), so the sampled columns of the GPU
+    result can be compared with it."""
+    import oracle
+    from paper_2504_14497_amd import workloads as W
+    _, msg = W.make_inputs(sh)
+    sk, pk = oracle.keygen(sh.seed)
+    t0 = time.time()
+    B = oracle.encrypt_columns(pk, msg, [0], sh.seed, nthreads=threads)
+    t_enc = time.time() - t0
+    t0 = time.time()
+    oracle.pcmm_cussen(A, B, cols=[0], nthreads=1)
+    t_one = time.time() - t0
+    ncols = int(target_seconds / max(t_one, 1e-3) * threads)
+    ncols = max(1, min(sh.l, (ncols // threads) * threads if ncols >= threads else ncols))
+    cols = list(range(ncols))
+    log(f"cpu baseline: one column {t_one:.2f} s, its encryption {t_enc:.2f} s; "
+        f"sampling {ncols} columns on {threads} threads")
+    B = oracle.encrypt_columns(pk, msg, cols, sh.seed, nthreads=threads)
+    t0 = time.time()
+    C = oracle.pcmm_cussen(A, B, cols=cols, nthreads=threads)
+    dt = time.time() - t0
+    return {"value": (ncols / sh.l) / dt, "unit": "PC-MM/s", "cores": threads, "kind": "oracle",
+            "sample": f"{ncols} of {sh.l} output columns of the same workload (all {sh.m} rows, both "
+                      f"points, compression of all {sh.n} columns of A), scaled by {sh.l}/{ncols}; "
+                      f"{dt:.1f} s wall on {threads} threads"}, C, cols
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large512_t4")
+    ap.add_argument("--group", type=int, default=0, help="Cussen column group g (0 = library default)")
+    ap.add_argument("--school-steps", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2504_14497_amd import costmodel as cm
+    from paper_2504_14497_amd import pcmm, workloads as W
+
+    pcmm.lib()
+    dev = pcmm.device_info()
+    sh = W.NAMED[args.workload]
+    A, msg = W.make_inputs(sh)
+    log(f"device {dev}; workload {sh}")
+    sk, pk = pcmm.keygen(sh.seed)
+    B = pcmm.encrypt(pk, msg, sh.seed)
+    torch.cuda.synchronize()
+
+    cfg = pcmm.CussenCfg(4, args.group, 0, 0, 1)  # profile: per-stage HIP events
+    C = pcmm.DevPoints.empty(sh.m, sh.l, 2, pcmm.AFFINE)
+    ws = torch.empty(pcmm.cussen_workspace_bytes(A, sh.bits, sh.l, pcmm.AFFINE, cfg),
+                     dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        pcmm.cussen(A, sh.bits, B, cfg=cfg, workspace=ws, out=C)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    stats = []
+    torch.cuda.synchronize()
+    t_wall = time.time()
+    e0.record(stream)
+    for _ in range(args.steps):
+        _, st = pcmm.cussen(A, sh.bits, B, cfg=cfg, workspace=ws, out=C)
+        stats.append(st)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.time() - t_wall
+    ms_step = e0.elapsed_time(e1) / args.steps
+    pcmm_per_s = 1000.0 / ms_step
+
+    st0 = stats[0]
+    per_col_muls, per_col_adds = st0["level_mults"], st0["level_adds"]
+    paper_adds = (4 * sh.bits * sh.l * per_col_muls + 2 * sh.l * per_col_adds
+                  + 2 * sh.m * sh.l * (sh.n - 1))
+    executed_adds = 2 * sh.l * (st0["table_adds"] + st0["accum_adds"])
+    stage = {k: float(np.mean([s[k] for s in stats])) for k in
+             ("ms_upload", "ms_table", "ms_accumulate", "ms_reduce", "ms_normalize", "ms_total")}
+
+    # schoolbook on the same inputs
+    Cs = pcmm.DevPoints.empty(sh.m, sh.l, 2, pcmm.AFFINE)
+    wss = torch.empty(pcmm.lib().pcmm_schoolbook_workspace(sh.m, sh.n, sh.l, pcmm.AFFINE),
+                      dtype=torch.uint8, device="cuda")
+    pcmm.schoolbook(A, sh.bits, B, workspace=wss)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(args.school_steps):
+        Cs = pcmm.schoolbook(A, sh.bits, B, workspace=wss)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms_school = s0.elapsed_time(s1) / args.school_steps
+    same = bool((Cs.to_host() == C.to_host()).all())
+
+    # roofline of the dominant kernel (accumulation): algorithmic multiply-adds
+    madds = 2 * sh.l * st0["accum_adds"]
+    acc_ms = stage["ms_accumulate"]
+    achieved = madds * MADS_MIXED_ADD / (acc_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_INT32_MAD / 1e12,
+                "unit": "TOP/s (32x32->64-bit multiply-adds)", "frac": achieved / (PEAK_INT32_MAD / 1e12),
+                "traffic": load_traffic(sh.name), "kernel": "accumulate_kernel",
+                "kernel_ms": acc_ms, "mixed_adds_per_launch": madds,
+                "mads_per_mixed_add": MADS_MIXED_ADD}
+
+    out = {
+        "metric": METRIC, "value": pcmm_per_s, "unit": "PC-MM/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic (seeded uniform plaintexts; ciphertexts encrypted on the GPU)",
+        "config": {"workload": f"{sh.name}: A {sh.m}x{sh.n} uniform {'signed' if sh.signed else 'unsigned'} "
+                               f"{sh.bits}-bit x B {sh.n}x{sh.l} EC-ElGamal/P-256 ciphertexts of uniform "
+                               f"{sh.msg_bits}-bit messages; Cussen N=4, g={args.group or 1}, "
+                               f"canonical affine output",
+                   "m": sh.m, "n": sh.n, "l": sh.l, "bits": sh.bits, "seed": sh.seed},
+        "point_adds_per_s": paper_adds / (ms_step * 1e-3),
+        "paper_model_point_adds": paper_adds,
+        "executed_point_adds_per_s": executed_adds / (ms_step * 1e-3),
+        "stage_ms": stage,
+        "wall_s": t_wall,
+        "schoolbook": {"value": 1000.0 / ms_school, "unit": "PC-MM/s", "ms_per_step": ms_school,
+                       "point_adds_per_s": cm.schoolbook_equiv_adds(sh.m, sh.n, sh.l, sh.bits)
+                       / (ms_school * 1e-3), "same_output_as_cussen": same},
+        "speedup_cussen_vs_schoolbook": ms_school / ms_step,
+        "roofline": roofline,
+        "device": dev,
+    }
+    if not args.no_cpu_baseline:
+        threads = max(1, min(os.cpu_count() or 1, 16))
+        base, Corc, cols = cpu_baseline(sh, A, args.cpu_seconds, threads)
+        Cg = C.to_host()
+        base["parity_on_sample"] = bool((Cg[:, cols] == Corc[:, cols]).all())
+        out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -87,12 +87,16 @@ typedef struct {
  *           one code and builds the table of their ciphertext combinations)
  *   k_split split of the n (inner) dimension over independent partial sums that
  *           are then added (0 = chosen from the shape)
- *   k_chunk columns of A whose tables are staged in LDS at once (0 = auto)  */
+ *   k_chunk columns of A whose tables are staged in LDS at once (0 = auto)
+ *   profile nonzero: record HIP events around every launch of the call on
+ *           its stream, wait for them, and return per-stage durations in the
+ *           stats (the call then returns after its GPU work has finished) */
 typedef struct {
     int32_t rounds;
     int32_t group;
     int32_t k_split;
     int32_t k_chunk;
+    int32_t profile;
 } pcmm_cussen_cfg;
 
 /* Operation counts of one pcmm_cussen call, derived from its plan. */
@@ -103,6 +107,10 @@ typedef struct {
     int64_t table_adds;      /* point additions executed per output column to build tables */
     int64_t accum_adds;      /* mixed additions executed per output column (all rows)      */
     int64_t max_entries;     /* largest table (entries) of one column (group)              */
+    int32_t k_split;         /* split of the inner dimension that was used                 */
+    int32_t lanes_per_chain; /* table-build batch: output columns per lane                 */
+    /* with cfg->profile: milliseconds from the first to the last event of each stage */
+    float ms_upload, ms_table, ms_accumulate, ms_reduce, ms_normalize, ms_total;
 } pcmm_cussen_stats;
 
 /* KeyGen (Sec. 2.4): x = scalar(seed, domain 0, index 0) in [1, q-1] and the

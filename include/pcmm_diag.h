@@ -44,6 +44,11 @@ pcmm_status pcmm_diag_point(int32_t op, const pcmm_mat *P, const pcmm_mat *Q, co
 pcmm_status pcmm_diag_probe(int32_t kind, int64_t iters, int32_t blocks, double *seconds,
                             double *ops);
 
+/* Copy `words` 32-bit words from src to dst (device).  A kernel of known
+ * traffic (4 * words bytes read and written once) used to calibrate hardware
+ * memory-traffic counters. */
+pcmm_status pcmm_diag_copy(const uint32_t *src, uint32_t *dst, int64_t words, void *stream);
+
 /* Device properties used for roofline figures. */
 pcmm_status pcmm_diag_device(int32_t *cus, int32_t *clock_khz, int64_t *lds_per_block,
                              char name[64]);

@@ -41,6 +41,8 @@ def lib():
         L.oracle_keygen.argtypes = [ctypes.c_uint64, vp, vp]
         L.oracle_encrypt.argtypes = [u8p, vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, vp,
                                      ctypes.c_int]
+        L.oracle_encrypt_indexed.argtypes = [u8p, vp, vp, ctypes.c_int64, ctypes.c_uint64, vp,
+                                             ctypes.c_int]
         L.oracle_decrypt_to_points.argtypes = [u8p, vp, ctypes.c_int64, vp, ctypes.c_int]
         L.oracle_alg2_plain.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp, vp,
                                         vp]
@@ -171,6 +173,32 @@ def encrypt(pk: bytes, msg, seed: int, idx0: int = 0, nthreads=None) -> np.ndarr
     _check(lib().oracle_encrypt(pk, _ptr(m), m.size, seed, idx0, _ptr(out),
                                 nthreads or default_threads()), "encrypt")
     return out.reshape(tuple(np.shape(msg)) + (128,))
+
+
+def encrypt_indexed(pk: bytes, msg, idx, seed: int, nthreads=None) -> np.ndarray:
+    """Element e encrypted with the nonce of index idx[e] (flat arrays)."""
+    m = np.ascontiguousarray(np.asarray(msg, dtype=np.int32).reshape(-1))
+    ix = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1))
+    if m.size != ix.size:
+        raise ValueError("msg and idx differ in length")
+    out = np.zeros((m.size, 128), dtype=np.uint8)
+    _check(lib().oracle_encrypt_indexed(pk, _ptr(m), _ptr(ix), m.size, seed, _ptr(out),
+                                        nthreads or default_threads()), "encrypt_indexed")
+    return out
+
+
+def encrypt_columns(pk: bytes, msg, cols, seed: int, nthreads=None) -> np.ndarray:
+    """Ciphertexts of msg[:, j] for j in cols with the nonces of their
+    positions in the full n x l matrix (index k * l + j); returns an n x l
+    array with only those columns filled."""
+    msg = np.asarray(msg, dtype=np.int32)
+    n, l = msg.shape
+    cols = list(cols)
+    kk, jj = np.meshgrid(np.arange(n), np.asarray(cols, dtype=np.int64), indexing="ij")
+    cts = encrypt_indexed(pk, msg[:, cols].reshape(-1), (kk * l + jj).reshape(-1), seed, nthreads)
+    B = np.zeros((n, l, 128), dtype=np.uint8)
+    B[:, cols] = cts.reshape(n, len(cols), 128)
+    return B
 
 
 def decrypt_to_points(sk: int, ct: np.ndarray, nthreads=None) -> np.ndarray:

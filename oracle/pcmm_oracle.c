@@ -720,13 +720,14 @@ typedef struct {
     const int32_t *msg;
     uint64_t seed;
     int64_t idx0;
+    const int64_t *idx; /* optional explicit nonce indices */
     uint8_t *out;
 } enc_ctx;
 
 static void enc_item(void *vctx, int64_t e) {
     enc_ctx *c = (enc_ctx *)vctx;
     apt G = pt_generator();
-    u256 r = scalar_from_seed(c->seed, 1, (uint64_t)(c->idx0 + e));
+    u256 r = scalar_from_seed(c->seed, 1, (uint64_t)(c->idx ? c->idx[e] : c->idx0 + e));
     u256 mq = scalar_from_int(c->msg[e]);
     apt C1 = smul_big(&r, &G);
     apt rH = smul_big(&r, &c->H);
@@ -745,6 +746,22 @@ int oracle_encrypt(const uint8_t pk[64], const int32_t *msg, int64_t count, uint
     c.msg = msg;
     c.seed = seed;
     c.idx0 = idx0;
+    c.idx = NULL;
+    c.out = ct_out;
+    run_parallel(enc_item, &c, count, nthreads);
+    return 0;
+}
+
+int oracle_encrypt_indexed(const uint8_t pk[64], const int32_t *msg, const int64_t *idx, int64_t count,
+                           uint64_t seed, uint8_t *ct_out, int nthreads) {
+    params();
+    if (count < 0 || (count > 0 && !idx)) return -1;
+    enc_ctx c;
+    c.H = pt_from_bytes(pk);
+    c.msg = msg;
+    c.seed = seed;
+    c.idx0 = 0;
+    c.idx = idx;
     c.out = ct_out;
     run_parallel(enc_item, &c, count, nthreads);
     return 0;

@@ -48,7 +48,9 @@ int oracle_repeated_add(uint64_t k, const uint8_t P[64], uint8_t R[64]);
 
 /* Scalar derivation for keys and nonces (counter-based, SplitMix64 mixing).
  * domain 0 = secret key, 1 = encryption nonce; idx = element index.
- * Result in [1, q-1], big-endian. */
+ * Result in [1, q-1], big-endian.  Parity unpinned: this is a project
+ * convention (the paper only says "uniform in [1, q-1]"); the tests check its
+ * range and spread, and that the GPU library derives the same scalars. */
 void oracle_scalar_from_seed(uint64_t seed, uint64_t domain, uint64_t idx, uint8_t out[32]);
 
 /* EC-ElGamal (Sec. 2.4).  keygen: x from (seed, 0, 0), H = xG.
@@ -57,6 +59,9 @@ void oracle_scalar_from_seed(uint64_t seed, uint64_t domain, uint64_t idx, uint8
 int oracle_keygen(uint64_t seed, uint8_t sk[32], uint8_t pk[64]);
 int oracle_encrypt(const uint8_t pk[64], const int32_t *msg, int64_t count, uint64_t seed,
                    int64_t idx0, uint8_t *ct_out, int nthreads);
+/* Encrypt with explicit nonce indices: element e uses r = scalar(seed, 1, idx[e]). */
+int oracle_encrypt_indexed(const uint8_t pk[64], const int32_t *msg, const int64_t *idx, int64_t count,
+                           uint64_t seed, uint8_t *ct_out, int nthreads);
 int oracle_decrypt_to_points(const uint8_t sk[32], const uint8_t *ct, int64_t count,
                              uint8_t *pt_out, int nthreads);
 

@@ -285,7 +285,7 @@ struct geometry {
 bool valid_cfg(const pcmm_cussen_cfg *cfg) {
     if (!cfg) return true;
     if (cfg->rounds < 0 || cfg->rounds > 8 || cfg->group < 0 || cfg->group > 4 || cfg->k_split < 0 ||
-        cfg->k_split > 64 || cfg->k_chunk < 0)
+        cfg->k_split > 64 || cfg->k_chunk < 0 || cfg->profile < 0)
         return false;
     if (cfg->k_split > 0 && (cfg->k_split & (cfg->k_split - 1))) return false;
     return true;
@@ -350,6 +350,22 @@ geometry make_geometry(const cussen_plan &P, int l, int c_form, const pcmm_cusse
     return G;
 }
 
+// events bracketing the stages of one profiled call
+struct stage_events {
+    hipEvent_t e[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipError_t create() {
+        for (auto &x : e) {
+            hipError_t r = hipEventCreate(&x);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    ~stage_events() {
+        for (auto &x : e)
+            if (x) hipEventDestroy(x);
+    }
+};
+
 // pinned staging for plan uploads, one per device; an event guards reuse
 struct staging {
     void *host = nullptr;
@@ -405,6 +421,7 @@ pcmm_status check_mats(int m, int n, const pcmm_mat *B, const pcmm_mat *C) {
 
 void fill_stats(const cussen_plan &P, pcmm_cussen_stats *st) {
     if (!st) return;
+    memset(st, 0, sizeof *st);
     st->level_mults = P.level_mults;
     st->level_adds = P.level_adds;
     st->table_entries = P.table_entries;
@@ -473,9 +490,18 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
     }
     geometry G = make_geometry(P, l, C->form, cfg);
     if (!workspace || ws_bytes < G.total) return PCMM_ENOMEM;
+    if (stats) {
+        stats->k_split = G.S;
+        stats->lanes_per_chain = G.J;
+    }
     char *ws = (char *)workspace;
+    const bool prof = cfg && cfg->profile;
+    stage_events ev;
+    if (prof) PCMM_HIP_TRY(ev.create());
+    if (prof) hipEventRecord(ev.e[0], s);
     st = upload_plan(P, ws + G.off_plan, s);
     if (st != PCMM_OK) return st;
+    if (prof) hipEventRecord(ev.e[1], s);
     // device views of the plan
     size_t off = 0;
     auto view = [&](size_t n_bytes) {
@@ -512,6 +538,7 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
         hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ta);
         PCMM_LAUNCH_CHECK();
     }
+    if (prof) hipEventRecord(ev.e[2], s);
     const int64_t ldc = std::max<int64_t>(64, (n_out + 63) / 64 * 64);
     const bool affine_out = C->form == PCMM_AFFINE;
     uint32_t *jac_out = affine_out ? (uint32_t *)(ws + G.off_cjac) : C->d;
@@ -544,6 +571,7 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
         hipLaunchKernelGGL(accumulate_kernel, grid, dim3(256), G.lds_bytes, s, aa);
         PCMM_LAUNCH_CHECK();
     }
+    if (prof) hipEventRecord(ev.e[3], s);
     if (G.S > 1) {
         int64_t threads = 2 * n_out * G.S;
         int64_t blocks = (threads + 255) / 256;
@@ -551,9 +579,21 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
                            G.S, n_out, jac_out, ld_jac, affine_out ? 0 : 1);
         PCMM_LAUNCH_CHECK();
     }
+    if (prof) hipEventRecord(ev.e[4], s);
     if (affine_out) {
-        return launch_normalize(jac_out, ld_jac, true, C->d, C->ld, false, n_out, 2, ws + G.off_norm,
-                                G.total - G.off_norm, s);
+        st = launch_normalize(jac_out, ld_jac, true, C->d, C->ld, false, n_out, 2, ws + G.off_norm,
+                              G.total - G.off_norm, s);
+        if (st != PCMM_OK) return st;
+    }
+    if (prof) {
+        hipEventRecord(ev.e[5], s);
+        PCMM_HIP_TRY(hipEventSynchronize(ev.e[5]));
+        if (stats) {
+            float *dst[5] = {&stats->ms_upload, &stats->ms_table, &stats->ms_accumulate, &stats->ms_reduce,
+                             &stats->ms_normalize};
+            for (int i = 0; i < 5; ++i) hipEventElapsedTime(dst[i], ev.e[i], ev.e[i + 1]);
+            hipEventElapsedTime(&stats->ms_total, ev.e[0], ev.e[5]);
+        }
     }
     return PCMM_OK;
 }

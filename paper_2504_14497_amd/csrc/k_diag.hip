@@ -160,7 +160,25 @@ __global__ void __launch_bounds__(256) probe_madd_kernel(uint32_t *out, uint32_t
     if (s == (0x12345678u ^ tid ^ seed)) out[tid] = s;
 }
 
+__global__ void __launch_bounds__(256) copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                   int64_t n4) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n4; x += (int64_t)gridDim.x * blockDim.x)
+        dst[x] = src[x];
+}
+
 }  // namespace
+
+extern "C" pcmm_status pcmm_diag_copy(const uint32_t *src, uint32_t *dst, int64_t words, void *stream) {
+    if (words < 0 || (words > 0 && (!src || !dst)) || (words & 3) || (((uintptr_t)src | (uintptr_t)dst) & 15))
+        return PCMM_EINVAL;
+    if (words == 0) return PCMM_OK;
+    int64_t n4 = words / 4;
+    int64_t blocks = std::min<int64_t>((n4 + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (const uint4 *)src,
+                       (uint4 *)dst, n4);
+    PCMM_LAUNCH_CHECK();
+    return PCMM_OK;
+}
 
 extern "C" pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint32_t *b,
                                        uint32_t *out, int64_t count, void *stream) {

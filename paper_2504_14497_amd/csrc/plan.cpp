@@ -17,38 +17,54 @@ inline int16_t base_operand(int t) { return (int16_t)(-1 - t); }
 // (or INT16_MIN for a zero entry).
 struct column_result {
     std::vector<int16_t> row_operand;  // per row
+    std::vector<int16_t> level1;       // operand of each distinct nonzero value, ascending
+    std::vector<int> row_rank;         // per row: rank of |a| among them, -1 for zero
     int64_t nN = 0, adds_counted = 0;
 };
 
 column_result compress_column(const std::vector<int> &vals, int N, int t, std::vector<plan_op> &ops,
                               int *nreg, int64_t *mul_bits) {
+    // Every value here is below 256 (|a| of an at most 8-bit entry, and the
+    // differences of sorted distinct such values), so "sort and eliminate
+    // duplicates" is a 256-entry presence table scanned in order, and the
+    // tracking pointer of a value is its rank in that table.
     const int m = (int)vals.size();
     column_result res;
     res.row_operand.assign(m, INT16_MIN);
-    // levels: level[w] = sorted unique nonzero values (then differenced if w < N)
     std::vector<std::vector<int>> level(N + 1);
-    std::vector<std::vector<int>> ptr(N + 1);  // ptr[w][i]: position in level w of element i of level w-1
-    level[0] = vals;
-    for (int w = 1; w <= N; ++w) {
-        const std::vector<int> &src = level[w - 1];
-        std::vector<int> u;
-        u.reserve(src.size());
-        for (int v : src)
-            if (v != 0) u.push_back(v);
-        std::sort(u.begin(), u.end());
-        u.erase(std::unique(u.begin(), u.end()), u.end());
-        ptr[w].resize(src.size());
-        for (size_t i = 0; i < src.size(); ++i) {
-            if (src[i] == 0) {
-                ptr[w][i] = -1;
-            } else {
-                ptr[w][i] = (int)(std::lower_bound(u.begin(), u.end(), src[i]) - u.begin());
+    int rank[256];
+    // level 1 from the rows
+    {
+        bool present[256] = {false};
+        for (int v : vals) present[v] = true;
+        present[0] = false;  // zeros are dropped: 0 * B needs no operation
+        for (int v = 1; v < 256; ++v)
+            if (present[v]) {
+                rank[v] = (int)level[1].size();
+                level[1].push_back(v);
             }
+    }
+    std::vector<int> row_rank(m);
+    for (int i = 0; i < m; ++i) row_rank[i] = vals[i] == 0 ? -1 : rank[vals[i]];
+    // ptr[w][i] for w >= 2: rank in level w of element i of level w-1
+    std::vector<std::vector<int>> ptr(N + 1);
+    for (int w = 1; w <= N; ++w) {
+        if (w >= 2) {
+            const std::vector<int> &src = level[w - 1];
+            bool present[256] = {false};
+            for (int v : src) present[v] = true;
+            for (int v = 1; v < 256; ++v)
+                if (present[v]) {
+                    rank[v] = (int)level[w].size();
+                    level[w].push_back(v);
+                }
+            ptr[w].resize(src.size());
+            for (size_t i = 0; i < src.size(); ++i) ptr[w][i] = rank[src[i]];
         }
         if (w != N) {
+            std::vector<int> &u = level[w];
             for (int i = (int)u.size() - 1; i >= 1; --i) u[i] -= u[i - 1];
         }
-        level[w] = std::move(u);
     }
     res.nN = (int64_t)level[N].size();
     for (int w = 1; w < N; ++w) res.adds_counted += (int64_t)level[w].size();
@@ -94,7 +110,9 @@ column_result compress_column(const std::vector<int> &vals, int N, int t, std::v
     }
     // un-sort level 1 back to the rows
     for (int i = 0; i < m; ++i)
-        if (ptr[1][i] >= 0) res.row_operand[i] = cur[ptr[1][i]];
+        if (row_rank[i] >= 0) res.row_operand[i] = cur[row_rank[i]];
+    res.level1 = std::move(cur);
+    res.row_rank = std::move(row_rank);
     return res;
 }
 
@@ -108,15 +126,17 @@ int build_cussen_plan(const int8_t *A, int m, int n, int bits, bool is_signed, i
     // validate A against the declared bit-width
     const int lo = is_signed ? -(1 << (bits - 1)) : 0;
     const int hi = is_signed ? (1 << (bits - 1)) - 1 : (1 << bits) - 1;
-    auto at = [&](int i, int k) -> int {
-        int8_t v = A[(int64_t)i * n + k];
-        return is_signed ? (int)v : (int)(uint8_t)v;
-    };
-    for (int i = 0; i < m; ++i)
+    // validate and transpose to column-major (columns are what gets compressed)
+    std::vector<int16_t> At((size_t)m * n);
+    for (int i = 0; i < m; ++i) {
+        const int8_t *row = A + (int64_t)i * n;
         for (int k = 0; k < n; ++k) {
-            int v = at(i, k);
+            int v = is_signed ? (int)row[k] : (int)(uint8_t)row[k];
             if (v < lo || v > hi) return -2;
+            At[(size_t)k * m + i] = (int16_t)v;
         }
+    }
+    auto at = [&](int i, int k) -> int { return At[(size_t)k * m + i]; };
     cussen_plan P;
     P.m = m;
     P.n = n;
@@ -133,13 +153,35 @@ int build_cussen_plan(const int8_t *A, int m, int n, int bits, bool is_signed, i
         int nreg = 0;
         // per-digit tables
         std::vector<std::vector<int16_t>> digit_operand(gg);
+        std::vector<int> vals(m);
         for (int t = 0; t < gg; ++t) {
-            std::vector<int> vals(m);
-            for (int i = 0; i < m; ++i) vals[i] = std::abs(at(i, k0 + t));
+            const int16_t *col = &At[(size_t)(k0 + t) * m];
+            for (int i = 0; i < m; ++i) vals[i] = std::abs((int)col[i]);
             column_result cr = compress_column(vals, N, t, P.ops, &nreg, &P.table_mul_bits);
             P.level_mults += cr.nN;
             P.level_adds += cr.adds_counted;
+            if (gg == 1) {
+                // one column: the table is the level-1 reconstruction itself,
+                // entry e = the e-th smallest distinct |a|; code = sign (e + 1)
+                for (int i = 0; i < m; ++i) {
+                    if (cr.row_rank[i] < 0) continue;
+                    P.codes[(size_t)grp * m + i] = (int16_t)(col[i] < 0 ? -(cr.row_rank[i] + 1) : cr.row_rank[i] + 1);
+                    ++P.accum_adds;
+                }
+                P.entries.insert(P.entries.end(), cr.level1.begin(), cr.level1.end());
+                P.max_entries = std::max(P.max_entries, (int)cr.level1.size());
+                P.table_entries += (int64_t)cr.level1.size();
+                break;
+            }
             digit_operand[t] = std::move(cr.row_operand);
+        }
+        if (gg == 1) {
+            if (nreg > 32000) return -1;
+            P.entry_begin.push_back((int32_t)P.entries.size());
+            P.op_begin.push_back((int32_t)P.ops.size());
+            P.nregs.push_back(nreg);
+            P.max_regs = std::max(P.max_regs, nreg);
+            continue;
         }
         // distinct row segments up to sign (first nonzero digit made positive);
         // a segment is keyed by its digits, 9 bits each

@@ -41,16 +41,21 @@ class PointBE(ctypes.Structure):
 
 class CussenCfg(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("group", ctypes.c_int32), ("k_split", ctypes.c_int32),
-                ("k_chunk", ctypes.c_int32)]
+                ("k_chunk", ctypes.c_int32), ("profile", ctypes.c_int32)]
 
 
 class CussenStats(ctypes.Structure):
     _fields_ = [("level_mults", ctypes.c_int64), ("level_adds", ctypes.c_int64),
                 ("table_entries", ctypes.c_int64), ("table_adds", ctypes.c_int64),
-                ("accum_adds", ctypes.c_int64), ("max_entries", ctypes.c_int64)]
+                ("accum_adds", ctypes.c_int64), ("max_entries", ctypes.c_int64),
+                ("k_split", ctypes.c_int32), ("lanes_per_chain", ctypes.c_int32),
+                ("ms_upload", ctypes.c_float), ("ms_table", ctypes.c_float),
+                ("ms_accumulate", ctypes.c_float), ("ms_reduce", ctypes.c_float),
+                ("ms_normalize", ctypes.c_float), ("ms_total", ctypes.c_float)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: (float(getattr(self, k)) if k.startswith("ms_") else int(getattr(self, k)))
+                for k, _ in self._fields_}
 
 
 _lib = None
@@ -85,6 +90,7 @@ _SIG = {
                          ctypes.POINTER(ctypes.c_double)], _I32),
     "pcmm_diag_device": ([ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64),
                           ctypes.c_char_p], _I32),
+    "pcmm_diag_copy": ([_VP, _VP, _I64, _VP], _I32),
 }
 
 EXPORTED = tuple(_SIG)
@@ -254,6 +260,13 @@ def diag_probe(kind: int, iters: int, blocks: int):
     o = ctypes.c_double()
     _call("pcmm_diag_probe", kind, iters, blocks, ctypes.byref(s), ctypes.byref(o))
     return s.value, o.value
+
+
+def diag_copy(src, dst, stream=None):
+    """Copy device tensor src into dst (same number of bytes, multiple of 16)."""
+    assert src.numel() * src.element_size() == dst.numel() * dst.element_size()
+    _call("pcmm_diag_copy", _tensor_ptr(src), _tensor_ptr(dst), src.numel() * src.element_size() // 4,
+          stream_ptr(stream))
 
 
 def device_info():

@@ -27,6 +27,16 @@ extern "C" {
 pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
                             int64_t count, void *stream);
 
+/* The same on the internal representation: operands and result are nine
+ * 29-bit limbs per element (Montgomery limbs, normal form: value < 2p, limbs
+ * 0..7 < 2^29, limb 8 < 2^25), limb w of element e at x[w * count + e], with
+ * no conversion.  op: 0 a+b, 1 a-b, 2 a*b (Montgomery), 3 a^2, 4 2(a-b),
+ * 5 3a, 6 4a, 7 -a, 8 full reduction (value < p), 9 2a, 10 normal form of
+ * arbitrary signed limbs a (|limb| < 2^30, 0 <= value < 2^259),
+ * 11 equality flag a = b (mod p) in limb 0, 12 zero flag a = 0 (mod p). */
+pcmm_status pcmm_diag_field_raw(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
+                                int64_t count, void *stream);
+
 /* Point operations, element-wise over count = P->rows * P->cols elements.
  * P, Q: affine npts 1.  k: device uint32 scalars (op 3).  R: Jacobian npts 1.
  * op: 0 P + Q by the mixed addition (P lifted to Z = 1);

@@ -13,41 +13,54 @@
 namespace pcmm {
 
 // ---------------------------------------------------------------------------
-// Structure-of-arrays point matrices: limb w of coordinate c of point pt of
-// element e lives at d[((pt * form + c) * 8 + w) * ld + e].
+// Structure-of-arrays point matrices at the library boundary: limb w (32-bit
+// word, canonical integer) of coordinate c of point pt of element e lives at
+// d[((pt * form + c) * 8 + w) * ld + e].
+// Internal workspaces keep Montgomery values in the same layout but with NL
+// (= 9) 29-bit limbs per coordinate: d[((pt * form + c) * NL + w) * ld + e].
 // ---------------------------------------------------------------------------
-struct soa {
-    uint32_t *d;
-    int64_t ld;
-    int32_t form;  // coordinates per point (2 affine, 3 Jacobian)
-};
+__device__ __forceinline__ fe fe_from_const(const fe_const &c) { return fe_from29(c_to29(c)); }
 
-__device__ __forceinline__ fe soa_load_raw(const uint32_t *__restrict__ d, int64_t ld, int plane,
-                                           int64_t e) {
+__device__ __forceinline__ bool fe_raw_eq(const fe &a, const fe &b) {
+    uint32_t x = 0;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x |= a.v[i] ^ b.v[i];
+    return x == 0;
+}
+
+// canonical words -> Montgomery limbs; values >= p are reduced
+__device__ __forceinline__ fe soa_load_mont(const uint32_t *__restrict__ d, int64_t ld, int plane,
+                                            int64_t e) {
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = d[(int64_t)(plane * 8 + k) * ld + e];
+    return fe_to_mont(fe_from_words(w));
+}
+
+// Montgomery limbs -> canonical words
+__device__ __forceinline__ void soa_store_canon(uint32_t *__restrict__ d, int64_t ld, int plane,
+                                                int64_t e, const fe &x) {
+    uint32_t w[8];
+    fe_to_words(fe_from_mont(x), w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d[(int64_t)(plane * 8 + k) * ld + e] = w[k];
+}
+
+// internal Montgomery limbs
+__device__ __forceinline__ fe soa_load_m(const uint32_t *__restrict__ d, int64_t ld, int plane, int64_t e) {
     fe r;
 #pragma unroll
-    for (int w = 0; w < 8; ++w) r.v[w] = d[(int64_t)(plane * 8 + w) * ld + e];
+    for (int w = 0; w < NL; ++w) r.v[w] = d[(int64_t)(plane * NL + w) * ld + e];
     return r;
 }
 
-__device__ __forceinline__ void soa_store_raw(uint32_t *__restrict__ d, int64_t ld, int plane,
-                                              int64_t e, const fe &x) {
+__device__ __forceinline__ void soa_store_m(uint32_t *__restrict__ d, int64_t ld, int plane, int64_t e,
+                                            const fe &x) {
 #pragma unroll
-    for (int w = 0; w < 8; ++w) d[(int64_t)(plane * 8 + w) * ld + e] = x.v[w];
+    for (int w = 0; w < NL; ++w) d[(int64_t)(plane * NL + w) * ld + e] = x.v[w];
 }
 
-// canonical limbs -> Montgomery; values >= p are reduced by the multiplication
-__device__ __forceinline__ fe soa_load_mont(const uint32_t *__restrict__ d, int64_t ld, int plane,
-                                            int64_t e) {
-    return fe_to_mont(soa_load_raw(d, ld, plane, e));
-}
-
-__device__ __forceinline__ void soa_store_canon(uint32_t *__restrict__ d, int64_t ld, int plane,
-                                                int64_t e, const fe &x) {
-    soa_store_raw(d, ld, plane, e, fe_from_mont(x));
-}
-
-// affine point `pt` of element e (form must be 2)
+// affine point `pt` of element e (form must be 2), canonical boundary layout
 __device__ __forceinline__ apt load_affine(const uint32_t *__restrict__ d, int64_t ld, int pt,
                                            int64_t e) {
     apt a;
@@ -78,23 +91,38 @@ __device__ __forceinline__ void store_jac(uint32_t *__restrict__ d, int64_t ld, 
     soa_store_canon(d, ld, pt * 3 + 2, e, j.Z);
 }
 
-// Montgomery-form Jacobian planes (internal workspaces keep Montgomery form
-// to skip conversions between kernels)
+// internal Montgomery Jacobian / affine points
 __device__ __forceinline__ jpt load_jac_m(const uint32_t *__restrict__ d, int64_t ld, int pt,
                                           int64_t e) {
     jpt j;
-    j.X = soa_load_raw(d, ld, pt * 3 + 0, e);
-    j.Y = soa_load_raw(d, ld, pt * 3 + 1, e);
-    j.Z = soa_load_raw(d, ld, pt * 3 + 2, e);
+    j.X = soa_load_m(d, ld, pt * 3 + 0, e);
+    j.Y = soa_load_m(d, ld, pt * 3 + 1, e);
+    j.Z = soa_load_m(d, ld, pt * 3 + 2, e);
     return j;
 }
 
 __device__ __forceinline__ void store_jac_m(uint32_t *__restrict__ d, int64_t ld, int pt, int64_t e,
                                             const jpt &j) {
-    soa_store_raw(d, ld, pt * 3 + 0, e, j.X);
-    soa_store_raw(d, ld, pt * 3 + 1, e, j.Y);
-    soa_store_raw(d, ld, pt * 3 + 2, e, j.Z);
+    soa_store_m(d, ld, pt * 3 + 0, e, j.X);
+    soa_store_m(d, ld, pt * 3 + 1, e, j.Y);
+    soa_store_m(d, ld, pt * 3 + 2, e, j.Z);
 }
+
+__device__ __forceinline__ apt load_aff_m(const uint32_t *__restrict__ d, int64_t ld, int pt, int64_t e) {
+    apt a;
+    a.x = soa_load_m(d, ld, pt * 2 + 0, e);
+    a.y = soa_load_m(d, ld, pt * 2 + 1, e);
+    return a;
+}
+
+__device__ __forceinline__ void store_aff_m(uint32_t *__restrict__ d, int64_t ld, int pt, int64_t e,
+                                            const apt &a) {
+    soa_store_m(d, ld, pt * 2 + 0, e, a.x);
+    soa_store_m(d, ld, pt * 2 + 1, e, a.y);
+}
+
+// words per internal (Montgomery) Jacobian matrix of two points per element
+constexpr int JAC2_PLANES = 2 * 3 * NL;
 
 // Alg. 1 (Montgomery ladder) over the low t bits of k, most significant
 // first: R0 <- inf, R1 <- P; per bit b: R_{1-b} <- R0 + R1, R_b <- 2 R_b.

@@ -45,11 +45,11 @@ __device__ __forceinline__ jpt jpt_infinity() {
 
 __device__ __forceinline__ bool jpt_is_inf(const jpt &P) { return fe_is_zero(P.Z); }
 
+// Affine infinity is encoded as x = 0, y = 0 (not a curve point, since b != 0).
+// x is compared by its raw limbs and y by value: negation maps y = 0 to the
+// non-canonical limbs of p, and a curve point with x = 0 has y != 0.
 __device__ __forceinline__ bool apt_is_inf(const apt &P) {
-    uint32_t x = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) x |= P.x.v[i] | P.y.v[i];
-    return x == 0;
+    return fe_is_raw_zero(P.x) && fe_is_zero(P.y);
 }
 
 __device__ __forceinline__ jpt jpt_from_affine(const apt &P) {
@@ -71,7 +71,7 @@ __device__ __forceinline__ jpt jpt_select(bool c, const jpt &a, const jpt &b) {
 __device__ __forceinline__ apt apt_neg(const apt &P) {
     apt r;
     r.x = P.x;
-    r.y = fe_neg(P.y);  // -0 = 0 keeps the identity encoding
+    r.y = fe_neg(P.y);  // -infinity = (0, p), still recognised by apt_is_inf
     return r;
 }
 
@@ -88,15 +88,13 @@ __device__ __forceinline__ jpt jpt_dbl(const jpt &P) {
     fe beta = fe_mul(P.X, gamma);
     fe t0 = fe_sub(P.X, delta);
     fe t1 = fe_add(P.X, delta);
-    fe alpha = fe_mul(t0, t1);
-    alpha = fe_add(fe_dbl(alpha), alpha);             // 3 (X - delta)(X + delta)
+    fe alpha = fe_mul3(fe_mul(t0, t1));               // 3 (X - delta)(X + delta)
     jpt R;
-    fe beta4 = fe_dbl(fe_dbl(beta));
+    fe beta4 = fe_mul4(beta);
     R.X = fe_sub(fe_sqr(alpha), fe_dbl(beta4));       // alpha^2 - 8 beta
     fe yz = fe_add(P.Y, P.Z);
     R.Z = fe_sub(fe_sub(fe_sqr(yz), gamma), delta);   // (Y + Z)^2 - gamma - delta
-    fe g2 = fe_sqr(gamma);
-    fe g8 = fe_dbl(fe_dbl(fe_dbl(g2)));
+    fe g8 = fe_dbl(fe_mul4(fe_sqr(gamma)));
     R.Y = fe_sub(fe_mul(alpha, fe_sub(beta4, R.X)), g8);
     return R;
 }
@@ -119,10 +117,9 @@ __device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
     fe s2 = fe_mul(fe_mul(Q.y, P.Z), z1z1);
     fe h = fe_sub(u2, P.X);
     fe hh = fe_sqr(h);
-    fe i4 = fe_dbl(fe_dbl(hh));
+    fe i4 = fe_mul4(hh);
     fe j = fe_mul(h, i4);
-    fe r = fe_sub(s2, P.Y);
-    r = fe_dbl(r);
+    fe r = fe_sub2(s2, P.Y);
     fe v = fe_mul(P.X, i4);
     jpt R;
     R.X = fe_sub(fe_sub(fe_sqr(r), j), fe_dbl(v));
@@ -150,7 +147,7 @@ __device__ __forceinline__ jpt jpt_add(const jpt &P, const jpt &Q) {
     fe h2 = fe_dbl(h);
     fe i = fe_sqr(h2);
     fe j = fe_mul(h, i);
-    fe r = fe_dbl(fe_sub(s2, s1));
+    fe r = fe_sub2(s2, s1);
     fe v = fe_mul(u1, i);
     jpt R;
     R.X = fe_sub(fe_sub(fe_sqr(r), j), fe_dbl(v));

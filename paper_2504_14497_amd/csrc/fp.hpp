@@ -1,31 +1,48 @@
 // fp.hpp -- arithmetic in the P-256 prime field on gfx950.
 //
 // The field is F_p with p = 2^256 - 2^224 + 2^192 + 2^96 - 1 (the curve of the
-// paper's implementation, Sec. 4.1).  An element lives in eight 32-bit VGPR
-// limbs (little-endian) in Montgomery form x R mod p with R = 2^256, always
-// fully reduced into [0, p), so equality and zero tests are limb compares.
+// paper's implementation, Sec. 4.1).
 //
-// Montgomery multiplication is word-serial (one 32-bit digit of b per round).
-// Because p = -1 (mod 2^32), the per-round quotient digit is the low word
-// itself, and adding that digit times p is a handful of shifted additions:
-//   t + m p = t - m + m 2^96 + m 2^192 - m 2^224 + m 2^256,
-// so after the exact division by 2^32 the round adds m at word 2 and word 5
-// and m (2^32 - 1) at words 6..7 -- no multiplications.
+// Representation: nine 29-bit limbs in 32-bit VGPRs ("unsaturated"),
+// value = sum_i v[i] 2^(29 i), in Montgomery form x R mod p with R = 2^261.
+// Every fe produced by the functions below is in normal form:
+//   limbs 0..7 < 2^29, limb 8 < 2^25, value < 2p (not necessarily < p).
+// Why 29 bits: gfx950 issues the 32 x 32 -> 64-bit multiply-add at full rate,
+// and with 29-bit limbs a whole column of a product (at most 9 partial
+// products plus 6 reduction terms, < 2^62) fits one 64-bit accumulator, so
+// every partial product is exactly one multiply-add into the accumulator and
+// no carry is propagated inside the multiplication.
+// Montgomery reduction: p = -1 (mod 2^29), so the per-column quotient digit is
+// simply the low 29 bits of the column, and its p_0 term folds into the carry
+// (acc + m (2^29 - 1) = acc - m + m 2^29).  p has 7 nonzero radix-2^29
+// digits, so a reduction costs 6 multiply-adds per digit.
+// Carries between limbs are handled with plain 32/64-bit integer shifts and
+// masks (no add-with-carry intrinsics).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace pcmm {
 
+constexpr int NL = 9;                       // limbs
+constexpr int LB = 29;                      // bits per limb
+constexpr uint32_t LMASK = (1u << LB) - 1;
+
 struct fe {
-    uint32_t v[8];
+    uint32_t v[NL];
 };
 
 // ---------------------------------------------------------------------------
-// Compile-time constants (computed from p alone, no external tables).
+// Compile-time constants, computed from p alone.
+// fe_const: canonical value as eight 32-bit words (little-endian);
+// fe29: the same value as nine 29-bit limbs.
 // ---------------------------------------------------------------------------
 struct fe_const {
     uint32_t v[8];
+};
+
+struct fe29 {
+    uint32_t v[NL];
 };
 
 constexpr fe_const P_WORDS = {{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 1u, 0xFFFFFFFFu}};
@@ -80,160 +97,282 @@ constexpr fe_const c_from_hex(const char *h) {
     return r;
 }
 
+// bits [29 i, 29 i + 29) of a 256-bit value
+constexpr fe29 c_to29(const fe_const &a) {
+    fe29 r{};
+    for (int i = 0; i < NL; ++i) {
+        int bit = LB * i;
+        uint64_t lo = a.v[bit / 32];
+        uint64_t hi = (bit / 32 + 1 < 8) ? a.v[bit / 32 + 1] : 0;
+        r.v[i] = (uint32_t)(((lo | (hi << 32)) >> (bit % 32)) & LMASK);
+    }
+    return r;
+}
+
 constexpr fe_const ONE_PLAIN = {{1, 0, 0, 0, 0, 0, 0, 0}};
-constexpr fe_const R_MOD_P = c_shift(ONE_PLAIN, 256);   // Montgomery form of 1
-constexpr fe_const R2_MOD_P = c_shift(R_MOD_P, 256);    // R^2 mod p
+constexpr fe_const R_MOD_P = c_shift(ONE_PLAIN, 261);    // Montgomery form of 1
+constexpr fe_const R2_MOD_P = c_shift(R_MOD_P, 261);     // R^2 mod p
+constexpr fe29 P29 = c_to29(P_WORDS);
+constexpr fe29 TWO_P29 = {{0x1ffffffeu, 0x1fffffffu, 0x1fffffffu, 0x3ffu, 0u, 0u, 0x80000u, 0x1fc00000u, 0x1ffffffu}};
+constexpr fe29 ONE29 = c_to29(ONE_PLAIN);
+constexpr fe29 R29 = c_to29(R_MOD_P);
+constexpr fe29 R2_29 = c_to29(R2_MOD_P);
+
+// 2p as limbs must be the radix-2^29 digits of 2p (checked at compile time)
+constexpr bool c_check_2p() {
+    fe_const two_p{};
+    uint32_t carry = 0;
+    for (int i = 0; i < 8; ++i) {
+        uint64_t s = (uint64_t)P_WORDS.v[i] * 2 + carry;
+        two_p.v[i] = (uint32_t)s;
+        carry = (uint32_t)(s >> 32);
+    }
+    fe29 d = c_to29(two_p);
+    d.v[8] |= carry << (256 - LB * 8);  // bit 256 of 2p lives in limb 8
+    for (int i = 0; i < NL; ++i)
+        if (d.v[i] != TWO_P29.v[i]) return false;
+    return true;
+}
+static_assert(c_check_2p(), "2p limbs");
 
 // ---------------------------------------------------------------------------
-// Basic limb helpers
+// Limb helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ fe fe_from(const fe_const &c) {
+__device__ __forceinline__ fe fe_from29(const fe29 &c) {
     fe r;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) r.v[i] = c.v[i];
+    for (int i = 0; i < NL; ++i) r.v[i] = c.v[i];
     return r;
 }
 
 __device__ __forceinline__ fe fe_zero() {
     fe r;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) r.v[i] = 0;
+    for (int i = 0; i < NL; ++i) r.v[i] = 0;
     return r;
 }
 
-__device__ __forceinline__ fe fe_one_mont() { return fe_from(R_MOD_P); }
-
-__device__ __forceinline__ bool fe_is_zero(const fe &a) {
-    uint32_t x = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) x |= a.v[i];
-    return x == 0;
-}
-
-__device__ __forceinline__ bool fe_eq(const fe &a, const fe &b) {
-    uint32_t x = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) x |= a.v[i] ^ b.v[i];
-    return x == 0;
-}
+__device__ __forceinline__ fe fe_one_mont() { return fe_from29(R29); }
 
 // r = c ? b : a, limb-wise (no branch)
 __device__ __forceinline__ fe fe_select(bool c, const fe &a, const fe &b) {
     fe r;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) r.v[i] = c ? b.v[i] : a.v[i];
+    for (int i = 0; i < NL; ++i) r.v[i] = c ? b.v[i] : a.v[i];
     return r;
 }
 
-// ---------------------------------------------------------------------------
-// Addition and subtraction mod p (inputs and outputs in [0, p))
-// ---------------------------------------------------------------------------
-// Carries are propagated through 64-bit sums (s = a + b + c, digit = low
-// word, carry = high word) rather than through the compiler's add-with-carry
-// intrinsics.
-__device__ __forceinline__ fe fe_add(const fe &a, const fe &b) {
-    fe s, t;
-    uint64_t c = 0;
+// value = 0 (mod p) for a normal-form value (which is then 0 or p)
+__device__ __forceinline__ bool fe_is_zero(const fe &a) {
+    uint32_t z = 0, q = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        c += (uint64_t)a.v[i] + b.v[i];
-        s.v[i] = (uint32_t)c;
-        c >>= 32;
+    for (int i = 0; i < NL; ++i) {
+        z |= a.v[i];
+        q |= a.v[i] ^ P29.v[i];
     }
-    // t = s - p; keep t when the sum overflowed 2^256 or s >= p
-    uint64_t bw = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        uint64_t d = (uint64_t)s.v[i] - P_WORDS.v[i] - bw;
-        t.v[i] = (uint32_t)d;
-        bw = d >> 63;
-    }
-    bool use_t = (c != 0) || (bw == 0);
-    return fe_select(use_t, s, t);
+    return z == 0 || q == 0;
 }
 
+// raw limbs all zero (used only for the affine encoding of infinity)
+__device__ __forceinline__ bool fe_is_raw_zero(const fe &a) {
+    uint32_t z = 0;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) z |= a.v[i];
+    return z == 0;
+}
+
+// signed carry propagation over limbs 0..7 into limb 8 (limbs as int32)
+__device__ __forceinline__ void fe_carry(fe &x) {
+#pragma unroll
+    for (int i = 0; i < NL - 1; ++i) {
+        int32_t c = (int32_t)x.v[i] >> LB;
+        x.v[i] &= LMASK;
+        x.v[i + 1] += (uint32_t)c;
+    }
+}
+
+// Normal form of a value 0 <= V < 2^260 held in signed limbs (|limb| < 2^31):
+// propagate carries, fold the bits at and above 2^256 with
+// 2^256 = 2^224 - 2^192 - 2^96 + 1 (mod p), i.e. V - h p with h = V >> 256,
+// which lands in [0, 2p), and propagate again.
+__device__ __forceinline__ fe fe_norm(fe x) {
+    fe_carry(x);
+    const uint32_t h = x.v[8] >> 24;         // 2^256 is bit 24 of limb 8
+    x.v[8] &= (1u << 24) - 1;
+    x.v[0] += h;                             // + h
+    x.v[3] -= h << 9;                        // - h 2^96  (96 = 3 * 29 + 9)
+    x.v[6] -= h << 18;                       // - h 2^192 (192 = 6 * 29 + 18)
+    x.v[7] += h << 21;                       // + h 2^224 (224 = 7 * 29 + 21)
+    fe_carry(x);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// Addition and subtraction (normal form in, normal form out)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ fe fe_add(const fe &a, const fe &b) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] + b.v[i];
+    return fe_norm(x);
+}
+
+// a - b + 2p, in (0, 4p)
 __device__ __forceinline__ fe fe_sub(const fe &a, const fe &b) {
-    fe d, t;
-    uint64_t bw = 0;
+    fe x;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        uint64_t x = (uint64_t)a.v[i] - b.v[i] - bw;
-        d.v[i] = (uint32_t)x;
-        bw = x >> 63;
-    }
-    uint64_t c = 0;
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] - b.v[i] + TWO_P29.v[i];
+    return fe_norm(x);
+}
+
+// 2 (a - b), in (0, 8p)
+__device__ __forceinline__ fe fe_sub2(const fe &a, const fe &b) {
+    fe x;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        c += (uint64_t)d.v[i] + P_WORDS.v[i];
-        t.v[i] = (uint32_t)c;
-        c >>= 32;
-    }
-    return fe_select(bw != 0, d, t);
+    for (int i = 0; i < NL; ++i) x.v[i] = (a.v[i] - b.v[i] + TWO_P29.v[i]) << 1;
+    return fe_norm(x);
 }
 
 __device__ __forceinline__ fe fe_neg(const fe &a) { return fe_sub(fe_zero(), a); }
 
-__device__ __forceinline__ fe fe_dbl(const fe &a) { return fe_add(a, a); }
-
-// ---------------------------------------------------------------------------
-// Montgomery multiplication: a b R^-1 mod p
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) {
-    // t holds a 9-word running value (t[8] is at most 1 between rounds)
-    uint32_t t[9];
+__device__ __forceinline__ fe fe_dbl(const fe &a) {
+    fe x;
 #pragma unroll
-    for (int j = 0; j < 9; ++j) t[j] = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        // t += a * b_i
-        uint32_t carry = 0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            uint64_t s = (uint64_t)a.v[j] * b.v[i] + t[j] + carry;
-            t[j] = (uint32_t)s;
-            carry = (uint32_t)(s >> 32);
-        }
-        uint64_t s8 = (uint64_t)t[8] + carry;
-        t[8] = (uint32_t)s8;
-        const uint32_t c9 = (uint32_t)(s8 >> 32);
-        // reduction by m = t[0]: u = t / 2^32 + m 2^64 + m 2^160 + m (2^32 - 1) 2^192
-        const uint32_t m = t[0];
-        const uint64_t mm = ((uint64_t)m << 32) - m;     // m (2^32 - 1)
-        const uint32_t add[8] = {0u, 0u, m, 0u, 0u, m, (uint32_t)mm, (uint32_t)(mm >> 32)};
-        uint64_t c = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            c += (uint64_t)t[k + 1] + add[k];
-            t[k] = (uint32_t)c;
-            c >>= 32;
-        }
-        t[8] = c9 + (uint32_t)c;
-    }
-    // t < 2p: subtract p once if needed
-    fe r, sb;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) r.v[i] = t[i];
-    uint64_t bw = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        uint64_t d = (uint64_t)r.v[i] - P_WORDS.v[i] - bw;
-        sb.v[i] = (uint32_t)d;
-        bw = d >> 63;
-    }
-    bool use_s = (t[8] != 0) || (bw == 0);
-    return fe_select(use_s, r, sb);
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] << 1;
+    return fe_norm(x);
 }
 
-__device__ __forceinline__ fe fe_sqr(const fe &a) { return fe_mul(a, a); }
+// 3a and 4a (value < 8p before normalisation)
+__device__ __forceinline__ fe fe_mul3(const fe &a) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] * 3u;
+    return fe_norm(x);
+}
+
+__device__ __forceinline__ fe fe_mul4(const fe &a) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] << 2;
+    return fe_norm(x);
+}
+
+__device__ __forceinline__ bool fe_eq(const fe &a, const fe &b) { return fe_is_zero(fe_sub(a, b)); }
+
+// ---------------------------------------------------------------------------
+// Montgomery multiplication a b 2^-261 mod p (product scanning, the
+// reduction interleaved column by column)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) {
+    uint64_t acc = 0;
+    uint32_t m[NL];
+    fe r;
+#pragma unroll
+    for (int c = 0; c < 2 * NL - 1; ++c) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int j = c - i;
+            if (j >= 0 && j < NL) acc += (uint64_t)a.v[i] * b.v[j];
+        }
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int j = c - i;
+            if (i < c && j >= 1 && j < NL && P29.v[j] != 0) acc += (uint64_t)m[i] * P29.v[j];
+        }
+        if (c < NL) {
+            m[c] = (uint32_t)acc & LMASK;
+            acc = (acc >> LB) + m[c];
+        } else {
+            r.v[c - NL] = (uint32_t)acc & LMASK;
+            acc >>= LB;
+        }
+    }
+    r.v[NL - 1] = (uint32_t)acc;
+    return r;
+}
+
+// squaring: cross products once with a doubled operand
+__device__ __forceinline__ fe fe_sqr(const fe &a) {
+    uint32_t d[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) d[i] = a.v[i] << 1;
+    uint64_t acc = 0;
+    uint32_t m[NL];
+    fe r;
+#pragma unroll
+    for (int c = 0; c < 2 * NL - 1; ++c) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int j = c - i;
+            if (i < j && j < NL) acc += (uint64_t)d[i] * a.v[j];
+        }
+        if ((c & 1) == 0 && c / 2 < NL) acc += (uint64_t)a.v[c / 2] * a.v[c / 2];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int j = c - i;
+            if (i < c && j >= 1 && j < NL && P29.v[j] != 0) acc += (uint64_t)m[i] * P29.v[j];
+        }
+        if (c < NL) {
+            m[c] = (uint32_t)acc & LMASK;
+            acc = (acc >> LB) + m[c];
+        } else {
+            r.v[c - NL] = (uint32_t)acc & LMASK;
+            acc >>= LB;
+        }
+    }
+    r.v[NL - 1] = (uint32_t)acc;
+    return r;
+}
 
 __device__ __forceinline__ fe fe_sqr_n(fe a, int n) {
     for (int i = 0; i < n; ++i) a = fe_sqr(a);
     return a;
 }
 
-__device__ __forceinline__ fe fe_to_mont(const fe &a) { return fe_mul(a, fe_from(R2_MOD_P)); }
+// ---------------------------------------------------------------------------
+// Conversions between canonical 8 x 32-bit words and Montgomery limbs
+// ---------------------------------------------------------------------------
+// canonical words (any value < 2^256) -> limbs of the same integer
+__device__ __forceinline__ fe fe_from_words(const uint32_t w[8]) {
+    fe r;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int bit = LB * i;
+        const int k = bit / 32, s = bit % 32;
+        uint64_t x = w[k];
+        if (k + 1 < 8) x |= (uint64_t)w[k + 1] << 32;
+        r.v[i] = (uint32_t)(x >> s) & LMASK;
+    }
+    return r;
+}
 
-__device__ __forceinline__ fe fe_from_mont(const fe &a) { return fe_mul(a, fe_from(ONE_PLAIN)); }
+// fully reduced value (< p) of a normal-form element, as limbs
+__device__ __forceinline__ fe fe_canon(const fe &a) {
+    fe t;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) t.v[i] = a.v[i] - P29.v[i];
+    fe_carry(t);
+    const bool neg = (int32_t)t.v[NL - 1] < 0;  // a < p: keep a
+    return fe_select(neg, t, a);
+}
+
+// limbs of a value < 2^256 -> eight 32-bit words
+__device__ __forceinline__ void fe_to_words(const fe &a, uint32_t w[8]) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int bit = 32 * k;
+        const int i = bit / LB, s = bit % LB;
+        uint64_t x = (uint64_t)a.v[i] >> s;
+        if (i + 1 < NL) x |= (uint64_t)a.v[i + 1] << (LB - s);
+        if (i + 2 < NL && 2 * LB - s < 32) x |= (uint64_t)a.v[i + 2] << (2 * LB - s);
+        w[k] = (uint32_t)x;
+    }
+}
+
+__device__ __forceinline__ fe fe_to_mont(const fe &a) { return fe_mul(a, fe_from29(R2_29)); }
+
+// Montgomery limbs -> canonical integer limbs in [0, p)
+__device__ __forceinline__ fe fe_from_mont(const fe &a) { return fe_canon(fe_mul(a, fe_from29(ONE29))); }
 
 // a^(p-2) = a^-1 for a != 0 (0 maps to 0).  p - 2 in 32-bit words from the
 // top: ffffffff 00000001 00000000 00000000 00000000 ffffffff ffffffff fffffffd.

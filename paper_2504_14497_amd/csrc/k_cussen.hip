@@ -25,7 +25,7 @@ using namespace pcmm;
 
 namespace {
 
-constexpr int ENTRY_WORDS = 16;  // affine entry: x (8 words), y (8 words), Montgomery form
+constexpr int ENTRY_WORDS = 20;  // affine entry: x (9 limbs), y (9 limbs), 2 pad words; Montgomery form
 
 struct tb_args {
     const plan_op *ops;
@@ -36,30 +36,18 @@ struct tb_args {
     int64_t ldb;
     int n, l, g, J, Lj, rmax, emax;
     int64_t n_lanes;
-    uint32_t *regs;     // [(r * rmax + reg) * 24 + word][lane]
-    uint32_t *table;    // [((grp * l + j) * 2 + pt) * emax + e][16 words]
+    uint32_t *regs;     // [(r * rmax + reg) * 27 + word][lane]
+    uint32_t *table;    // [((grp * l + j) * 2 + pt) * emax + e][ENTRY_WORDS]
 };
 
+constexpr int JAC_WORDS = 3 * NL;
+
 __device__ __forceinline__ jpt reg_load(const tb_args &a, int r, int reg, int64_t lane) {
-    const uint32_t *base = a.regs + (int64_t)(r * a.rmax + reg) * 24 * a.n_lanes;
-    jpt P;
-#pragma unroll
-    for (int w = 0; w < 8; ++w) {
-        P.X.v[w] = base[(int64_t)w * a.n_lanes + lane];
-        P.Y.v[w] = base[(int64_t)(8 + w) * a.n_lanes + lane];
-        P.Z.v[w] = base[(int64_t)(16 + w) * a.n_lanes + lane];
-    }
-    return P;
+    return load_jac_m(a.regs + (int64_t)(r * a.rmax + reg) * JAC_WORDS * a.n_lanes, a.n_lanes, 0, lane);
 }
 
 __device__ __forceinline__ void reg_store(const tb_args &a, int r, int reg, int64_t lane, const jpt &P) {
-    uint32_t *base = a.regs + (int64_t)(r * a.rmax + reg) * 24 * a.n_lanes;
-#pragma unroll
-    for (int w = 0; w < 8; ++w) {
-        base[(int64_t)w * a.n_lanes + lane] = P.X.v[w];
-        base[(int64_t)(8 + w) * a.n_lanes + lane] = P.Y.v[w];
-        base[(int64_t)(16 + w) * a.n_lanes + lane] = P.Z.v[w];
-    }
+    store_jac_m(a.regs + (int64_t)(r * a.rmax + reg) * JAC_WORDS * a.n_lanes, a.n_lanes, 0, lane, P);
 }
 
 __device__ __forceinline__ apt base_point(const apt Bt[4], int t) {
@@ -130,7 +118,7 @@ __global__ void __launch_bounds__(256) table_build_kernel(tb_args a) {
             fe z = reg_load(a, r, opd, lane).Z;
             uint32_t *slot = a.table + (T * a.emax + e) * ENTRY_WORDS;
 #pragma unroll
-            for (int w = 0; w < 8; ++w) slot[w] = prod.v[w];
+            for (int w = 0; w < NL; ++w) slot[w] = prod.v[w];
             if (!fe_is_zero(z)) prod = fe_mul(prod, z);
         }
     }
@@ -149,7 +137,7 @@ __global__ void __launch_bounds__(256) table_build_kernel(tb_args a) {
                 jpt P = reg_load(a, r, opd, lane);
                 fe pre;
 #pragma unroll
-                for (int w = 0; w < 8; ++w) pre.v[w] = slot[w];
+                for (int w = 0; w < NL; ++w) pre.v[w] = slot[w];
                 if (fe_is_zero(P.Z)) {
                     A.x = fe_zero();
                     A.y = fe_zero();
@@ -160,9 +148,9 @@ __global__ void __launch_bounds__(256) table_build_kernel(tb_args a) {
                 }
             }
 #pragma unroll
-            for (int w = 0; w < 8; ++w) {
+            for (int w = 0; w < NL; ++w) {
                 slot[w] = A.x.v[w];
-                slot[8 + w] = A.y.v[w];
+                slot[NL + w] = A.y.v[w];
             }
         }
     }
@@ -221,9 +209,9 @@ __global__ void __launch_bounds__(256) accumulate_kernel(acc_args a) {
                                       ((int64_t)pair_l * a.emax + e) * ENTRY_WORDS;
                 apt Q;
 #pragma unroll
-                for (int w = 0; w < 8; ++w) {
+                for (int w = 0; w < NL; ++w) {
                     Q.x.v[w] = ent[w];
-                    Q.y.v[w] = ent[8 + w];
+                    Q.y.v[w] = ent[NL + w];
                 }
                 if (code < 0) Q.y = fe_neg(Q.y);
                 acc = jpt_add_affine(acc, Q);
@@ -233,7 +221,7 @@ __global__ void __launch_bounds__(256) accumulate_kernel(acc_args a) {
     if (!active) return;
     const int j = p >> 1, pt = p & 1;
     const int64_t e_out = (int64_t)i * a.l + j;
-    uint32_t *dst = a.out + (int64_t)split * 48 * a.ld_out;
+    uint32_t *dst = a.out + (int64_t)split * JAC2_PLANES * a.ld_out;
     if (a.out_canonical) store_jac(dst, a.ld_out, pt, e_out, acc);
     else store_jac_m(dst, a.ld_out, pt, e_out, acc);
 }
@@ -249,11 +237,11 @@ __global__ void __launch_bounds__(256) reduce_kernel(const uint32_t *__restrict_
     const bool valid = rest < 2 * n_out;
     const int64_t e = valid ? rest >> 1 : 0;
     const int pt = (int)(rest & 1);
-    jpt P = valid ? load_jac_m(part + (int64_t)s * 48 * ld_part, ld_part, pt, e) : jpt_infinity();
+    jpt P = valid ? load_jac_m(part + (int64_t)s * JAC2_PLANES * ld_part, ld_part, pt, e) : jpt_infinity();
     for (int off = S >> 1; off >= 1; off >>= 1) {
         jpt Q;
 #pragma unroll
-        for (int w = 0; w < 8; ++w) {
+        for (int w = 0; w < NL; ++w) {
             Q.X.v[w] = __shfl_down(P.X.v[w], off, 64);
             Q.Y.v[w] = __shfl_down(P.Y.v[w], off, 64);
             Q.Z.v[w] = __shfl_down(P.Z.v[w], off, 64);
@@ -337,13 +325,13 @@ geometry make_geometry(const cussen_plan &P, int l, int c_form, const pcmm_cusse
     G.plan_bytes = plan_device_bytes(P);
     G.off_plan = 0;
     G.off_regs = align256(G.plan_bytes);
-    size_t regs_bytes = (size_t)G.J * std::max(P.max_regs, 1) * 24 * 4 * (size_t)G.n_lanes;
+    size_t regs_bytes = (size_t)G.J * std::max(P.max_regs, 1) * JAC_WORDS * 4 * (size_t)G.n_lanes;
     G.off_table = G.off_regs + align256(regs_bytes);
     size_t table_bytes = (size_t)P.ngroups * npairs * emax * ENTRY_WORDS * 4;
     G.off_part = G.off_table + align256(table_bytes);
-    size_t part_bytes = S > 1 ? (size_t)S * 48 * ldc * 4 : 0;
+    size_t part_bytes = S > 1 ? (size_t)S * JAC2_PLANES * ldc * 4 : 0;
     G.off_cjac = G.off_part + align256(part_bytes);
-    size_t cjac_bytes = c_form == PCMM_AFFINE ? (size_t)48 * ldc * 4 : 0;
+    size_t cjac_bytes = c_form == PCMM_AFFINE ? (size_t)JAC2_PLANES * ldc * 4 : 0;
     G.off_norm = G.off_cjac + align256(cjac_bytes);
     size_t norm_bytes = c_form == PCMM_AFFINE ? normalize_scratch_bytes((int64_t)m * l, 2) : 0;
     G.total = G.off_norm + align256(norm_bytes) + 256;

@@ -26,6 +26,32 @@ __global__ void __launch_bounds__(256) field_op_kernel(int op, const uint32_t *_
     soa_store_canon(out, n, 0, e, r);
 }
 
+__global__ void __launch_bounds__(256) field_raw_kernel(int op, const uint32_t *__restrict__ a,
+                                                         const uint32_t *__restrict__ b,
+                                                         uint32_t *__restrict__ out, int64_t n) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    fe x = soa_load_m(a, n, 0, e);
+    fe y = soa_load_m(b, n, 0, e);
+    fe r = fe_zero();
+    switch (op) {
+        case 0: r = fe_add(x, y); break;
+        case 1: r = fe_sub(x, y); break;
+        case 2: r = fe_mul(x, y); break;
+        case 3: r = fe_sqr(x); break;
+        case 4: r = fe_sub2(x, y); break;
+        case 5: r = fe_mul3(x); break;
+        case 6: r = fe_mul4(x); break;
+        case 7: r = fe_neg(x); break;
+        case 8: r = fe_canon(x); break;
+        case 9: r = fe_dbl(x); break;
+        case 10: r = fe_norm(x); break;
+        case 11: r.v[0] = fe_eq(x, y) ? 1u : 0u; break;
+        default: r.v[0] = fe_is_zero(x) ? 1u : 0u; break;
+    }
+    soa_store_m(out, n, 0, e, r);
+}
+
 __global__ void __launch_bounds__(256) point_op_kernel(int op, const uint32_t *__restrict__ P,
                                                         int64_t ldp, const uint32_t *__restrict__ Q,
                                                         int64_t ldq, const uint32_t *__restrict__ K,
@@ -131,16 +157,16 @@ __global__ void __launch_bounds__(256) probe_femul_kernel(uint32_t *out, uint32_
     uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     fe x, y;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        x.v[i] = (seed ^ (tid * 2654435761u)) + i * 77u;
-        y.v[i] = 0x9E3779B9u * (i + 3) + tid;
+    for (int i = 0; i < NL; ++i) {
+        x.v[i] = ((seed ^ (tid * 2654435761u)) + i * 77u) & LMASK;
+        y.v[i] = (0x9E3779B9u * (i + 3) + tid) & LMASK;
     }
-    x.v[7] &= 0x7FFFFFFFu;
-    y.v[7] &= 0x7FFFFFFFu;
+    x.v[NL - 1] &= 0xFFFFFFu;
+    y.v[NL - 1] &= 0xFFFFFFu;
     for (int64_t it = 0; it < iters; ++it) x = fe_mul(x, y);
     uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s ^= x.v[i];
+    for (int i = 0; i < NL; ++i) s ^= x.v[i];
     if (s == 0x12345678u) out[tid] = s;
 }
 
@@ -148,15 +174,14 @@ __global__ void __launch_bounds__(256) probe_madd_kernel(uint32_t *out, uint32_t
     uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     // a fixed valid affine point (the generator) added over and over
     apt g;
-    g.x = fe_to_mont(fe_from(GX_PLAIN));
-    g.y = fe_to_mont(fe_from(GY_PLAIN));
+    g.x = fe_to_mont(fe_from_const(GX_PLAIN));
+    g.y = fe_to_mont(fe_from_const(GY_PLAIN));
     jpt acc = jpt_from_affine(g);
-    acc.X.v[0] ^= seed & 0;  // keep the chain data-dependent on launch arguments
     acc = jpt_dbl(acc);
     for (int64_t it = 0; it < iters; ++it) acc = jpt_add_affine(acc, g);
     uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s ^= acc.X.v[i] ^ acc.Z.v[i];
+    for (int i = 0; i < NL; ++i) s ^= acc.X.v[i] ^ acc.Z.v[i];
     if (s == (0x12345678u ^ tid ^ seed)) out[tid] = s;
 }
 
@@ -189,6 +214,18 @@ extern "C" pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint
     if (blocks > 0x7FFFFFFF) return PCMM_EINVAL;
     hipLaunchKernelGGL(field_op_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, op,
                        a, b, out, count);
+    PCMM_LAUNCH_CHECK();
+    return PCMM_OK;
+}
+
+extern "C" pcmm_status pcmm_diag_field_raw(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
+                                           int64_t count, void *stream) {
+    if (op < 0 || op > 12 || count < 0) return PCMM_EINVAL;
+    if (count == 0) return PCMM_OK;
+    if (!a || !b || !out) return PCMM_EINVAL;
+    int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(field_raw_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, op, a, b, out,
+                       count);
     PCMM_LAUNCH_CHECK();
     return PCMM_OK;
 }

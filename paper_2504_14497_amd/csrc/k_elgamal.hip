@@ -92,10 +92,7 @@ __device__ void derive_scalar(uint64_t seed, uint64_t domain, uint64_t idx, uint
 }
 
 __device__ __forceinline__ apt table_entry(const uint32_t *__restrict__ tab, int idx) {
-    apt a;
-    a.x = soa_load_raw(tab, TABLE_POINTS, 0, idx);
-    a.y = soa_load_raw(tab, TABLE_POINTS, 1, idx);
-    return a;
+    return load_aff_m(tab, TABLE_POINTS, 0, idx);
 }
 
 // k B from the 4-bit window table of B (k as 8 little-endian words)
@@ -114,12 +111,8 @@ struct point16 {
 
 __device__ __forceinline__ apt point16_mont(const point16 &p) {
     apt a;
-    for (int i = 0; i < 8; ++i) {
-        a.x.v[i] = p.w[i];
-        a.y.v[i] = p.w[8 + i];
-    }
-    a.x = fe_to_mont(a.x);
-    a.y = fe_to_mont(a.y);
+    a.x = fe_to_mont(fe_from_words(p.w));
+    a.y = fe_to_mont(fe_from_words(p.w + 8));
     return a;
 }
 
@@ -141,19 +134,15 @@ __global__ void __launch_bounds__(64) table_build_kernel(point16 base, uint32_t 
 // flag = 1 if the canonical affine point is a finite point on the curve
 __global__ void on_curve_kernel(point16 p, uint32_t *flag) {
     if (threadIdx.x != 0) return;
-    fe xc, yc;
-    for (int i = 0; i < 8; ++i) {
-        xc.v[i] = p.w[i];
-        yc.v[i] = p.w[8 + i];
-    }
+    fe xc = fe_from_words(p.w), yc = fe_from_words(p.w + 8);
     // reject non-canonical coordinates (>= p): the round trip would change them
     fe x = fe_to_mont(xc), y = fe_to_mont(yc);
-    bool canon = fe_eq(fe_from_mont(x), xc) && fe_eq(fe_from_mont(y), yc);
-    fe b = fe_to_mont(fe_from(CURVE_B_PLAIN));
+    bool canon = fe_raw_eq(fe_from_mont(x), xc) && fe_raw_eq(fe_from_mont(y), yc);
+    fe b = fe_to_mont(fe_from_const(CURVE_B_PLAIN));
     fe rhs = fe_mul(fe_sqr(x), x);
     fe x3 = fe_add(fe_dbl(x), x);
     rhs = fe_add(fe_sub(rhs, x3), b);
-    bool ok = canon && fe_eq(fe_sqr(y), rhs) && !(fe_is_zero(x) && fe_is_zero(y));
+    bool ok = canon && fe_eq(fe_sqr(y), rhs) && !(fe_is_raw_zero(xc) && fe_is_raw_zero(yc));
     *flag = ok ? 1u : 0u;
 }
 
@@ -225,11 +214,8 @@ __global__ void keygen_kernel(const uint32_t *__restrict__ tabG, uint64_t seed, 
     jpt H = fixed_base_mul(tabG, x);
     apt A = jpt_to_affine_with(H, fe_inv(H.Z));
     for (int i = 0; i < 8; ++i) out[i] = x[i];
-    fe hx = fe_from_mont(A.x), hy = fe_from_mont(A.y);
-    for (int i = 0; i < 8; ++i) {
-        out[8 + i] = hx.v[i];
-        out[16 + i] = hy.v[i];
-    }
+    fe_to_words(fe_from_mont(A.x), out + 8);
+    fe_to_words(fe_from_mont(A.y), out + 16);
 }
 
 // --- per-device generator table ---------------------------------------------
@@ -238,7 +224,7 @@ uint32_t *g_table[64] = {nullptr};
 
 pcmm_status build_table(const point16 &base, uint32_t *table_out, void *tmp, size_t tmp_bytes, hipStream_t s) {
     // tmp layout: [jacobian 960 x 24 words][normalize scratch]
-    size_t jac_bytes = (size_t)TABLE_POINTS * 24 * sizeof(uint32_t);
+    size_t jac_bytes = (size_t)TABLE_POINTS * 3 * NL * sizeof(uint32_t);
     size_t need = jac_bytes + normalize_scratch_bytes(TABLE_POINTS, 1);
     if (tmp_bytes < need) return PCMM_ENOMEM;
     uint32_t *jac = (uint32_t *)tmp;
@@ -250,10 +236,10 @@ pcmm_status build_table(const point16 &base, uint32_t *table_out, void *tmp, siz
 }
 
 size_t table_tmp_bytes() {
-    return (size_t)TABLE_POINTS * 24 * sizeof(uint32_t) + normalize_scratch_bytes(TABLE_POINTS, 1);
+    return (size_t)TABLE_POINTS * 3 * NL * sizeof(uint32_t) + normalize_scratch_bytes(TABLE_POINTS, 1);
 }
 
-size_t table_bytes() { return (size_t)TABLE_POINTS * 16 * sizeof(uint32_t); }
+size_t table_bytes() { return (size_t)TABLE_POINTS * 2 * NL * sizeof(uint32_t); }
 
 void be32_to_words(const uint8_t be[32], uint32_t w[8]) {
     for (int i = 0; i < 8; ++i) {

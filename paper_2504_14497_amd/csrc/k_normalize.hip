@@ -30,8 +30,8 @@ __global__ void __launch_bounds__(256) normalize_kernel(const uint32_t *in, int6
         int64_t e = t + (int64_t)j * T;
         if (e >= n_elem) break;
         for (int pt = 0; pt < npts; ++pt, ++slot) {
-            fe z = IN_MONT ? soa_load_raw(in, ld_in, pt * 3 + 2, e) : soa_load_mont(in, ld_in, pt * 3 + 2, e);
-            soa_store_raw(prefix, ld_pre, 0, t + (int64_t)slot * T, acc);
+            fe z = IN_MONT ? soa_load_m(in, ld_in, pt * 3 + 2, e) : soa_load_mont(in, ld_in, pt * 3 + 2, e);
+            soa_store_m(prefix, ld_pre, 0, t + (int64_t)slot * T, acc);
             if (!fe_is_zero(z)) acc = fe_mul(acc, z);
         }
     }
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) normalize_kernel(const uint32_t *in, int6
             if (pt >= npts) continue;
             --slot;
             bool inf = fe_is_zero(P[pt].Z);
-            fe pre = soa_load_raw(prefix, ld_pre, 0, t + (int64_t)slot * T);
+            fe pre = soa_load_m(prefix, ld_pre, 0, t + (int64_t)slot * T);
             fe zinv = fe_mul(inv, pre);
             if (!inf) inv = fe_mul(inv, P[pt].Z);
             A[pt] = jpt_to_affine_with(P[pt], zinv);
@@ -65,8 +65,7 @@ __global__ void __launch_bounds__(256) normalize_kernel(const uint32_t *in, int6
         for (int pt = 0; pt < 2; ++pt) {
             if (pt >= npts) continue;
             if (OUT_MONT) {
-                soa_store_raw(out, ld_out, pt * 2 + 0, e, A[pt].x);
-                soa_store_raw(out, ld_out, pt * 2 + 1, e, A[pt].y);
+                store_aff_m(out, ld_out, pt, e, A[pt]);
             } else {
                 store_affine(out, ld_out, pt, e, A[pt]);
             }
@@ -92,7 +91,7 @@ size_t normalize_scratch_bytes(int64_t n_elem, int npts) {
     int64_t th;
     int per;
     normalize_geometry(n_elem, &th, &per);
-    return (size_t)th * (size_t)per * (size_t)npts * 8 * sizeof(uint32_t);
+    return (size_t)th * (size_t)per * (size_t)npts * NL * sizeof(uint32_t);
 }
 
 pcmm_status launch_normalize(const uint32_t *in, int64_t ld_in, bool in_mont, uint32_t *out,
@@ -103,7 +102,7 @@ pcmm_status launch_normalize(const uint32_t *in, int64_t ld_in, bool in_mont, ui
     int per;
     normalize_geometry(n_elem, &th, &per);
     int64_t ld_pre = th * per * npts;
-    if (scratch_bytes < (size_t)ld_pre * 8 * sizeof(uint32_t)) return PCMM_ENOMEM;
+    if (scratch_bytes < (size_t)ld_pre * NL * sizeof(uint32_t)) return PCMM_ENOMEM;
     // prefix slot s of thread t lives at column t + s * th (slots < per * npts)
     unsigned blocks = (unsigned)(th / 256);
 void (*kern)(const uint32_t *, int64_t, uint32_t *, int64_t, int64_t, int, uint32_t *, int64_t, int) =

@@ -56,7 +56,7 @@ extern "C" size_t pcmm_schoolbook_workspace(int32_t m, int32_t n, int32_t l, int
     int64_t n_out = (int64_t)m * l;
     int64_t ldc = std::max<int64_t>(64, (n_out + 63) / 64 * 64);
     size_t bytes = align256((size_t)m * n);
-    if (c_form == PCMM_AFFINE) bytes += align256((size_t)48 * ldc * 4) + align256(normalize_scratch_bytes(n_out, 2));
+    if (c_form == PCMM_AFFINE) bytes += align256((size_t)JAC2_PLANES * ldc * 4) + align256(normalize_scratch_bytes(n_out, 2));
     return bytes + 256;
 }
 
@@ -88,7 +88,7 @@ extern "C" pcmm_status pcmm_schoolbook(const int8_t *A, int32_t m, int32_t n, in
                        B->ld, jac, ld_jac, affine_out ? 0 : 1);
     PCMM_LAUNCH_CHECK();
     if (affine_out) {
-        size_t off = align256((size_t)m * n) + align256((size_t)48 * ldc * 4);
+        size_t off = align256((size_t)m * n) + align256((size_t)JAC2_PLANES * ldc * 4);
         return launch_normalize(jac, ld_jac, true, C->d, C->ld, false, n_out, 2, ws + off, ws_bytes - off, s);
     }
     return PCMM_OK;

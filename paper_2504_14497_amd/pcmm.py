@@ -91,6 +91,7 @@ _SIG = {
     "pcmm_diag_device": ([ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64),
                           ctypes.c_char_p], _I32),
     "pcmm_diag_copy": ([_VP, _VP, _I64, _VP], _I32),
+    "pcmm_diag_field_raw": ([_I32, _VP, _VP, _VP, _I64, _VP], _I32),
 }
 
 EXPORTED = tuple(_SIG)
@@ -228,6 +229,23 @@ def diag_field(op: int, a, b=None, stream=None):
           stream_ptr(stream))
     torch.cuda.synchronize()
     return limbs_to_ints(to.cpu().numpy().view(np.uint32))
+
+
+LIMB_BITS, NLIMBS = 29, 9
+
+
+def diag_field_raw(op: int, a_limbs: np.ndarray, b_limbs: np.ndarray = None, stream=None) -> np.ndarray:
+    """Raw-limb field op on (count, 9) int64/uint32 limb arrays; returns (count, 9) uint32."""
+    import torch
+    a = np.ascontiguousarray(np.asarray(a_limbs, dtype=np.int64).astype(np.uint32).T)
+    b = a if b_limbs is None else np.ascontiguousarray(np.asarray(b_limbs, dtype=np.int64).astype(np.uint32).T)
+    n = a.shape[1]
+    ta = torch.from_numpy(a.view(np.int32)).cuda().contiguous()
+    tb = torch.from_numpy(b.view(np.int32)).cuda().contiguous()
+    to = torch.zeros_like(ta)
+    _call("pcmm_diag_field_raw", op, _tensor_ptr(ta), _tensor_ptr(tb), _tensor_ptr(to), n, stream_ptr(stream))
+    torch.cuda.synchronize()
+    return np.ascontiguousarray(to.cpu().numpy().view(np.uint32).T)
 
 
 def diag_point(op: int, P: np.ndarray, Q: np.ndarray = None, k=None, t: int = 0, stream=None):

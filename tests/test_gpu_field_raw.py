@@ -1,0 +1,107 @@
+"""GPU field arithmetic on its internal representation (nine 29-bit limbs,
+Montgomery R = 2^261), checked against exact integer arithmetic.
+
+Operands are arbitrary normal-form values -- every value in [0, 2p), including
+the non-canonical [p, 2p) range that intermediate results can take -- plus
+adversarial limb patterns.  Each result must equal the plain definition modulo
+p and must itself be in normal form (limbs 0..7 < 2^29, limb 8 < 2^25,
+value < 2p).
+"""
+import random
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+P = 2**256 - 2**224 + 2**192 + 2**96 - 1
+R = 2**261
+RINV = pow(R, -1, P)
+LB, NL = 29, 9
+MASK = (1 << LB) - 1
+
+
+def limbs(v):
+    return [(v >> (LB * i)) & MASK for i in range(NL)]
+
+
+def value(row):
+    return sum(int(x) << (LB * i) for i, x in enumerate(row))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_14497_amd import pcmm
+    pcmm.lib()
+    return pcmm
+
+
+def _operands(n, seed):
+    rnd = random.Random(seed)
+    edge = [0, 1, 2, P - 1, P, P + 1, 2 * P - 1, 2 * P - 2, 2**256 - 1, 2**256, 2**256 + 1,
+            2**255, 2**224, 2**192, 2**96, P - 2**96, P + 2**96, (2**256) % P, 2**232 - 1,
+            sum(MASK << (LB * i) for i in range(8)), R % P, (R * R) % P]
+    edge = [v for v in edge if v < 2 * P]
+    vals = edge + [rnd.randrange(2 * P) for _ in range(n)]
+    a = list(vals)
+    b = [rnd.choice(vals) for _ in vals]
+    rnd.shuffle(b)
+    # every pair of edge values
+    for x in edge:
+        for y in edge:
+            a.append(x)
+            b.append(y)
+    return a, b
+
+
+def _check_normal(out):
+    assert (out[:, :8] < (1 << LB)).all()
+    assert (out[:, 8] < (1 << 25)).all()
+    for row in out:
+        assert value(row) < 2 * P
+
+
+def test_raw_field_ops_vs_integers(dev):
+    a, b = _operands(6000, 11)
+    A = np.array([limbs(v) for v in a], dtype=np.int64)
+    B = np.array([limbs(v) for v in b], dtype=np.int64)
+    cases = {
+        0: lambda x, y: (x + y) % P,
+        1: lambda x, y: (x - y) % P,
+        2: lambda x, y: (x * y * RINV) % P,
+        3: lambda x, y: (x * x * RINV) % P,
+        4: lambda x, y: (2 * (x - y)) % P,
+        5: lambda x, y: (3 * x) % P,
+        6: lambda x, y: (4 * x) % P,
+        7: lambda x, y: (-x) % P,
+        9: lambda x, y: (2 * x) % P,
+    }
+    for op, f in cases.items():
+        out = dev.diag_field_raw(op, A, B)
+        _check_normal(out)
+        bad = [i for i in range(len(a)) if value(out[i]) % P != f(a[i], b[i])]
+        assert not bad, (op, bad[:5], [(hex(a[i]), hex(b[i])) for i in bad[:3]])
+    out = dev.diag_field_raw(8, A, B)  # full reduction
+    assert all(value(out[i]) == a[i] % P for i in range(len(a)))
+    eq = dev.diag_field_raw(11, A, B)[:, 0]
+    assert all(bool(eq[i]) == ((a[i] - b[i]) % P == 0) for i in range(len(a)))
+    z = dev.diag_field_raw(12, A, B)[:, 0]
+    assert all(bool(z[i]) == (a[i] % P == 0) for i in range(len(a)))
+
+
+def test_raw_normalisation_of_signed_limbs(dev):
+    rnd = random.Random(5)
+    rows, vals = [], []
+    while len(rows) < 4000:
+        row = [rnd.randrange(-(1 << 30) + 1, 1 << 30) for _ in range(NL)]
+        v = sum(x << (LB * i) for i, x in enumerate(row))
+        if 0 <= v < 2**259:
+            rows.append(row)
+            vals.append(v)
+    A = np.array(rows, dtype=np.int64)
+    out = dev.diag_field_raw(10, A, A)
+    _check_normal(out)
+    assert all(value(out[i]) % P == vals[i] % P for i in range(len(vals)))

@@ -90,13 +90,25 @@ typedef struct {
  *   k_chunk columns of A whose tables are staged in LDS at once (0 = auto)
  *   profile nonzero: record HIP events around every launch of the call on
  *           its stream, wait for them, and return per-stage durations in the
- *           stats (the call then returns after its GPU work has finished) */
+ *           stats (the call then returns after its GPU work has finished)
+ *   stage_events  NULL, or an array of PCMM_STAGE_EVENTS hipEvent_t handles
+ *           owned by the caller (created with timing enabled).  The call
+ *           records the boundaries of its stages into them on its stream --
+ *           before the plan upload, after it, after the table build, the
+ *           accumulation, the split-k reduction and the normalisation -- and
+ *           does not wait for them, so consecutive calls still overlap host
+ *           planning with GPU work.  The caller reads the durations with
+ *           hipEventElapsedTime once the stream has reached the last one.
+ *           With profile nonzero as well, these events are the ones waited
+ *           on and read into the stats. */
+#define PCMM_STAGE_EVENTS 6
 typedef struct {
     int32_t rounds;
     int32_t group;
     int32_t k_split;
     int32_t k_chunk;
     int32_t profile;
+    void **stage_events;
 } pcmm_cussen_cfg;
 
 /* Operation counts of one pcmm_cussen call, derived from its plan. */

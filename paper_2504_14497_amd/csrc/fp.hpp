@@ -9,13 +9,16 @@
 //   limbs 0..7 < 2^29, limb 8 < 2^25, value < 2p (not necessarily < p).
 // Why 29 bits: gfx950 issues the 32 x 32 -> 64-bit multiply-add at full rate,
 // and with 29-bit limbs a whole column of a product (at most 9 partial
-// products plus 6 reduction terms, < 2^62) fits one 64-bit accumulator, so
+// products plus 4 reduction terms, < 2^62) fits one 64-bit accumulator, so
 // every partial product is exactly one multiply-add into the accumulator and
 // no carry is propagated inside the multiplication.
-// Montgomery reduction: p = -1 (mod 2^29), so the per-column quotient digit is
-// simply the low 29 bits of the column, and its p_0 term folds into the carry
-// (acc + m (2^29 - 1) = acc - m + m 2^29).  p has 7 nonzero radix-2^29
-// digits, so a reduction costs 6 multiply-adds per digit.
+// Montgomery reduction: p = -1 (mod 2^29), so the per-column quotient digit m
+// is simply the low 29 bits of the column.  In signed radix-2^29 digits
+//   p = -1 + 2^9 B^3 + 2^18 B^6 - 2^21 B^7 + 2^24 B^8      (B = 2^29),
+// so adding m p clears the low 29 bits of the column (the -1 digit: the
+// carry out is just the column shifted right) and adds four multiples of m
+// to later columns: four multiply-adds per quotient digit.  The column
+// accumulators are therefore signed 64-bit.
 // Carries between limbs are handled with plain 32/64-bit integer shifts and
 // masks (no add-with-carry intrinsics).
 #pragma once
@@ -263,8 +266,37 @@ __device__ __forceinline__ bool fe_eq(const fe &a, const fe &b) { return fe_is_z
 // Montgomery multiplication a b 2^-261 mod p (product scanning, the
 // reduction interleaved column by column)
 // ---------------------------------------------------------------------------
+// red_terms adds to column c the contributions m_i p_j (i + j = c) of the
+// earlier quotient digits m_i, for the nonzero signed digits p_3, p_6, p_7,
+// p_8 of p (see the header).  The multipliers are kept opaque to the compiler
+// so that each term stays one 32 x 32 -> 64-bit multiply-add instead of
+// becoming a 64-bit shift plus an add.
+struct red_consts {
+    uint32_t k9, k18, k24;
+    int32_t kn21;
+};
+
+__device__ __forceinline__ red_consts red_consts_make() {
+    red_consts k{1u << 9, 1u << 18, 1u << 24, -(1 << 21)};
+    asm("" : "+s"(k.k9), "+s"(k.k18), "+s"(k.k24), "+s"(k.kn21));
+    return k;
+}
+
+__device__ __forceinline__ void red_terms(int64_t &acc, const uint32_t *m, int c, const red_consts &k) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int j = c - i;
+        if (i >= c) continue;
+        if (j == 3) acc += (int64_t)((uint64_t)m[i] * k.k9);
+        if (j == 6) acc += (int64_t)((uint64_t)m[i] * k.k18);
+        if (j == 7) acc += (int64_t)(int32_t)m[i] * (int64_t)k.kn21;
+        if (j == 8) acc += (int64_t)((uint64_t)m[i] * k.k24);
+    }
+}
+
 __device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) {
-    uint64_t acc = 0;
+    const red_consts k = red_consts_make();
+    int64_t acc = 0;
     uint32_t m[NL];
     fe r;
 #pragma unroll
@@ -272,31 +304,25 @@ __device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) {
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
             const int j = c - i;
-            if (j >= 0 && j < NL) acc += (uint64_t)a.v[i] * b.v[j];
+            if (j >= 0 && j < NL) acc += (int64_t)((uint64_t)a.v[i] * b.v[j]);
         }
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int j = c - i;
-            if (i < c && j >= 1 && j < NL && P29.v[j] != 0) acc += (uint64_t)m[i] * P29.v[j];
-        }
-        if (c < NL) {
+        red_terms(acc, m, c, k);
+        if (c < NL)
             m[c] = (uint32_t)acc & LMASK;
-            acc = (acc >> LB) + m[c];
-        } else {
+        else
             r.v[c - NL] = (uint32_t)acc & LMASK;
-            acc >>= LB;
-        }
+        acc >>= LB;  // exact after m p clears the low bits; arithmetic shift
     }
     r.v[NL - 1] = (uint32_t)acc;
     return r;
 }
 
-// squaring: cross products once with a doubled operand
 __device__ __forceinline__ fe fe_sqr(const fe &a) {
+    const red_consts k = red_consts_make();
     uint32_t d[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i) d[i] = a.v[i] << 1;
-    uint64_t acc = 0;
+    int64_t acc = 0;
     uint32_t m[NL];
     fe r;
 #pragma unroll
@@ -304,21 +330,15 @@ __device__ __forceinline__ fe fe_sqr(const fe &a) {
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
             const int j = c - i;
-            if (i < j && j < NL) acc += (uint64_t)d[i] * a.v[j];
+            if (i < j && j < NL) acc += (int64_t)((uint64_t)d[i] * a.v[j]);
         }
-        if ((c & 1) == 0 && c / 2 < NL) acc += (uint64_t)a.v[c / 2] * a.v[c / 2];
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int j = c - i;
-            if (i < c && j >= 1 && j < NL && P29.v[j] != 0) acc += (uint64_t)m[i] * P29.v[j];
-        }
-        if (c < NL) {
+        if ((c & 1) == 0 && c / 2 < NL) acc += (int64_t)((uint64_t)a.v[c / 2] * a.v[c / 2]);
+        red_terms(acc, m, c, k);
+        if (c < NL)
             m[c] = (uint32_t)acc & LMASK;
-            acc = (acc >> LB) + m[c];
-        } else {
+        else
             r.v[c - NL] = (uint32_t)acc & LMASK;
-            acc >>= LB;
-        }
+        acc >>= LB;
     }
     r.v[NL - 1] = (uint32_t)acc;
     return r;

@@ -340,7 +340,7 @@ geometry make_geometry(const cussen_plan &P, int l, int c_form, const pcmm_cusse
 
 // events bracketing the stages of one profiled call
 struct stage_events {
-    hipEvent_t e[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t e[PCMM_STAGE_EVENTS] = {};
     hipError_t create() {
         for (auto &x : e) {
             hipError_t r = hipEventCreate(&x);
@@ -466,15 +466,29 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
     if (rc == -2) return PCMM_ERANGE;
     if (rc) return PCMM_EINVAL;
     fill_stats(P, stats);
+    hipEvent_t ev[PCMM_STAGE_EVENTS] = {};
+    const bool caller_events = cfg && cfg->stage_events;
+    if (caller_events) {
+        for (int i = 0; i < PCMM_STAGE_EVENTS; ++i) {
+            ev[i] = (hipEvent_t)cfg->stage_events[i];
+            if (!ev[i]) return PCMM_EINVAL;
+        }
+    }
+    // calls without the stage pipeline still mark every caller event
+    auto record_all = [&]() -> pcmm_status {
+        if (caller_events)
+            for (int i = 0; i < PCMM_STAGE_EVENTS; ++i) PCMM_HIP_TRY(hipEventRecord(ev[i], s));
+        return PCMM_OK;
+    };
     const int64_t n_out = (int64_t)m * l;
-    if (n_out == 0) return PCMM_OK;
+    if (n_out == 0) return record_all();
     if (n == 0) {
         // empty inner dimension: every output is the identity
         int64_t blocks = (n_out + 255) / 256;
         hipLaunchKernelGGL(fill_infinity_kernel, dim3((unsigned)blocks), dim3(256), 0, s, C->d, C->ld, n_out,
                            C->form);
         PCMM_LAUNCH_CHECK();
-        return PCMM_OK;
+        return record_all();
     }
     geometry G = make_geometry(P, l, C->form, cfg);
     if (!workspace || ws_bytes < G.total) return PCMM_ENOMEM;
@@ -483,13 +497,17 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
         stats->lanes_per_chain = G.J;
     }
     char *ws = (char *)workspace;
-    const bool prof = cfg && cfg->profile;
-    stage_events ev;
-    if (prof) PCMM_HIP_TRY(ev.create());
-    if (prof) hipEventRecord(ev.e[0], s);
+    const bool wait_prof = cfg && cfg->profile;
+    const bool prof = wait_prof || caller_events;
+    stage_events own;
+    if (wait_prof && !caller_events) {
+        PCMM_HIP_TRY(own.create());
+        for (int i = 0; i < PCMM_STAGE_EVENTS; ++i) ev[i] = own.e[i];
+    }
+    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[0], s));
     st = upload_plan(P, ws + G.off_plan, s);
     if (st != PCMM_OK) return st;
-    if (prof) hipEventRecord(ev.e[1], s);
+    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[1], s));
     // device views of the plan
     size_t off = 0;
     auto view = [&](size_t n_bytes) {
@@ -526,7 +544,7 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
         hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ta);
         PCMM_LAUNCH_CHECK();
     }
-    if (prof) hipEventRecord(ev.e[2], s);
+    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[2], s));
     const int64_t ldc = std::max<int64_t>(64, (n_out + 63) / 64 * 64);
     const bool affine_out = C->form == PCMM_AFFINE;
     uint32_t *jac_out = affine_out ? (uint32_t *)(ws + G.off_cjac) : C->d;
@@ -559,7 +577,7 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
         hipLaunchKernelGGL(accumulate_kernel, grid, dim3(256), G.lds_bytes, s, aa);
         PCMM_LAUNCH_CHECK();
     }
-    if (prof) hipEventRecord(ev.e[3], s);
+    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[3], s));
     if (G.S > 1) {
         int64_t threads = 2 * n_out * G.S;
         int64_t blocks = (threads + 255) / 256;
@@ -567,20 +585,20 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
                            G.S, n_out, jac_out, ld_jac, affine_out ? 0 : 1);
         PCMM_LAUNCH_CHECK();
     }
-    if (prof) hipEventRecord(ev.e[4], s);
+    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[4], s));
     if (affine_out) {
         st = launch_normalize(jac_out, ld_jac, true, C->d, C->ld, false, n_out, 2, ws + G.off_norm,
                               G.total - G.off_norm, s);
         if (st != PCMM_OK) return st;
     }
-    if (prof) {
-        hipEventRecord(ev.e[5], s);
-        PCMM_HIP_TRY(hipEventSynchronize(ev.e[5]));
+    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[5], s));
+    if (wait_prof) {
+        PCMM_HIP_TRY(hipEventSynchronize(ev[5]));
         if (stats) {
             float *dst[5] = {&stats->ms_upload, &stats->ms_table, &stats->ms_accumulate, &stats->ms_reduce,
                              &stats->ms_normalize};
-            for (int i = 0; i < 5; ++i) hipEventElapsedTime(dst[i], ev.e[i], ev.e[i + 1]);
-            hipEventElapsedTime(&stats->ms_total, ev.e[0], ev.e[5]);
+            for (int i = 0; i < 5; ++i) PCMM_HIP_TRY(hipEventElapsedTime(dst[i], ev[i], ev[i + 1]));
+            PCMM_HIP_TRY(hipEventElapsedTime(&stats->ms_total, ev[0], ev[5]));
         }
     }
     return PCMM_OK;

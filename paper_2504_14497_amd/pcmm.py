@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpcmm.so")
 
 AFFINE = 2
 JACOBIAN = 3
+STAGE_EVENTS = 6  # PCMM_STAGE_EVENTS
 
 _STATUS = {0: "PCMM_OK", -1: "PCMM_EINVAL", -2: "PCMM_ERANGE", -3: "PCMM_ENOMEM",
            -4: "PCMM_EDEVICE", -5: "PCMM_ENOTONCURVE"}
@@ -41,7 +42,24 @@ class PointBE(ctypes.Structure):
 
 class CussenCfg(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("group", ctypes.c_int32), ("k_split", ctypes.c_int32),
-                ("k_chunk", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("k_chunk", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("stage_events", ctypes.POINTER(ctypes.c_void_p))]
+
+
+def cussen_cfg(rounds=4, group=0, k_split=0, k_chunk=0, profile=0, stage_events=None) -> CussenCfg:
+    """A pcmm_cussen_cfg.  stage_events: None or PCMM_STAGE_EVENTS torch.cuda
+    Events (timing enabled, each recorded once beforehand so that its HIP
+    handle exists) that the call records its stage boundaries into."""
+    cfg = CussenCfg(rounds, group, k_split, k_chunk, profile, None)
+    if stage_events is not None:
+        if len(stage_events) != STAGE_EVENTS:
+            raise ValueError(f"need {STAGE_EVENTS} events")
+        arr = (ctypes.c_void_p * STAGE_EVENTS)(*[int(e.cuda_event) for e in stage_events])
+        if not all(arr):
+            raise ValueError("record each event once before handing it over")
+        cfg.stage_events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+        cfg._keep = (arr, tuple(stage_events))
+    return cfg
 
 
 class CussenStats(ctypes.Structure):
@@ -399,8 +417,10 @@ def cussen(A, bits: int, B: DevPoints, c_form: int = AFFINE, cfg: CussenCfg = No
     A, signed = _host_A(A)
     m, n = A.shape
     C = out if out is not None else DevPoints.empty(m, B.cols, 2, c_form)
-    need = cussen_workspace_bytes(A, bits, B.cols, C.form, cfg)
-    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need)
+    if workspace is not None:
+        ws = workspace  # the library rejects one that is too small (PCMM_ENOMEM)
+    else:
+        ws = _workspace(cussen_workspace_bytes(A, bits, B.cols, C.form, cfg))
     st = CussenStats()
     _call("pcmm_cussen", A.ctypes.data_as(_VP), m, n, bits, signed, B.ref(), C.ref(),
           ctypes.byref(cfg) if cfg is not None else None, _tensor_ptr(ws), ws.numel(),

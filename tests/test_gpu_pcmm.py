@@ -145,6 +145,32 @@ def test_degenerate_sizes(dev, orc):
     assert (C[2] == B[1]).all() and (C[[0, 1, 3]] == 0).all()
 
 
+def test_caller_stage_events(dev, orc):
+    """Stage events handed in by the caller are recorded (also on the paths
+    that launch no stage pipeline) and do not change the result."""
+    import torch
+    B = random_cts(orc, 6, 5, 600)
+    Bd = _upload(dev, B)
+    A = np.random.default_rng(6).integers(0, 16, size=(7, 6), dtype=np.uint8)
+    stream = torch.cuda.current_stream()
+    log("stage events")
+    for A_, Bd_ in ((A, Bd), (np.zeros((2, 0), np.uint8), dev.DevPoints.empty(0, 5, 2, dev.AFFINE)),
+                    (np.zeros((0, 6), np.uint8), Bd)):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(dev.STAGE_EVENTS)]
+        for e in evs:
+            e.record(stream)
+        torch.cuda.synchronize()
+        C, _ = dev.cussen(A_, 4, Bd_, cfg=dev.cussen_cfg(4, 1, stage_events=evs))
+        torch.cuda.synchronize()
+        if A_.size:
+            assert (C.to_host() == orc.pcmm_cussen(A_, B)).all()
+        dts = [evs[i].elapsed_time(evs[i + 1]) for i in range(dev.STAGE_EVENTS - 1)]
+        assert all(d >= 0 for d in dts)
+        assert abs(sum(dts) - evs[0].elapsed_time(evs[-1])) < 1e-2
+    with pytest.raises(ValueError):
+        dev.cussen_cfg(4, 1, stage_events=evs[:3])
+
+
 def test_out_of_range_is_rejected(dev, orc):
     B = random_cts(orc, 2, 2, 500)
     Bd = _upload(dev, B)

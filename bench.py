@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--school-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run the plain copy kernel over BYTES (read BYTES, write BYTES) three "
+                         "times, to scale the HBM byte counters of a profiler run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -119,6 +122,16 @@ def main():
     from paper_2504_14497_amd import pcmm, workloads as W
 
     pcmm.lib()
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy // 16 * 16
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            pcmm.diag_copy(src, dst)
+        torch.cuda.synchronize()
+        assert bool((dst == 1).all())
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}), flush=True)
+        return
     dev = pcmm.device_info()
     sh = W.NAMED[args.workload]
     A, msg = W.make_inputs(sh)

@@ -117,7 +117,7 @@ __device__ __forceinline__ apt point16_mont(const point16 &p) {
 }
 
 // 2^(4w) B and its multiples for window w = thread index (Jacobian, Montgomery)
-__global__ void __launch_bounds__(64) table_build_kernel(point16 base, uint32_t *__restrict__ jac_tmp) {
+__global__ void __launch_bounds__(64) fixed_base_table_kernel(point16 base, uint32_t *__restrict__ jac_tmp) {
     int w = threadIdx.x;
     if (w >= WINDOWS) return;
     apt b = point16_mont(base);
@@ -229,7 +229,7 @@ pcmm_status build_table(const point16 &base, uint32_t *table_out, void *tmp, siz
     if (tmp_bytes < need) return PCMM_ENOMEM;
     uint32_t *jac = (uint32_t *)tmp;
     void *scratch = (char *)tmp + jac_bytes;
-    hipLaunchKernelGGL(table_build_kernel, dim3(1), dim3(64), 0, s, base, jac);
+    hipLaunchKernelGGL(fixed_base_table_kernel, dim3(1), dim3(64), 0, s, base, jac);
     PCMM_LAUNCH_CHECK();
     return launch_normalize(jac, TABLE_POINTS, true, table_out, TABLE_POINTS, true, TABLE_POINTS, 1, scratch,
                             tmp_bytes - jac_bytes, s);

@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large512_t4")
     ap.add_argument("--group", type=int, default=0, help="Cussen column group g (0 = library default)")
+    ap.add_argument("--k-chunk", type=int, default=0, help="column groups staged in LDS at once (0 = library default)")
+    ap.add_argument("--k-split", type=int, default=0, help="split of the inner dimension (0 = library default)")
     ap.add_argument("--school-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,7 +144,7 @@ def main():
 
     stream = torch.cuda.current_stream()
     C = pcmm.DevPoints.empty(sh.m, sh.l, 2, pcmm.AFFINE)
-    cfg = pcmm.cussen_cfg(4, args.group)
+    cfg = pcmm.cussen_cfg(4, args.group, args.k_split, args.k_chunk)
     ws = torch.empty(pcmm.cussen_workspace_bytes(A, sh.bits, sh.l, pcmm.AFFINE, cfg),
                      dtype=torch.uint8, device="cuda")
     # one set of stage events per timed step, recorded by the library on the
@@ -153,7 +155,8 @@ def main():
     for evs in step_events:
         for e in evs:
             e.record(stream)
-    step_cfgs = [pcmm.cussen_cfg(4, args.group, stage_events=evs) for evs in step_events]
+    step_cfgs = [pcmm.cussen_cfg(4, args.group, args.k_split, args.k_chunk, stage_events=evs)
+                 for evs in step_events]
     for _ in range(args.warmup):
         pcmm.cussen(A, sh.bits, B, cfg=cfg, workspace=ws, out=C)
     torch.cuda.synchronize()

@@ -84,7 +84,12 @@ typedef struct {
  *   rounds  N, compression rounds of Alg. 2 (default 4, as in the paper; 1..8)
  *   group   columns of A per code (default 1 = Alg. 3 exactly, one column of A
  *           per compression; g > 1 compresses row segments of g columns into
- *           one code and builds the table of their ciphertext combinations)
+ *           one code and builds the table of their ciphertext combinations;
+ *           1..4, or PCMM_GROUP_AUTO: the autotuner builds the plans for
+ *           g = 1..4 and keeps the one of least predicted GPU time, from a
+ *           cost model of accumulation slots, table additions and table
+ *           entries fitted to MI355X measurements; the choice is cached per
+ *           shape (m, n, l, bits, signedness, rounds) for the process)
  *   k_split split of the n (inner) dimension over independent partial sums that
  *           are then added (0 = chosen from the shape)
  *   k_chunk columns of A whose tables are staged in LDS at once (0 = auto)
@@ -102,6 +107,7 @@ typedef struct {
  *           With profile nonzero as well, these events are the ones waited
  *           on and read into the stats. */
 #define PCMM_STAGE_EVENTS 6
+#define PCMM_GROUP_AUTO (-1)
 typedef struct {
     int32_t rounds;
     int32_t group;
@@ -121,6 +127,8 @@ typedef struct {
     int64_t max_entries;     /* largest table (entries) of one column (group)              */
     int32_t k_split;         /* split of the inner dimension that was used                 */
     int32_t lanes_per_chain; /* table-build batch: output columns per lane                 */
+    int32_t group;           /* columns of A per code that was used (after autotuning)     */
+    int32_t reserved;
     /* with cfg->profile: milliseconds from the first to the last event of each stage */
     float ms_upload, ms_table, ms_accumulate, ms_reduce, ms_normalize, ms_total;
 } pcmm_cussen_stats;
@@ -171,6 +179,49 @@ pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_t bits, int
 pcmm_status pcmm_cussen_workspace(const int8_t *A, int32_t m, int32_t n, int32_t l, int32_t bits,
                                   int32_t is_signed, int32_t c_form, const pcmm_cussen_cfg *cfg,
                                   size_t *bytes);
+
+/* Compiled plans: one or more Cussen PC-MMs, compressed once on the host and
+ * run any number of times (a static plaintext A served against fresh
+ * ciphertexts), or many uneven PC-MMs run together.  A run queues the same
+ * few kernels whatever the number of problems: one table build over all
+ * problems, one persistent accumulation kernel whose workgroups take
+ * (problem, row tile, pair tile, split) tiles from a device queue, one
+ * split-k reduction and one affine normalisation.  The plan's host image
+ * (plans and per-problem geometry) is immutable after creation and is copied
+ * to the workspace at the start of every run, so a run can be captured into
+ * a hipGraph and replayed (the matrices and workspace are those given at
+ * capture).  A plan is bound to the device that was current at creation. */
+#define PCMM_PLAN_MAX_PROBLEMS 64
+typedef struct pcmm_plan_s *pcmm_plan;
+
+typedef struct {
+    const int8_t *A;     /* host, m x n row-major, read only during pcmm_plan_create */
+    int32_t m, n, l;     /* C = A B with B n x l                                     */
+    int32_t bits, is_signed;
+    int32_t c_form;      /* PCMM_AFFINE (canonical, normalised) or PCMM_JACOBIAN     */
+    pcmm_cussen_cfg cfg; /* rounds, group (or PCMM_GROUP_AUTO), k_split, k_chunk; its
+                            profile and stage_events fields are ignored here          */
+} pcmm_problem;
+
+/* Compresses every A (host threads over problems) and lays out the
+ * workspace.  count: 1..PCMM_PLAN_MAX_PROBLEMS.  *out receives a handle that
+ * pcmm_plan_destroy releases.  PCMM_ERANGE if an A entry is outside its
+ * bit-width; PCMM_EINVAL for bad shapes or cfg; PCMM_ENOMEM if host memory
+ * runs out. */
+pcmm_status pcmm_plan_create(const pcmm_problem *problems, int32_t count, pcmm_plan *out);
+pcmm_status pcmm_plan_destroy(pcmm_plan plan);
+/* Device workspace bytes a run needs (tables, partial sums, the plan image). */
+pcmm_status pcmm_plan_workspace(pcmm_plan plan, size_t *bytes);
+/* Operation counts and the chosen geometry of problem `index`. */
+pcmm_status pcmm_plan_stats(pcmm_plan plan, int32_t index, pcmm_cussen_stats *stats);
+/* Runs every problem of the plan: B[i] (n_i x l_i affine ciphertexts) and
+ * C[i] (m_i x l_i, the problem's c_form) are host arrays of `count` matrix
+ * descriptors of device memory; B[i] and C[i] must not alias.  stage_events:
+ * NULL or PCMM_STAGE_EVENTS caller-owned events recorded at the stage
+ * boundaries (as in pcmm_cussen_cfg).  Queues the work on `stream` and
+ * returns without waiting.  Runs that overlap on one workspace race. */
+pcmm_status pcmm_plan_run(pcmm_plan plan, const pcmm_mat *B, pcmm_mat *C, void *workspace,
+                          size_t ws_bytes, void **stage_events, void *stream);
 
 /* Host-only: the compression plan's operation counts for A (no GPU work). */
 pcmm_status pcmm_cussen_plan_stats(const int8_t *A, int32_t m, int32_t n, int32_t bits,

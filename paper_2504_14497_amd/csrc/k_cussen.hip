@@ -1,24 +1,39 @@
-// k_cussen.hip -- Cussen PC-MM (Alg. 3 with Alg. 2) on gfx950.
+// k_cussen.hip -- Cussen PC-MM (Alg. 3 with Alg. 2) on gfx950, for one
+// problem (pcmm_cussen) or a compiled plan of up to 64 problems (pcmm_plan_*).
 //
-// Three kernels:
-//   table_build   one lane per (column group, J output columns j, point): runs
-//                 the group's straight-line program (level-N ladders, prefix
-//                 sums, digit combinations) on B[k0.., j], keeps every
-//                 register in a lane-private scratch (structure of arrays, so
-//                 the lanes' accesses coalesce), then converts its tables to
-//                 affine with one inversion for all of its J tables.
-//   accumulate    C_ij += sign * T_kj[code_ik]: each workgroup stages the tables
-//                 of a chunk of column groups for its (j, point) pairs in LDS;
-//                 every lane owns one accumulator (row i, pair) in VGPRs and
-//                 walks the chunk with mixed additions.  The inner dimension
-//                 may be split over independent partial sums.
+// Every run queues the same kernels whatever the number of problems; each
+// kernel finds the problem of its block (or tile) by a binary search over the
+// per-problem prefix offsets held in the descriptors of the plan image:
+//   table_build   one lane per (problem, column group, J output columns j,
+//                 point): runs the group's straight-line program (level-N
+//                 ladders, prefix sums, digit combinations) on B[k0.., j],
+//                 keeps every register in a lane-private scratch (structure of
+//                 arrays, so the lanes' accesses coalesce), then converts its
+//                 tables to affine with one inversion for all of its J tables.
+//   accumulate    persistent: workgroups take tiles (problem, row tile, pair
+//                 tile, split) from a device queue, the most expensive tiles
+//                 first.  For a tile, C_ij += sign * T_kj[code_ik]: the
+//                 workgroup stages the tables of a chunk of column groups for
+//                 its (j, point) pairs in LDS; every lane owns one accumulator
+//                 (row i, pair) in VGPRs and walks the chunk with mixed
+//                 additions.  The inner dimension may be split over
+//                 independent partial sums.
 //   reduce        adds the split-k partial sums of one output with a tree of
 //                 point additions across the lanes of a wavefront (shuffles).
+//   normalize     Jacobian -> canonical affine C with batched inversion.
+#include <algorithm>
+#include <atomic>
+#include <cstddef>
+#include <cstring>
+#include <map>
 #include <mutex>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
 #include "normalize.hpp"
+#include "normalize_dev.hpp"
 #include "plan.hpp"
 
 using namespace pcmm;
@@ -26,28 +41,75 @@ using namespace pcmm;
 namespace {
 
 constexpr int ENTRY_WORDS = 20;  // affine entry: x (9 limbs), y (9 limbs), 2 pad words; Montgomery form
+constexpr int JAC_WORDS = 3 * NL;
+constexpr int MAX_PROBLEMS = PCMM_PLAN_MAX_PROBLEMS;
 
-struct tb_args {
-    const plan_op *ops;
-    const int32_t *op_begin;
-    const int32_t *entry_begin;
-    const int16_t *entries;
-    const uint32_t *B;  // n x l ciphertexts, affine canonical
-    int64_t ldb;
-    int n, l, g, J, Lj, rmax, emax;
-    int64_t n_lanes;
-    uint32_t *regs;     // [(r * rmax + reg) * 27 + word][lane]
-    uint32_t *table;    // [((grp * l + j) * 2 + pt) * emax + e][ENTRY_WORDS]
+// One problem of a run, as the kernels see it.  Offsets o_* are bytes into
+// the plan image, w_* bytes into the workspace; the image sits at the start
+// of the workspace, descriptors first.
+struct prob_desc {
+    int32_t m, n, l, g;
+    int32_t ngroups, emax, rmax, c_form;
+    int32_t J, Lj, tm, pp;
+    int32_t kc, S, gps, io;  // io: index of the problem's matrices in the run
+    int32_t tiles_x, tiles_y, norm_per, pad;
+    int64_t n_lanes, tb_block0;
+    int64_t tile0;
+    int64_t red_block0, red_threads;
+    int64_t norm_block0, norm_threads;
+    int64_t ldj;     // ld of the internal Jacobian buffers (partials, C before normalisation)
+    int64_t ld_pre;  // ld of the normalisation prefixes
+    int64_t o_ops, o_op_begin, o_entry_begin, o_entries, o_codes;
+    int64_t w_regs, w_table, w_part, w_cjac, w_norm;
 };
 
-constexpr int JAC_WORDS = 3 * NL;
+struct io_ptrs {
+    const uint32_t *B;  // n x l ciphertexts, affine canonical
+    uint32_t *C;        // m x l, canonical, the problem's c_form
+    int64_t ldb, ldc;
+};
 
-__device__ __forceinline__ jpt reg_load(const tb_args &a, int r, int reg, int64_t lane) {
-    return load_jac_m(a.regs + (int64_t)(r * a.rmax + reg) * JAC_WORDS * a.n_lanes, a.n_lanes, 0, lane);
+struct run_args {
+    char *ws;            // workspace; the plan image starts here
+    int32_t count;       // descriptors
+    int32_t pad;
+    int64_t total_tiles;
+    int64_t ctr_off;     // byte offset of the accumulation queue counter
+    io_ptrs io[MAX_PROBLEMS];
+};
+
+__device__ __forceinline__ const prob_desc *descs(const run_args &a) { return (const prob_desc *)a.ws; }
+
+// last problem whose prefix value (the int64 at byte offset key_off of its
+// descriptor) is <= x; problems with empty ranges are skipped by construction
+__device__ __forceinline__ int find_problem(const run_args &a, size_t key_off, int64_t x) {
+    const char *d = (const char *)descs(a);
+    int lo = 0, hi = a.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t k = *(const int64_t *)(d + (size_t)mid * sizeof(prob_desc) + key_off);
+        if (k <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
-__device__ __forceinline__ void reg_store(const tb_args &a, int r, int reg, int64_t lane, const jpt &P) {
-    store_jac_m(a.regs + (int64_t)(r * a.rmax + reg) * JAC_WORDS * a.n_lanes, a.n_lanes, 0, lane, P);
+template <typename T>
+__device__ __forceinline__ T *at(const run_args &a, int64_t off) {
+    return (T *)(a.ws + off);
+}
+
+// --------------------------------------------------------------------------
+// Table build
+// --------------------------------------------------------------------------
+__device__ __forceinline__ jpt reg_load(const uint32_t *regs, int rmax, int64_t n_lanes, int r, int reg,
+                                        int64_t lane) {
+    return load_jac_m(regs + (int64_t)(r * rmax + reg) * JAC_WORDS * n_lanes, n_lanes, 0, lane);
+}
+
+__device__ __forceinline__ void reg_store(uint32_t *regs, int rmax, int64_t n_lanes, int r, int reg, int64_t lane,
+                                          const jpt &P) {
+    store_jac_m(regs + (int64_t)(r * rmax + reg) * JAC_WORDS * n_lanes, n_lanes, 0, lane, P);
 }
 
 __device__ __forceinline__ apt base_point(const apt Bt[4], int t) {
@@ -58,34 +120,49 @@ __device__ __forceinline__ apt base_point(const apt Bt[4], int t) {
     return r;
 }
 
-__global__ void __launch_bounds__(256) table_build_kernel(tb_args a) {
-    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane >= a.n_lanes) return;
-    const int lanes_per_group = 2 * a.Lj;
+__global__ void __launch_bounds__(256) table_build_kernel(run_args a) {
+    // the accumulation that follows on the stream starts its queue at zero
+    if (blockIdx.x == 0 && threadIdx.x == 0) *at<int32_t>(a, a.ctr_off) = 0;
+    const int b = find_problem(a, offsetof(prob_desc, tb_block0), blockIdx.x);
+    const prob_desc &d = descs(a)[b];
+    const int64_t lane = ((int64_t)blockIdx.x - d.tb_block0) * blockDim.x + threadIdx.x;
+    if (lane >= d.n_lanes) return;
+    const plan_op *ops = at<const plan_op>(a, d.o_ops);
+    const int32_t *op_begin = at<const int32_t>(a, d.o_op_begin);
+    const int32_t *entry_begin = at<const int32_t>(a, d.o_entry_begin);
+    const int16_t *entries = at<const int16_t>(a, d.o_entries);
+    uint32_t *regs = at<uint32_t>(a, d.w_regs);
+    uint32_t *table = at<uint32_t>(a, d.w_table);
+    const uint32_t *B = a.io[d.io].B;
+    const int64_t ldb = a.io[d.io].ldb;
+    const int l = d.l, rmax = d.rmax, emax = d.emax;
+    const int64_t n_lanes = d.n_lanes;
+
+    const int lanes_per_group = 2 * d.Lj;
     const int grp = (int)(lane / lanes_per_group);
     const int rem = (int)(lane % lanes_per_group);
     const int jslot = rem >> 1;
     const int pt = rem & 1;
-    const int k0 = grp * a.g;
-    const int gg = min(a.g, a.n - k0);
-    const int ob = a.op_begin[grp], oe = a.op_begin[grp + 1];
-    const int eb = a.entry_begin[grp], ee = a.entry_begin[grp + 1];
+    const int k0 = grp * d.g;
+    const int gg = min(d.g, d.n - k0);
+    const int ob = op_begin[grp], oe = op_begin[grp + 1];
+    const int eb = entry_begin[grp], ee = entry_begin[grp + 1];
     const int E = ee - eb;
 
     fe prod = fe_one_mont();
     int last_r = -1;
-    for (int r = 0; r < a.J; ++r) {
-        const int j = jslot + r * a.Lj;
-        if (j >= a.l) break;
+    for (int r = 0; r < d.J; ++r) {
+        const int j = jslot + r * d.Lj;
+        if (j >= l) break;
         last_r = r;
         apt Bt[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            if (t < gg) Bt[t] = load_affine(a.B, a.ldb, pt, (int64_t)(k0 + t) * a.l + j);
+            if (t < gg) Bt[t] = load_affine(B, ldb, pt, (int64_t)(k0 + t) * l + j);
             else Bt[t] = Bt[0];
         }
         for (int o = ob; o < oe; ++o) {
-            const plan_op op = a.ops[o];
+            const plan_op op = ops[o];
             jpt R;
             if (op.kind == OP_MUL) {
                 int s = op.s;
@@ -93,30 +170,31 @@ __global__ void __launch_bounds__(256) table_build_kernel(tb_args a) {
                 R = ladder_small((uint32_t)s, bits, base_point(Bt, -1 - op.a));
             } else {
                 if (op.a >= 0 && op.b >= 0) {
-                    jpt Q = reg_load(a, r, op.b, lane);
+                    jpt Q = reg_load(regs, rmax, n_lanes, r, op.b, lane);
                     if (op.neg_b) Q = jpt_neg(Q);
-                    R = jpt_add(reg_load(a, r, op.a, lane), Q);
+                    R = jpt_add(reg_load(regs, rmax, n_lanes, r, op.a, lane), Q);
                 } else if (op.b < 0) {
                     apt Q = base_point(Bt, -1 - op.b);
                     if (op.neg_b) Q = apt_neg(Q);
-                    jpt P = op.a >= 0 ? reg_load(a, r, op.a, lane) : jpt_from_affine(base_point(Bt, -1 - op.a));
+                    jpt P = op.a >= 0 ? reg_load(regs, rmax, n_lanes, r, op.a, lane)
+                                      : jpt_from_affine(base_point(Bt, -1 - op.a));
                     R = jpt_add_affine(P, Q);
                 } else {
                     // a is a base point, b a register: a + (+-b) = (+-b) + a
-                    jpt Q = reg_load(a, r, op.b, lane);
+                    jpt Q = reg_load(regs, rmax, n_lanes, r, op.b, lane);
                     if (op.neg_b) Q = jpt_neg(Q);
                     R = jpt_add_affine(Q, base_point(Bt, -1 - op.a));
                 }
             }
-            reg_store(a, r, op.dst, lane, R);
+            reg_store(regs, rmax, n_lanes, r, op.dst, lane, R);
         }
         // forward pass of the batched inversion over this table's register entries
-        const int64_t T = ((int64_t)grp * a.l + j) * 2 + pt;
+        const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
         for (int e = 0; e < E; ++e) {
-            const int16_t opd = a.entries[eb + e];
+            const int16_t opd = entries[eb + e];
             if (opd < 0) continue;
-            fe z = reg_load(a, r, opd, lane).Z;
-            uint32_t *slot = a.table + (T * a.emax + e) * ENTRY_WORDS;
+            fe z = reg_load(regs, rmax, n_lanes, r, opd, lane).Z;
+            uint32_t *slot = table + (T * emax + e) * ENTRY_WORDS;
 #pragma unroll
             for (int w = 0; w < NL; ++w) slot[w] = prod.v[w];
             if (!fe_is_zero(z)) prod = fe_mul(prod, z);
@@ -125,16 +203,16 @@ __global__ void __launch_bounds__(256) table_build_kernel(tb_args a) {
     if (last_r < 0) return;
     fe inv = fe_inv(prod);
     for (int r = last_r; r >= 0; --r) {
-        const int j = jslot + r * a.Lj;
-        const int64_t T = ((int64_t)grp * a.l + j) * 2 + pt;
+        const int j = jslot + r * d.Lj;
+        const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
         for (int e = E - 1; e >= 0; --e) {
-            const int16_t opd = a.entries[eb + e];
-            uint32_t *slot = a.table + (T * a.emax + e) * ENTRY_WORDS;
+            const int16_t opd = entries[eb + e];
+            uint32_t *slot = table + (T * emax + e) * ENTRY_WORDS;
             apt A;
             if (opd < 0) {
-                A = load_affine(a.B, a.ldb, pt, (int64_t)(k0 + (-1 - opd)) * a.l + j);
+                A = load_affine(B, ldb, pt, (int64_t)(k0 + (-1 - opd)) * l + j);
             } else {
-                jpt P = reg_load(a, r, opd, lane);
+                jpt P = reg_load(regs, rmax, n_lanes, r, opd, lane);
                 fe pre;
 #pragma unroll
                 for (int w = 0; w < NL; ++w) pre.v[w] = slot[w];
@@ -157,56 +235,48 @@ __global__ void __launch_bounds__(256) table_build_kernel(tb_args a) {
 }
 
 // --------------------------------------------------------------------------
-// Accumulation
+// Accumulation (persistent)
 // --------------------------------------------------------------------------
-struct acc_args {
-    const uint32_t *table;   // affine Montgomery entries
-    const int16_t *codes;    // [grp * m + i]
-    int m, l, ngroups, emax;
-    int tm, pp;              // rows and (j, point) pairs per workgroup (tm * pp = 256)
-    int kc;                  // groups staged per LDS chunk
-    int groups_per_split;
-    uint32_t *out;           // Jacobian, Montgomery: partial sums or C
-    int64_t ld_out;
-    int out_canonical;       // store canonical limbs (C given as Jacobian) instead of Montgomery
-};
-
-__global__ void __launch_bounds__(256) accumulate_kernel(acc_args a) {
-    extern __shared__ uint32_t lds[];
+// One tile: rows bx * tm .. + tm, (j, point) pairs by * pp .. + pp, column
+// groups of split bz.  Every thread of the workgroup calls this with the same
+// tile (the LDS staging has barriers).
+__device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_desc &d, int bx, int by, int bz,
+                                                uint32_t *lds) {
     const int tid = threadIdx.x;
-    const int row_l = tid % a.tm;
-    const int pair_l = tid / a.tm;
-    const int i = blockIdx.x * a.tm + row_l;
-    const int p0 = blockIdx.y * a.pp;
+    const int tm = d.tm, pp = d.pp, emax = d.emax, m = d.m, l = d.l;
+    const int row_l = tid % tm;
+    const int pair_l = tid / tm;
+    const int i = bx * tm + row_l;
+    const int p0 = by * pp;
     const int p = p0 + pair_l;
-    const int npairs = 2 * a.l;
-    const bool active = i < a.m && p < npairs;
-    const int split = blockIdx.z;
-    const int g_begin = split * a.groups_per_split;
-    const int g_end = min(a.ngroups, g_begin + a.groups_per_split);
-    const int pairs_here = min(a.pp, npairs - p0);
-    const int chunk_words_per_group = a.pp * a.emax * ENTRY_WORDS;
+    const int npairs = 2 * l;
+    const bool active = i < m && p < npairs;
+    const int g_begin = bz * d.gps;
+    const int g_end = min(d.ngroups, g_begin + d.gps);
+    const int pairs_here = min(pp, npairs - p0);
+    const int chunk_words_per_group = pp * emax * ENTRY_WORDS;
+    const uint32_t *table = at<const uint32_t>(a, d.w_table);
+    const int16_t *codes = at<const int16_t>(a, d.o_codes);
 
     jpt acc = jpt_infinity();
-    for (int gc = g_begin; gc < g_end; gc += a.kc) {
-        const int kn = min(a.kc, g_end - gc);
+    for (int gc = g_begin; gc < g_end; gc += d.kc) {
+        const int kn = min(d.kc, g_end - gc);
         // stage the tables of groups gc .. gc+kn-1 for pairs p0 .. p0+pairs_here-1
         __syncthreads();
         for (int kk = 0; kk < kn; ++kk) {
-            const uint4 *src =
-                (const uint4 *)(a.table + ((int64_t)(gc + kk) * npairs + p0) * a.emax * ENTRY_WORDS);
+            const uint4 *src = (const uint4 *)(table + ((int64_t)(gc + kk) * npairs + p0) * emax * ENTRY_WORDS);
             uint4 *dst = (uint4 *)(lds + (int64_t)kk * chunk_words_per_group);
-            const int n4 = pairs_here * a.emax * ENTRY_WORDS / 4;
+            const int n4 = pairs_here * emax * ENTRY_WORDS / 4;
             for (int x = tid; x < n4; x += blockDim.x) dst[x] = src[x];
         }
         __syncthreads();
         if (active) {
             for (int kk = 0; kk < kn; ++kk) {
-                const int code = a.codes[(int64_t)(gc + kk) * a.m + i];
+                const int code = codes[(int64_t)(gc + kk) * m + i];
                 if (code == 0) continue;
                 const int e = (code < 0 ? -code : code) - 1;
-                const uint32_t *ent = lds + (int64_t)kk * chunk_words_per_group +
-                                      ((int64_t)pair_l * a.emax + e) * ENTRY_WORDS;
+                const uint32_t *ent =
+                    lds + (int64_t)kk * chunk_words_per_group + ((int64_t)pair_l * emax + e) * ENTRY_WORDS;
                 apt Q;
 #pragma unroll
                 for (int w = 0; w < NL; ++w) {
@@ -220,24 +290,53 @@ __global__ void __launch_bounds__(256) accumulate_kernel(acc_args a) {
     }
     if (!active) return;
     const int j = p >> 1, pt = p & 1;
-    const int64_t e_out = (int64_t)i * a.l + j;
-    uint32_t *dst = a.out + (int64_t)split * JAC2_PLANES * a.ld_out;
-    if (a.out_canonical) store_jac(dst, a.ld_out, pt, e_out, acc);
-    else store_jac_m(dst, a.ld_out, pt, e_out, acc);
+    const int64_t e_out = (int64_t)i * l + j;
+    if (d.S > 1) {
+        store_jac_m(at<uint32_t>(a, d.w_part) + (int64_t)bz * JAC2_PLANES * d.ldj, d.ldj, pt, e_out, acc);
+    } else if (d.c_form == PCMM_AFFINE) {
+        store_jac_m(at<uint32_t>(a, d.w_cjac), d.ldj, pt, e_out, acc);
+    } else {
+        store_jac(a.io[d.io].C, a.io[d.io].ldc, pt, e_out, acc);
+    }
+}
+
+__global__ void __launch_bounds__(256) accumulate_kernel(run_args a) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int32_t s_tile;
+    int32_t *ctr = at<int32_t>(a, a.ctr_off);
+    for (;;) {
+        __syncthreads();  // every thread has read s_tile and finished with the LDS tables
+        if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1);
+        __syncthreads();
+        const int64_t tile = __builtin_amdgcn_readfirstlane(s_tile);  // uniform over the workgroup
+        if (tile >= a.total_tiles) return;
+        const int b = find_problem(a, offsetof(prob_desc, tile0), tile);
+        const prob_desc &d = descs(a)[b];
+        const int64_t u = tile - d.tile0;
+        const int64_t txy = (int64_t)d.tiles_x * d.tiles_y;
+        const int bz = (int)(u / txy);
+        const int64_t r = u - (int64_t)bz * txy;
+        const int by = (int)(r / d.tiles_x);
+        const int bx = (int)(r - (int64_t)by * d.tiles_x);
+        accumulate_tile(a, d, bx, by, bz, lds);
+    }
 }
 
 // sum of S (power of two <= 64) partial sums per output point; lanes s of one
-// output are consecutive
-__global__ void __launch_bounds__(256) reduce_kernel(const uint32_t *__restrict__ part, int64_t ld_part, int S,
-                                                     int64_t n_out, uint32_t *__restrict__ out, int64_t ld_out,
-                                                     int out_canonical) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// output are consecutive, and a problem's threads start at a block boundary
+__global__ void __launch_bounds__(256) reduce_kernel(run_args a) {
+    const int b = find_problem(a, offsetof(prob_desc, red_block0), blockIdx.x);
+    const prob_desc &d = descs(a)[b];
+    const int64_t t = ((int64_t)blockIdx.x - d.red_block0) * blockDim.x + threadIdx.x;
+    const int S = d.S;
+    const int64_t n_out = (int64_t)d.m * d.l;
     const int s = (int)(t % S);
     const int64_t rest = t / S;  // (e, pt) pairs, pt fastest
     const bool valid = rest < 2 * n_out;
     const int64_t e = valid ? rest >> 1 : 0;
     const int pt = (int)(rest & 1);
-    jpt P = valid ? load_jac_m(part + (int64_t)s * JAC2_PLANES * ld_part, ld_part, pt, e) : jpt_infinity();
+    const uint32_t *part = at<const uint32_t>(a, d.w_part);
+    jpt P = valid ? load_jac_m(part + (int64_t)s * JAC2_PLANES * d.ldj, d.ldj, pt, e) : jpt_infinity();
     for (int off = S >> 1; off >= 1; off >>= 1) {
         jpt Q;
 #pragma unroll
@@ -250,46 +349,106 @@ __global__ void __launch_bounds__(256) reduce_kernel(const uint32_t *__restrict_
         if (s < off) P = R;
     }
     if (valid && s == 0) {
-        if (out_canonical) store_jac(out, ld_out, pt, e, P);
-        else store_jac_m(out, ld_out, pt, e, P);
+        if (d.c_form == PCMM_AFFINE) store_jac_m(at<uint32_t>(a, d.w_cjac), d.ldj, pt, e, P);
+        else store_jac(a.io[d.io].C, a.io[d.io].ldc, pt, e, P);
     }
 }
 
+__global__ void __launch_bounds__(256) normalize_batch_kernel(run_args a) {
+    const int b = find_problem(a, offsetof(prob_desc, norm_block0), blockIdx.x);
+    const prob_desc &d = descs(a)[b];
+    const int64_t t = ((int64_t)blockIdx.x - d.norm_block0) * blockDim.x + threadIdx.x;
+    normalize_points<true, false>(at<const uint32_t>(a, d.w_cjac), d.ldj, a.io[d.io].C, a.io[d.io].ldc,
+                                  (int64_t)d.m * d.l, 2, at<uint32_t>(a, d.w_norm), d.ld_pre, d.norm_per, t,
+                                  d.norm_threads);
+}
+
+__global__ void fill_infinity_kernel(uint32_t *out, int64_t ld, int64_t n, int form) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    for (int pt = 0; pt < 2; ++pt)
+        for (int c = 0; c < form; ++c)
+            for (int w = 0; w < 8; ++w) out[((int64_t)(pt * form + c) * 8 + w) * ld + e] = 0u;
+}
+
 // --------------------------------------------------------------------------
-// Host side
+// Host side: configuration, autotuning, geometry
 // --------------------------------------------------------------------------
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct geometry {
-    int J, Lj;
-    int64_t n_lanes;
-    int tm, pp, kc, S, groups_per_split;
-    size_t lds_bytes;
-    // workspace layout (byte offsets)
-    size_t off_plan, off_regs, off_table, off_part, off_cjac, off_norm, total;
-    size_t plan_bytes;
-};
-
 bool valid_cfg(const pcmm_cussen_cfg *cfg) {
     if (!cfg) return true;
-    if (cfg->rounds < 0 || cfg->rounds > 8 || cfg->group < 0 || cfg->group > 4 || cfg->k_split < 0 ||
-        cfg->k_split > 64 || cfg->k_chunk < 0 || cfg->profile < 0)
+    if (cfg->rounds < 0 || cfg->rounds > 8 || cfg->group < PCMM_GROUP_AUTO || cfg->group > 4 ||
+        cfg->k_split < 0 || cfg->k_split > 64 || cfg->k_chunk < 0 || cfg->profile < 0)
         return false;
     if (cfg->k_split > 0 && (cfg->k_split & (cfg->k_split - 1))) return false;
     return true;
 }
 
 int cfg_rounds(const pcmm_cussen_cfg *cfg) { return cfg && cfg->rounds > 0 ? cfg->rounds : 4; }
-int cfg_group(const pcmm_cussen_cfg *cfg) { return cfg && cfg->group > 0 ? cfg->group : 1; }
 
-size_t plan_device_bytes(const cussen_plan &P) {
-    return align256(P.ops.size() * sizeof(plan_op)) + align256(P.op_begin.size() * 4) +
-           align256(P.entry_begin.size() * 4) + align256(P.entries.size() * 2) + align256(P.codes.size() * 2);
+// Predicted GPU time (ps per output column and point) of a plan on MI355X:
+// accumulation slots (rows x column groups, a wavefront pays for a slot even
+// where some of its rows have a zero code), table additions and table
+// entries (affine conversion), with costs fitted to measurements of the
+// accumulation and table-build kernels at 512 x 512 x 512, t = 2 and 4,
+// g = 1..4 (least squares over the eight runs, each within 7%).
+double predicted_cost(const cussen_plan &P) {
+    return 67.7 * (double)P.m * P.ngroups + 112.2 * (double)P.table_adds + 182.8 * (double)P.table_entries;
 }
 
-geometry make_geometry(const cussen_plan &P, int l, int c_form, const pcmm_cussen_cfg *cfg) {
-    geometry G{};
-    const int m = P.m;
+std::mutex g_tune_lock;
+std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;  // (m, n, bits, signed, N) -> g
+
+// Builds the plan for cfg's group, or for the autotuned one.
+int build_plan_cfg(const int8_t *A, int m, int n, int bits, bool sgn, const pcmm_cussen_cfg *cfg,
+                   cussen_plan *out) {
+    const int N = cfg_rounds(cfg);
+    const int group = cfg ? cfg->group : 0;
+    if (group != PCMM_GROUP_AUTO) return build_cussen_plan(A, m, n, bits, sgn, N, group > 0 ? group : 1, out);
+    const auto key = std::make_tuple(m, n, bits, (int)sgn, N);
+    {
+        std::lock_guard<std::mutex> guard(g_tune_lock);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return build_cussen_plan(A, m, n, bits, sgn, N, it->second, out);
+    }
+    int best_g = 1;
+    double best = 0;
+    const int gmax = std::max(1, std::min(4, n));
+    for (int g = 1; g <= gmax; ++g) {
+        cussen_plan P;
+        int rc = build_cussen_plan(A, m, n, bits, sgn, N, g, &P);
+        if (rc) return rc;
+        const double c = predicted_cost(P);
+        if (g == 1 || c < best) {
+            best = c;
+            best_g = g;
+            *out = std::move(P);
+        }
+    }
+    std::lock_guard<std::mutex> guard(g_tune_lock);
+    g_tune_cache[key] = best_g;
+    return 0;
+}
+
+// Per-problem geometry and the sizes of its workspace regions.
+struct job {
+    cussen_plan P;
+    int index = 0;  // the caller's problem index (matrices of the run)
+    int l = 0, c_form = PCMM_AFFINE;
+    int J = 1, Lj = 1;
+    int64_t n_lanes = 0;
+    int tm = 256, pp = 1, kc = 1, S = 1, gps = 0, tiles_x = 1, tiles_y = 1;
+    size_t lds_bytes = 0;
+    int64_t ldj = 64, norm_threads = 0, ld_pre = 0;
+    int norm_per = 0;
+    size_t regs_bytes = 0, table_bytes = 0, part_bytes = 0, cjac_bytes = 0, norm_bytes = 0;
+    double tile_cost = 0;
+};
+
+void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
+    const cussen_plan &P = G.P;
+    const int m = P.m, l = G.l;
     const int emax = std::max(P.max_entries, 1);
     // table build: J chains per lane so that one inversion serves >= ~64 entries,
     // while keeping >= ~16K lanes
@@ -304,9 +463,11 @@ geometry make_geometry(const cussen_plan &P, int l, int c_form, const pcmm_cusse
     G.n_lanes = (int64_t)P.ngroups * 2 * G.Lj;
     // accumulation tile
     const int npairs = 2 * l;
-    G.tm = m >= 256 ? 256 : (m > 128 ? 256 : (m > 64 ? 128 : 64));
+    G.tm = m > 128 ? 256 : (m > 64 ? 128 : 64);
     G.pp = 256 / G.tm;
-    const int64_t wg_base = (int64_t)((m + G.tm - 1) / G.tm) * ((npairs + G.pp - 1) / G.pp);
+    G.tiles_x = (m + G.tm - 1) / G.tm;
+    G.tiles_y = (npairs + G.pp - 1) / G.pp;
+    const int64_t wg_base = (int64_t)G.tiles_x * G.tiles_y;
     const size_t group_bytes = (size_t)G.pp * emax * ENTRY_WORDS * 4;
     int kc = cfg && cfg->k_chunk > 0 ? cfg->k_chunk : (int)std::max<size_t>(1, (64 * 1024) / group_bytes);
     kc = std::max(1, std::min(kc, std::max(P.ngroups, 1)));
@@ -319,23 +480,332 @@ geometry make_geometry(const cussen_plan &P, int l, int c_form, const pcmm_cusse
     }
     while (S > 1 && (P.ngroups + S - 1) / S < 1) S /= 2;
     G.S = S;
-    G.groups_per_split = P.ngroups > 0 ? (P.ngroups + S - 1) / S : 0;
-    // workspace layout
-    const int64_t ldc = std::max<int64_t>(64, ((int64_t)m * l + 63) / 64 * 64);
-    G.plan_bytes = plan_device_bytes(P);
-    G.off_plan = 0;
-    G.off_regs = align256(G.plan_bytes);
-    size_t regs_bytes = (size_t)G.J * std::max(P.max_regs, 1) * JAC_WORDS * 4 * (size_t)G.n_lanes;
-    G.off_table = G.off_regs + align256(regs_bytes);
-    size_t table_bytes = (size_t)P.ngroups * npairs * emax * ENTRY_WORDS * 4;
-    G.off_part = G.off_table + align256(table_bytes);
-    size_t part_bytes = S > 1 ? (size_t)S * JAC2_PLANES * ldc * 4 : 0;
-    G.off_cjac = G.off_part + align256(part_bytes);
-    size_t cjac_bytes = c_form == PCMM_AFFINE ? (size_t)JAC2_PLANES * ldc * 4 : 0;
-    G.off_norm = G.off_cjac + align256(cjac_bytes);
-    size_t norm_bytes = c_form == PCMM_AFFINE ? normalize_scratch_bytes((int64_t)m * l, 2) : 0;
-    G.total = G.off_norm + align256(norm_bytes) + 256;
-    return G;
+    G.gps = P.ngroups > 0 ? (P.ngroups + S - 1) / S : 0;
+    G.tile_cost = (double)G.tm * G.pp * G.gps;
+    // workspace regions
+    const int64_t n_out = (int64_t)m * l;
+    G.ldj = std::max<int64_t>(64, (n_out + 63) / 64 * 64);
+    G.regs_bytes = (size_t)G.J * std::max(P.max_regs, 1) * JAC_WORDS * 4 * (size_t)G.n_lanes;
+    G.table_bytes = (size_t)P.ngroups * npairs * emax * ENTRY_WORDS * 4;
+    G.part_bytes = S > 1 ? (size_t)S * JAC2_PLANES * G.ldj * 4 : 0;
+    const bool affine = G.c_form == PCMM_AFFINE;
+    G.cjac_bytes = affine ? (size_t)JAC2_PLANES * G.ldj * 4 : 0;
+    if (affine) {
+        normalize_geometry(n_out, &G.norm_threads, &G.norm_per);
+        G.ld_pre = G.norm_threads * G.norm_per * 2;
+        G.norm_bytes = normalize_scratch_bytes(n_out, 2);
+    }
+}
+
+size_t plan_arrays_bytes(const cussen_plan &P) {
+    return align256(P.ops.size() * sizeof(plan_op)) + align256(P.op_begin.size() * 4) +
+           align256(P.entry_begin.size() * 4) + align256(P.entries.size() * 2) + align256(P.codes.size() * 2);
+}
+
+}  // namespace
+
+// A compiled set of problems (the executor's unit; pcmm_cussen builds one of
+// a single problem per call).
+struct pcmm_plan_s {
+    int device = 0;
+    int count = 0;
+    std::vector<int32_t> m, n, l, c_form;
+    std::vector<pcmm_cussen_stats> stats;
+    std::vector<job> jobs;     // problems with GPU work, in execution order
+    std::vector<int> fills;    // problems with n == 0 (all outputs are the identity)
+    std::vector<char> image;   // descriptors + plan arrays
+    void *pinned = nullptr;    // immutable pinned copy of `image` (plans only)
+    size_t ctr_off = 0, ws_bytes = 256;
+    int64_t tb_blocks = 0, tiles = 0, red_blocks = 0, norm_blocks = 0;
+    size_t max_lds = 0;
+    int acc_grid = 0;
+    ~pcmm_plan_s() {
+        if (pinned) hipHostFree(pinned);
+    }
+};
+
+namespace {
+
+void fill_stats(const job &G, pcmm_cussen_stats *st) {
+    memset(st, 0, sizeof *st);
+    const cussen_plan &P = G.P;
+    st->level_mults = P.level_mults;
+    st->level_adds = P.level_adds;
+    st->table_entries = P.table_entries;
+    st->table_adds = P.table_adds;
+    st->accum_adds = P.accum_adds;
+    st->max_entries = P.max_entries;
+    st->k_split = G.S;
+    st->lanes_per_chain = G.J;
+    st->group = P.g;
+}
+
+// Lays out descriptors, plan image and workspace regions of the plan's jobs,
+// and sizes the grids of the non-persistent kernels.
+pcmm_status finish_plan(pcmm_plan_s &pl) {
+    // most expensive accumulation tiles first (the queue hands them out in order)
+    std::stable_sort(pl.jobs.begin(), pl.jobs.end(),
+                     [](const job &x, const job &y) { return x.tile_cost > y.tile_cost; });
+    const size_t nd = pl.jobs.size();
+    size_t img = align256(nd * sizeof(prob_desc));
+    std::vector<prob_desc> D(nd);
+    for (size_t k = 0; k < nd; ++k) {
+        const job &G = pl.jobs[k];
+        D[k] = prob_desc{};
+        D[k].o_ops = (int64_t)img;
+        img += align256(G.P.ops.size() * sizeof(plan_op));
+        D[k].o_op_begin = (int64_t)img;
+        img += align256(G.P.op_begin.size() * 4);
+        D[k].o_entry_begin = (int64_t)img;
+        img += align256(G.P.entry_begin.size() * 4);
+        D[k].o_entries = (int64_t)img;
+        img += align256(G.P.entries.size() * 2);
+        D[k].o_codes = (int64_t)img;
+        img += align256(G.P.codes.size() * 2);
+    }
+    pl.ctr_off = img;
+    size_t ws = img + 256;
+    int64_t tb = 0, tiles = 0, red = 0, norm = 0;
+    pl.max_lds = 0;
+    for (size_t k = 0; k < nd; ++k) {
+        const job &G = pl.jobs[k];
+        prob_desc &d = D[k];
+        d.m = G.P.m;
+        d.n = G.P.n;
+        d.l = G.l;
+        d.g = G.P.g;
+        d.ngroups = G.P.ngroups;
+        d.emax = std::max(G.P.max_entries, 1);
+        d.rmax = std::max(G.P.max_regs, 1);
+        d.c_form = G.c_form;
+        d.J = G.J;
+        d.Lj = G.Lj;
+        d.tm = G.tm;
+        d.pp = G.pp;
+        d.kc = G.kc;
+        d.S = G.S;
+        d.gps = G.gps;
+        d.io = G.index;
+        d.tiles_x = G.tiles_x;
+        d.tiles_y = G.tiles_y;
+        d.norm_per = G.norm_per;
+        d.n_lanes = G.n_lanes;
+        d.tb_block0 = tb;
+        tb += (G.n_lanes + 255) / 256;
+        d.tile0 = tiles;
+        tiles += (int64_t)G.tiles_x * G.tiles_y * G.S;
+        d.red_block0 = red;
+        d.red_threads = G.S > 1 ? (2 * (int64_t)G.P.m * G.l * G.S + 255) / 256 * 256 : 0;
+        red += d.red_threads / 256;
+        d.norm_block0 = norm;
+        d.norm_threads = G.norm_threads;
+        norm += G.norm_threads / 256;
+        d.ldj = G.ldj;
+        d.ld_pre = G.ld_pre;
+        d.w_regs = (int64_t)ws;
+        ws += align256(G.regs_bytes);
+        d.w_table = (int64_t)ws;
+        ws += align256(G.table_bytes);
+        d.w_part = (int64_t)ws;
+        ws += align256(G.part_bytes);
+        d.w_cjac = (int64_t)ws;
+        ws += align256(G.cjac_bytes);
+        d.w_norm = (int64_t)ws;
+        ws += align256(G.norm_bytes);
+        pl.max_lds = std::max(pl.max_lds, G.lds_bytes);
+    }
+    pl.ws_bytes = ws + 256;
+    pl.tb_blocks = tb;
+    pl.tiles = tiles;
+    pl.red_blocks = red;
+    pl.norm_blocks = norm;
+    if (tb > 0x7FFFFFFF || red > 0x7FFFFFFF || norm > 0x7FFFFFFF || tiles > 0x7FFFFFFF - (1 << 20))
+        return PCMM_EINVAL;
+    pl.image.assign(img, 0);
+    memcpy(pl.image.data(), D.data(), nd * sizeof(prob_desc));
+    for (size_t k = 0; k < nd; ++k) {
+        const cussen_plan &P = pl.jobs[k].P;
+        auto put = [&](int64_t off, const void *src, size_t bytes) {
+            if (bytes) memcpy(pl.image.data() + off, src, bytes);
+        };
+        put(D[k].o_ops, P.ops.data(), P.ops.size() * sizeof(plan_op));
+        put(D[k].o_op_begin, P.op_begin.data(), P.op_begin.size() * 4);
+        put(D[k].o_entry_begin, P.entry_begin.data(), P.entry_begin.size() * 4);
+        put(D[k].o_entries, P.entries.data(), P.entries.size() * 2);
+        put(D[k].o_codes, P.codes.data(), P.codes.size() * 2);
+    }
+    return PCMM_OK;
+}
+
+std::mutex g_occ_lock;
+std::map<std::pair<int, size_t>, int64_t> g_occ_cache;  // (device, LDS bytes) -> resident workgroups
+
+// Binds pl to the current device and sizes the persistent accumulation grid:
+// the workgroups that fit on the device at once, or the tiles if fewer.
+pcmm_status bind_device(pcmm_plan_s &pl) {
+    PCMM_HIP_TRY(hipGetDevice(&pl.device));
+    pl.acc_grid = 0;
+    if (pl.tiles == 0) return PCMM_OK;
+    if (pl.max_lds > 64 * 1024)
+        PCMM_HIP_TRY(hipFuncSetAttribute((const void *)accumulate_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)pl.max_lds));
+    const auto key = std::make_pair(pl.device, pl.max_lds);
+    int64_t cap = 0;
+    {
+        std::lock_guard<std::mutex> guard(g_occ_lock);
+        auto it = g_occ_cache.find(key);
+        if (it != g_occ_cache.end()) cap = it->second;
+    }
+    if (cap == 0) {
+        int per_cu = 0, cus = 0;
+        PCMM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, accumulate_kernel, 256, pl.max_lds));
+        PCMM_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl.device));
+        cap = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
+        std::lock_guard<std::mutex> guard(g_occ_lock);
+        g_occ_cache[key] = cap;
+    }
+    pl.acc_grid = (int)std::min<int64_t>(pl.tiles, cap);
+    return PCMM_OK;
+}
+
+// Compiles problems into pl (host threads over problems; no device calls).
+// Returns the first error in problem order.
+pcmm_status build_plan(const pcmm_problem *probs, int count, pcmm_plan_s &pl) {
+    if (!probs || count < 1 || count > MAX_PROBLEMS) return PCMM_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        const pcmm_problem &q = probs[i];
+        if (q.m < 0 || q.n < 0 || q.l < 0 || (q.c_form != PCMM_AFFINE && q.c_form != PCMM_JACOBIAN) ||
+            !valid_cfg(&q.cfg))
+            return PCMM_EINVAL;
+    }
+    pl.count = count;
+    pl.m.resize(count);
+    pl.n.resize(count);
+    pl.l.resize(count);
+    pl.c_form.resize(count);
+    pl.stats.assign(count, pcmm_cussen_stats{});
+    std::vector<job> built(count);
+    std::vector<int> rcs(count, 0);
+    auto work = [&](int i) {
+        const pcmm_problem &q = probs[i];
+        job &G = built[i];
+        rcs[i] = build_plan_cfg(q.A, q.m, q.n, q.bits, q.is_signed != 0, &q.cfg, &G.P);
+        if (rcs[i]) return;
+        G.index = i;
+        G.l = q.l;
+        G.c_form = q.c_form;
+        make_geometry(G, &q.cfg);
+    };
+    const int nthreads = std::min(count, std::max(1, std::min(16, (int)std::thread::hardware_concurrency())));
+    if (nthreads <= 1) {
+        for (int i = 0; i < count; ++i) work(i);
+    } else {
+        std::atomic<int> next{0};
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthreads; ++t)
+            pool.emplace_back([&]() {
+                for (int i = next++; i < count; i = next++) work(i);
+            });
+        for (auto &th : pool) th.join();
+    }
+    for (int i = 0; i < count; ++i) {
+        if (rcs[i] == -2) return PCMM_ERANGE;
+        if (rcs[i]) return PCMM_EINVAL;
+    }
+    for (int i = 0; i < count; ++i) {
+        const pcmm_problem &q = probs[i];
+        pl.m[i] = q.m;
+        pl.n[i] = q.n;
+        pl.l[i] = q.l;
+        pl.c_form[i] = q.c_form;
+        fill_stats(built[i], &pl.stats[i]);
+        if ((int64_t)q.m * q.l == 0) continue;
+        if (q.n == 0) {
+            pl.fills.push_back(i);
+            continue;
+        }
+        pl.jobs.push_back(std::move(built[i]));
+    }
+    return finish_plan(pl);
+}
+
+pcmm_status check_mats(int m, int n, int l, int c_form, const pcmm_mat *B, const pcmm_mat *C) {
+    if (!B || !C) return PCMM_EINVAL;
+    if (B->rows != n || B->cols != l || B->npts != 2 || B->form != PCMM_AFFINE) return PCMM_EINVAL;
+    if (B->ld < (int64_t)n * l || ((int64_t)n * l > 0 && !B->d)) return PCMM_EINVAL;
+    if (C->rows != m || C->cols != l || C->npts != 2 || C->form != c_form) return PCMM_EINVAL;
+    if (C->ld < (int64_t)m * l || ((int64_t)m * l > 0 && !C->d)) return PCMM_EINVAL;
+    if (B->d == C->d && (int64_t)n * l > 0 && (int64_t)m * l > 0) return PCMM_EINVAL;
+    return PCMM_OK;
+}
+
+// Queues a run of pl.  image_src: pinned host copy of pl.image that stays
+// unchanged until the copy has executed.  ev: PCMM_STAGE_EVENTS events or
+// null.
+pcmm_status enqueue_plan(const pcmm_plan_s &pl, const void *image_src, const pcmm_mat *B, pcmm_mat *C,
+                         void *workspace, size_t ws_bytes, hipEvent_t *ev, hipStream_t s) {
+    auto rec = [&](int i) -> pcmm_status {
+        if (ev) PCMM_HIP_TRY(hipEventRecord(ev[i], s));
+        return PCMM_OK;
+    };
+    pcmm_status st;
+#define PCMM_REC(i)                          \
+    do {                                     \
+        if ((st = rec(i)) != PCMM_OK) return st; \
+    } while (0)
+    const bool gpu_work = !pl.jobs.empty();
+    PCMM_REC(0);
+    run_args ra{};
+    if (gpu_work) {
+        ra.ws = (char *)workspace;
+        ra.count = (int32_t)pl.jobs.size();
+        ra.total_tiles = pl.tiles;
+        ra.ctr_off = (int64_t)pl.ctr_off;
+        for (int i = 0; i < pl.count; ++i) ra.io[i] = io_ptrs{B[i].d, C[i].d, B[i].ld, C[i].ld};
+        PCMM_HIP_TRY(hipMemcpyAsync(workspace, image_src, pl.image.size(), hipMemcpyHostToDevice, s));
+    }
+    PCMM_REC(1);
+    if (gpu_work) {
+        hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)pl.tb_blocks), dim3(256), 0, s, ra);
+        PCMM_LAUNCH_CHECK();
+    }
+    PCMM_REC(2);
+    if (gpu_work) {
+        if (pl.max_lds > 64 * 1024)
+            PCMM_HIP_TRY(hipFuncSetAttribute((const void *)accumulate_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.max_lds));
+        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)pl.acc_grid), dim3(256), pl.max_lds, s, ra);
+        PCMM_LAUNCH_CHECK();
+    }
+    PCMM_REC(3);
+    if (pl.red_blocks > 0) {
+        hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)pl.red_blocks), dim3(256), 0, s, ra);
+        PCMM_LAUNCH_CHECK();
+    }
+    PCMM_REC(4);
+    if (pl.norm_blocks > 0) {
+        hipLaunchKernelGGL(normalize_batch_kernel, dim3((unsigned)pl.norm_blocks), dim3(256), 0, s, ra);
+        PCMM_LAUNCH_CHECK();
+    }
+    for (int i : pl.fills) {
+        const int64_t n_out = (int64_t)pl.m[i] * pl.l[i];
+        hipLaunchKernelGGL(fill_infinity_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, s, C[i].d,
+                           C[i].ld, n_out, C[i].form);
+        PCMM_LAUNCH_CHECK();
+    }
+    PCMM_REC(5);
+#undef PCMM_REC
+    return PCMM_OK;
+}
+
+pcmm_status check_run(const pcmm_plan_s &pl, const pcmm_mat *B, pcmm_mat *C, void *workspace, size_t ws_bytes) {
+    if (!B || !C) return PCMM_EINVAL;
+    for (int i = 0; i < pl.count; ++i) {
+        pcmm_status st = check_mats(pl.m[i], pl.n[i], pl.l[i], pl.c_form[i], &B[i], &C[i]);
+        if (st != PCMM_OK) return st;
+    }
+    if (!pl.jobs.empty() && (!workspace || ws_bytes < pl.ws_bytes)) return PCMM_ENOMEM;
+    return PCMM_OK;
 }
 
 // events bracketing the stages of one profiled call
@@ -354,7 +824,8 @@ struct stage_events {
     }
 };
 
-// pinned staging for plan uploads, one per device; an event guards reuse
+// pinned staging for the plan image of pcmm_cussen calls, one per device; an
+// event guards reuse
 struct staging {
     void *host = nullptr;
     size_t bytes = 0;
@@ -363,67 +834,20 @@ struct staging {
 std::mutex g_stage_lock;
 staging g_stage[64];
 
-pcmm_status upload_plan(const cussen_plan &P, void *dev, hipStream_t s) {
-    int devid = 0;
-    PCMM_HIP_TRY(hipGetDevice(&devid));
-    if (devid < 0 || devid >= 64) return PCMM_EDEVICE;
-    const size_t bytes = plan_device_bytes(P);
-    std::lock_guard<std::mutex> guard(g_stage_lock);
-    staging &st = g_stage[devid];
-    if (st.done) PCMM_HIP_TRY(hipEventSynchronize(st.done));
-    if (st.bytes < bytes) {
-        if (st.host) hipHostFree(st.host);
-        st.host = nullptr;
-        st.bytes = 0;
-        PCMM_HIP_TRY(hipHostMalloc(&st.host, bytes, hipHostMallocDefault));
-        st.bytes = bytes;
-    }
-    if (!st.done) PCMM_HIP_TRY(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
-    char *h = (char *)st.host;
-    size_t off = 0;
-    auto put = [&](const void *src, size_t n) {
-        if (n) memcpy(h + off, src, n);
-        off += align256(n);
-    };
-    put(P.ops.data(), P.ops.size() * sizeof(plan_op));
-    put(P.op_begin.data(), P.op_begin.size() * 4);
-    put(P.entry_begin.data(), P.entry_begin.size() * 4);
-    put(P.entries.data(), P.entries.size() * 2);
-    put(P.codes.data(), P.codes.size() * 2);
-    PCMM_HIP_TRY(hipMemcpyAsync(dev, st.host, bytes, hipMemcpyHostToDevice, s));
-    PCMM_HIP_TRY(hipEventRecord(st.done, s));
-    return PCMM_OK;
-}
-
-pcmm_status check_mats(int m, int n, const pcmm_mat *B, const pcmm_mat *C) {
-    if (!B || !C || m < 0 || n < 0) return PCMM_EINVAL;
-    if (B->rows != n || B->cols < 0 || B->npts != 2 || B->form != PCMM_AFFINE) return PCMM_EINVAL;
-    const int l = B->cols;
-    if (B->ld < (int64_t)n * l || ((int64_t)n * l > 0 && !B->d)) return PCMM_EINVAL;
-    if (C->rows != m || C->cols != l || C->npts != 2 || (C->form != PCMM_AFFINE && C->form != PCMM_JACOBIAN))
-        return PCMM_EINVAL;
-    if (C->ld < (int64_t)m * l || ((int64_t)m * l > 0 && !C->d)) return PCMM_EINVAL;
-    if (B->d == C->d && (int64_t)n * l > 0 && (int64_t)m * l > 0) return PCMM_EINVAL;
-    return PCMM_OK;
-}
-
-void fill_stats(const cussen_plan &P, pcmm_cussen_stats *st) {
-    if (!st) return;
-    memset(st, 0, sizeof *st);
-    st->level_mults = P.level_mults;
-    st->level_adds = P.level_adds;
-    st->table_entries = P.table_entries;
-    st->table_adds = P.table_adds;
-    st->accum_adds = P.accum_adds;
-    st->max_entries = P.max_entries;
-}
-
-__global__ void fill_infinity_kernel(uint32_t *out, int64_t ld, int64_t n, int form) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    for (int pt = 0; pt < 2; ++pt)
-        for (int c = 0; c < form; ++c)
-            for (int w = 0; w < 8; ++w) out[((int64_t)(pt * form + c) * 8 + w) * ld + e] = 0u;
+pcmm_problem single_problem(const int8_t *A, int m, int n, int l, int bits, int is_signed, int c_form,
+                            const pcmm_cussen_cfg *cfg) {
+    pcmm_problem q{};
+    q.A = A;
+    q.m = m;
+    q.n = n;
+    q.l = l;
+    q.bits = bits;
+    q.is_signed = is_signed;
+    q.c_form = c_form;
+    if (cfg) q.cfg = *cfg;
+    q.cfg.profile = 0;
+    q.cfg.stage_events = nullptr;
+    return q;
 }
 
 }  // namespace
@@ -431,41 +855,37 @@ __global__ void fill_infinity_kernel(uint32_t *out, int64_t ld, int64_t n, int f
 extern "C" pcmm_status pcmm_cussen_plan_stats(const int8_t *A, int32_t m, int32_t n, int32_t bits,
                                               int32_t is_signed, const pcmm_cussen_cfg *cfg,
                                               pcmm_cussen_stats *stats) {
-    if (!stats || !valid_cfg(cfg)) return PCMM_EINVAL;
-    cussen_plan P;
-    int rc = build_cussen_plan(A, m, n, bits, is_signed != 0, cfg_rounds(cfg), cfg_group(cfg), &P);
+    if (!stats || !valid_cfg(cfg) || m < 0 || n < 0) return PCMM_EINVAL;
+    job G;
+    int rc = build_plan_cfg(A, m, n, bits, is_signed != 0, cfg, &G.P);
     if (rc == -2) return PCMM_ERANGE;
     if (rc) return PCMM_EINVAL;
-    fill_stats(P, stats);
+    G.l = 1;
+    make_geometry(G, cfg);
+    fill_stats(G, stats);
+    stats->k_split = 0;
+    stats->lanes_per_chain = 0;
     return PCMM_OK;
 }
 
 extern "C" pcmm_status pcmm_cussen_workspace(const int8_t *A, int32_t m, int32_t n, int32_t l, int32_t bits,
                                              int32_t is_signed, int32_t c_form, const pcmm_cussen_cfg *cfg,
                                              size_t *bytes) {
-    if (!bytes || l < 0 || !valid_cfg(cfg) || (c_form != PCMM_AFFINE && c_form != PCMM_JACOBIAN))
-        return PCMM_EINVAL;
-    cussen_plan P;
-    int rc = build_cussen_plan(A, m, n, bits, is_signed != 0, cfg_rounds(cfg), cfg_group(cfg), &P);
-    if (rc == -2) return PCMM_ERANGE;
-    if (rc) return PCMM_EINVAL;
-    *bytes = make_geometry(P, l, c_form, cfg).total;
+    if (!bytes || !valid_cfg(cfg)) return PCMM_EINVAL;
+    pcmm_plan_s pl;
+    pcmm_problem q = single_problem(A, m, n, l, bits, is_signed, c_form, cfg);
+    pcmm_status st = build_plan(&q, 1, pl);
+    if (st != PCMM_OK) return st;
+    *bytes = pl.ws_bytes;
     return PCMM_OK;
 }
 
 extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
                                    const pcmm_mat *B, pcmm_mat *C, const pcmm_cussen_cfg *cfg, void *workspace,
                                    size_t ws_bytes, pcmm_cussen_stats *stats, void *stream) {
-    pcmm_status st = check_mats(m, n, B, C);
-    if (st != PCMM_OK) return st;
-    if (!valid_cfg(cfg)) return PCMM_EINVAL;
-    const int l = B->cols;
+    if (!B || !C || !valid_cfg(cfg)) return PCMM_EINVAL;
+    if (C->form != PCMM_AFFINE && C->form != PCMM_JACOBIAN) return PCMM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    cussen_plan P;
-    int rc = build_cussen_plan(A, m, n, bits, is_signed != 0, cfg_rounds(cfg), cfg_group(cfg), &P);
-    if (rc == -2) return PCMM_ERANGE;
-    if (rc) return PCMM_EINVAL;
-    fill_stats(P, stats);
     hipEvent_t ev[PCMM_STAGE_EVENTS] = {};
     const bool caller_events = cfg && cfg->stage_events;
     if (caller_events) {
@@ -474,124 +894,42 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
             if (!ev[i]) return PCMM_EINVAL;
         }
     }
-    // calls without the stage pipeline still mark every caller event
-    auto record_all = [&]() -> pcmm_status {
-        if (caller_events)
-            for (int i = 0; i < PCMM_STAGE_EVENTS; ++i) PCMM_HIP_TRY(hipEventRecord(ev[i], s));
-        return PCMM_OK;
-    };
-    const int64_t n_out = (int64_t)m * l;
-    if (n_out == 0) return record_all();
-    if (n == 0) {
-        // empty inner dimension: every output is the identity
-        int64_t blocks = (n_out + 255) / 256;
-        hipLaunchKernelGGL(fill_infinity_kernel, dim3((unsigned)blocks), dim3(256), 0, s, C->d, C->ld, n_out,
-                           C->form);
-        PCMM_LAUNCH_CHECK();
-        return record_all();
-    }
-    geometry G = make_geometry(P, l, C->form, cfg);
-    if (!workspace || ws_bytes < G.total) return PCMM_ENOMEM;
-    if (stats) {
-        stats->k_split = G.S;
-        stats->lanes_per_chain = G.J;
-    }
-    char *ws = (char *)workspace;
+    pcmm_plan_s pl;
+    pcmm_problem q = single_problem(A, m, n, B->cols, bits, is_signed, C->form, cfg);
+    pcmm_status st = build_plan(&q, 1, pl);
+    if (st != PCMM_OK) return st;
+    if (stats) *stats = pl.stats[0];
+    st = check_run(pl, B, C, workspace, ws_bytes);
+    if (st != PCMM_OK) return st;
+    st = bind_device(pl);
+    if (st != PCMM_OK) return st;
     const bool wait_prof = cfg && cfg->profile;
-    const bool prof = wait_prof || caller_events;
     stage_events own;
     if (wait_prof && !caller_events) {
         PCMM_HIP_TRY(own.create());
         for (int i = 0; i < PCMM_STAGE_EVENTS; ++i) ev[i] = own.e[i];
     }
-    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[0], s));
-    st = upload_plan(P, ws + G.off_plan, s);
-    if (st != PCMM_OK) return st;
-    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[1], s));
-    // device views of the plan
-    size_t off = 0;
-    auto view = [&](size_t n_bytes) {
-        char *p = ws + G.off_plan + off;
-        off += align256(n_bytes);
-        return p;
-    };
-    const plan_op *d_ops = (const plan_op *)view(P.ops.size() * sizeof(plan_op));
-    const int32_t *d_op_begin = (const int32_t *)view(P.op_begin.size() * 4);
-    const int32_t *d_entry_begin = (const int32_t *)view(P.entry_begin.size() * 4);
-    const int16_t *d_entries = (const int16_t *)view(P.entries.size() * 2);
-    const int16_t *d_codes = (const int16_t *)view(P.codes.size() * 2);
-    const int emax = std::max(P.max_entries, 1);
-
-    tb_args ta;
-    ta.ops = d_ops;
-    ta.op_begin = d_op_begin;
-    ta.entry_begin = d_entry_begin;
-    ta.entries = d_entries;
-    ta.B = B->d;
-    ta.ldb = B->ld;
-    ta.n = n;
-    ta.l = l;
-    ta.g = P.g;
-    ta.J = G.J;
-    ta.Lj = G.Lj;
-    ta.rmax = std::max(P.max_regs, 1);
-    ta.emax = emax;
-    ta.n_lanes = G.n_lanes;
-    ta.regs = (uint32_t *)(ws + G.off_regs);
-    ta.table = (uint32_t *)(ws + G.off_table);
+    const bool prof = wait_prof || caller_events;
     {
-        int64_t blocks = (G.n_lanes + 255) / 256;
-        hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ta);
-        PCMM_LAUNCH_CHECK();
-    }
-    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[2], s));
-    const int64_t ldc = std::max<int64_t>(64, (n_out + 63) / 64 * 64);
-    const bool affine_out = C->form == PCMM_AFFINE;
-    uint32_t *jac_out = affine_out ? (uint32_t *)(ws + G.off_cjac) : C->d;
-    const int64_t ld_jac = affine_out ? ldc : C->ld;
-    acc_args aa;
-    aa.table = ta.table;
-    aa.codes = d_codes;
-    aa.m = m;
-    aa.l = l;
-    aa.ngroups = P.ngroups;
-    aa.emax = emax;
-    aa.tm = G.tm;
-    aa.pp = G.pp;
-    aa.kc = G.kc;
-    aa.groups_per_split = G.groups_per_split;
-    if (G.S > 1) {
-        aa.out = (uint32_t *)(ws + G.off_part);
-        aa.ld_out = ldc;
-        aa.out_canonical = 0;
-    } else {
-        aa.out = jac_out;
-        aa.ld_out = ld_jac;
-        aa.out_canonical = affine_out ? 0 : 1;
-    }
-    {
-        dim3 grid((unsigned)((m + G.tm - 1) / G.tm), (unsigned)((2 * l + G.pp - 1) / G.pp), (unsigned)G.S);
-        if (G.lds_bytes > 64 * 1024)
-            PCMM_HIP_TRY(hipFuncSetAttribute((const void *)accumulate_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.lds_bytes));
-        hipLaunchKernelGGL(accumulate_kernel, grid, dim3(256), G.lds_bytes, s, aa);
-        PCMM_LAUNCH_CHECK();
-    }
-    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[3], s));
-    if (G.S > 1) {
-        int64_t threads = 2 * n_out * G.S;
-        int64_t blocks = (threads + 255) / 256;
-        hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const uint32_t *)aa.out, ldc,
-                           G.S, n_out, jac_out, ld_jac, affine_out ? 0 : 1);
-        PCMM_LAUNCH_CHECK();
-    }
-    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[4], s));
-    if (affine_out) {
-        st = launch_normalize(jac_out, ld_jac, true, C->d, C->ld, false, n_out, 2, ws + G.off_norm,
-                              G.total - G.off_norm, s);
+        // stage the image in the device's pinned buffer, once its previous copy has executed
+        std::lock_guard<std::mutex> guard(g_stage_lock);
+        if (pl.device < 0 || pl.device >= 64) return PCMM_EDEVICE;
+        staging &sg = g_stage[pl.device];
+        const size_t bytes = std::max<size_t>(pl.image.size(), 256);
+        if (sg.done) PCMM_HIP_TRY(hipEventSynchronize(sg.done));
+        if (sg.bytes < bytes) {
+            if (sg.host) hipHostFree(sg.host);
+            sg.host = nullptr;
+            sg.bytes = 0;
+            PCMM_HIP_TRY(hipHostMalloc(&sg.host, bytes, hipHostMallocDefault));
+            sg.bytes = bytes;
+        }
+        if (!sg.done) PCMM_HIP_TRY(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
+        if (!pl.image.empty()) memcpy(sg.host, pl.image.data(), pl.image.size());
+        st = enqueue_plan(pl, sg.host, B, C, workspace, ws_bytes, prof ? ev : nullptr, s);
         if (st != PCMM_OK) return st;
+        PCMM_HIP_TRY(hipEventRecord(sg.done, s));
     }
-    if (prof) PCMM_HIP_TRY(hipEventRecord(ev[5], s));
     if (wait_prof) {
         PCMM_HIP_TRY(hipEventSynchronize(ev[5]));
         if (stats) {
@@ -602,4 +940,68 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
         }
     }
     return PCMM_OK;
+}
+
+extern "C" pcmm_status pcmm_plan_create(const pcmm_problem *problems, int32_t count, pcmm_plan *out) {
+    if (!out) return PCMM_EINVAL;
+    *out = nullptr;
+    pcmm_plan_s *pl = new (std::nothrow) pcmm_plan_s;
+    if (!pl) return PCMM_ENOMEM;
+    pcmm_status st;
+    try {
+        st = build_plan(problems, count, *pl);
+    } catch (const std::bad_alloc &) {
+        st = PCMM_ENOMEM;
+    }
+    if (st == PCMM_OK) st = bind_device(*pl);
+    if (st == PCMM_OK && !pl->image.empty()) {
+        if (hipHostMalloc(&pl->pinned, pl->image.size(), hipHostMallocDefault) != hipSuccess) {
+            pl->pinned = nullptr;
+            st = PCMM_EDEVICE;
+        } else {
+            memcpy(pl->pinned, pl->image.data(), pl->image.size());
+        }
+    }
+    if (st != PCMM_OK) {
+        delete pl;
+        return st;
+    }
+    *out = pl;
+    return PCMM_OK;
+}
+
+extern "C" pcmm_status pcmm_plan_destroy(pcmm_plan plan) {
+    delete plan;
+    return PCMM_OK;
+}
+
+extern "C" pcmm_status pcmm_plan_workspace(pcmm_plan plan, size_t *bytes) {
+    if (!plan || !bytes) return PCMM_EINVAL;
+    *bytes = plan->ws_bytes;
+    return PCMM_OK;
+}
+
+extern "C" pcmm_status pcmm_plan_stats(pcmm_plan plan, int32_t index, pcmm_cussen_stats *stats) {
+    if (!plan || !stats || index < 0 || index >= plan->count) return PCMM_EINVAL;
+    *stats = plan->stats[index];
+    return PCMM_OK;
+}
+
+extern "C" pcmm_status pcmm_plan_run(pcmm_plan plan, const pcmm_mat *B, pcmm_mat *C, void *workspace,
+                                     size_t ws_bytes, void **stage_events, void *stream) {
+    if (!plan) return PCMM_EINVAL;
+    int dev = -1;
+    PCMM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != plan->device) return PCMM_EDEVICE;
+    pcmm_status st = check_run(*plan, B, C, workspace, ws_bytes);
+    if (st != PCMM_OK) return st;
+    hipEvent_t ev[PCMM_STAGE_EVENTS] = {};
+    if (stage_events) {
+        for (int i = 0; i < PCMM_STAGE_EVENTS; ++i) {
+            ev[i] = (hipEvent_t)stage_events[i];
+            if (!ev[i]) return PCMM_EINVAL;
+        }
+    }
+    return enqueue_plan(*plan, plan->pinned, B, C, workspace, ws_bytes, stage_events ? ev : nullptr,
+                        (hipStream_t)stream);
 }

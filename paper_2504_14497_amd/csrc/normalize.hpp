@@ -7,6 +7,10 @@
 
 namespace pcmm {
 
+// Threads (a multiple of 256) and points per thread used to normalise n_elem
+// elements: about 24 elements per thread, so that one inversion serves them.
+void normalize_geometry(int64_t n_elem, int64_t *threads, int *per_thread);
+
 // Scratch bytes needed by launch_normalize for n_elem elements of npts points.
 size_t normalize_scratch_bytes(int64_t n_elem, int npts);
 

@@ -67,13 +67,25 @@ class CussenStats(ctypes.Structure):
                 ("table_entries", ctypes.c_int64), ("table_adds", ctypes.c_int64),
                 ("accum_adds", ctypes.c_int64), ("max_entries", ctypes.c_int64),
                 ("k_split", ctypes.c_int32), ("lanes_per_chain", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("ms_upload", ctypes.c_float), ("ms_table", ctypes.c_float),
                 ("ms_accumulate", ctypes.c_float), ("ms_reduce", ctypes.c_float),
                 ("ms_normalize", ctypes.c_float), ("ms_total", ctypes.c_float)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if k.startswith("ms_") else int(getattr(self, k)))
-                for k, _ in self._fields_}
+                for k, _ in self._fields_ if k != "reserved"}
+
+
+GROUP_AUTO = -1          # PCMM_GROUP_AUTO
+PLAN_MAX_PROBLEMS = 64   # PCMM_PLAN_MAX_PROBLEMS
+
+
+class Problem(ctypes.Structure):
+    """pcmm_problem"""
+    _fields_ = [("A", ctypes.c_void_p), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("l", ctypes.c_int32),
+                ("bits", ctypes.c_int32), ("is_signed", ctypes.c_int32), ("c_form", ctypes.c_int32),
+                ("cfg", CussenCfg)]
 
 
 _lib = None
@@ -97,6 +109,12 @@ _SIG = {
                                ctypes.POINTER(ctypes.c_size_t)], _I32),
     "pcmm_cussen_plan_stats": ([_VP, _I32, _I32, _I32, _I32, ctypes.POINTER(CussenCfg),
                                 ctypes.POINTER(CussenStats)], _I32),
+    "pcmm_plan_create": ([ctypes.POINTER(Problem), _I32, ctypes.POINTER(_VP)], _I32),
+    "pcmm_plan_destroy": ([_VP], _I32),
+    "pcmm_plan_workspace": ([_VP, ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "pcmm_plan_stats": ([_VP, _I32, ctypes.POINTER(CussenStats)], _I32),
+    "pcmm_plan_run": ([_VP, ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP, ctypes.c_size_t,
+                       ctypes.POINTER(_VP), _VP], _I32),
     "pcmm_normalize": ([ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP, ctypes.c_size_t, _VP], _I32),
     "pcmm_normalize_workspace": ([_I64, _I32], ctypes.c_size_t),
     "pcmm_decrypt_to_points": ([_VP, ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP], _I32),
@@ -464,3 +482,67 @@ def decrypt_to_points(sk: bytes, C: DevPoints, stream=None) -> DevPoints:
 
 def strerror(code: int) -> str:
     return lib().pcmm_strerror(code).decode()
+
+
+class Plan:
+    """A compiled pcmm_plan of one or more Cussen PC-MMs (pcmm_plan_*).
+
+    problems: sequence of (A, bits, l, c_form, cfg) with A a host int8 (signed)
+    or uint8 (unsigned) m x n matrix and cfg a CussenCfg or None."""
+
+    def __init__(self, problems):
+        arr = (Problem * len(problems))()
+        self.shapes = []
+        for k, (A, bits, l, c_form, cfg) in enumerate(problems):
+            A, signed = _host_A(A)
+            m, n = A.shape
+            arr[k] = Problem(A.ctypes.data, m, n, l, bits, signed, c_form,
+                             cfg if cfg is not None else CussenCfg(4, 0, 0, 0, 0, None))
+            self.shapes.append((m, n, l, c_form))
+        h = ctypes.c_void_p()
+        _call("pcmm_plan_create", arr, len(problems), ctypes.byref(h))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pcmm_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _call("pcmm_plan_workspace", self.h, ctypes.byref(n))
+        return n.value
+
+    def stats(self, index: int) -> dict:
+        st = CussenStats()
+        _call("pcmm_plan_stats", self.h, index, ctypes.byref(st))
+        return st.as_dict()
+
+    def outputs(self):
+        return [DevPoints.empty(m, l, 2, c_form) for (m, n, l, c_form) in self.shapes]
+
+    def run(self, B, C=None, workspace=None, stage_events=None, stream=None):
+        """B: list of DevPoints (n_i x l_i ciphertexts); C: list of DevPoints
+        or None (allocated).  Queues the run; returns C."""
+        if C is None:
+            C = self.outputs()
+        if len(B) != len(self.shapes) or len(C) != len(self.shapes):
+            raise ValueError("one B and one C per problem")
+        Bm = (Mat * len(B))(*[b.mat for b in B])
+        Cm = (Mat * len(C))(*[c.mat for c in C])
+        ws = workspace if workspace is not None else _workspace(self.workspace_bytes())
+        evp = None
+        if stage_events is not None:
+            if len(stage_events) != STAGE_EVENTS:
+                raise ValueError(f"need {STAGE_EVENTS} events")
+            evp = (ctypes.c_void_p * STAGE_EVENTS)(*[int(e.cuda_event) for e in stage_events])
+        _call("pcmm_plan_run", self.h, Bm, Cm, _tensor_ptr(ws), ws.numel(), evp, stream_ptr(stream))
+        for c in C:
+            c._keep = (ws,)
+        return C

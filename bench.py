@@ -96,6 +96,97 @@ def cpu_baseline(sh, A, target_seconds, threads):
                       f"{dt:.1f} s wall on {threads} threads"}, C, cols
 
 
+def time_region(fn, reps, stream):
+    """Mean ms per call of fn() over `reps` back-to-back calls on `stream`."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batch_leg(reps):
+    """64 uneven PC-MMs (m, n, l ~ U{32..512}, t ~ U{1, 2, 4, 8}, 8-bit
+    messages): separate pcmm_cussen calls, separate cached plans, one batched
+    plan (eager), and the batched plan replayed from a hipGraph."""
+    import torch
+    from paper_2504_14497_amd import pcmm, workloads as W
+    bw = W.batch_workload()
+    stream = torch.cuda.current_stream()
+    As, Bs = [], []
+    for sh in bw.shapes:
+        A, msg = W.make_inputs(sh)
+        _, pk = pcmm.keygen(sh.seed)
+        As.append(A)
+        Bs.append(pcmm.encrypt(pk, msg, sh.seed))
+    torch.cuda.synchronize()
+    count = len(As)
+    t0 = time.time()
+    plan = pcmm.Plan([(A, sh.bits, sh.l, pcmm.AFFINE, pcmm.cussen_cfg(4, 1)) for A, sh in zip(As, bw.shapes)])
+    t_plan = time.time() - t0
+    ws = torch.empty(plan.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    Cb = plan.outputs()
+    # separate calls share one workspace of the largest single size
+    single_ws = max(pcmm.cussen_workspace_bytes(A, sh.bits, sh.l, pcmm.AFFINE, pcmm.cussen_cfg(4, 1))
+                    for A, sh in zip(As, bw.shapes))
+    ws1 = torch.empty(single_ws, dtype=torch.uint8, device="cuda")
+    Cs = plan.outputs()
+    cfg1 = pcmm.cussen_cfg(4, 1)
+
+    def singles():
+        for k in range(count):
+            pcmm.cussen(As[k], bw.shapes[k].bits, Bs[k], cfg=cfg1, workspace=ws1, out=Cs[k])
+
+    plans1 = [pcmm.Plan([(A, sh.bits, sh.l, pcmm.AFFINE, cfg1)]) for A, sh in zip(As, bw.shapes)]
+    Cp = plan.outputs()
+
+    def cached():
+        for k in range(count):
+            plans1[k].run([Bs[k]], [Cp[k]], ws1)
+
+    def batched():
+        plan.run(Bs, Cb, ws)
+
+    singles()
+    cached()
+    batched()
+    torch.cuda.synchronize()
+    same = all(torch.equal(Cs[k].t, Cb[k].t) and torch.equal(Cp[k].t, Cb[k].t) for k in range(count))
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            plan.run(Bs, Cb, ws)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    for c in Cb:
+        c.t.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    same = same and all(torch.equal(Cs[k].t, Cb[k].t) for k in range(count))
+    ms = {"single_calls": time_region(singles, reps, stream),
+          "single_cached_plans": time_region(cached, reps, stream),
+          "batched": time_region(batched, reps, stream),
+          "batched_graph": time_region(g.replay, reps, stream)}
+    acc = sum(2 * sh.l * plan.stats(k)["accum_adds"] for k, sh in enumerate(bw.shapes))
+    out = {"workload": f"{count} PC-MMs, m, n, l uniform in 32..512, A unsigned with bit-width uniform over "
+                       f"(1, 2, 4, 8), ciphertexts of uniform 8-bit messages, Cussen N=4 g=1 (seed {bw.seed})",
+           "unit": "PC-MM/s", "reps": reps, "same_output": bool(same), "host_plan_s": t_plan,
+           "workspace_gb": ws.numel() / 1e9, "mixed_adds": acc}
+    for k, v in ms.items():
+        out[k] = {"ms": v, "pcmm_per_s": count * 1000.0 / v}
+    out["speedup_batched_graph_vs_single_calls"] = ms["single_calls"] / ms["batched_graph"]
+    out["speedup_batched_graph_vs_cached_plans"] = ms["single_cached_plans"] / ms["batched_graph"]
+    del ws, ws1
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +199,8 @@ def main():
     ap.add_argument("--school-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=3, help="timed repetitions of each batch form")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-PC-MM batch comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run the plain copy kernel over BYTES (read BYTES, write BYTES) three "
                          "times, to scale the HBM byte counters of a profiler run")
@@ -181,10 +274,22 @@ def main():
     paper_adds = (4 * sh.bits * sh.l * per_col_muls + 2 * sh.l * per_col_adds
                   + 2 * sh.m * sh.l * (sh.n - 1))
     executed_adds = 2 * sh.l * (st0["table_adds"] + st0["accum_adds"])
+    step_gpu_ms = [evs[0].elapsed_time(evs[-1]) for evs in step_events]
     names = ("ms_upload", "ms_table", "ms_accumulate", "ms_reduce", "ms_normalize")
     stage = {k: float(np.mean([evs[i].elapsed_time(evs[i + 1]) for evs in step_events]))
              for i, k in enumerate(names)}
     stage["ms_total"] = float(np.mean([evs[0].elapsed_time(evs[-1]) for evs in step_events]))
+
+    # the same PC-MM with its plan compiled once (a static A served against ciphertexts)
+    plan = pcmm.Plan([(A, sh.bits, sh.l, pcmm.AFFINE, cfg)])
+    wsp = torch.empty(plan.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    Cp = plan.outputs()
+    plan.run([B], Cp, wsp)
+    ms_cached = time_region(lambda: plan.run([B], Cp, wsp), args.steps, stream)
+    cached_same = bool(torch.equal(Cp[0].t, C.t))
+    del wsp
+    # the autotuned group for this shape
+    tuned = pcmm.cussen_plan_stats(A, sh.bits, pcmm.cussen_cfg(4, pcmm.GROUP_AUTO))
 
     # schoolbook on the same inputs
     Cs = pcmm.DevPoints.empty(sh.m, sh.l, 2, pcmm.AFFINE)
@@ -226,6 +331,11 @@ def main():
         "paper_model_point_adds": paper_adds,
         "executed_point_adds_per_s": executed_adds / (ms_step * 1e-3),
         "stage_ms": stage,
+        "step_gpu_ms": {"median": float(np.median(step_gpu_ms)), "min": float(np.min(step_gpu_ms)),
+                        "max": float(np.max(step_gpu_ms))},
+        "cached_plan": {"value": 1000.0 / ms_cached, "unit": "PC-MM/s", "ms_per_step": ms_cached,
+                        "same_output": cached_same},
+        "autotuned_group": tuned["group"],
         "wall_s": t_wall,
         "schoolbook": {"value": 1000.0 / ms_school, "unit": "PC-MM/s", "ms_per_step": ms_school,
                        "point_adds_per_s": cm.schoolbook_equiv_adds(sh.m, sh.n, sh.l, sh.bits)
@@ -234,6 +344,9 @@ def main():
         "roofline": roofline,
         "device": dev,
     }
+    if not args.no_batch:
+        del ws
+        out["batch"] = batch_leg(args.batch_reps)
     if not args.no_cpu_baseline:
         threads = max(1, min(os.cpu_count() or 1, 16))
         base, Corc, cols = cpu_baseline(sh, A, args.cpu_seconds, threads)

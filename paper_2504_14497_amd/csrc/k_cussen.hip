@@ -43,6 +43,8 @@ namespace {
 constexpr int ENTRY_WORDS = 20;  // affine entry: x (9 limbs), y (9 limbs), 2 pad words; Montgomery form
 constexpr int JAC_WORDS = 3 * NL;
 constexpr int MAX_PROBLEMS = PCMM_PLAN_MAX_PROBLEMS;
+constexpr size_t LDS_BUDGET = 150 * 1024;  // per workgroup, of the 160 KB of a CU
+constexpr size_t LDS_CHUNK = 64 * 1024;    // default tables staged at once
 
 // One problem of a run, as the kernels see it.  Offsets o_* are bytes into
 // the plan image, w_* bytes into the workspace; the image sits at the start
@@ -59,7 +61,9 @@ struct prob_desc {
     int64_t norm_block0, norm_threads;
     int64_t ldj;     // ld of the internal Jacobian buffers (partials, C before normalisation)
     int64_t ld_pre;  // ld of the normalisation prefixes
-    int64_t o_ops, o_op_begin, o_entry_begin, o_entries, o_codes;
+    int64_t o_ops, o_op_begin, o_entry_begin, o_entries;
+    int64_t o_lists, o_chunk_off, o_chunk_len;  // nonzero codes per (split, LDS chunk), see pack_codes
+    int32_t chunks_per_split, pad2;
     int64_t w_regs, w_table, w_part, w_cjac, w_norm;
 };
 
@@ -256,7 +260,9 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
     const int pairs_here = min(pp, npairs - p0);
     const int chunk_words_per_group = pp * emax * ENTRY_WORDS;
     const uint32_t *table = at<const uint32_t>(a, d.w_table);
-    const int16_t *codes = at<const int16_t>(a, d.o_codes);
+    const int32_t *lists = at<const int32_t>(a, d.o_lists);
+    const int64_t *chunk_off = at<const int64_t>(a, d.o_chunk_off);
+    const int32_t *chunk_len = at<const int32_t>(a, d.o_chunk_len);
 
     jpt acc = jpt_infinity();
     for (int gc = g_begin; gc < g_end; gc += d.kc) {
@@ -271,9 +277,15 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
         }
         __syncthreads();
         if (active) {
-            for (int kk = 0; kk < kn; ++kk) {
-                const int code = codes[(int64_t)(gc + kk) * m + i];
+            // this row's nonzero codes of the chunk, as (group in chunk, code)
+            const int chunk = bz * d.chunks_per_split + (gc - g_begin) / d.kc;
+            const int len = chunk_len[chunk];
+            const int32_t *lst = lists + chunk_off[chunk] * m + i;
+            for (int it = 0; it < len; ++it) {
+                const int32_t v = lst[(int64_t)it * m];
+                const int code = (int16_t)(v & 0xFFFF);
                 if (code == 0) continue;
+                const int kk = v >> 16;
                 const int e = (code < 0 ? -code : code) - 1;
                 const uint32_t *ent =
                     lds + (int64_t)kk * chunk_words_per_group + ((int64_t)pair_l * emax + e) * ENTRY_WORDS;
@@ -419,6 +431,7 @@ int build_plan_cfg(const int8_t *A, int m, int n, int bits, bool sgn, const pcmm
         cussen_plan P;
         int rc = build_cussen_plan(A, m, n, bits, sgn, N, g, &P);
         if (rc) return rc;
+        if (g > 1 && (size_t)std::max(P.max_entries, 1) * ENTRY_WORDS * 4 > LDS_BUDGET) continue;
         const double c = predicted_cost(P);
         if (g == 1 || c < best) {
             best = c;
@@ -444,6 +457,10 @@ struct job {
     int norm_per = 0;
     size_t regs_bytes = 0, table_bytes = 0, part_bytes = 0, cjac_bytes = 0, norm_bytes = 0;
     double tile_cost = 0;
+    int chunks_per_split = 0;
+    std::vector<int32_t> lists, chunk_len;
+    std::vector<int64_t> chunk_off;
+    bool fits = true;  // one column group's tables for one pair fit the LDS budget
 };
 
 void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
@@ -463,16 +480,26 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     G.n_lanes = (int64_t)P.ngroups * 2 * G.Lj;
     // accumulation tile
     const int npairs = 2 * l;
-    G.tm = m > 128 ? 256 : (m > 64 ? 128 : 64);
+    // rows per tile: the fewest padded rows, the larger tile on ties (each
+    // staged table entry then serves more rows), among the tiles whose pairs'
+    // tables of one column group fit the default LDS chunk (the persistent
+    // kernel reserves the largest chunk of all problems of a run, and two
+    // workgroups per CU, which the registers allow, need <= 80 KB each)
+    G.tm = 256;
+    for (int tm : {128, 64, 32}) {
+        if ((size_t)(256 / tm) * emax * ENTRY_WORDS * 4 > LDS_CHUNK) break;
+        if ((int64_t)(m + tm - 1) / tm * tm < (int64_t)(m + G.tm - 1) / G.tm * G.tm) G.tm = tm;
+    }
     G.pp = 256 / G.tm;
     G.tiles_x = (m + G.tm - 1) / G.tm;
     G.tiles_y = (npairs + G.pp - 1) / G.pp;
     const int64_t wg_base = (int64_t)G.tiles_x * G.tiles_y;
     const size_t group_bytes = (size_t)G.pp * emax * ENTRY_WORDS * 4;
-    int kc = cfg && cfg->k_chunk > 0 ? cfg->k_chunk : (int)std::max<size_t>(1, (64 * 1024) / group_bytes);
+    int kc = cfg && cfg->k_chunk > 0 ? cfg->k_chunk : (int)std::max<size_t>(1, LDS_CHUNK / group_bytes);
     kc = std::max(1, std::min(kc, std::max(P.ngroups, 1)));
-    while (kc > 1 && (size_t)kc * group_bytes > 150 * 1024) --kc;
+    while (kc > 1 && (size_t)kc * group_bytes > LDS_BUDGET) --kc;
     G.kc = kc;
+    G.fits = group_bytes <= LDS_BUDGET;
     G.lds_bytes = (size_t)kc * group_bytes;
     int S = cfg && cfg->k_split > 0 ? cfg->k_split : 1;
     if (!(cfg && cfg->k_split > 0)) {
@@ -497,9 +524,51 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     }
 }
 
-size_t plan_arrays_bytes(const cussen_plan &P) {
-    return align256(P.ops.size() * sizeof(plan_op)) + align256(P.op_begin.size() * 4) +
-           align256(P.entry_begin.size() * 4) + align256(P.entries.size() * 2) + align256(P.codes.size() * 2);
+// The accumulation walks, per (split, LDS chunk of kc column groups), only
+// the nonzero codes of each row: slot-major lists lists[(chunk_off + slot) * m
+// + i] = (group in chunk) << 16 | (code & 0xffff), padded with 0 (no
+// operation) up to the chunk's longest row.  A wavefront then runs as many
+// mixed additions as its rows' largest count of nonzero codes rather than
+// one per column group, which matters where many codes are zero (small
+// bit-widths).
+void pack_codes(job &G) {
+    const cussen_plan &P = G.P;
+    const int m = P.m;
+    G.chunks_per_split = G.gps > 0 ? (G.gps + G.kc - 1) / G.kc : 0;
+    const int nchunks = G.S * G.chunks_per_split;
+    G.chunk_off.assign(nchunks, 0);
+    G.chunk_len.assign(nchunks, 0);
+    std::vector<int32_t> cnt(m);
+    int64_t total = 0;
+    for (int c = 0; c < nchunks; ++c) {
+        const int bz = c / std::max(G.chunks_per_split, 1);
+        const int g0 = bz * G.gps + (c % std::max(G.chunks_per_split, 1)) * G.kc;
+        const int g1 = std::min({P.ngroups, bz * G.gps + G.gps, g0 + G.kc});
+        int len = 0;
+        for (int i = 0; i < m; ++i) {
+            int k = 0;
+            for (int g = g0; g < g1; ++g) k += P.codes[(size_t)g * m + i] != 0;
+            len = std::max(len, k);
+        }
+        G.chunk_off[c] = total;
+        G.chunk_len[c] = len;
+        total += len;
+    }
+    G.lists.assign((size_t)total * m, 0);
+    for (int c = 0; c < nchunks; ++c) {
+        const int bz = c / std::max(G.chunks_per_split, 1);
+        const int g0 = bz * G.gps + (c % std::max(G.chunks_per_split, 1)) * G.kc;
+        const int g1 = std::min({P.ngroups, bz * G.gps + G.gps, g0 + G.kc});
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int g = g0; g < g1; ++g) {
+            const int16_t *row = &P.codes[(size_t)g * m];
+            for (int i = 0; i < m; ++i) {
+                if (!row[i]) continue;
+                G.lists[(size_t)(G.chunk_off[c] + cnt[i]++) * m + i] =
+                    (int32_t)(((uint32_t)(g - g0) << 16) | (uint16_t)row[i]);
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -560,8 +629,12 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         img += align256(G.P.entry_begin.size() * 4);
         D[k].o_entries = (int64_t)img;
         img += align256(G.P.entries.size() * 2);
-        D[k].o_codes = (int64_t)img;
-        img += align256(G.P.codes.size() * 2);
+        D[k].o_lists = (int64_t)img;
+        img += align256(G.lists.size() * 4);
+        D[k].o_chunk_off = (int64_t)img;
+        img += align256(G.chunk_off.size() * 8);
+        D[k].o_chunk_len = (int64_t)img;
+        img += align256(G.chunk_len.size() * 4);
     }
     pl.ctr_off = img;
     size_t ws = img + 256;
@@ -589,6 +662,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         d.tiles_x = G.tiles_x;
         d.tiles_y = G.tiles_y;
         d.norm_per = G.norm_per;
+        d.chunks_per_split = G.chunks_per_split;
         d.n_lanes = G.n_lanes;
         d.tb_block0 = tb;
         tb += (G.n_lanes + 255) / 256;
@@ -632,7 +706,10 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         put(D[k].o_op_begin, P.op_begin.data(), P.op_begin.size() * 4);
         put(D[k].o_entry_begin, P.entry_begin.data(), P.entry_begin.size() * 4);
         put(D[k].o_entries, P.entries.data(), P.entries.size() * 2);
-        put(D[k].o_codes, P.codes.data(), P.codes.size() * 2);
+        const job &G = pl.jobs[k];
+        put(D[k].o_lists, G.lists.data(), G.lists.size() * 4);
+        put(D[k].o_chunk_off, G.chunk_off.data(), G.chunk_off.size() * 8);
+        put(D[k].o_chunk_len, G.chunk_len.data(), G.chunk_len.size() * 4);
     }
     return PCMM_OK;
 }
@@ -695,6 +772,7 @@ pcmm_status build_plan(const pcmm_problem *probs, int count, pcmm_plan_s &pl) {
         G.l = q.l;
         G.c_form = q.c_form;
         make_geometry(G, &q.cfg);
+        if (G.fits && (int64_t)q.m * q.l > 0 && q.n > 0) pack_codes(G);
     };
     const int nthreads = std::min(count, std::max(1, std::min(16, (int)std::thread::hardware_concurrency())));
     if (nthreads <= 1) {
@@ -711,6 +789,9 @@ pcmm_status build_plan(const pcmm_problem *probs, int count, pcmm_plan_s &pl) {
     for (int i = 0; i < count; ++i) {
         if (rcs[i] == -2) return PCMM_ERANGE;
         if (rcs[i]) return PCMM_EINVAL;
+        // a table larger than the LDS budget (g > 1 with very many distinct
+        // row segments) has no accumulation geometry
+        if (!built[i].fits && (int64_t)probs[i].m * probs[i].l > 0 && probs[i].n > 0) return PCMM_EINVAL;
     }
     for (int i = 0; i < count; ++i) {
         const pcmm_problem &q = probs[i];

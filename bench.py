@@ -187,6 +187,86 @@ def batch_leg(reps):
     return out
 
 
+def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
+    """Encrypted linear layers served by the continuous-batching scheduler:
+    4 static layers W (256 x 1024, uniform signed 8-bit, resident plans),
+    requests X (1024 x 8 ciphertexts of uniform 8-bit messages, a fresh
+    matrix per request, resident in HBM) picking a layer uniformly; Poisson
+    arrivals at fractions of the measured capacity."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2504_14497_amd import pcmm, workloads as W
+    from paper_2504_14497_amd.serving import (DONE, GpuExecutor, Request, Server, latency_summary,
+                                              poisson_arrivals, run_arrivals)
+    base = W.SERVE_LAYER
+    layers = []
+    for k in range(4):
+        sh = W.PCMMShape(base.m, base.n, base.l, base.bits, True, base.msg_bits, seed=base.seed + k,
+                         name=f"layer{k}")
+        layers.append(W.make_inputs(sh)[0])
+    cfg = pcmm.cussen_cfg(4, 1)
+    t0 = time.time()
+    plan = pcmm.Plan([(Wk, base.bits, base.l, pcmm.AFFINE, cfg) for Wk in layers])
+    plan.make_resident()
+    t_plan = time.time() - t0
+    n, l, m = base.n, base.l, base.m
+    rng = np.random.default_rng(base.seed)
+    msg = torch.from_numpy(rng.integers(0, 1 << base.msg_bits, size=(n_requests * n, l)).astype(np.int32))
+    _, pk = pcmm.keygen(base.seed)
+    big = pcmm.encrypt(pk, msg.numpy(), base.seed)  # one call; request k owns rows k*n .. k*n + n - 1
+    per = n * l
+
+    def view(k):
+        v = pcmm.DevPoints.__new__(pcmm.DevPoints)
+        v.t, v.rows, v.cols, v.npts, v.form = big.t, n, l, 2, pcmm.AFFINE
+        v.mat = pcmm.Mat(n, l, 2, pcmm.AFFINE, big.mat.ld, big.mat.d + k * per * 4)
+        return v
+
+    X = [view(k) for k in range(n_requests)]
+    Cs = [pcmm.DevPoints.empty(m, l, 2, pcmm.AFFINE) for _ in range(n_requests)]
+    which = rng.integers(0, 4, size=n_requests)
+    ws = torch.empty(int(budget_gb * 1e9), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    ex = GpuExecutor(plan, ws, slots=slots, count=4)
+
+    def fresh_requests(count):
+        return [Request(rid=k, layer=int(which[k]), X=X[k], C=Cs[k]) for k in range(count)]
+
+    def run(rate, count):
+        srv = Server(ex, budget=ws.numel(), slots=slots, max_batch=max_batch)
+        reqs = fresh_requests(count)
+        arr = poisson_arrivals(count, rate, seed=17) if rate else np.zeros(count)
+        wall = run_arrivals(srv, reqs, arr)
+        torch.cuda.synchronize()
+        assert all(r.state == DONE for r in reqs)
+        sizes = [b for _, b, _ in srv.batches]
+        out = latency_summary(reqs)
+        out.update({"offered_req_per_s": rate, "achieved_req_per_s": count / wall,
+                    "mean_batch": float(np.mean(sizes)), "batches": len(sizes)})
+        return out
+
+    run(0, min(64, n_requests))                     # warm-up
+    burst = run(0, min(512, n_requests))             # all at once: capacity
+    capacity = burst["achieved_req_per_s"]
+    sweep = [dict(run(f * capacity, n_requests), fraction=f) for f in fractions]
+    # identity: requests of the last sweep re-run alone equal their mixed results
+    wsa = torch.empty(plan.selected_workspace_bytes([0]), dtype=torch.uint8, device="cuda")
+    same = True
+    for k in range(0, n_requests, max(1, n_requests // 8)):
+        alone = pcmm.DevPoints.empty(m, l, 2, pcmm.AFFINE)
+        plan.run_selected([int(which[k])], [X[k]], [alone], wsa)
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(alone.t, Cs[k].t))
+    return {"workload": f"4 layers W {m}x{n} uniform signed {base.bits}-bit (plans resident), requests X "
+                        f"{n}x{l} ciphertexts of uniform {base.msg_bits}-bit messages, a fresh X per request, "
+                        f"layer uniform; Poisson arrivals; Cussen N=4 g=1",
+            "requests_per_rate": n_requests, "slots": slots, "max_batch": max_batch,
+            "budget_gb": budget_gb, "request_workspace_mb": plan.stats(0)["workspace_bytes"] / 1e6,
+            "host_plan_s": t_plan, "capacity_req_per_s": capacity, "burst": burst, "sweep": sweep,
+            "alone_equals_mix": same}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +281,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=3, help="timed repetitions of each batch form")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-PC-MM batch comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
+    ap.add_argument("--serve-fractions", default="0.25,0.5,0.75,1.0,1.25",
+                    help="arrival rates as fractions of the measured capacity")
+    ap.add_argument("--serve-budget-gb", type=float, default=40.0, help="workspace budget of the server")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run the plain copy kernel over BYTES (read BYTES, write BYTES) three "
                          "times, to scale the HBM byte counters of a profiler run")
@@ -347,6 +432,10 @@ def main():
     if not args.no_batch:
         del ws
         out["batch"] = batch_leg(args.batch_reps)
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        out["serving"] = serve_leg(args.serve_requests, [float(x) for x in args.serve_fractions.split(",")],
+                                   args.serve_budget_gb, slots=2, max_batch=32)
     if not args.no_cpu_baseline:
         threads = max(1, min(os.cpu_count() or 1, 16))
         base, Corc, cols = cpu_baseline(sh, A, args.cpu_seconds, threads)

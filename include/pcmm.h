@@ -125,6 +125,8 @@ typedef struct {
     int64_t table_adds;      /* point additions executed per output column to build tables */
     int64_t accum_adds;      /* mixed additions executed per output column (all rows)      */
     int64_t max_entries;     /* largest table (entries) of one column (group)              */
+    int64_t workspace_bytes; /* device workspace of this problem's tables, scratch and
+                                partial sums within a plan run (0 without GPU work)      */
     int32_t k_split;         /* split of the inner dimension that was used                 */
     int32_t lanes_per_chain; /* table-build batch: output columns per lane                 */
     int32_t group;           /* columns of A per code that was used (after autotuning)     */
@@ -222,6 +224,27 @@ pcmm_status pcmm_plan_stats(pcmm_plan plan, int32_t index, pcmm_cussen_stats *st
  * returns without waiting.  Runs that overlap on one workspace race. */
 pcmm_status pcmm_plan_run(pcmm_plan plan, const pcmm_mat *B, pcmm_mat *C, void *workspace,
                           size_t ws_bytes, void **stage_events, void *stream);
+
+/* Resident plans and selected runs (serving static layers).
+ * pcmm_plan_make_resident copies the plan's compiled arrays once, on
+ * `stream`, into caller-owned device memory of pcmm_plan_resident_bytes()
+ * bytes, which must stay allocated and unchanged while the plan runs
+ * selections; runs queued on other streams must be ordered after that copy.
+ * pcmm_plan_run_selected then runs the problems which[0..k) of the plan
+ * (1 <= k <= PCMM_PLAN_MAX_PROBLEMS; an index may repeat: every entry is an
+ * independent PC-MM with its own B[r] and C[r]) with the same kernels as
+ * pcmm_plan_run, uploading only a small block of descriptors per run.  The
+ * workspace holds the selected problems' tables and partial sums
+ * (pcmm_plan_selected_workspace(); the sum of their stats' workspace_bytes
+ * plus a few KB).  Runs on different streams with different workspaces may
+ * overlap on the device; up to 8 runs of one plan can be in flight before a
+ * further call waits for the oldest to have started executing. */
+pcmm_status pcmm_plan_resident_bytes(pcmm_plan plan, size_t *bytes);
+pcmm_status pcmm_plan_make_resident(pcmm_plan plan, void *device_mem, size_t bytes, void *stream);
+pcmm_status pcmm_plan_selected_workspace(pcmm_plan plan, const int32_t *which, int32_t k, size_t *bytes);
+pcmm_status pcmm_plan_run_selected(pcmm_plan plan, const int32_t *which, int32_t k, const pcmm_mat *B,
+                                   pcmm_mat *C, void *workspace, size_t ws_bytes, void **stage_events,
+                                   void *stream);
 
 /* Host-only: the compression plan's operation counts for A (no GPU work). */
 pcmm_status pcmm_cussen_plan_stats(const int8_t *A, int32_t m, int32_t n, int32_t bits,

@@ -74,7 +74,8 @@ struct io_ptrs {
 };
 
 struct run_args {
-    char *ws;            // workspace; the plan image starts here
+    char *ws;            // workspace; the run's descriptors start here
+    const char *plan;    // base of the plan arrays (o_* offsets): the workspace, or a resident copy
     int32_t count;       // descriptors
     int32_t pad;
     int64_t total_tiles;
@@ -101,6 +102,11 @@ __device__ __forceinline__ int find_problem(const run_args &a, size_t key_off, i
 template <typename T>
 __device__ __forceinline__ T *at(const run_args &a, int64_t off) {
     return (T *)(a.ws + off);
+}
+
+template <typename T>
+__device__ __forceinline__ const T *plan_at(const run_args &a, int64_t off) {
+    return (const T *)(a.plan + off);
 }
 
 // --------------------------------------------------------------------------
@@ -131,10 +137,10 @@ __global__ void __launch_bounds__(256) table_build_kernel(run_args a) {
     const prob_desc &d = descs(a)[b];
     const int64_t lane = ((int64_t)blockIdx.x - d.tb_block0) * blockDim.x + threadIdx.x;
     if (lane >= d.n_lanes) return;
-    const plan_op *ops = at<const plan_op>(a, d.o_ops);
-    const int32_t *op_begin = at<const int32_t>(a, d.o_op_begin);
-    const int32_t *entry_begin = at<const int32_t>(a, d.o_entry_begin);
-    const int16_t *entries = at<const int16_t>(a, d.o_entries);
+    const plan_op *ops = plan_at<plan_op>(a, d.o_ops);
+    const int32_t *op_begin = plan_at<int32_t>(a, d.o_op_begin);
+    const int32_t *entry_begin = plan_at<int32_t>(a, d.o_entry_begin);
+    const int16_t *entries = plan_at<int16_t>(a, d.o_entries);
     uint32_t *regs = at<uint32_t>(a, d.w_regs);
     uint32_t *table = at<uint32_t>(a, d.w_table);
     const uint32_t *B = a.io[d.io].B;
@@ -260,9 +266,9 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
     const int pairs_here = min(pp, npairs - p0);
     const int chunk_words_per_group = pp * emax * ENTRY_WORDS;
     const uint32_t *table = at<const uint32_t>(a, d.w_table);
-    const int32_t *lists = at<const int32_t>(a, d.o_lists);
-    const int64_t *chunk_off = at<const int64_t>(a, d.o_chunk_off);
-    const int32_t *chunk_len = at<const int32_t>(a, d.o_chunk_len);
+    const int32_t *lists = plan_at<int32_t>(a, d.o_lists);
+    const int64_t *chunk_off = plan_at<int64_t>(a, d.o_chunk_off);
+    const int32_t *chunk_len = plan_at<int32_t>(a, d.o_chunk_len);
 
     jpt acc = jpt_infinity();
     for (int gc = g_begin; gc < g_end; gc += d.kc) {
@@ -456,6 +462,7 @@ struct job {
     int64_t ldj = 64, norm_threads = 0, ld_pre = 0;
     int norm_per = 0;
     size_t regs_bytes = 0, table_bytes = 0, part_bytes = 0, cjac_bytes = 0, norm_bytes = 0;
+    size_t footprint = 0;  // workspace bytes of this problem's regions
     double tile_cost = 0;
     int chunks_per_split = 0;
     std::vector<int32_t> lists, chunk_len;
@@ -522,6 +529,8 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
         G.ld_pre = G.norm_threads * G.norm_per * 2;
         G.norm_bytes = normalize_scratch_bytes(n_out, 2);
     }
+    G.footprint = align256(G.regs_bytes) + align256(G.table_bytes) + align256(G.part_bytes) +
+                  align256(G.cjac_bytes) + align256(G.norm_bytes);
 }
 
 // The accumulation walks, per (split, LDS chunk of kc column groups), only
@@ -573,6 +582,27 @@ void pack_codes(job &G) {
 
 }  // namespace
 
+namespace {
+
+// What a run queues: descriptors copied to the start of the workspace, the
+// accumulation queue counter after them, then the problems' regions.
+struct run_layout {
+    int32_t count = 0;  // descriptors
+    size_t copy_bytes = 0, ctr_off = 0, ws_bytes = 256;
+    int64_t tb_blocks = 0, tiles = 0, red_blocks = 0, norm_blocks = 0;
+    size_t max_lds = 0;
+    int acc_grid = 0;
+    std::vector<int> fills;  // run indices whose inner dimension is empty (identity outputs)
+};
+
+// pinned staging for descriptor blocks of selected runs; an event guards reuse
+struct stage_slot {
+    void *host = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
 // A compiled set of problems (the executor's unit; pcmm_cussen builds one of
 // a single problem per call).
 struct pcmm_plan_s {
@@ -581,15 +611,21 @@ struct pcmm_plan_s {
     std::vector<int32_t> m, n, l, c_form;
     std::vector<pcmm_cussen_stats> stats;
     std::vector<job> jobs;     // problems with GPU work, in execution order
-    std::vector<int> fills;    // problems with n == 0 (all outputs are the identity)
+    std::vector<int> job_of;   // problem index -> job index, or -1
+    std::vector<prob_desc> desc;  // the full run's descriptors (templates of selected runs)
     std::vector<char> image;   // descriptors + plan arrays
     void *pinned = nullptr;    // immutable pinned copy of `image` (plans only)
-    size_t ctr_off = 0, ws_bytes = 256;
-    int64_t tb_blocks = 0, tiles = 0, red_blocks = 0, norm_blocks = 0;
-    size_t max_lds = 0;
-    int acc_grid = 0;
+    run_layout full;           // the run of every problem once
+    const char *resident = nullptr;  // device copy of the image (pcmm_plan_make_resident)
+    std::mutex stage_lock;
+    std::vector<stage_slot> ring;
+    int ring_next = 0;
     ~pcmm_plan_s() {
         if (pinned) hipHostFree(pinned);
+        for (auto &r : ring) {
+            if (r.host) hipHostFree(r.host);
+            if (r.done) hipEventDestroy(r.done);
+        }
     }
 };
 
@@ -604,6 +640,7 @@ void fill_stats(const job &G, pcmm_cussen_stats *st) {
     st->table_adds = P.table_adds;
     st->accum_adds = P.accum_adds;
     st->max_entries = P.max_entries;
+    st->workspace_bytes = (int64_t)G.footprint;
     st->k_split = G.S;
     st->lanes_per_chain = G.J;
     st->group = P.g;
@@ -636,10 +673,13 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         D[k].o_chunk_len = (int64_t)img;
         img += align256(G.chunk_len.size() * 4);
     }
-    pl.ctr_off = img;
+    run_layout &L = pl.full;
+    L.count = (int32_t)nd;
+    L.copy_bytes = img;
+    L.ctr_off = img;
     size_t ws = img + 256;
     int64_t tb = 0, tiles = 0, red = 0, norm = 0;
-    pl.max_lds = 0;
+    L.max_lds = 0;
     for (size_t k = 0; k < nd; ++k) {
         const job &G = pl.jobs[k];
         prob_desc &d = D[k];
@@ -686,13 +726,16 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         ws += align256(G.cjac_bytes);
         d.w_norm = (int64_t)ws;
         ws += align256(G.norm_bytes);
-        pl.max_lds = std::max(pl.max_lds, G.lds_bytes);
+        L.max_lds = std::max(L.max_lds, G.lds_bytes);
     }
-    pl.ws_bytes = ws + 256;
-    pl.tb_blocks = tb;
-    pl.tiles = tiles;
-    pl.red_blocks = red;
-    pl.norm_blocks = norm;
+    L.ws_bytes = ws + 256;
+    L.tb_blocks = tb;
+    L.tiles = tiles;
+    L.red_blocks = red;
+    L.norm_blocks = norm;
+    pl.desc = D;
+    pl.job_of.assign(pl.count, -1);
+    for (size_t k = 0; k < nd; ++k) pl.job_of[pl.jobs[k].index] = (int)k;
     if (tb > 0x7FFFFFFF || red > 0x7FFFFFFF || norm > 0x7FFFFFFF || tiles > 0x7FFFFFFF - (1 << 20))
         return PCMM_EINVAL;
     pl.image.assign(img, 0);
@@ -717,16 +760,15 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
 std::mutex g_occ_lock;
 std::map<std::pair<int, size_t>, int64_t> g_occ_cache;  // (device, LDS bytes) -> resident workgroups
 
-// Binds pl to the current device and sizes the persistent accumulation grid:
-// the workgroups that fit on the device at once, or the tiles if fewer.
-pcmm_status bind_device(pcmm_plan_s &pl) {
-    PCMM_HIP_TRY(hipGetDevice(&pl.device));
-    pl.acc_grid = 0;
-    if (pl.tiles == 0) return PCMM_OK;
-    if (pl.max_lds > 64 * 1024)
+// Sizes the persistent accumulation grid of L on `device` (current): the
+// workgroups that fit on the device at once, or the tiles if fewer.
+pcmm_status size_acc_grid(int device, run_layout &L) {
+    L.acc_grid = 0;
+    if (L.tiles == 0) return PCMM_OK;
+    if (L.max_lds > 64 * 1024)
         PCMM_HIP_TRY(hipFuncSetAttribute((const void *)accumulate_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)pl.max_lds));
-    const auto key = std::make_pair(pl.device, pl.max_lds);
+                                         (int)L.max_lds));
+    const auto key = std::make_pair(device, L.max_lds);
     int64_t cap = 0;
     {
         std::lock_guard<std::mutex> guard(g_occ_lock);
@@ -735,14 +777,20 @@ pcmm_status bind_device(pcmm_plan_s &pl) {
     }
     if (cap == 0) {
         int per_cu = 0, cus = 0;
-        PCMM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, accumulate_kernel, 256, pl.max_lds));
-        PCMM_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl.device));
+        PCMM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, accumulate_kernel, 256, L.max_lds));
+        PCMM_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
         cap = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
         std::lock_guard<std::mutex> guard(g_occ_lock);
         g_occ_cache[key] = cap;
     }
-    pl.acc_grid = (int)std::min<int64_t>(pl.tiles, cap);
+    L.acc_grid = (int)std::min<int64_t>(L.tiles, cap);
     return PCMM_OK;
+}
+
+// Binds pl to the current device.
+pcmm_status bind_device(pcmm_plan_s &pl) {
+    PCMM_HIP_TRY(hipGetDevice(&pl.device));
+    return size_acc_grid(pl.device, pl.full);
 }
 
 // Compiles problems into pl (host threads over problems; no device calls).
@@ -800,9 +848,10 @@ pcmm_status build_plan(const pcmm_problem *probs, int count, pcmm_plan_s &pl) {
         pl.l[i] = q.l;
         pl.c_form[i] = q.c_form;
         fill_stats(built[i], &pl.stats[i]);
+        if ((int64_t)q.m * q.l == 0 || q.n == 0) pl.stats[i].workspace_bytes = 0;
         if ((int64_t)q.m * q.l == 0) continue;
         if (q.n == 0) {
-            pl.fills.push_back(i);
+            pl.full.fills.push_back(i);
             continue;
         }
         pl.jobs.push_back(std::move(built[i]));
@@ -820,56 +869,59 @@ pcmm_status check_mats(int m, int n, int l, int c_form, const pcmm_mat *B, const
     return PCMM_OK;
 }
 
-// Queues a run of pl.  image_src: pinned host copy of pl.image that stays
-// unchanged until the copy has executed.  ev: PCMM_STAGE_EVENTS events or
-// null.
-pcmm_status enqueue_plan(const pcmm_plan_s &pl, const void *image_src, const pcmm_mat *B, pcmm_mat *C,
-                         void *workspace, size_t ws_bytes, hipEvent_t *ev, hipStream_t s) {
+// Queues a run: copies L.copy_bytes from the pinned host block copy_src
+// (unchanged until the copy has executed) to the start of the workspace, then
+// the kernels.  plan_base: device base of the plan arrays, or null for the
+// workspace itself.  B, C: the run's n_io matrices.  ev: PCMM_STAGE_EVENTS
+// events or null.
+pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *plan_base, const pcmm_mat *B,
+                        pcmm_mat *C, int n_io, void *workspace, hipEvent_t *ev, hipStream_t s) {
     auto rec = [&](int i) -> pcmm_status {
         if (ev) PCMM_HIP_TRY(hipEventRecord(ev[i], s));
         return PCMM_OK;
     };
     pcmm_status st;
-#define PCMM_REC(i)                          \
-    do {                                     \
+#define PCMM_REC(i)                              \
+    do {                                         \
         if ((st = rec(i)) != PCMM_OK) return st; \
     } while (0)
-    const bool gpu_work = !pl.jobs.empty();
+    const bool gpu_work = L.count > 0;
     PCMM_REC(0);
     run_args ra{};
     if (gpu_work) {
         ra.ws = (char *)workspace;
-        ra.count = (int32_t)pl.jobs.size();
-        ra.total_tiles = pl.tiles;
-        ra.ctr_off = (int64_t)pl.ctr_off;
-        for (int i = 0; i < pl.count; ++i) ra.io[i] = io_ptrs{B[i].d, C[i].d, B[i].ld, C[i].ld};
-        PCMM_HIP_TRY(hipMemcpyAsync(workspace, image_src, pl.image.size(), hipMemcpyHostToDevice, s));
+        ra.plan = plan_base ? plan_base : (const char *)workspace;
+        ra.count = L.count;
+        ra.total_tiles = L.tiles;
+        ra.ctr_off = (int64_t)L.ctr_off;
+        for (int i = 0; i < n_io; ++i) ra.io[i] = io_ptrs{B[i].d, C[i].d, B[i].ld, C[i].ld};
+        PCMM_HIP_TRY(hipMemcpyAsync(workspace, copy_src, L.copy_bytes, hipMemcpyHostToDevice, s));
     }
     PCMM_REC(1);
     if (gpu_work) {
-        hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)pl.tb_blocks), dim3(256), 0, s, ra);
+        hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)L.tb_blocks), dim3(256), 0, s, ra);
         PCMM_LAUNCH_CHECK();
     }
     PCMM_REC(2);
     if (gpu_work) {
-        if (pl.max_lds > 64 * 1024)
+        if (L.max_lds > 64 * 1024)
             PCMM_HIP_TRY(hipFuncSetAttribute((const void *)accumulate_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.max_lds));
-        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)pl.acc_grid), dim3(256), pl.max_lds, s, ra);
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.max_lds));
+        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)L.acc_grid), dim3(256), L.max_lds, s, ra);
         PCMM_LAUNCH_CHECK();
     }
     PCMM_REC(3);
-    if (pl.red_blocks > 0) {
-        hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)pl.red_blocks), dim3(256), 0, s, ra);
+    if (L.red_blocks > 0) {
+        hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)L.red_blocks), dim3(256), 0, s, ra);
         PCMM_LAUNCH_CHECK();
     }
     PCMM_REC(4);
-    if (pl.norm_blocks > 0) {
-        hipLaunchKernelGGL(normalize_batch_kernel, dim3((unsigned)pl.norm_blocks), dim3(256), 0, s, ra);
+    if (L.norm_blocks > 0) {
+        hipLaunchKernelGGL(normalize_batch_kernel, dim3((unsigned)L.norm_blocks), dim3(256), 0, s, ra);
         PCMM_LAUNCH_CHECK();
     }
-    for (int i : pl.fills) {
-        const int64_t n_out = (int64_t)pl.m[i] * pl.l[i];
+    for (int i : L.fills) {
+        const int64_t n_out = (int64_t)C[i].rows * C[i].cols;
         hipLaunchKernelGGL(fill_infinity_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, s, C[i].d,
                            C[i].ld, n_out, C[i].form);
         PCMM_LAUNCH_CHECK();
@@ -879,13 +931,17 @@ pcmm_status enqueue_plan(const pcmm_plan_s &pl, const void *image_src, const pcm
     return PCMM_OK;
 }
 
-pcmm_status check_run(const pcmm_plan_s &pl, const pcmm_mat *B, pcmm_mat *C, void *workspace, size_t ws_bytes) {
+// Matrices of a run of problems which[0..k) of pl (all problems in order
+// when which is null) against the workspace it needs.
+pcmm_status check_run(const pcmm_plan_s &pl, const int32_t *which, int k, const pcmm_mat *B, pcmm_mat *C,
+                      void *workspace, size_t ws_bytes, size_t need, bool gpu_work) {
     if (!B || !C) return PCMM_EINVAL;
-    for (int i = 0; i < pl.count; ++i) {
-        pcmm_status st = check_mats(pl.m[i], pl.n[i], pl.l[i], pl.c_form[i], &B[i], &C[i]);
+    for (int r = 0; r < k; ++r) {
+        const int i = which ? which[r] : r;
+        pcmm_status st = check_mats(pl.m[i], pl.n[i], pl.l[i], pl.c_form[i], &B[r], &C[r]);
         if (st != PCMM_OK) return st;
     }
-    if (!pl.jobs.empty() && (!workspace || ws_bytes < pl.ws_bytes)) return PCMM_ENOMEM;
+    if (gpu_work && (!workspace || ws_bytes < need)) return PCMM_ENOMEM;
     return PCMM_OK;
 }
 
@@ -957,7 +1013,7 @@ extern "C" pcmm_status pcmm_cussen_workspace(const int8_t *A, int32_t m, int32_t
     pcmm_problem q = single_problem(A, m, n, l, bits, is_signed, c_form, cfg);
     pcmm_status st = build_plan(&q, 1, pl);
     if (st != PCMM_OK) return st;
-    *bytes = pl.ws_bytes;
+    *bytes = pl.full.ws_bytes;
     return PCMM_OK;
 }
 
@@ -980,7 +1036,7 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
     pcmm_status st = build_plan(&q, 1, pl);
     if (st != PCMM_OK) return st;
     if (stats) *stats = pl.stats[0];
-    st = check_run(pl, B, C, workspace, ws_bytes);
+    st = check_run(pl, nullptr, 1, B, C, workspace, ws_bytes, pl.full.ws_bytes, pl.full.count > 0);
     if (st != PCMM_OK) return st;
     st = bind_device(pl);
     if (st != PCMM_OK) return st;
@@ -997,6 +1053,7 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
         if (pl.device < 0 || pl.device >= 64) return PCMM_EDEVICE;
         staging &sg = g_stage[pl.device];
         const size_t bytes = std::max<size_t>(pl.image.size(), 256);
+        (void)ws_bytes;
         if (sg.done) PCMM_HIP_TRY(hipEventSynchronize(sg.done));
         if (sg.bytes < bytes) {
             if (sg.host) hipHostFree(sg.host);
@@ -1007,7 +1064,7 @@ extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_
         }
         if (!sg.done) PCMM_HIP_TRY(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
         if (!pl.image.empty()) memcpy(sg.host, pl.image.data(), pl.image.size());
-        st = enqueue_plan(pl, sg.host, B, C, workspace, ws_bytes, prof ? ev : nullptr, s);
+        st = enqueue_run(pl.full, sg.host, nullptr, B, C, 1, workspace, prof ? ev : nullptr, s);
         if (st != PCMM_OK) return st;
         PCMM_HIP_TRY(hipEventRecord(sg.done, s));
     }
@@ -1058,7 +1115,7 @@ extern "C" pcmm_status pcmm_plan_destroy(pcmm_plan plan) {
 
 extern "C" pcmm_status pcmm_plan_workspace(pcmm_plan plan, size_t *bytes) {
     if (!plan || !bytes) return PCMM_EINVAL;
-    *bytes = plan->ws_bytes;
+    *bytes = plan->full.ws_bytes;
     return PCMM_OK;
 }
 
@@ -1074,7 +1131,8 @@ extern "C" pcmm_status pcmm_plan_run(pcmm_plan plan, const pcmm_mat *B, pcmm_mat
     int dev = -1;
     PCMM_HIP_TRY(hipGetDevice(&dev));
     if (dev != plan->device) return PCMM_EDEVICE;
-    pcmm_status st = check_run(*plan, B, C, workspace, ws_bytes);
+    pcmm_status st = check_run(*plan, nullptr, plan->count, B, C, workspace, ws_bytes, plan->full.ws_bytes,
+                               plan->full.count > 0);
     if (st != PCMM_OK) return st;
     hipEvent_t ev[PCMM_STAGE_EVENTS] = {};
     if (stage_events) {
@@ -1083,6 +1141,139 @@ extern "C" pcmm_status pcmm_plan_run(pcmm_plan plan, const pcmm_mat *B, pcmm_mat
             if (!ev[i]) return PCMM_EINVAL;
         }
     }
-    return enqueue_plan(*plan, plan->pinned, B, C, workspace, ws_bytes, stage_events ? ev : nullptr,
-                        (hipStream_t)stream);
+    return enqueue_run(plan->full, plan->pinned, nullptr, B, C, plan->count, workspace, stage_events ? ev : nullptr,
+                       (hipStream_t)stream);
+}
+
+namespace {
+
+// Layout and descriptors of a run of problems which[0..k) of pl.
+pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, run_layout &L,
+                            std::vector<prob_desc> &D) {
+    if (!which || k < 1 || k > MAX_PROBLEMS) return PCMM_EINVAL;
+    std::vector<int> order;
+    L = run_layout{};
+    for (int r = 0; r < k; ++r) {
+        const int i = which[r];
+        if (i < 0 || i >= pl.count) return PCMM_EINVAL;
+        if (pl.job_of[i] >= 0) order.push_back(r);
+        else if ((int64_t)pl.m[i] * pl.l[i] > 0 && pl.n[i] == 0) L.fills.push_back(r);
+    }
+    // most expensive accumulation tiles first
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return pl.jobs[pl.job_of[which[x]]].tile_cost > pl.jobs[pl.job_of[which[y]]].tile_cost;
+    });
+    const size_t nd = order.size();
+    L.count = (int32_t)nd;
+    L.copy_bytes = align256(nd * sizeof(prob_desc));
+    L.ctr_off = L.copy_bytes;
+    size_t ws = L.ctr_off + 256;
+    D.resize(nd);
+    int64_t tb = 0, tiles = 0, red = 0, norm = 0;
+    for (size_t q = 0; q < nd; ++q) {
+        const int r = order[q];
+        const int jk = pl.job_of[which[r]];
+        const job &G = pl.jobs[jk];
+        prob_desc d = pl.desc[jk];
+        d.io = r;
+        d.tb_block0 = tb;
+        tb += (G.n_lanes + 255) / 256;
+        d.tile0 = tiles;
+        tiles += (int64_t)G.tiles_x * G.tiles_y * G.S;
+        d.red_block0 = red;
+        red += d.red_threads / 256;
+        d.norm_block0 = norm;
+        norm += d.norm_threads / 256;
+        d.w_regs = (int64_t)ws;
+        ws += align256(G.regs_bytes);
+        d.w_table = (int64_t)ws;
+        ws += align256(G.table_bytes);
+        d.w_part = (int64_t)ws;
+        ws += align256(G.part_bytes);
+        d.w_cjac = (int64_t)ws;
+        ws += align256(G.cjac_bytes);
+        d.w_norm = (int64_t)ws;
+        ws += align256(G.norm_bytes);
+        L.max_lds = std::max(L.max_lds, G.lds_bytes);
+        D[q] = d;
+    }
+    L.ws_bytes = ws + 256;
+    L.tb_blocks = tb;
+    L.tiles = tiles;
+    L.red_blocks = red;
+    L.norm_blocks = norm;
+    return PCMM_OK;
+}
+
+constexpr int RING_SLOTS = 8;
+
+}  // namespace
+
+extern "C" pcmm_status pcmm_plan_resident_bytes(pcmm_plan plan, size_t *bytes) {
+    if (!plan || !bytes) return PCMM_EINVAL;
+    *bytes = std::max<size_t>(plan->image.size(), 256);
+    return PCMM_OK;
+}
+
+extern "C" pcmm_status pcmm_plan_make_resident(pcmm_plan plan, void *device_mem, size_t bytes, void *stream) {
+    if (!plan || !device_mem || bytes < std::max<size_t>(plan->image.size(), 256)) return PCMM_EINVAL;
+    int dev = -1;
+    PCMM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != plan->device) return PCMM_EDEVICE;
+    if (!plan->image.empty())
+        PCMM_HIP_TRY(hipMemcpyAsync(device_mem, plan->pinned, plan->image.size(), hipMemcpyHostToDevice,
+                                    (hipStream_t)stream));
+    plan->resident = (const char *)device_mem;
+    return PCMM_OK;
+}
+
+extern "C" pcmm_status pcmm_plan_selected_workspace(pcmm_plan plan, const int32_t *which, int32_t k,
+                                                    size_t *bytes) {
+    if (!plan || !bytes) return PCMM_EINVAL;
+    run_layout L;
+    std::vector<prob_desc> D;
+    pcmm_status st = selected_layout(*plan, which, k, L, D);
+    if (st != PCMM_OK) return st;
+    *bytes = L.ws_bytes;
+    return PCMM_OK;
+}
+
+extern "C" pcmm_status pcmm_plan_run_selected(pcmm_plan plan, const int32_t *which, int32_t k, const pcmm_mat *B,
+                                              pcmm_mat *C, void *workspace, size_t ws_bytes, void **stage_events,
+                                              void *stream) {
+    if (!plan || !plan->resident) return PCMM_EINVAL;
+    int dev = -1;
+    PCMM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != plan->device) return PCMM_EDEVICE;
+    run_layout L;
+    std::vector<prob_desc> D;
+    pcmm_status st = selected_layout(*plan, which, k, L, D);
+    if (st != PCMM_OK) return st;
+    st = check_run(*plan, which, k, B, C, workspace, ws_bytes, L.ws_bytes, L.count > 0);
+    if (st != PCMM_OK) return st;
+    hipEvent_t ev[PCMM_STAGE_EVENTS] = {};
+    if (stage_events) {
+        for (int i = 0; i < PCMM_STAGE_EVENTS; ++i) {
+            ev[i] = (hipEvent_t)stage_events[i];
+            if (!ev[i]) return PCMM_EINVAL;
+        }
+    }
+    st = size_acc_grid(plan->device, L);
+    if (st != PCMM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> guard(plan->stage_lock);
+    if (plan->ring.empty()) plan->ring.resize(RING_SLOTS);
+    stage_slot &slot = plan->ring[plan->ring_next];
+    plan->ring_next = (plan->ring_next + 1) % RING_SLOTS;
+    if (!slot.host) {
+        PCMM_HIP_TRY(hipHostMalloc(&slot.host, align256(MAX_PROBLEMS * sizeof(prob_desc)), hipHostMallocDefault));
+        PCMM_HIP_TRY(hipEventCreateWithFlags(&slot.done, hipEventDisableTiming));
+    } else {
+        PCMM_HIP_TRY(hipEventSynchronize(slot.done));
+    }
+    if (!D.empty()) memcpy(slot.host, D.data(), D.size() * sizeof(prob_desc));
+    st = enqueue_run(L, slot.host, plan->resident, B, C, k, workspace, stage_events ? ev : nullptr, s);
+    if (st != PCMM_OK) return st;
+    PCMM_HIP_TRY(hipEventRecord(slot.done, s));
+    return PCMM_OK;
 }

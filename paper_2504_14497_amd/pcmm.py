@@ -66,6 +66,7 @@ class CussenStats(ctypes.Structure):
     _fields_ = [("level_mults", ctypes.c_int64), ("level_adds", ctypes.c_int64),
                 ("table_entries", ctypes.c_int64), ("table_adds", ctypes.c_int64),
                 ("accum_adds", ctypes.c_int64), ("max_entries", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64),
                 ("k_split", ctypes.c_int32), ("lanes_per_chain", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("ms_upload", ctypes.c_float), ("ms_table", ctypes.c_float),
@@ -115,6 +116,11 @@ _SIG = {
     "pcmm_plan_stats": ([_VP, _I32, ctypes.POINTER(CussenStats)], _I32),
     "pcmm_plan_run": ([_VP, ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP, ctypes.c_size_t,
                        ctypes.POINTER(_VP), _VP], _I32),
+    "pcmm_plan_resident_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "pcmm_plan_make_resident": ([_VP, _VP, ctypes.c_size_t, _VP], _I32),
+    "pcmm_plan_selected_workspace": ([_VP, ctypes.POINTER(_I32), _I32, ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "pcmm_plan_run_selected": ([_VP, ctypes.POINTER(_I32), _I32, ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP,
+                                ctypes.c_size_t, ctypes.POINTER(_VP), _VP], _I32),
     "pcmm_normalize": ([ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP, ctypes.c_size_t, _VP], _I32),
     "pcmm_normalize_workspace": ([_I64, _I32], ctypes.c_size_t),
     "pcmm_decrypt_to_points": ([_VP, ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP], _I32),
@@ -546,3 +552,32 @@ class Plan:
         for c in C:
             c._keep = (ws,)
         return C
+
+    # resident plans and selected runs (serving)
+    def make_resident(self, stream=None):
+        """Copies the compiled arrays to a device buffer kept by this object."""
+        import torch
+        n = ctypes.c_size_t()
+        _call("pcmm_plan_resident_bytes", self.h, ctypes.byref(n))
+        self.resident = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        _call("pcmm_plan_make_resident", self.h, _tensor_ptr(self.resident), n.value, stream_ptr(stream))
+
+    def selected_workspace_bytes(self, which) -> int:
+        w = (ctypes.c_int32 * len(which))(*which)
+        n = ctypes.c_size_t()
+        _call("pcmm_plan_selected_workspace", self.h, w, len(which), ctypes.byref(n))
+        return n.value
+
+    def run_selected(self, which, B, C, workspace, stage_events=None, stream=None):
+        """Runs problems `which` (repeats allowed) on B[r] -> C[r]; queues and returns."""
+        if len(B) != len(which) or len(C) != len(which):
+            raise ValueError("one B and one C per selected problem")
+        w = (ctypes.c_int32 * len(which))(*which)
+        Bm = (Mat * len(B))(*[b.mat for b in B])
+        Cm = (Mat * len(C))(*[c.mat for c in C])
+        evp = None
+        if stage_events is not None:
+            evp = (ctypes.c_void_p * STAGE_EVENTS)(*[int(e.cuda_event) for e in stage_events])
+        ws_ptr, ws_n = (workspace if isinstance(workspace, tuple)
+                        else (_tensor_ptr(workspace), workspace.numel()))
+        _call("pcmm_plan_run_selected", self.h, w, len(which), Bm, Cm, ws_ptr, ws_n, evp, stream_ptr(stream))

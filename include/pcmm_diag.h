@@ -33,7 +33,11 @@ pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint32_t *b, ui
  * no conversion.  op: 0 a+b, 1 a-b, 2 a*b (Montgomery), 3 a^2, 4 2(a-b),
  * 5 3a, 6 4a, 7 -a, 8 full reduction (value < p), 9 2a, 10 normal form of
  * arbitrary signed limbs a (|limb| < 2^30, 0 <= value < 2^259),
- * 11 equality flag a = b (mod p) in limb 0, 12 zero flag a = 0 (mod p). */
+ * 11 equality flag a = b (mod p) in limb 0, 12 zero flag a = 0 (mod p);
+ * lazy forms (carry-only results: limbs 0..7 < 2^29, the rest in limb 8):
+ * 13 a-b+2p in (0, 4p), 14 4a in [0, 8p), 15 a-3b (mod p, normal form, one
+ * limb pass adding 6p), 16 a-2b (likewise, adding 4p),
+ * 17 (a-b+2p) * 4b with both operands carry-only (normal form). */
 pcmm_status pcmm_diag_field_raw(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
                                 int64_t count, void *stream);
 

@@ -110,25 +110,28 @@ __device__ __forceinline__ jpt fix_equal_operands(bool same, const jpt &R, const
     return R;
 }
 
-// P + Q with Q affine (madd-2007-bl), complete.
+// P + Q with Q affine (madd-2007-bl, 7M + 4S), complete.  Lazy reduction:
+// H (< 4p) and I = 4 H^2 (< 8p) stay carry-only (their products are below
+// 32 p^2), X3 = r^2 - J - 2V and Y3 = r (V - X3) - 2 Y1 J are each one limb
+// pass plus one normalisation, and Z3 = (Z1 + H)^2 - Z1Z1 - HH is computed as
+// the equal 2 Z1 H.
 __device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
     fe z1z1 = fe_sqr(P.Z);
     fe u2 = fe_mul(Q.x, z1z1);
     fe s2 = fe_mul(fe_mul(Q.y, P.Z), z1z1);
-    fe h = fe_sub(u2, P.X);
+    fe h = fe_sub_w(u2, P.X);           // (0, 4p)
     fe hh = fe_sqr(h);
-    fe i4 = fe_mul4(hh);
+    fe i4 = fe_mul4_w(hh);              // [0, 8p)
     fe j = fe_mul(h, i4);
     fe r = fe_sub2(s2, P.Y);
     fe v = fe_mul(P.X, i4);
     jpt R;
-    R.X = fe_sub(fe_sub(fe_sqr(r), j), fe_dbl(v));
-    R.Y = fe_sub(fe_mul(r, fe_sub(v, R.X)), fe_dbl(fe_mul(P.Y, j)));
-    fe zh = fe_add(P.Z, h);
-    R.Z = fe_sub(fe_sub(fe_sqr(zh), z1z1), hh);
+    R.X = fe_sub_sub2(fe_sqr(r), j, v);
+    R.Y = fe_sub2x(fe_mul(r, fe_sub_w(v, R.X)), fe_mul(P.Y, j));
+    R.Z = fe_dbl(fe_mul(P.Z, h));
     bool p_inf = jpt_is_inf(P);
     bool q_inf = apt_is_inf(Q);
-    bool same = fe_is_zero(h) && fe_is_zero(r) && !p_inf && !q_inf;
+    bool same = fe_is_zero(hh) && fe_is_zero(r) && !p_inf && !q_inf;
     R = fix_equal_operands(same, R, P);
     R = jpt_select(p_inf, R, jpt_from_affine(Q));
     R = jpt_select(q_inf, R, P);

@@ -138,6 +138,28 @@ constexpr bool c_check_2p() {
 }
 static_assert(c_check_2p(), "2p limbs");
 
+// K p as radix-2^29 digits: limbs 0..7 < 2^29, limb 8 the rest (exact)
+struct fe29w {
+    int64_t v[NL];
+};
+
+constexpr fe29w c_kp(int K) {
+    fe29w r{};
+    int64_t carry = 0;
+    for (int i = 0; i < NL; ++i) {
+        int64_t t = (int64_t)K * P29.v[i] + carry;
+        if (i < NL - 1) {
+            r.v[i] = t & LMASK;
+            carry = t >> LB;
+        } else {
+            r.v[i] = t;
+        }
+    }
+    return r;
+}
+
+constexpr fe29w KP4 = c_kp(4), KP6 = c_kp(6);
+
 // ---------------------------------------------------------------------------
 // Limb helpers
 // ---------------------------------------------------------------------------
@@ -261,6 +283,50 @@ __device__ __forceinline__ fe fe_mul4(const fe &a) {
 }
 
 __device__ __forceinline__ bool fe_eq(const fe &a, const fe &b) { return fe_is_zero(fe_sub(a, b)); }
+
+// ---------------------------------------------------------------------------
+// Lazy forms.  A carry-only ("weak") result has limbs 0..7 in [0, 2^29) and
+// the rest of the value in limb 8, without the fold below 2p.  fe_mul and
+// fe_sqr accept such operands as long as the product of the operands' bounds
+// is at most 32 p^2 (then a b < p 2^261 and the Montgomery result is again
+// below 2p, in normal form), with limb 8 below 2^27 (column sums stay below
+// 2^63).
+// ---------------------------------------------------------------------------
+// a - b + 2p in (0, 4p) for a, b normal; weak
+__device__ __forceinline__ fe fe_sub_w(const fe &a, const fe &b) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] - b.v[i] + TWO_P29.v[i];
+    fe_carry(x);
+    return x;
+}
+
+// 4a in [0, 8p) for a normal; weak
+__device__ __forceinline__ fe fe_mul4_w(const fe &a) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] << 2;
+    fe_carry(x);
+    return x;
+}
+
+// a - b - 2c (mod p) for a, b, c normal: one limb pass adding the digits of
+// 6p (signed limb sums in (-3 2^29, 2^30), value in (0, 8p)), then
+// normalised
+__device__ __forceinline__ fe fe_sub_sub2(const fe &a, const fe &b, const fe &c) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] - b.v[i] - (c.v[i] << 1) + (uint32_t)KP6.v[i];
+    return fe_norm(x);
+}
+
+// a - 2b (mod p) for a, b normal: adds the digits of 4p, value in (0, 6p)
+__device__ __forceinline__ fe fe_sub2x(const fe &a, const fe &b) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] - (b.v[i] << 1) + (uint32_t)KP4.v[i];
+    return fe_norm(x);
+}
 
 // ---------------------------------------------------------------------------
 // Montgomery multiplication a b 2^-261 mod p (product scanning, the

@@ -122,12 +122,35 @@ __device__ __forceinline__ void reg_store(uint32_t *regs, int rmax, int64_t n_la
     store_jac_m(regs + (int64_t)(r * rmax + reg) * JAC_WORDS * n_lanes, n_lanes, 0, lane, P);
 }
 
-__device__ __forceinline__ apt base_point(const apt Bt[4], int t) {
-    apt r = Bt[0];
-    if (t == 1) r = Bt[1];
-    if (t == 2) r = Bt[2];
-    if (t == 3) r = Bt[3];
-    return r;
+// One op of a group's straight-line program for output column j, point pt
+// and chain r: reads its operands (registers or the group's base points
+// B[k0 + t, j]) and writes its destination register.  Kept out of line so
+// that the kernel holds little state across it (higher occupancy).
+__device__ __noinline__ void run_op(const plan_op op, const uint32_t *__restrict__ B, int64_t ldb, int l, int k0,
+                                    int j, int pt, uint32_t *regs, int rmax, int64_t n_lanes, int r,
+                                    int64_t lane) {
+    jpt R;
+    if (op.kind == OP_MUL) {
+        const int s = op.s;
+        const int bits = 32 - __builtin_clz((unsigned)s);
+        R = ladder_small((uint32_t)s, bits, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
+    } else if (op.a >= 0 && op.b >= 0) {
+        jpt Q = reg_load(regs, rmax, n_lanes, r, op.b, lane);
+        if (op.neg_b) Q = jpt_neg(Q);
+        R = jpt_add(reg_load(regs, rmax, n_lanes, r, op.a, lane), Q);
+    } else if (op.b < 0) {
+        apt Q = load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.b) * l + j);
+        if (op.neg_b) Q = apt_neg(Q);
+        jpt P = op.a >= 0 ? reg_load(regs, rmax, n_lanes, r, op.a, lane)
+                          : jpt_from_affine(load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
+        R = jpt_add_affine(P, Q);
+    } else {
+        // a is a base point, b a register: a + (+-b) = (+-b) + a
+        jpt Q = reg_load(regs, rmax, n_lanes, r, op.b, lane);
+        if (op.neg_b) Q = jpt_neg(Q);
+        R = jpt_add_affine(Q, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
+    }
+    reg_store(regs, rmax, n_lanes, r, op.dst, lane, R);
 }
 
 __global__ void __launch_bounds__(256) table_build_kernel(run_args a) {
@@ -154,7 +177,6 @@ __global__ void __launch_bounds__(256) table_build_kernel(run_args a) {
     const int jslot = rem >> 1;
     const int pt = rem & 1;
     const int k0 = grp * d.g;
-    const int gg = min(d.g, d.n - k0);
     const int ob = op_begin[grp], oe = op_begin[grp + 1];
     const int eb = entry_begin[grp], ee = entry_begin[grp + 1];
     const int E = ee - eb;
@@ -165,39 +187,7 @@ __global__ void __launch_bounds__(256) table_build_kernel(run_args a) {
         const int j = jslot + r * d.Lj;
         if (j >= l) break;
         last_r = r;
-        apt Bt[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (t < gg) Bt[t] = load_affine(B, ldb, pt, (int64_t)(k0 + t) * l + j);
-            else Bt[t] = Bt[0];
-        }
-        for (int o = ob; o < oe; ++o) {
-            const plan_op op = ops[o];
-            jpt R;
-            if (op.kind == OP_MUL) {
-                int s = op.s;
-                int bits = 32 - __builtin_clz((unsigned)s);
-                R = ladder_small((uint32_t)s, bits, base_point(Bt, -1 - op.a));
-            } else {
-                if (op.a >= 0 && op.b >= 0) {
-                    jpt Q = reg_load(regs, rmax, n_lanes, r, op.b, lane);
-                    if (op.neg_b) Q = jpt_neg(Q);
-                    R = jpt_add(reg_load(regs, rmax, n_lanes, r, op.a, lane), Q);
-                } else if (op.b < 0) {
-                    apt Q = base_point(Bt, -1 - op.b);
-                    if (op.neg_b) Q = apt_neg(Q);
-                    jpt P = op.a >= 0 ? reg_load(regs, rmax, n_lanes, r, op.a, lane)
-                                      : jpt_from_affine(base_point(Bt, -1 - op.a));
-                    R = jpt_add_affine(P, Q);
-                } else {
-                    // a is a base point, b a register: a + (+-b) = (+-b) + a
-                    jpt Q = reg_load(regs, rmax, n_lanes, r, op.b, lane);
-                    if (op.neg_b) Q = jpt_neg(Q);
-                    R = jpt_add_affine(Q, base_point(Bt, -1 - op.a));
-                }
-            }
-            reg_store(regs, rmax, n_lanes, r, op.dst, lane, R);
-        }
+        for (int o = ob; o < oe; ++o) run_op(ops[o], B, ldb, l, k0, j, pt, regs, rmax, n_lanes, r, lane);
         // forward pass of the batched inversion over this table's register entries
         const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
         for (int e = 0; e < E; ++e) {

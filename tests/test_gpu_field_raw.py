@@ -57,11 +57,11 @@ def _operands(n, seed):
     return a, b
 
 
-def _check_normal(out):
+def _check_normal(out, bound=2 * P, top_bits=25):
     assert (out[:, :8] < (1 << LB)).all()
-    assert (out[:, 8] < (1 << 25)).all()
+    assert (out[:, 8] < (1 << top_bits)).all()
     for row in out:
-        assert value(row) < 2 * P
+        assert value(row) < bound
 
 
 def test_raw_field_ops_vs_integers(dev):
@@ -82,6 +82,19 @@ def test_raw_field_ops_vs_integers(dev):
     for op, f in cases.items():
         out = dev.diag_field_raw(op, A, B)
         _check_normal(out)
+        bad = [i for i in range(len(a)) if value(out[i]) % P != f(a[i], b[i])]
+        assert not bad, (op, bad[:5], [(hex(a[i]), hex(b[i])) for i in bad[:3]])
+    # lazy (carry-only) forms and the operations that consume them
+    lazy = {
+        13: (lambda x, y: (x - y) % P, 4 * P, 26),
+        14: (lambda x, y: (4 * x) % P, 8 * P, 27),
+        15: (lambda x, y: (x - 3 * y) % P, 2 * P, 25),
+        16: (lambda x, y: (x - 2 * y) % P, 2 * P, 25),
+        17: (lambda x, y: ((x - y) * 4 * y * RINV) % P, 2 * P, 25),
+    }
+    for op, (f, bound, top) in lazy.items():
+        out = dev.diag_field_raw(op, A, B)
+        _check_normal(out, bound, top)
         bad = [i for i in range(len(a)) if value(out[i]) % P != f(a[i], b[i])]
         assert not bad, (op, bad[:5], [(hex(a[i]), hex(b[i])) for i in bad[:3]])
     out = dev.diag_field_raw(8, A, B)  # full reduction

@@ -81,21 +81,21 @@ __device__ __forceinline__ jpt jpt_neg(const jpt &P) {
     return r;
 }
 
-// 2P, a = -3 (dbl-2001-b).  Z = 0 stays Z = 0.
+// 2P, a = -3 (dbl-2001-b).  Z = 0 stays Z = 0.  Lazy reduction as in
+// jpt_add_affine: X1 -+ delta stay carry-only (their product is below
+// 16 p^2), X3 = alpha^2 - 8 beta and Y3 = alpha (4 beta - X3) - 8 gamma^2 are
+// one limb pass plus one normalisation each, and Z3 = (Y1 + Z1)^2 - gamma -
+// delta is computed as the equal 2 Y1 Z1.
 __device__ __forceinline__ jpt jpt_dbl(const jpt &P) {
     fe delta = fe_sqr(P.Z);
     fe gamma = fe_sqr(P.Y);
     fe beta = fe_mul(P.X, gamma);
-    fe t0 = fe_sub(P.X, delta);
-    fe t1 = fe_add(P.X, delta);
-    fe alpha = fe_mul3(fe_mul(t0, t1));               // 3 (X - delta)(X + delta)
+    fe alpha = fe_mul3(fe_mul(fe_sub_w(P.X, delta), fe_add_w(P.X, delta)));  // 3 (X - delta)(X + delta)
     jpt R;
     fe beta4 = fe_mul4(beta);
-    R.X = fe_sub(fe_sqr(alpha), fe_dbl(beta4));       // alpha^2 - 8 beta
-    fe yz = fe_add(P.Y, P.Z);
-    R.Z = fe_sub(fe_sub(fe_sqr(yz), gamma), delta);   // (Y + Z)^2 - gamma - delta
-    fe g8 = fe_dbl(fe_mul4(fe_sqr(gamma)));
-    R.Y = fe_sub(fe_mul(alpha, fe_sub(beta4, R.X)), g8);
+    R.X = fe_sub2x(fe_sqr(alpha), beta4);
+    R.Z = fe_dbl(fe_mul(P.Y, P.Z));
+    R.Y = fe_sub2x(fe_mul(alpha, fe_sub_w(beta4, R.X)), fe_mul4(fe_sqr(gamma)));
     return R;
 }
 
@@ -138,7 +138,9 @@ __device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
     return R;
 }
 
-// P + Q, both Jacobian (add-2007-bl), complete.
+// P + Q, both Jacobian (add-2007-bl), complete.  Lazy reduction as in
+// jpt_add_affine; I = (2H)^2 is computed as 4 H^2 and Z3 =
+// ((Z1 + Z2)^2 - Z1Z1 - Z2Z2) H as the equal 2 Z1 Z2 H.
 __device__ __forceinline__ jpt jpt_add(const jpt &P, const jpt &Q) {
     fe z1z1 = fe_sqr(P.Z);
     fe z2z2 = fe_sqr(Q.Z);
@@ -146,20 +148,19 @@ __device__ __forceinline__ jpt jpt_add(const jpt &P, const jpt &Q) {
     fe u2 = fe_mul(Q.X, z1z1);
     fe s1 = fe_mul(fe_mul(P.Y, Q.Z), z2z2);
     fe s2 = fe_mul(fe_mul(Q.Y, P.Z), z1z1);
-    fe h = fe_sub(u2, u1);
-    fe h2 = fe_dbl(h);
-    fe i = fe_sqr(h2);
+    fe h = fe_sub_w(u2, u1);           // (0, 4p)
+    fe hh = fe_sqr(h);
+    fe i = fe_mul4_w(hh);              // [0, 8p)
     fe j = fe_mul(h, i);
     fe r = fe_sub2(s2, s1);
     fe v = fe_mul(u1, i);
     jpt R;
-    R.X = fe_sub(fe_sub(fe_sqr(r), j), fe_dbl(v));
-    R.Y = fe_sub(fe_mul(r, fe_sub(v, R.X)), fe_dbl(fe_mul(s1, j)));
-    fe zz = fe_add(P.Z, Q.Z);
-    R.Z = fe_mul(fe_sub(fe_sub(fe_sqr(zz), z1z1), z2z2), h);
+    R.X = fe_sub_sub2(fe_sqr(r), j, v);
+    R.Y = fe_sub2x(fe_mul(r, fe_sub_w(v, R.X)), fe_mul(s1, j));
+    R.Z = fe_dbl(fe_mul(fe_mul(P.Z, Q.Z), h));
     bool p_inf = jpt_is_inf(P);
     bool q_inf = jpt_is_inf(Q);
-    bool same = fe_is_zero(h) && fe_is_zero(r) && !p_inf && !q_inf;
+    bool same = fe_is_zero(hh) && fe_is_zero(r) && !p_inf && !q_inf;
     R = fix_equal_operands(same, R, P);
     R = jpt_select(p_inf, R, Q);
     R = jpt_select(q_inf, R, P);

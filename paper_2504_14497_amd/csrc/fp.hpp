@@ -301,6 +301,15 @@ __device__ __forceinline__ fe fe_sub_w(const fe &a, const fe &b) {
     return x;
 }
 
+// a + b in [0, 4p) for a, b normal; weak
+__device__ __forceinline__ fe fe_add_w(const fe &a, const fe &b) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] + b.v[i];
+    fe_carry(x);
+    return x;
+}
+
 // 4a in [0, 8p) for a normal; weak
 __device__ __forceinline__ fe fe_mul4_w(const fe &a) {
     fe x;

@@ -153,7 +153,9 @@ __device__ __noinline__ void run_op(const plan_op op, const uint32_t *__restrict
     reg_store(regs, rmax, n_lanes, r, op.dst, lane, R);
 }
 
-__global__ void __launch_bounds__(256) table_build_kernel(run_args a) {
+// Two wavefronts per SIMD (<= 256 VGPRs): the kernel waits on its register
+// scratch in HBM, and a second wavefront hides much of that latency.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) table_build_kernel(run_args a) {
     // the accumulation that follows on the stream starts its queue at zero
     if (blockIdx.x == 0 && threadIdx.x == 0) *at<int32_t>(a, a.ctr_off) = 0;
     const int b = find_problem(a, offsetof(prob_desc, tb_block0), blockIdx.x);
@@ -330,22 +332,34 @@ __global__ void __launch_bounds__(256) accumulate_kernel(run_args a) {
     }
 }
 
-// sum of S (power of two <= 64) partial sums per output point; lanes s of one
-// output are consecutive, and a problem's threads start at a block boundary
+// Sum of the S (power of two <= 64) split-k partial sums of each output
+// point.  An output's partials are spread over RL = min(S, 8) consecutive
+// lanes; lane q adds partials q, q + RL, ... sequentially (every addition is
+// useful), then the RL lanes combine by a shuffle tree of log2(RL) levels.
+// A problem's threads start at a block boundary and RL divides 64, so the
+// lanes of one output are in one wavefront.
+constexpr int REDUCE_LANES = 8;
+
 __global__ void __launch_bounds__(256) reduce_kernel(run_args a) {
     const int b = find_problem(a, offsetof(prob_desc, red_block0), blockIdx.x);
     const prob_desc &d = descs(a)[b];
     const int64_t t = ((int64_t)blockIdx.x - d.red_block0) * blockDim.x + threadIdx.x;
     const int S = d.S;
+    const int RL = S < REDUCE_LANES ? S : REDUCE_LANES;
     const int64_t n_out = (int64_t)d.m * d.l;
-    const int s = (int)(t % S);
-    const int64_t rest = t / S;  // (e, pt) pairs, pt fastest
+    const int q = (int)(t % RL);
+    const int64_t rest = t / RL;  // (e, pt) pairs, pt fastest
     const bool valid = rest < 2 * n_out;
     const int64_t e = valid ? rest >> 1 : 0;
     const int pt = (int)(rest & 1);
     const uint32_t *part = at<const uint32_t>(a, d.w_part);
-    jpt P = valid ? load_jac_m(part + (int64_t)s * JAC2_PLANES * d.ldj, d.ldj, pt, e) : jpt_infinity();
-    for (int off = S >> 1; off >= 1; off >>= 1) {
+    jpt P = jpt_infinity();
+    if (valid) {
+        P = load_jac_m(part + (int64_t)q * JAC2_PLANES * d.ldj, d.ldj, pt, e);
+        for (int s = q + RL; s < S; s += RL)
+            P = jpt_add(P, load_jac_m(part + (int64_t)s * JAC2_PLANES * d.ldj, d.ldj, pt, e));
+    }
+    for (int off = RL >> 1; off >= 1; off >>= 1) {
         jpt Q;
 #pragma unroll
         for (int w = 0; w < NL; ++w) {
@@ -354,9 +368,9 @@ __global__ void __launch_bounds__(256) reduce_kernel(run_args a) {
             Q.Z.v[w] = __shfl_down(P.Z.v[w], off, 64);
         }
         jpt R = jpt_add(P, Q);
-        if (s < off) P = R;
+        if (q < off) P = R;
     }
-    if (valid && s == 0) {
+    if (valid && q == 0) {
         if (d.c_form == PCMM_AFFINE) store_jac_m(at<uint32_t>(a, d.w_cjac), d.ldj, pt, e, P);
         else store_jac(a.io[d.io].C, a.io[d.io].ldc, pt, e, P);
     }
@@ -699,7 +713,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         d.tile0 = tiles;
         tiles += (int64_t)G.tiles_x * G.tiles_y * G.S;
         d.red_block0 = red;
-        d.red_threads = G.S > 1 ? (2 * (int64_t)G.P.m * G.l * G.S + 255) / 256 * 256 : 0;
+        d.red_threads = G.S > 1 ? (2 * (int64_t)G.P.m * G.l * std::min(G.S, REDUCE_LANES) + 255) / 256 * 256 : 0;
         red += d.red_threads / 256;
         d.norm_block0 = norm;
         d.norm_threads = G.norm_threads;

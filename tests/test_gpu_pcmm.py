@@ -93,6 +93,23 @@ def test_cussen_configurations_vs_oracle(dev, orc, group, rounds):
         assert (C.to_host() == ref).all()
 
 
+@pytest.mark.parametrize("split", [8, 16, 64])
+def test_deep_split_k_vs_oracle(dev, orc, split):
+    """Split-k with several partial sums per reduction lane (the reduction
+    adds partials sequentially before its shuffle tree), more splits than
+    column groups on some of them, signed codes."""
+    rng = np.random.default_rng(split)
+    B = random_cts(orc, 70, 3, 210)
+    A = rng.integers(-8, 8, size=(9, 70)).astype(np.int8)
+    ref = orc.pcmm_cussen(A, B)
+    Bd = _upload(dev, B)
+    for group in (1, 2):
+        log("split", split, "group", group)
+        C, st = dev.cussen(A, 4, Bd, cfg=dev.CussenCfg(4, group, split, 0))
+        assert st["k_split"] == split
+        assert (C.to_host() == ref).all(), (split, group)
+
+
 def test_exceptional_cases_vs_oracle(dev, orc):
     # equal ciphertexts down a column (accumulator meets P = Q, tables meet
     # P = Q through repeated differences) and opposite ones (P = -Q)

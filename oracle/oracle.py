@@ -48,11 +48,11 @@ def lib():
                                         vp]
         L.oracle_alg2_point.argtypes = [vp, ctypes.c_int, ctypes.c_int, u8p, vp]
         L.oracle_pcmm_schoolbook.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                             ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int]
+                                             vp, vp, vp, ctypes.c_int, ctypes.c_int]
         L.oracle_pcmm_cussen.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int]
+                                         vp, vp, vp, ctypes.c_int, ctypes.c_int]
         L.oracle_pcmm_closed_form.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                              ctypes.c_int, u8p, vp, ctypes.c_uint64, vp, vp,
+                                              u8p, vp, ctypes.c_uint64, vp, vp,
                                               ctypes.c_int, vp, ctypes.c_int]
         _lib = L
     return _lib
@@ -232,25 +232,29 @@ def alg2_point(a, N: int, P: bytes) -> np.ndarray:
 
 # ---------------------------------------------------------------- PC-MM
 
+def _plain(A):
+    """A as int32 values (the oracle takes the plaintexts themselves)."""
+    A = np.asarray(A)
+    if A.dtype not in (np.int8, np.uint8, np.int16, np.uint16, np.int32):
+        raise TypeError("A must be an integer matrix")
+    return np.ascontiguousarray(A, dtype=np.int32)
+
+
 def _mm_args(A, B, cols):
-    A = np.ascontiguousarray(A)
-    is_signed = 1 if A.dtype == np.int8 else 0
-    if A.dtype not in (np.int8, np.uint8):
-        raise TypeError("A must be int8 (signed) or uint8 (unsigned)")
-    A8 = A.view(np.int8)
+    A32 = _plain(A)
     B = np.ascontiguousarray(B, dtype=np.uint8)
-    m, n = A.shape
+    m, n = A32.shape
     n2, l, w = B.shape
     if n2 != n or w != 128:
         raise ValueError("shape mismatch")
     colarr = None if cols is None else np.ascontiguousarray(np.asarray(cols, dtype=np.int32))
-    return A8, is_signed, m, n, l, B, colarr
+    return A32, m, n, l, B, colarr
 
 
 def pcmm_schoolbook(A, B, cols=None, nthreads=None, out=None) -> np.ndarray:
-    A8, s, m, n, l, B, colarr = _mm_args(A, B, cols)
+    A32, m, n, l, B, colarr = _mm_args(A, B, cols)
     C = out if out is not None else np.zeros((m, l, 128), dtype=np.uint8)
-    _check(lib().oracle_pcmm_schoolbook(_ptr(A8), s, m, n, l, _ptr(B), _ptr(C),
+    _check(lib().oracle_pcmm_schoolbook(_ptr(A32), m, n, l, _ptr(B), _ptr(C),
                                         None if colarr is None else _ptr(colarr),
                                         -1 if colarr is None else colarr.size,
                                         nthreads or default_threads()), "schoolbook")
@@ -258,9 +262,9 @@ def pcmm_schoolbook(A, B, cols=None, nthreads=None, out=None) -> np.ndarray:
 
 
 def pcmm_cussen(A, B, N: int = 4, cols=None, nthreads=None, out=None) -> np.ndarray:
-    A8, s, m, n, l, B, colarr = _mm_args(A, B, cols)
+    A32, m, n, l, B, colarr = _mm_args(A, B, cols)
     C = out if out is not None else np.zeros((m, l, 128), dtype=np.uint8)
-    _check(lib().oracle_pcmm_cussen(_ptr(A8), s, m, n, l, N, _ptr(B), _ptr(C),
+    _check(lib().oracle_pcmm_cussen(_ptr(A32), m, n, l, N, _ptr(B), _ptr(C),
                                     None if colarr is None else _ptr(colarr),
                                     -1 if colarr is None else colarr.size,
                                     nthreads or default_threads()), "cussen")
@@ -268,17 +272,15 @@ def pcmm_cussen(A, B, N: int = 4, cols=None, nthreads=None, out=None) -> np.ndar
 
 
 def pcmm_closed_form(A, l: int, sk: int, msg, seed: int, ii, jj, nthreads=None) -> np.ndarray:
-    A = np.ascontiguousarray(A)
-    is_signed = 1 if A.dtype == np.int8 else 0
-    A8 = A.view(np.int8)
-    m, n = A.shape
+    A32 = _plain(A)
+    m, n = A32.shape
     msg = np.ascontiguousarray(np.asarray(msg, dtype=np.int32))
     if msg.shape != (n, l):
         raise ValueError("msg must be n x l")
     ii = np.ascontiguousarray(np.asarray(ii, dtype=np.int32))
     jj = np.ascontiguousarray(np.asarray(jj, dtype=np.int32))
     out = np.zeros((ii.size, 128), dtype=np.uint8)
-    _check(lib().oracle_pcmm_closed_form(_ptr(A8), is_signed, m, n, l, _b32(sk), _ptr(msg), seed,
+    _check(lib().oracle_pcmm_closed_form(_ptr(A32), m, n, l, _b32(sk), _ptr(msg), seed,
                                          _ptr(ii), _ptr(jj), ii.size, _ptr(out),
                                          nthreads or default_threads()), "closed_form")
     return out

@@ -828,13 +828,12 @@ int oracle_alg2_point(const int64_t *a, int n, int N, const uint8_t Pb[64], uint
 /* Exported: PC-MM                                                           */
 /* ------------------------------------------------------------------------ */
 
-static int64_t a_at(const int8_t *A, int is_signed, int64_t idx) {
-    return is_signed ? (int64_t)A[idx] : (int64_t)(uint8_t)A[idx];
-}
+/* A holds the plaintext values themselves (int32), row-major m x n */
+static int64_t a_at(const int32_t *A, int64_t idx) { return (int64_t)A[idx]; }
 
 typedef struct {
-    const int8_t *A;
-    int is_signed, m, n, l, N;
+    const int32_t *A;
+    int m, n, l, N;
     const uint8_t *B;
     uint8_t *C;
     const int32_t *cols;
@@ -852,7 +851,7 @@ static void school_item(void *vctx, int64_t item) {
             apt acc = pt_infinity();
             for (int k = 0; k < c->n; ++k) {
                 apt Bk = pt_from_bytes(c->B + ((int64_t)k * c->l + j) * 128 + pt * 64);
-                apt term = smul_signed(a_at(c->A, c->is_signed, (int64_t)i * c->n + k), &Bk);
+                apt term = smul_signed(a_at(c->A, (int64_t)i * c->n + k), &Bk);
                 acc = pt_add(&acc, &term);
             }
             pt_to_bytes(c->C + ((int64_t)i * c->l + j) * 128 + pt * 64, &acc);
@@ -875,7 +874,7 @@ static void cussen_item(void *vctx, int64_t item) {
             alg2_reconstruct_point(&c->plans[k], &Bk, col); /* |a_ik| B_kj */
             for (int i = 0; i < m; ++i) {
                 apt term = col[i];
-                if (a_at(c->A, c->is_signed, (int64_t)i * c->n + k) < 0) term = pt_neg(&term);
+                if (a_at(c->A, (int64_t)i * c->n + k) < 0) term = pt_neg(&term);
                 acc[2 * i + pt] = pt_add(&acc[2 * i + pt], &term);
             }
         }
@@ -894,17 +893,17 @@ static int mm_check(int m, int n, int l, const int32_t *cols, int ncols) {
     return 0;
 }
 
-int oracle_pcmm_schoolbook(const int8_t *A, int is_signed, int m, int n, int l,
+int oracle_pcmm_schoolbook(const int32_t *A, int m, int n, int l,
                            const uint8_t *B, uint8_t *C, const int32_t *cols, int ncols,
                            int nthreads) {
     params();
     if (mm_check(m, n, l, cols, ncols)) return -1;
-    mm_ctx c = {A, is_signed, m, n, l, 0, B, C, ncols >= 0 ? cols : NULL, NULL};
+    mm_ctx c = {A, m, n, l, 0, B, C, ncols >= 0 ? cols : NULL, NULL};
     run_parallel(school_item, &c, ncols >= 0 ? ncols : l, nthreads);
     return 0;
 }
 
-int oracle_pcmm_cussen(const int8_t *A, int is_signed, int m, int n, int l, int N,
+int oracle_pcmm_cussen(const int32_t *A, int m, int n, int l, int N,
                        const uint8_t *B, uint8_t *C, const int32_t *cols, int ncols,
                        int nthreads) {
     params();
@@ -914,13 +913,13 @@ int oracle_pcmm_cussen(const int8_t *A, int is_signed, int m, int n, int l, int 
     int64_t *colv = (int64_t *)malloc(sizeof(int64_t) * (m > 0 ? m : 1));
     for (int k = 0; k < n; ++k) {
         for (int i = 0; i < m; ++i) {
-            int64_t a = a_at(A, is_signed, (int64_t)i * n + k);
+            int64_t a = a_at(A, (int64_t)i * n + k);
             colv[i] = a < 0 ? -a : a;
         }
         alg2_compress(&plans[k], colv, m, N);
     }
     free(colv);
-    mm_ctx c = {A, is_signed, m, n, l, N, B, C, ncols >= 0 ? cols : NULL, plans};
+    mm_ctx c = {A, m, n, l, N, B, C, ncols >= 0 ? cols : NULL, plans};
     run_parallel(cussen_item, &c, ncols >= 0 ? ncols : l, nthreads);
     for (int k = 0; k < n; ++k) alg2_free(&plans[k]);
     free(plans);
@@ -928,8 +927,8 @@ int oracle_pcmm_cussen(const int8_t *A, int is_signed, int m, int n, int l, int 
 }
 
 typedef struct {
-    const int8_t *A;
-    int is_signed, m, n, l;
+    const int32_t *A;
+    int m, n, l;
     u256 x;
     const int32_t *msg;
     uint64_t seed;
@@ -942,7 +941,7 @@ static void cf_item(void *vctx, int64_t p) {
     int i = c->ii[p], j = c->jj[p];
     u256 e1 = {{0, 0, 0, 0}}, e2 = {{0, 0, 0, 0}}, t, u;
     for (int k = 0; k < c->n; ++k) {
-        u256 a = scalar_from_int(a_at(c->A, c->is_signed, (int64_t)i * c->n + k));
+        u256 a = scalar_from_int(a_at(c->A, (int64_t)i * c->n + k));
         u256 r = scalar_from_seed(c->seed, 1, (uint64_t)k * (uint64_t)c->l + (uint64_t)j);
         u256 mk = scalar_from_int(c->msg[(int64_t)k * c->l + j]);
         mod_mul(&t, &a, &r, &FQ);
@@ -959,7 +958,7 @@ static void cf_item(void *vctx, int64_t p) {
     pt_to_bytes(c->out + p * 128 + 64, &C2);
 }
 
-int oracle_pcmm_closed_form(const int8_t *A, int is_signed, int m, int n, int l,
+int oracle_pcmm_closed_form(const int32_t *A, int m, int n, int l,
                             const uint8_t sk[32], const int32_t *msg, uint64_t seed,
                             const int32_t *ii, const int32_t *jj, int npos, uint8_t *out,
                             int nthreads) {
@@ -969,7 +968,6 @@ int oracle_pcmm_closed_form(const int8_t *A, int is_signed, int m, int n, int l,
         if (ii[p] < 0 || ii[p] >= m || jj[p] < 0 || jj[p] >= l) return -1;
     cf_ctx c;
     c.A = A;
-    c.is_signed = is_signed;
     c.m = m;
     c.n = n;
     c.l = l;

@@ -76,15 +76,15 @@ int oracle_alg2_plain(const int64_t *a, int n, int N, int64_t Cs, int64_t *out,
 /* Alg. 2 with a ciphertext point as the scalar: out[i] = a_i P (n points). */
 int oracle_alg2_point(const int64_t *a, int n, int N, const uint8_t P[64], uint8_t *out);
 
-/* PC-MM.  A: m x n int8 row-major (signed if is_signed, else unsigned in
- * 0..255 read from the same bytes).  B: n x l ciphertexts row-major
+/* PC-MM.  A: m x n row-major plaintext values (int32; any sign and size).
+ * B: n x l ciphertexts row-major
  * (128 bytes each).  C: m x l ciphertexts row-major.  Only the output columns
  * listed in cols[0..ncols) are computed (ncols < 0: all columns); other
  * columns of C are left untouched. */
-int oracle_pcmm_schoolbook(const int8_t *A, int is_signed, int m, int n, int l,
+int oracle_pcmm_schoolbook(const int32_t *A, int m, int n, int l,
                            const uint8_t *B, uint8_t *C, const int32_t *cols, int ncols,
                            int nthreads);
-int oracle_pcmm_cussen(const int8_t *A, int is_signed, int m, int n, int l, int N,
+int oracle_pcmm_cussen(const int32_t *A, int m, int n, int l, int N,
                        const uint8_t *B, uint8_t *C, const int32_t *cols, int ncols,
                        int nthreads);
 
@@ -92,7 +92,7 @@ int oracle_pcmm_cussen(const int8_t *A, int is_signed, int m, int n, int l, int 
  * e1 = sum_k a_ik r_kj, e2 = sum_k a_ik (x r_kj + msg_kj)  (mod q),
  * C_ij = (e1 G, e2 G).  Nonces r_kj = scalar(seed, 1, k*l + j).
  * ii/jj: npos positions; out: npos ciphertexts. */
-int oracle_pcmm_closed_form(const int8_t *A, int is_signed, int m, int n, int l,
+int oracle_pcmm_closed_form(const int32_t *A, int m, int n, int l,
                             const uint8_t sk[32], const int32_t *msg, uint64_t seed,
                             const int32_t *ii, const int32_t *jj, int npos, uint8_t *out,
                             int nthreads);

@@ -52,13 +52,15 @@ def rng_for(seed: int) -> np.random.Generator:
 
 def gen_plain_matrix(rng: np.random.Generator, rows: int, cols: int, bits: int,
                      signed: bool) -> np.ndarray:
-    """Uniform t-bit plaintext matrix: int8 when signed, uint8 otherwise."""
-    if not (1 <= bits <= 8):
-        raise ValueError("bits must be in 1..8")
+    """Uniform t-bit plaintext matrix: int8 / uint8 for t <= 8, int16 / uint16
+    for 9 <= t <= 16 (signed: [-2^(t-1), 2^(t-1)), unsigned: [0, 2^t))."""
+    if not (1 <= bits <= 16):
+        raise ValueError("bits must be in 1..16")
+    wide = bits > 8
     if signed:
         lo, hi = -(1 << (bits - 1)), (1 << (bits - 1))
-        return rng.integers(lo, hi, size=(rows, cols), dtype=np.int64).astype(np.int8)
-    return rng.integers(0, 1 << bits, size=(rows, cols), dtype=np.int64).astype(np.uint8)
+        return rng.integers(lo, hi, size=(rows, cols), dtype=np.int64).astype(np.int16 if wide else np.int8)
+    return rng.integers(0, 1 << bits, size=(rows, cols), dtype=np.int64).astype(np.uint16 if wide else np.uint8)
 
 
 def gen_messages(rng: np.random.Generator, rows: int, cols: int, bits: int) -> np.ndarray:

@@ -158,6 +158,28 @@ def test_closed_form_and_decryption(orc, signed):
         assert not (orc.pcmm_cussen(np.ascontiguousarray(A.T), B) == C_c).all()
 
 
+@pytest.mark.parametrize("bits,signed", [(12, True), (16, False), (16, True)])
+def test_wide_plaintexts_closed_form_and_decryption(orc, bits, signed):
+    """t up to 16 (Tab. A1/A2 and the vector experiments use t in 4..16):
+    schoolbook = Cussen = the closed form, and decryption gives (A.B) G."""
+    shape = W.PCMMShape(4, 5, 2, bits, signed, 8, seed=40 + bits + signed)
+    A, msg = W.make_inputs(shape)
+    assert A.dtype == (np.int16 if signed else np.uint16)
+    sk, pk = orc.keygen(shape.seed)
+    B = orc.encrypt(pk, msg, shape.seed)
+    C_c = orc.pcmm_cussen(A, B)
+    assert (orc.pcmm_schoolbook(A, B) == C_c).all()
+    ii, jj = np.meshgrid(np.arange(shape.m), np.arange(shape.l), indexing="ij")
+    C_f = orc.pcmm_closed_form(A, shape.l, sk, msg, shape.seed, ii.ravel(), jj.ravel())
+    assert (C_f.reshape(C_c.shape) == C_c).all()
+    AB = A.astype(np.int64) @ msg.astype(np.int64)
+    pts = orc.decrypt_to_points(sk, C_c)
+    p, b, gx, gy, q = orc.curve_params()
+    G = orc.generator()
+    for (i, j), v in np.ndenumerate(AB):
+        assert _pt(pts[i, j]) == orc.ladder_big(int(v) % q, G)
+
+
 def test_schoolbook_equals_cussen_every_round_count(orc):
     rnd = random.Random(31)
     rng = np.random.default_rng(31)

@@ -36,12 +36,14 @@
  *               limb `w` of coordinate `c` of point `pt` at
  *                 d[((pt * form + c) * 8 + w) * ld + e]
  *               so each limb plane is contiguous over elements (coalesced).
- *   Ints        plaintext matrices A are host arrays, row-major int8 (signed)
- *               or uint8 (unsigned, same bytes read as 0..255); `bits` is the
- *               declared bit-width t (1..8): entries must satisfy
- *               0 <= a < 2^t (unsigned) or -2^(t-1) <= a < 2^(t-1) (signed),
- *               else PCMM_ERANGE.  Keeping n max|a| max|b| below the message
- *               bound of the decryptor (Sec. 2.4) is the caller's duty.
+ *   Ints        plaintext matrices A are host arrays, row-major, whose element
+ *               width follows the declared bit-width t = `bits` (1..16):
+ *               int8 (signed) / uint8 (unsigned) for t <= 8, int16 / uint16
+ *               for 9 <= t <= 16.  Entries must satisfy 0 <= a < 2^t
+ *               (unsigned) or -2^(t-1) <= a < 2^(t-1) (signed), else
+ *               PCMM_ERANGE.  Cussen column groups of g > 3 need t <= 8.
+ *               Keeping n max|a| max|b| below the message bound of the
+ *               decryptor (Sec. 2.4) is the caller's duty.
  * ------------------------------------------------------------------------
  */
 #ifndef PCMM_H
@@ -162,7 +164,7 @@ size_t pcmm_encrypt_workspace(void);
  * ciphertexts, affine.  C: device m x l ciphertexts, PCMM_JACOBIAN (write-only;
  * run pcmm_normalize for canonical affine bytes) or PCMM_AFFINE (normalised
  * here through `workspace`).  workspace: pcmm_schoolbook_workspace() bytes. */
-pcmm_status pcmm_schoolbook(const int8_t *A, int32_t m, int32_t n, int32_t bits,
+pcmm_status pcmm_schoolbook(const void *A, int32_t m, int32_t n, int32_t bits,
                             int32_t is_signed, const pcmm_mat *B, pcmm_mat *C,
                             void *workspace, size_t ws_bytes, void *stream);
 size_t pcmm_schoolbook_workspace(int32_t m, int32_t n, int32_t l, int32_t c_form);
@@ -174,11 +176,11 @@ size_t pcmm_schoolbook_workspace(int32_t m, int32_t n, int32_t l, int32_t c_form
  * pcmm_schoolbook plus cfg (NULL = defaults) and a workspace of
  * pcmm_cussen_workspace() bytes (plan, tables, partial sums).  stats may be
  * NULL; when given it receives the plan's operation counts. */
-pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
+pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
                         const pcmm_mat *B, pcmm_mat *C, const pcmm_cussen_cfg *cfg,
                         void *workspace, size_t ws_bytes, pcmm_cussen_stats *stats,
                         void *stream);
-pcmm_status pcmm_cussen_workspace(const int8_t *A, int32_t m, int32_t n, int32_t l, int32_t bits,
+pcmm_status pcmm_cussen_workspace(const void *A, int32_t m, int32_t n, int32_t l, int32_t bits,
                                   int32_t is_signed, int32_t c_form, const pcmm_cussen_cfg *cfg,
                                   size_t *bytes);
 
@@ -197,7 +199,7 @@ pcmm_status pcmm_cussen_workspace(const int8_t *A, int32_t m, int32_t n, int32_t
 typedef struct pcmm_plan_s *pcmm_plan;
 
 typedef struct {
-    const int8_t *A;     /* host, m x n row-major, read only during pcmm_plan_create */
+    const void *A;       /* host, m x n row-major (see PC-MM plaintexts), read only during pcmm_plan_create */
     int32_t m, n, l;     /* C = A B with B n x l                                     */
     int32_t bits, is_signed;
     int32_t c_form;      /* PCMM_AFFINE (canonical, normalised) or PCMM_JACOBIAN     */
@@ -247,7 +249,7 @@ pcmm_status pcmm_plan_run_selected(pcmm_plan plan, const int32_t *which, int32_t
                                    void *stream);
 
 /* Host-only: the compression plan's operation counts for A (no GPU work). */
-pcmm_status pcmm_cussen_plan_stats(const int8_t *A, int32_t m, int32_t n, int32_t bits,
+pcmm_status pcmm_cussen_plan_stats(const void *A, int32_t m, int32_t n, int32_t bits,
                                    int32_t is_signed, const pcmm_cussen_cfg *cfg,
                                    pcmm_cussen_stats *stats);
 

@@ -423,7 +423,7 @@ std::mutex g_tune_lock;
 std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;  // (m, n, bits, signed, N) -> g
 
 // Builds the plan for cfg's group, or for the autotuned one.
-int build_plan_cfg(const int8_t *A, int m, int n, int bits, bool sgn, const pcmm_cussen_cfg *cfg,
+int build_plan_cfg(const void *A, int m, int n, int bits, bool sgn, const pcmm_cussen_cfg *cfg,
                    cussen_plan *out) {
     const int N = cfg_rounds(cfg);
     const int group = cfg ? cfg->group : 0;
@@ -975,7 +975,7 @@ struct staging {
 std::mutex g_stage_lock;
 staging g_stage[64];
 
-pcmm_problem single_problem(const int8_t *A, int m, int n, int l, int bits, int is_signed, int c_form,
+pcmm_problem single_problem(const void *A, int m, int n, int l, int bits, int is_signed, int c_form,
                             const pcmm_cussen_cfg *cfg) {
     pcmm_problem q{};
     q.A = A;
@@ -993,7 +993,7 @@ pcmm_problem single_problem(const int8_t *A, int m, int n, int l, int bits, int 
 
 }  // namespace
 
-extern "C" pcmm_status pcmm_cussen_plan_stats(const int8_t *A, int32_t m, int32_t n, int32_t bits,
+extern "C" pcmm_status pcmm_cussen_plan_stats(const void *A, int32_t m, int32_t n, int32_t bits,
                                               int32_t is_signed, const pcmm_cussen_cfg *cfg,
                                               pcmm_cussen_stats *stats) {
     if (!stats || !valid_cfg(cfg) || m < 0 || n < 0) return PCMM_EINVAL;
@@ -1009,7 +1009,7 @@ extern "C" pcmm_status pcmm_cussen_plan_stats(const int8_t *A, int32_t m, int32_
     return PCMM_OK;
 }
 
-extern "C" pcmm_status pcmm_cussen_workspace(const int8_t *A, int32_t m, int32_t n, int32_t l, int32_t bits,
+extern "C" pcmm_status pcmm_cussen_workspace(const void *A, int32_t m, int32_t n, int32_t l, int32_t bits,
                                              int32_t is_signed, int32_t c_form, const pcmm_cussen_cfg *cfg,
                                              size_t *bytes) {
     if (!bytes || !valid_cfg(cfg)) return PCMM_EINVAL;
@@ -1021,7 +1021,7 @@ extern "C" pcmm_status pcmm_cussen_workspace(const int8_t *A, int32_t m, int32_t
     return PCMM_OK;
 }
 
-extern "C" pcmm_status pcmm_cussen(const int8_t *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
+extern "C" pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
                                    const pcmm_mat *B, pcmm_mat *C, const pcmm_cussen_cfg *cfg, void *workspace,
                                    size_t ws_bytes, pcmm_cussen_stats *stats, void *stream) {
     if (!B || !C || !valid_cfg(cfg)) return PCMM_EINVAL;

@@ -7,12 +7,19 @@
 // loads of B[k, :] coalesce.
 #include "common.hpp"
 #include "normalize.hpp"
+#include "plan.hpp"
 
 using namespace pcmm;
 
 namespace {
 
-__global__ void __launch_bounds__(256) schoolbook_kernel(const int8_t *__restrict__ A, int m, int n, int l, int bits,
+// plaintext element x: int8 / uint8 up to 8 bits, int16 / uint16 beyond
+__device__ __forceinline__ int plain_at_dev(const void *A, int64_t x, int bits, int is_signed) {
+    if (bits <= 8) return is_signed ? (int)((const int8_t *)A)[x] : (int)((const uint8_t *)A)[x];
+    return is_signed ? (int)((const int16_t *)A)[x] : (int)((const uint16_t *)A)[x];
+}
+
+__global__ void __launch_bounds__(256) schoolbook_kernel(const void *__restrict__ A, int m, int n, int l, int bits,
                                                          int is_signed, const uint32_t *__restrict__ B, int64_t ldb,
                                                          uint32_t *__restrict__ out, int64_t ld_out,
                                                          int out_canonical) {
@@ -24,8 +31,7 @@ __global__ void __launch_bounds__(256) schoolbook_kernel(const int8_t *__restric
     const int i = (int)(t / (2 * (int64_t)l));
     jpt acc = jpt_infinity();
     for (int k = 0; k < n; ++k) {
-        const int8_t raw = A[(int64_t)i * n + k];
-        const int a = is_signed ? (int)raw : (int)(uint8_t)raw;
+        const int a = plain_at_dev(A, (int64_t)i * n + k, bits, is_signed);
         if (a == 0) continue;
         apt b = load_affine(B, ldb, pt, (int64_t)k * l + j);
         if (a < 0) b = apt_neg(b);
@@ -39,15 +45,18 @@ __global__ void __launch_bounds__(256) schoolbook_kernel(const int8_t *__restric
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-bool a_in_range(const int8_t *A, int64_t count, int bits, bool is_signed) {
+bool a_in_range(const void *A, int64_t count, int bits, bool is_signed) {
     const int lo = is_signed ? -(1 << (bits - 1)) : 0;
     const int hi = is_signed ? (1 << (bits - 1)) - 1 : (1 << bits) - 1;
     for (int64_t x = 0; x < count; ++x) {
-        int v = is_signed ? (int)A[x] : (int)(uint8_t)A[x];
+        const int v = plain_at(A, x, bits, is_signed);
         if (v < lo || v > hi) return false;
     }
     return true;
 }
+
+// device bytes of A: 2 per element, enough for either element width
+size_t a_bytes(int32_t m, int32_t n) { return align256((size_t)m * n * 2); }
 
 }  // namespace
 
@@ -55,15 +64,15 @@ extern "C" size_t pcmm_schoolbook_workspace(int32_t m, int32_t n, int32_t l, int
     if (m < 0 || n < 0 || l < 0) return 0;
     int64_t n_out = (int64_t)m * l;
     int64_t ldc = std::max<int64_t>(64, (n_out + 63) / 64 * 64);
-    size_t bytes = align256((size_t)m * n);
+    size_t bytes = a_bytes(m, n);
     if (c_form == PCMM_AFFINE) bytes += align256((size_t)JAC2_PLANES * ldc * 4) + align256(normalize_scratch_bytes(n_out, 2));
     return bytes + 256;
 }
 
-extern "C" pcmm_status pcmm_schoolbook(const int8_t *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
+extern "C" pcmm_status pcmm_schoolbook(const void *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
                                        const pcmm_mat *B, pcmm_mat *C, void *workspace, size_t ws_bytes,
                                        void *stream) {
-    if (!B || !C || m < 0 || n < 0 || bits < 1 || bits > 8) return PCMM_EINVAL;
+    if (!B || !C || m < 0 || n < 0 || bits < 1 || bits > 16) return PCMM_EINVAL;
     if (B->rows != n || B->cols < 0 || B->npts != 2 || B->form != PCMM_AFFINE) return PCMM_EINVAL;
     const int l = B->cols;
     const int64_t n_out = (int64_t)m * l;
@@ -77,18 +86,19 @@ extern "C" pcmm_status pcmm_schoolbook(const int8_t *A, int32_t m, int32_t n, in
     if (!workspace || ws_bytes < pcmm_schoolbook_workspace(m, n, l, C->form)) return PCMM_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
-    int8_t *dA = (int8_t *)ws;
-    if ((int64_t)m * n > 0) PCMM_HIP_TRY(hipMemcpyAsync(dA, A, (size_t)m * n, hipMemcpyHostToDevice, s));
+    void *dA = ws;
+    const size_t elem = bits <= 8 ? 1 : 2;
+    if ((int64_t)m * n > 0) PCMM_HIP_TRY(hipMemcpyAsync(dA, A, (size_t)m * n * elem, hipMemcpyHostToDevice, s));
     const bool affine_out = C->form == PCMM_AFFINE;
     const int64_t ldc = std::max<int64_t>(64, (n_out + 63) / 64 * 64);
-    uint32_t *jac = affine_out ? (uint32_t *)(ws + align256((size_t)m * n)) : C->d;
+    uint32_t *jac = affine_out ? (uint32_t *)(ws + a_bytes(m, n)) : C->d;
     const int64_t ld_jac = affine_out ? ldc : C->ld;
     int64_t blocks = (2 * n_out + 255) / 256;
     hipLaunchKernelGGL(schoolbook_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dA, m, n, l, bits, is_signed, B->d,
                        B->ld, jac, ld_jac, affine_out ? 0 : 1);
     PCMM_LAUNCH_CHECK();
     if (affine_out) {
-        size_t off = align256((size_t)m * n) + align256((size_t)JAC2_PLANES * ldc * 4);
+        size_t off = a_bytes(m, n) + align256((size_t)JAC2_PLANES * ldc * 4);
         return launch_normalize(jac, ld_jac, true, C->d, C->ld, false, n_out, 2, ws + off, ws_bytes - off, s);
     }
     return PCMM_OK;

@@ -22,45 +22,50 @@ struct column_result {
     int64_t nN = 0, adds_counted = 0;
 };
 
+// Sorted distinct nonzero values of v (v >= 0) into uniq, and for each
+// element of v its index among them (-1 for 0) into rank_of.  Values below
+// 256 (at most 8-bit entries and their differences) use a presence table
+// scanned in order; wider ones sort.
+void distinct_ranks(const std::vector<int> &v, std::vector<int> &uniq, std::vector<int> &rank_of) {
+    uniq.clear();
+    rank_of.resize(v.size());
+    int vmax = 0;
+    for (int x : v) vmax = std::max(vmax, x);
+    if (vmax < 256) {
+        bool present[256] = {false};
+        int rank[256];
+        for (int x : v) present[x] = true;
+        present[0] = false;  // zeros are dropped: 0 * B needs no operation
+        for (int x = 1; x <= vmax; ++x)
+            if (present[x]) {
+                rank[x] = (int)uniq.size();
+                uniq.push_back(x);
+            }
+        for (size_t i = 0; i < v.size(); ++i) rank_of[i] = v[i] == 0 ? -1 : rank[v[i]];
+        return;
+    }
+    for (int x : v)
+        if (x != 0) uniq.push_back(x);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    for (size_t i = 0; i < v.size(); ++i)
+        rank_of[i] = v[i] == 0 ? -1 : (int)(std::lower_bound(uniq.begin(), uniq.end(), v[i]) - uniq.begin());
+}
+
 column_result compress_column(const std::vector<int> &vals, int N, int t, std::vector<plan_op> &ops,
                               int *nreg, int64_t *mul_bits) {
-    // Every value here is below 256 (|a| of an at most 8-bit entry, and the
-    // differences of sorted distinct such values), so "sort and eliminate
-    // duplicates" is a 256-entry presence table scanned in order, and the
-    // tracking pointer of a value is its rank in that table.
+    // "sort and eliminate duplicates" gives each level's distinct values; the
+    // tracking pointer of a value is its rank among them
     const int m = (int)vals.size();
     column_result res;
     res.row_operand.assign(m, INT16_MIN);
     std::vector<std::vector<int>> level(N + 1);
-    int rank[256];
-    // level 1 from the rows
-    {
-        bool present[256] = {false};
-        for (int v : vals) present[v] = true;
-        present[0] = false;  // zeros are dropped: 0 * B needs no operation
-        for (int v = 1; v < 256; ++v)
-            if (present[v]) {
-                rank[v] = (int)level[1].size();
-                level[1].push_back(v);
-            }
-    }
-    std::vector<int> row_rank(m);
-    for (int i = 0; i < m; ++i) row_rank[i] = vals[i] == 0 ? -1 : rank[vals[i]];
+    std::vector<int> row_rank;
+    distinct_ranks(vals, level[1], row_rank);
     // ptr[w][i] for w >= 2: rank in level w of element i of level w-1
     std::vector<std::vector<int>> ptr(N + 1);
     for (int w = 1; w <= N; ++w) {
-        if (w >= 2) {
-            const std::vector<int> &src = level[w - 1];
-            bool present[256] = {false};
-            for (int v : src) present[v] = true;
-            for (int v = 1; v < 256; ++v)
-                if (present[v]) {
-                    rank[v] = (int)level[w].size();
-                    level[w].push_back(v);
-                }
-            ptr[w].resize(src.size());
-            for (size_t i = 0; i < src.size(); ++i) ptr[w][i] = rank[src[i]];
-        }
+        if (w >= 2) distinct_ranks(level[w - 1], level[w], ptr[w]);
         if (w != N) {
             std::vector<int> &u = level[w];
             for (int i = (int)u.size() - 1; i >= 1; --i) u[i] -= u[i - 1];
@@ -118,22 +123,26 @@ column_result compress_column(const std::vector<int> &vals, int N, int t, std::v
 
 }  // namespace
 
-int build_cussen_plan(const int8_t *A, int m, int n, int bits, bool is_signed, int N, int g,
+int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int N, int g,
                       cussen_plan *out) {
-    if (!out || m < 0 || n < 0 || bits < 1 || bits > 8 || N < 1 || N > 8 || g < 1 || g > 4) return -1;
+    if (!out || m < 0 || n < 0 || bits < 1 || bits > 16 || N < 1 || N > 8 || g < 1 || g > 4) return -1;
     if ((int64_t)m * n > 0 && !A) return -1;
     if (m > 32767) return -1;
+    // row segments of g digits are keyed with 9 bits per digit up to 8-bit
+    // entries and 17 bits beyond (so at most 3 digits fit the 64-bit key)
+    const int key_bits = bits <= 8 ? 9 : 17;
+    if (g * key_bits > 64) return -1;
     // validate A against the declared bit-width
     const int lo = is_signed ? -(1 << (bits - 1)) : 0;
     const int hi = is_signed ? (1 << (bits - 1)) - 1 : (1 << bits) - 1;
     // validate and transpose to column-major (columns are what gets compressed)
-    std::vector<int16_t> At((size_t)m * n);
+    std::vector<int32_t> At((size_t)m * n);
     for (int i = 0; i < m; ++i) {
-        const int8_t *row = A + (int64_t)i * n;
         for (int k = 0; k < n; ++k) {
-            int v = is_signed ? (int)row[k] : (int)(uint8_t)row[k];
+            const int64_t x = (int64_t)i * n + k;
+            const int v = plain_at(A, x, bits, is_signed);
             if (v < lo || v > hi) return -2;
-            At[(size_t)k * m + i] = (int16_t)v;
+            At[(size_t)k * m + i] = v;
         }
     }
     auto at = [&](int i, int k) -> int { return At[(size_t)k * m + i]; };
@@ -155,7 +164,7 @@ int build_cussen_plan(const int8_t *A, int m, int n, int bits, bool is_signed, i
         std::vector<std::vector<int16_t>> digit_operand(gg);
         std::vector<int> vals(m);
         for (int t = 0; t < gg; ++t) {
-            const int16_t *col = &At[(size_t)(k0 + t) * m];
+            const int32_t *col = &At[(size_t)(k0 + t) * m];
             for (int i = 0; i < m; ++i) vals[i] = std::abs((int)col[i]);
             column_result cr = compress_column(vals, N, t, P.ops, &nreg, &P.table_mul_bits);
             P.level_mults += cr.nN;
@@ -184,9 +193,9 @@ int build_cussen_plan(const int8_t *A, int m, int n, int bits, bool is_signed, i
             continue;
         }
         // distinct row segments up to sign (first nonzero digit made positive);
-        // a segment is keyed by its digits, 9 bits each
+        // a segment is keyed by its digits, key_bits each
         std::vector<int16_t> entry_operands;
-        const bool direct = gg <= 2;
+        const bool direct = gg <= 2 && key_bits == 9;
         if (direct && (int)stamp.size() < (1 << (9 * gg))) {
             stamp.assign((size_t)1 << 18, -1);
             slot.assign((size_t)1 << 18, 0);
@@ -204,7 +213,7 @@ int build_cussen_plan(const int8_t *A, int m, int n, int bits, bool is_signed, i
             uint64_t key = 0;
             for (int t = 0; t < gg; ++t) {
                 seg[t] *= sigma;
-                key |= (uint64_t)(seg[t] + 256) << (9 * t);
+                key |= (uint64_t)(seg[t] + (1 << (key_bits - 1))) << (key_bits * t);
             }
             int e = -1;
             if (direct) {

@@ -51,10 +51,18 @@ struct cussen_plan {
     int64_t table_entries = 0;
 };
 
-// Validates A (m x n, int8 row-major; unsigned entries read as uint8) against
-// its declared bit-width and builds the plan.  Returns 0, or -1 (bad
-// arguments) / -2 (an entry outside the bit-width).
-int build_cussen_plan(const int8_t *A, int m, int n, int bits, bool is_signed, int N, int g,
+// Plaintext element x of A: int8 / uint8 for bits <= 8, int16 / uint16 for
+// 9..16 bits (row-major).
+inline int plain_at(const void *A, int64_t x, int bits, bool is_signed) {
+    if (bits <= 8) return is_signed ? (int)((const int8_t *)A)[x] : (int)((const uint8_t *)A)[x];
+    return is_signed ? (int)((const int16_t *)A)[x] : (int)((const uint16_t *)A)[x];
+}
+
+// Validates A (m x n row-major, elements as plain_at reads them) against its
+// declared bit-width (1..16) and builds the plan.  Returns 0, or -1 (bad
+// arguments, including g > 3 with entries wider than 8 bits) / -2 (an entry
+// outside the bit-width).
+int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int N, int g,
                       cussen_plan *out);
 
 }  // namespace pcmm

@@ -374,14 +374,26 @@ def _workspace(nbytes, device="cuda"):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def _host_A(A):
+_NARROW = {np.dtype(np.int16): np.int8, np.dtype(np.uint16): np.uint8}
+_WIDE = {np.dtype(np.int8): np.int16, np.dtype(np.uint8): np.uint16}
+
+
+def _host_A(A, bits: int):
+    """A as the library reads it: signedness from the dtype (int8/int16
+    signed, uint8/uint16 unsigned), element width from bits (1 byte up to 8
+    bits, 2 bytes for 9..16)."""
     A = np.ascontiguousarray(A)
-    if A.dtype == np.int8:
-        signed = 1
-    elif A.dtype == np.uint8:
-        signed = 0
-    else:
-        raise TypeError("A must be int8 (signed) or uint8 (unsigned)")
+    if A.dtype not in (np.int8, np.uint8, np.int16, np.uint16):
+        raise TypeError("A must be int8 / int16 (signed) or uint8 / uint16 (unsigned)")
+    signed = 1 if A.dtype in (np.int8, np.int16) else 0
+    if bits > 8 and A.dtype.itemsize == 1:
+        A = A.astype(_WIDE[A.dtype])
+    elif bits <= 8 and A.dtype.itemsize == 2:
+        narrow = _NARROW[A.dtype]
+        info = np.iinfo(narrow)
+        if A.size and (A.min() < info.min or A.max() > info.max):
+            raise PCMMError(-2, "plaintext entries outside the declared bit-width")
+        A = A.astype(narrow)
     return A, signed
 
 
@@ -415,19 +427,19 @@ def encrypt(pk: bytes, msg, seed: int, idx0: int = 0, stream=None) -> DevPoints:
 
 
 def schoolbook(A, bits: int, B: DevPoints, c_form: int = AFFINE, stream=None, workspace=None):
-    A, signed = _host_A(A)
+    A, signed = _host_A(A, bits)
     m, n = A.shape
     C = DevPoints.empty(m, B.cols, 2, c_form)
     need = lib().pcmm_schoolbook_workspace(m, n, B.cols, c_form)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need)
     _call("pcmm_schoolbook", A.ctypes.data_as(_VP), m, n, bits, signed, B.ref(), C.ref(),
           _tensor_ptr(ws), ws.numel(), stream_ptr(stream))
-    C._keep = (ws,)
+    C._keep = (ws, A)  # the host copy of A is queued asynchronously
     return C
 
 
 def cussen_workspace_bytes(A, bits: int, l: int, c_form: int = AFFINE, cfg: CussenCfg = None) -> int:
-    A, signed = _host_A(A)
+    A, signed = _host_A(A, bits)
     m, n = A.shape
     nb = ctypes.c_size_t()
     _call("pcmm_cussen_workspace", A.ctypes.data_as(_VP), m, n, l, bits, signed, c_form,
@@ -438,7 +450,7 @@ def cussen_workspace_bytes(A, bits: int, l: int, c_form: int = AFFINE, cfg: Cuss
 def cussen(A, bits: int, B: DevPoints, c_form: int = AFFINE, cfg: CussenCfg = None, stream=None,
            workspace=None, out: DevPoints = None):
     """Cussen PC-MM; returns (C, stats dict)."""
-    A, signed = _host_A(A)
+    A, signed = _host_A(A, bits)
     m, n = A.shape
     C = out if out is not None else DevPoints.empty(m, B.cols, 2, c_form)
     if workspace is not None:
@@ -455,7 +467,7 @@ def cussen(A, bits: int, B: DevPoints, c_form: int = AFFINE, cfg: CussenCfg = No
 
 def cussen_plan_stats(A, bits: int, cfg: CussenCfg = None) -> dict:
     """Operation counts of the compression plan (host only, no GPU work)."""
-    A, signed = _host_A(A)
+    A, signed = _host_A(A, bits)
     m, n = A.shape
     st = CussenStats()
     _call("pcmm_cussen_plan_stats", A.ctypes.data_as(_VP), m, n, bits, signed,
@@ -493,14 +505,17 @@ def strerror(code: int) -> str:
 class Plan:
     """A compiled pcmm_plan of one or more Cussen PC-MMs (pcmm_plan_*).
 
-    problems: sequence of (A, bits, l, c_form, cfg) with A a host int8 (signed)
-    or uint8 (unsigned) m x n matrix and cfg a CussenCfg or None."""
+    problems: sequence of (A, bits, l, c_form, cfg) with A a host m x n
+    int8 / int16 (signed) or uint8 / uint16 (unsigned) matrix and cfg a
+    CussenCfg or None."""
 
     def __init__(self, problems):
         arr = (Problem * len(problems))()
+        keep = []  # converted copies of A stay alive until pcmm_plan_create returns
         self.shapes = []
         for k, (A, bits, l, c_form, cfg) in enumerate(problems):
-            A, signed = _host_A(A)
+            A, signed = _host_A(A, bits)
+            keep.append(A)
             m, n = A.shape
             arr[k] = Problem(A.ctypes.data, m, n, l, bits, signed, c_form,
                              cfg if cfg is not None else CussenCfg(4, 0, 0, 0, 0, None))

@@ -53,7 +53,9 @@ def _oracle_column_counts(orc, A, N):
 
 
 @pytest.mark.parametrize("shape", [W.TINY, W.SIGNED128, W.PCMMShape(37, 23, 5, 3, False, 4, seed=9),
-                                   W.PCMMShape(64, 40, 3, 8, False, 8, seed=10)])
+                                   W.PCMMShape(64, 40, 3, 8, False, 8, seed=10),
+                                   W.PCMMShape(300, 12, 3, 12, True, 8, seed=11),
+                                   W.PCMMShape(200, 10, 2, 16, False, 8, seed=12)])
 @pytest.mark.parametrize("N", [1, 2, 4])
 def test_plan_counts_match_oracle_alg2(orc, shape, N):
     A, _ = W.make_inputs(shape)
@@ -111,8 +113,22 @@ def test_validation_errors():
     A = np.array([[-8, 7]], dtype=np.int8)
     pcmm.cussen_plan_stats(A, 4)
     with pytest.raises(pcmm.PCMMError) as ei:
-        pcmm.cussen_plan_stats(A, 9)
+        pcmm.cussen_plan_stats(A, 17)
     assert ei.value.code == -1
+    # 9..16-bit plaintexts are 16-bit arrays (8-bit arrays are widened)
+    pcmm.cussen_plan_stats(A, 12)
+    W = np.array([[-2048, 2047, 0]], dtype=np.int16)
+    st = pcmm.cussen_plan_stats(W, 12, pcmm.CussenCfg(4, 3, 0, 0))
+    assert st["group"] == 3 and st["accum_adds"] == 1
+    with pytest.raises(pcmm.PCMMError) as ei:
+        pcmm.cussen_plan_stats(W, 11)
+    assert ei.value.code == -2  # -2048 is not a signed 11-bit value
+    with pytest.raises(pcmm.PCMMError) as ei:
+        pcmm.cussen_plan_stats(np.array([[65535, 1, 2, 3]], dtype=np.uint16), 16, pcmm.CussenCfg(4, 4, 0, 0))
+    assert ei.value.code == -1  # four 16-bit digits do not fit one segment key
+    with pytest.raises(pcmm.PCMMError) as ei:
+        pcmm.cussen_plan_stats(np.array([[300]], dtype=np.uint16), 8)
+    assert ei.value.code == -2  # 300 does not fit the 8-bit element it would be narrowed to
     with pytest.raises(pcmm.PCMMError) as ei:
         pcmm.cussen_plan_stats(A, 4, pcmm.CussenCfg(4, 5, 0, 0))  # group > 4
     assert ei.value.code == -1

@@ -110,6 +110,30 @@ def test_deep_split_k_vs_oracle(dev, orc, split):
         assert (C.to_host() == ref).all(), (split, group)
 
 
+@pytest.mark.parametrize("bits,signed", [(12, True), (16, False), (16, True), (9, False)])
+def test_wide_plaintexts_vs_oracle(dev, orc, bits, signed):
+    """9..16-bit plaintexts (16-bit arrays): schoolbook and Cussen (g = 1..3)
+    equal the oracle; the vector case n = l = 1 too."""
+    rng = np.random.default_rng(bits * 2 + signed)
+    lo, hi = (-(1 << (bits - 1)), 1 << (bits - 1)) if signed else (0, 1 << bits)
+    dt = np.int16 if signed else np.uint16
+    A = rng.integers(lo, hi, size=(70, 9)).astype(dt)
+    A[3, :] = hi - 1  # the extreme value and repeats down a column
+    A[5, :] = lo
+    B = random_cts(orc, 9, 3, 900 + bits)
+    ref = orc.pcmm_cussen(A, B)
+    Bd = _upload(dev, B)
+    log("wide", bits, signed)
+    assert (dev.schoolbook(A, bits, Bd).to_host() == ref).all()
+    for group in (1, 2, 3):
+        C, st = dev.cussen(A, bits, Bd, cfg=dev.CussenCfg(4, group, 0, 0))
+        assert (C.to_host() == ref).all(), group
+    v = A[:, :1].copy()
+    Bv = _upload(dev, B[:1, :1].copy())
+    C, _ = dev.cussen(v, bits, Bv)
+    assert (C.to_host() == orc.pcmm_cussen(v, B[:1, :1].copy())).all()
+
+
 def test_exceptional_cases_vs_oracle(dev, orc):
     # equal ciphertexts down a column (accumulator meets P = Q, tables meet
     # P = Q through repeated differences) and opposite ones (P = -Q)

@@ -187,6 +187,49 @@ def batch_leg(reps):
     return out
 
 
+def vector_leg(ms, ts, l_batch, reps):
+    """Vector x ciphertext-scalar (PC-MM with n = 1): an m-entry plaintext
+    vector times one ciphertext (latency of one call), and times l_batch
+    ciphertexts in one call (throughput), by schoolbook and Cussen."""
+    import torch
+    from paper_2504_14497_amd import pcmm, workloads as W
+    stream = torch.cuda.current_stream()
+    out = []
+    for t in ts:
+        for m in ms:
+            sh = W.PCMMShape(m, 1, l_batch, t, False, 8, seed=1000 + 17 * t + m, name=f"vec{m}_t{t}")
+            A, msg = W.make_inputs(sh)
+            _, pk = pcmm.keygen(sh.seed)
+            Bl = pcmm.encrypt(pk, msg, sh.seed)
+            B1 = pcmm.encrypt(pk, msg[:, :1].copy(), sh.seed)
+            row = {"m": m, "t": t}
+            for l, B, key in ((1, B1, "one"), (l_batch, Bl, "batch")):
+                cfg = pcmm.cussen_cfg(4, 1)
+                wsc = torch.empty(pcmm.cussen_workspace_bytes(A, t, l, pcmm.AFFINE, cfg), dtype=torch.uint8,
+                                  device="cuda")
+                wss = torch.empty(pcmm.lib().pcmm_schoolbook_workspace(m, 1, l, pcmm.AFFINE), dtype=torch.uint8,
+                                  device="cuda")
+                C = pcmm.DevPoints.empty(m, l, 2, pcmm.AFFINE)
+                Cc, _ = pcmm.cussen(A, t, B, cfg=cfg, workspace=wsc, out=C)
+                Cs = pcmm.schoolbook(A, t, B, workspace=wss)
+                torch.cuda.synchronize()
+                same = bool(torch.equal(Cc.t, Cs.t))
+                ms_c = time_region(lambda: pcmm.cussen(A, t, B, cfg=cfg, workspace=wsc, out=C), reps, stream)
+                ms_s = time_region(lambda: pcmm.schoolbook(A, t, B, workspace=wss), reps, stream)
+                if key == "one":
+                    row.update({"cussen_us": ms_c * 1e3, "schoolbook_us": ms_s * 1e3,
+                                "speedup": ms_s / ms_c, "same_output": same})
+                else:
+                    row.update({"cussen_products_per_s": l / (ms_c * 1e-3),
+                                "schoolbook_products_per_s": l / (ms_s * 1e-3),
+                                "batch_speedup": ms_s / ms_c, "batch_same_output": same})
+            out.append(row)
+    return {"what": f"a uniform unsigned t-bit m-vector times one EC-ElGamal ciphertext (n = l = 1; latency of "
+                    f"one call incl. host planning and normalisation), and times {l_batch} ciphertexts in one "
+                    f"call (products/s)", "reps": reps, "rows": out,
+            "context": "paper (Raspberry Pi 5, m = 512, t = 4): schoolbook 59153.174 us, Cussen 399.094 us"}
+
+
 def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
     """Encrypted linear layers served by the continuous-batching scheduler:
     4 static layers W (256 x 1024, uniform signed 8-bit, resident plans),
@@ -282,6 +325,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3, help="timed repetitions of each batch form")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-PC-MM batch comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--no-vector", action="store_true", help="skip the vector x ciphertext-scalar microbench")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--serve-fractions", default="0.25,0.5,0.75,1.0,1.25",
                     help="arrival rates as fractions of the measured capacity")
@@ -432,6 +476,8 @@ def main():
     if not args.no_batch:
         del ws
         out["batch"] = batch_leg(args.batch_reps)
+    if not args.no_vector:
+        out["vector"] = vector_leg((8, 64, 512), (4, 8, 16), 4096, 20)
     if not args.no_serve:
         torch.cuda.empty_cache()
         out["serving"] = serve_leg(args.serve_requests, [float(x) for x in args.serve_fractions.split(",")],

@@ -436,6 +436,24 @@ def main():
     ms_school = s0.elapsed_time(s1) / args.school_steps
     same = bool((Cs.to_host() == C.to_host()).all())
 
+    # Strassen (the paper's third method, schoolbook leaves) on the same inputs
+    strassen = []
+    for depth in (1, 2, 3):
+        wst = torch.empty(pcmm.strassen_workspace_bytes(sh.m, sh.n, sh.l, pcmm.AFFINE, depth),
+                          dtype=torch.uint8, device="cuda")
+        Cst, sst = pcmm.strassen(A, sh.bits, B, depth=depth, workspace=wst)
+        torch.cuda.synchronize()
+        same_st = bool(torch.equal(Cst.t, C.t))
+        ms_st = time_region(lambda: pcmm.strassen(A, sh.bits, B, depth=depth, workspace=wst), args.school_steps,
+                            stream)
+        strassen.append({"depth": depth, "value": 1000.0 / ms_st, "unit": "PC-MM/s", "ms_per_step": ms_st,
+                         "leaf_bits": sst["leaf_bits"], "leaves": sst["leaves"],
+                         "block_point_adds": sst["block_adds"], "same_output_as_cussen": same_st,
+                         "paper_model_point_adds_per_s": (cm.strassen_equiv_adds(sh.n, sh.bits) / (ms_st * 1e-3)
+                                                          if sh.m == sh.n == sh.l and sh.n & (sh.n - 1) == 0
+                                                          else None)})
+        del wst
+
     # roofline of the dominant kernel (accumulation): algorithmic multiply-adds
     madds = 2 * sh.l * st0["accum_adds"]
     acc_ms = stage["ms_accumulate"]
@@ -470,6 +488,8 @@ def main():
                        "point_adds_per_s": cm.schoolbook_equiv_adds(sh.m, sh.n, sh.l, sh.bits)
                        / (ms_school * 1e-3), "same_output_as_cussen": same},
         "speedup_cussen_vs_schoolbook": ms_school / ms_step,
+        "strassen": strassen,
+        "speedup_cussen_vs_best_strassen": min(x["ms_per_step"] for x in strassen) / ms_step,
         "roofline": roofline,
         "device": dev,
     }

@@ -248,6 +248,39 @@ pcmm_status pcmm_plan_run_selected(pcmm_plan plan, const int32_t *which, int32_t
                                    pcmm_mat *C, void *workspace, size_t ws_bytes, void **stage_events,
                                    void *stream);
 
+/* Strassen PC-MM (Sec. 3.1): the 2 x 2 block recursion with seven block
+ * products M1..M7 and C11 = M1 + M4 - M5 + M7, C12 = M3 + M5, C21 = M2 + M4,
+ * C22 = M1 - M2 + M3 + M6, run breadth first to `depth` levels; the leaf
+ * products use the schoolbook method (Alg. 1 per term, ladders over each
+ * leaf's bit-width, which grows by at most one bit per level as the
+ * plaintext blocks are summed).  The plaintext sums are formed on the host;
+ * every ciphertext block sum and every leaf product runs on the GPU.  Shapes
+ * that are not multiples of 2^depth are padded (zero plaintexts, infinity
+ * ciphertexts) and C is cropped.  Same arguments as pcmm_schoolbook plus
+ * cfg (NULL = defaults) and stats (may be NULL).  PCMM_ERANGE also when a
+ * leaf plaintext would not fit 16-bit signed.
+ *   depth  0 = automatic (as many levels as keep leaves >= 64 in every
+ *          dimension; none for small shapes, which then run the schoolbook
+ *          product), 1..6 = that many levels. */
+typedef struct {
+    int32_t depth;
+    int32_t reserved;
+} pcmm_strassen_cfg;
+
+typedef struct {
+    int32_t depth;            /* levels used                                  */
+    int32_t leaf_bits;        /* largest bit-width of a leaf plaintext          */
+    int64_t leaves;           /* 7^depth leaf products                        */
+    int64_t block_adds;       /* point additions of the ciphertext block sums */
+    int64_t leaf_ladder_ops;  /* ladder steps (addition + doubling) of the leaves */
+} pcmm_strassen_stats;
+
+pcmm_status pcmm_strassen(const void *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
+                          const pcmm_mat *B, pcmm_mat *C, const pcmm_strassen_cfg *cfg,
+                          void *workspace, size_t ws_bytes, pcmm_strassen_stats *stats, void *stream);
+pcmm_status pcmm_strassen_workspace(int32_t m, int32_t n, int32_t l, int32_t c_form,
+                                    const pcmm_strassen_cfg *cfg, size_t *bytes);
+
 /* Host-only: the compression plan's operation counts for A (no GPU work). */
 pcmm_status pcmm_cussen_plan_stats(const void *A, int32_t m, int32_t n, int32_t bits,
                                    int32_t is_signed, const pcmm_cussen_cfg *cfg,

@@ -44,3 +44,26 @@ def plain_matrix_counts_cussen(n: int, mul_v: float, add_v: float):
 
 def plain_matrix_counts_schoolbook(n: int):
     return n ** 3, n * n * (n - 1)
+
+
+def _strassen_block_elems(n: int) -> int:
+    """Sum over recursion levels d of 7^d (n / 2^(d+1))^2: block elements per
+    block addition, with the recursion down to 1 x 1 blocks (n a power of 2)."""
+    k = n.bit_length() - 1
+    return sum(7 ** d * (n >> (d + 1)) ** 2 for d in range(k))
+
+
+def strassen_plain_counts(n: int):
+    """Plaintext n x n Strassen (Sec. 3.1): 7^log2(n) scalar multiplications
+    and 18 block additions per recursion node (Tab. A3, A4)."""
+    k = n.bit_length() - 1
+    return 7 ** k, 18 * _strassen_block_elems(n)
+
+
+def strassen_equiv_adds(n: int, t: int) -> int:
+    """Equivalent point additions of Strassen PC-MM (Tab. A6): every scalar x
+    ciphertext product costs 2 ECSMs of 2t additions each, and each recursion
+    node adds 13 ciphertext blocks (2 points per ciphertext); the 5 plaintext
+    block additions are free."""
+    k = n.bit_length() - 1
+    return 4 * t * 7 ** k + 26 * _strassen_block_elems(n)

@@ -78,6 +78,18 @@ class CussenStats(ctypes.Structure):
                 for k, _ in self._fields_ if k != "reserved"}
 
 
+class StrassenCfg(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class StrassenStats(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("leaf_bits", ctypes.c_int32), ("leaves", ctypes.c_int64),
+                ("block_adds", ctypes.c_int64), ("leaf_ladder_ops", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 GROUP_AUTO = -1          # PCMM_GROUP_AUTO
 PLAN_MAX_PROBLEMS = 64   # PCMM_PLAN_MAX_PROBLEMS
 
@@ -121,6 +133,10 @@ _SIG = {
     "pcmm_plan_selected_workspace": ([_VP, ctypes.POINTER(_I32), _I32, ctypes.POINTER(ctypes.c_size_t)], _I32),
     "pcmm_plan_run_selected": ([_VP, ctypes.POINTER(_I32), _I32, ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP,
                                 ctypes.c_size_t, ctypes.POINTER(_VP), _VP], _I32),
+    "pcmm_strassen": ([_VP, _I32, _I32, _I32, _I32, ctypes.POINTER(Mat), ctypes.POINTER(Mat),
+                       ctypes.POINTER(StrassenCfg), _VP, ctypes.c_size_t, ctypes.POINTER(StrassenStats), _VP], _I32),
+    "pcmm_strassen_workspace": ([_I32, _I32, _I32, _I32, ctypes.POINTER(StrassenCfg),
+                                 ctypes.POINTER(ctypes.c_size_t)], _I32),
     "pcmm_normalize": ([ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP, ctypes.c_size_t, _VP], _I32),
     "pcmm_normalize_workspace": ([_I64, _I32], ctypes.c_size_t),
     "pcmm_decrypt_to_points": ([_VP, ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP], _I32),
@@ -436,6 +452,28 @@ def schoolbook(A, bits: int, B: DevPoints, c_form: int = AFFINE, stream=None, wo
           _tensor_ptr(ws), ws.numel(), stream_ptr(stream))
     C._keep = (ws, A)  # the host copy of A is queued asynchronously
     return C
+
+
+def strassen(A, bits: int, B: DevPoints, c_form: int = AFFINE, depth: int = 0, stream=None, workspace=None):
+    """Strassen PC-MM (schoolbook leaves); returns (C, stats dict)."""
+    A, signed = _host_A(A, bits)
+    m, n = A.shape
+    C = DevPoints.empty(m, B.cols, 2, c_form)
+    cfg = StrassenCfg(depth, 0)
+    need = ctypes.c_size_t()
+    _call("pcmm_strassen_workspace", m, n, B.cols, c_form, ctypes.byref(cfg), ctypes.byref(need))
+    ws = workspace if workspace is not None else _workspace(need.value)
+    st = StrassenStats()
+    _call("pcmm_strassen", A.ctypes.data_as(_VP), m, n, bits, signed, B.ref(), C.ref(), ctypes.byref(cfg),
+          _tensor_ptr(ws), ws.numel(), ctypes.byref(st), stream_ptr(stream))
+    C._keep = (ws, A)
+    return C, st.as_dict()
+
+
+def strassen_workspace_bytes(m: int, n: int, l: int, c_form: int = AFFINE, depth: int = 0) -> int:
+    need = ctypes.c_size_t()
+    _call("pcmm_strassen_workspace", m, n, l, c_form, ctypes.byref(StrassenCfg(depth, 0)), ctypes.byref(need))
+    return need.value
 
 
 def cussen_workspace_bytes(A, bits: int, l: int, c_form: int = AFFINE, cfg: CussenCfg = None) -> int:

@@ -23,6 +23,7 @@ def test_tab_a6_pcmm_equivalent_additions():
     for r in rows:
         n, t = r["n"], r["t"]
         assert cm.schoolbook_equiv_adds(n, n, n, t) == r["schoolbook"]
+        assert cm.strassen_equiv_adds(n, t) == r["strassen"], (n, t)
         got = cm.cussen_equiv_adds_square(n, t, muls[n][f"t{t}"], adds[n][f"t{t}"])
         assert got == r["proposed"], (n, t, got, r["proposed"])
         # the per-column form agrees with the averaged form
@@ -46,7 +47,7 @@ def test_tab_a3_a4_plain_matrix_counts():
     for r3, r4 in zip(A3, A4):
         n = r3["n"]
         assert cm.plain_matrix_counts_schoolbook(n) == (r3["schoolbook"], r4["schoolbook"])
-        assert r3["strassen"] == 7 ** (n.bit_length() - 1)  # 7^(log2 n) block multiplications
+        assert cm.strassen_plain_counts(n) == (r3["strassen"], r4["strassen"]), n
         for t in TS:
             mu, ad = cm.plain_matrix_counts_cussen(n, muls[n][f"t{t}"], adds[n][f"t{t}"])
             assert (mu, ad) == (r3[f"t{t}"], r4[f"t{t}"]), (n, t)

@@ -243,6 +243,7 @@ def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
     from paper_2504_14497_amd.serving import (DONE, GpuExecutor, Request, Server, latency_summary,
                                               poisson_arrivals, run_arrivals)
     base = W.SERVE_LAYER
+    stream = torch.cuda.current_stream()
     layers = []
     for k in range(4):
         sh = W.PCMMShape(base.m, base.n, base.l, base.bits, True, base.msg_bits, seed=base.seed + k,
@@ -301,13 +302,39 @@ def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
         plan.run_selected([int(which[k])], [X[k]], [alone], wsa)
         torch.cuda.synchronize()
         same = same and bool(torch.equal(alone.t, Cs[k].t))
+    # full decryption of served outputs (bounded discrete log), checked against
+    # the exact integer products
+    bound = n * (1 << (base.bits - 1)) * ((1 << base.msg_bits) - 1)
+    t0 = time.time()
+    table = pcmm.DlogTable(20)
+    torch.cuda.synchronize()
+    t_table = time.time() - t0
+    ks = list(range(min(64, n_requests)))
+    # decrypt request by request inside one timed region
+    msg_np = msg.numpy()
+    outs = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    pcmm.decrypt(b"\x00" * 31 + b"\x01", Cs[0], bound, table)  # warm-up (wrong key: values unused)
+    sk, _ = pcmm.keygen(base.seed)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in ks:
+        outs.append(pcmm.decrypt(sk, Cs[k], bound, table))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_dec = e0.elapsed_time(e1)
+    exact = all(bool((outs[x].cpu().numpy() == layers[int(which[k])].astype(np.int64)
+                      @ msg_np[k * n:(k + 1) * n].astype(np.int64)).all()) for x, k in enumerate(ks))
+    decrypt = {"elements": len(ks) * m * l, "ms": ms_dec, "elements_per_s": len(ks) * m * l / (ms_dec * 1e-3),
+               "log2_baby": 20, "bound": bound, "table_build_s": t_table, "exact_integer_products": exact}
     return {"workload": f"4 layers W {m}x{n} uniform signed {base.bits}-bit (plans resident), requests X "
                         f"{n}x{l} ciphertexts of uniform {base.msg_bits}-bit messages, a fresh X per request, "
                         f"layer uniform; Poisson arrivals; Cussen N=4 g=1",
             "requests_per_rate": n_requests, "slots": slots, "max_batch": max_batch,
             "budget_gb": budget_gb, "request_workspace_mb": plan.stats(0)["workspace_bytes"] / 1e6,
             "host_plan_s": t_plan, "capacity_req_per_s": capacity, "burst": burst, "sweep": sweep,
-            "alone_equals_mix": same}
+            "alone_equals_mix": same, "decrypt": decrypt}
 
 
 def main():

@@ -281,6 +281,28 @@ pcmm_status pcmm_strassen(const void *A, int32_t m, int32_t n, int32_t bits, int
 pcmm_status pcmm_strassen_workspace(int32_t m, int32_t n, int32_t l, int32_t c_form,
                                     const pcmm_strassen_cfg *cfg, size_t *bytes);
 
+/* Full decryption (Sec. 2.4): m = phi^-1(C2 - x C1) for phi(m) = m G, with
+ * the message bound the scheme needs (|m| <= bound), by baby-step
+ * giant-step.  The baby-step table holds j G for 0 <= j < 2^log2_baby
+ * (4..24) and a hash index on x; it is built once on the GPU into
+ * caller-owned device memory of pcmm_dlog_table_bytes() bytes
+ * (pcmm_dlog_table_build, scratch of pcmm_dlog_table_workspace() bytes) and
+ * serves every later decryption.  pcmm_decrypt writes, for each element e of
+ * the affine ciphertext matrix C, the integer m_e to out[e] (device int64,
+ * rows * cols, row-major), or INT64_MIN when |m_e| > bound (no match).  A
+ * decryption costs one variable-base scalar multiplication per element plus
+ * 2 ceil(bound / (2^(log2_baby + 1) - 1)) + 1 giant steps; bound must keep
+ * the giant multiples below 2^32 * (2^(log2_baby + 1) - 1).  workspace:
+ * pcmm_decrypt_workspace() bytes. */
+pcmm_status pcmm_dlog_table_bytes(int32_t log2_baby, size_t *bytes);
+pcmm_status pcmm_dlog_table_workspace(int32_t log2_baby, size_t *bytes);
+pcmm_status pcmm_dlog_table_build(int32_t log2_baby, void *table, size_t bytes, void *workspace,
+                                  size_t ws_bytes, void *stream);
+pcmm_status pcmm_decrypt_workspace(int64_t elements, int64_t bound, int32_t log2_baby, size_t *bytes);
+pcmm_status pcmm_decrypt(const uint8_t sk_be[32], const pcmm_mat *C, int64_t bound, const void *table,
+                         size_t table_bytes, int32_t log2_baby, int64_t *out, void *workspace,
+                         size_t ws_bytes, void *stream);
+
 /* Host-only: the compression plan's operation counts for A (no GPU work). */
 pcmm_status pcmm_cussen_plan_stats(const void *A, int32_t m, int32_t n, int32_t bits,
                                    int32_t is_signed, const pcmm_cussen_cfg *cfg,

@@ -137,6 +137,12 @@ _SIG = {
                        ctypes.POINTER(StrassenCfg), _VP, ctypes.c_size_t, ctypes.POINTER(StrassenStats), _VP], _I32),
     "pcmm_strassen_workspace": ([_I32, _I32, _I32, _I32, ctypes.POINTER(StrassenCfg),
                                  ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "pcmm_dlog_table_bytes": ([_I32, ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "pcmm_dlog_table_workspace": ([_I32, ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "pcmm_dlog_table_build": ([_I32, _VP, ctypes.c_size_t, _VP, ctypes.c_size_t, _VP], _I32),
+    "pcmm_decrypt_workspace": ([_I64, _I64, _I32, ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "pcmm_decrypt": ([_VP, ctypes.POINTER(Mat), _I64, _VP, ctypes.c_size_t, _I32, _VP, _VP, ctypes.c_size_t,
+                      _VP], _I32),
     "pcmm_normalize": ([ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP, ctypes.c_size_t, _VP], _I32),
     "pcmm_normalize_workspace": ([_I64, _I32], ctypes.c_size_t),
     "pcmm_decrypt_to_points": ([_VP, ctypes.POINTER(Mat), ctypes.POINTER(Mat), _VP], _I32),
@@ -634,3 +640,34 @@ class Plan:
         ws_ptr, ws_n = (workspace if isinstance(workspace, tuple)
                         else (_tensor_ptr(workspace), workspace.numel()))
         _call("pcmm_plan_run_selected", self.h, w, len(which), Bm, Cm, ws_ptr, ws_n, evp, stream_ptr(stream))
+
+
+class DlogTable:
+    """Baby-step table for pcmm_decrypt (j G, j < 2^log2_baby, hash index on x)."""
+
+    def __init__(self, log2_baby: int = 20, stream=None):
+        import torch
+        self.log2 = log2_baby
+        n = ctypes.c_size_t()
+        _call("pcmm_dlog_table_bytes", log2_baby, ctypes.byref(n))
+        self.t = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        w = ctypes.c_size_t()
+        _call("pcmm_dlog_table_workspace", log2_baby, ctypes.byref(w))
+        ws = _workspace(w.value)
+        _call("pcmm_dlog_table_build", log2_baby, _tensor_ptr(self.t), self.t.numel(), _tensor_ptr(ws), ws.numel(),
+              stream_ptr(stream))
+        self._keep = ws
+
+
+def decrypt(sk: bytes, C: DevPoints, bound: int, table: DlogTable, stream=None, workspace=None):
+    """Integers m with C = Enc(m), |m| <= bound (int64 device tensor, rows x
+    cols; INT64_MIN where no such m)."""
+    import torch
+    assert C.form == AFFINE and C.npts == 2
+    out = torch.empty((C.rows, C.cols), dtype=torch.int64, device="cuda")
+    n = ctypes.c_size_t()
+    _call("pcmm_decrypt_workspace", C.rows * C.cols, bound, table.log2, ctypes.byref(n))
+    ws = workspace if workspace is not None else _workspace(n.value)
+    _call("pcmm_decrypt", sk, C.ref(), bound, _tensor_ptr(table.t), table.t.numel(), table.log2,
+          _tensor_ptr(out), _tensor_ptr(ws), ws.numel(), stream_ptr(stream))
+    return out

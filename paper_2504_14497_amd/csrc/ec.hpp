@@ -133,8 +133,10 @@ __device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
     bool q_inf = apt_is_inf(Q);
     bool same = fe_is_zero(hh) && fe_is_zero(r) && !p_inf && !q_inf;
     R = fix_equal_operands(same, R, P);
-    R = jpt_select(p_inf, R, jpt_from_affine(Q));
-    R = jpt_select(q_inf, R, P);
+    // infinity operands are rare: the selects run only when some lane of the
+    // wavefront has one (uniform branches, then per-lane selects)
+    if (__ballot(p_inf)) R = jpt_select(p_inf, R, jpt_from_affine(Q));
+    if (__ballot(q_inf)) R = jpt_select(q_inf, R, P);
     return R;
 }
 
@@ -162,8 +164,8 @@ __device__ __forceinline__ jpt jpt_add(const jpt &P, const jpt &Q) {
     bool q_inf = jpt_is_inf(Q);
     bool same = fe_is_zero(hh) && fe_is_zero(r) && !p_inf && !q_inf;
     R = fix_equal_operands(same, R, P);
-    R = jpt_select(p_inf, R, Q);
-    R = jpt_select(q_inf, R, P);
+    if (__ballot(p_inf)) R = jpt_select(p_inf, R, Q);
+    if (__ballot(q_inf)) R = jpt_select(q_inf, R, P);
     return R;
 }
 

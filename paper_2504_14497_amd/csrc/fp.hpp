@@ -357,19 +357,33 @@ __device__ __forceinline__ red_consts red_consts_make() {
     return k;
 }
 
+// CHAIN = true sums each column as one chain of 32 x 32 + 64-bit
+// multiply-adds: the accumulator passes through an empty register constraint
+// after every term, which stops the compiler from splitting the column into
+// parallel partial sums that cost one extra 64-bit add each (15 per product).
+// That suits the point formulas, whose independent products give the
+// scheduler parallelism enough; a lone serial chain of products (the
+// inversion, prefix products) is latency-bound and keeps the split form.
+template <bool CHAIN>
+__device__ __forceinline__ void chain(int64_t &acc) {
+    if constexpr (CHAIN) asm("" : "+v"(acc));
+}
+
+template <bool CHAIN>
 __device__ __forceinline__ void red_terms(int64_t &acc, const uint32_t *m, int c, const red_consts &k) {
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
         const int j = c - i;
         if (i >= c) continue;
-        if (j == 3) acc += (int64_t)((uint64_t)m[i] * k.k9);
-        if (j == 6) acc += (int64_t)((uint64_t)m[i] * k.k18);
-        if (j == 7) acc += (int64_t)(int32_t)m[i] * (int64_t)k.kn21;
-        if (j == 8) acc += (int64_t)((uint64_t)m[i] * k.k24);
+        if (j == 3) { acc += (int64_t)((uint64_t)m[i] * k.k9); chain<CHAIN>(acc); }
+        if (j == 6) { acc += (int64_t)((uint64_t)m[i] * k.k18); chain<CHAIN>(acc); }
+        if (j == 7) { acc += (int64_t)(int32_t)m[i] * (int64_t)k.kn21; chain<CHAIN>(acc); }
+        if (j == 8) { acc += (int64_t)((uint64_t)m[i] * k.k24); chain<CHAIN>(acc); }
     }
 }
 
-__device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) {
+template <bool CHAIN>
+__device__ __forceinline__ fe fe_mul_t(const fe &a, const fe &b) {
     const red_consts k = red_consts_make();
     int64_t acc = 0;
     uint32_t m[NL];
@@ -379,9 +393,9 @@ __device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) {
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
             const int j = c - i;
-            if (j >= 0 && j < NL) acc += (int64_t)((uint64_t)a.v[i] * b.v[j]);
+            if (j >= 0 && j < NL) { acc += (int64_t)((uint64_t)a.v[i] * b.v[j]); chain<CHAIN>(acc); }
         }
-        red_terms(acc, m, c, k);
+        red_terms<CHAIN>(acc, m, c, k);
         if (c < NL)
             m[c] = (uint32_t)acc & LMASK;
         else
@@ -392,7 +406,8 @@ __device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) {
     return r;
 }
 
-__device__ __forceinline__ fe fe_sqr(const fe &a) {
+template <bool CHAIN>
+__device__ __forceinline__ fe fe_sqr_t(const fe &a) {
     const red_consts k = red_consts_make();
     uint32_t d[NL];
 #pragma unroll
@@ -405,10 +420,10 @@ __device__ __forceinline__ fe fe_sqr(const fe &a) {
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
             const int j = c - i;
-            if (i < j && j < NL) acc += (int64_t)((uint64_t)d[i] * a.v[j]);
+            if (i < j && j < NL) { acc += (int64_t)((uint64_t)d[i] * a.v[j]); chain<CHAIN>(acc); }
         }
-        if ((c & 1) == 0 && c / 2 < NL) acc += (int64_t)((uint64_t)a.v[c / 2] * a.v[c / 2]);
-        red_terms(acc, m, c, k);
+        if ((c & 1) == 0 && c / 2 < NL) { acc += (int64_t)((uint64_t)a.v[c / 2] * a.v[c / 2]); chain<CHAIN>(acc); }
+        red_terms<CHAIN>(acc, m, c, k);
         if (c < NL)
             m[c] = (uint32_t)acc & LMASK;
         else
@@ -419,8 +434,14 @@ __device__ __forceinline__ fe fe_sqr(const fe &a) {
     return r;
 }
 
+// one-chain forms for the point formulas, split forms for serial chains
+__device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) { return fe_mul_t<true>(a, b); }
+__device__ __forceinline__ fe fe_sqr(const fe &a) { return fe_sqr_t<true>(a); }
+__device__ __forceinline__ fe fe_mul_ilp(const fe &a, const fe &b) { return fe_mul_t<false>(a, b); }
+__device__ __forceinline__ fe fe_sqr_ilp(const fe &a) { return fe_sqr_t<false>(a); }
+
 __device__ __forceinline__ fe fe_sqr_n(fe a, int n) {
-    for (int i = 0; i < n; ++i) a = fe_sqr(a);
+    for (int i = 0; i < n; ++i) a = fe_sqr_ilp(a);
     return a;
 }
 
@@ -464,29 +485,29 @@ __device__ __forceinline__ void fe_to_words(const fe &a, uint32_t w[8]) {
     }
 }
 
-__device__ __forceinline__ fe fe_to_mont(const fe &a) { return fe_mul(a, fe_from29(R2_29)); }
+__device__ __forceinline__ fe fe_to_mont(const fe &a) { return fe_mul_ilp(a, fe_from29(R2_29)); }
 
 // Montgomery limbs -> canonical integer limbs in [0, p)
-__device__ __forceinline__ fe fe_from_mont(const fe &a) { return fe_canon(fe_mul(a, fe_from29(ONE29))); }
+__device__ __forceinline__ fe fe_from_mont(const fe &a) { return fe_canon(fe_mul_ilp(a, fe_from29(ONE29))); }
 
 // a^(p-2) = a^-1 for a != 0 (0 maps to 0).  p - 2 in 32-bit words from the
 // top: ffffffff 00000001 00000000 00000000 00000000 ffffffff ffffffff fffffffd.
 // x_k below is a^(2^k - 1); the chain uses 255 squarings and 12 products.
 __device__ __noinline__ fe fe_inv(const fe &a) {
     fe x1 = a;
-    fe x2 = fe_mul(fe_sqr(x1), x1);
-    fe x3 = fe_mul(fe_sqr(x2), x1);
-    fe x6 = fe_mul(fe_sqr_n(x3, 3), x3);
-    fe x12 = fe_mul(fe_sqr_n(x6, 6), x6);
-    fe x15 = fe_mul(fe_sqr_n(x12, 3), x3);
-    fe x30 = fe_mul(fe_sqr_n(x15, 15), x15);
-    fe x32 = fe_mul(fe_sqr_n(x30, 2), x2);
+    fe x2 = fe_mul_ilp(fe_sqr_ilp(x1), x1);
+    fe x3 = fe_mul_ilp(fe_sqr_ilp(x2), x1);
+    fe x6 = fe_mul_ilp(fe_sqr_n(x3, 3), x3);
+    fe x12 = fe_mul_ilp(fe_sqr_n(x6, 6), x6);
+    fe x15 = fe_mul_ilp(fe_sqr_n(x12, 3), x3);
+    fe x30 = fe_mul_ilp(fe_sqr_n(x15, 15), x15);
+    fe x32 = fe_mul_ilp(fe_sqr_n(x30, 2), x2);
     fe r = x32;                               // word 7: 32 ones
-    r = fe_mul(fe_sqr_n(r, 32), x1);          // word 6: 0x00000001
-    r = fe_mul(fe_sqr_n(r, 128), x32);        // words 5..3 zero, word 2: 32 ones
-    r = fe_mul(fe_sqr_n(r, 32), x32);         // word 1: 32 ones
-    r = fe_mul(fe_sqr_n(r, 30), x30);         // word 0: 30 ones,
-    r = fe_mul(fe_sqr_n(r, 2), x1);           //         then bits 0 1
+    r = fe_mul_ilp(fe_sqr_n(r, 32), x1);          // word 6: 0x00000001
+    r = fe_mul_ilp(fe_sqr_n(r, 128), x32);        // words 5..3 zero, word 2: 32 ones
+    r = fe_mul_ilp(fe_sqr_n(r, 32), x32);         // word 1: 32 ones
+    r = fe_mul_ilp(fe_sqr_n(r, 30), x30);         // word 0: 30 ones,
+    r = fe_mul_ilp(fe_sqr_n(r, 2), x1);           //         then bits 0 1
     return r;
 }
 

@@ -28,7 +28,7 @@ __device__ __forceinline__ void normalize_points(const uint32_t *in, int64_t ld_
         for (int pt = 0; pt < npts; ++pt, ++slot) {
             fe z = IN_MONT ? soa_load_m(in, ld_in, pt * 3 + 2, e) : soa_load_mont(in, ld_in, pt * 3 + 2, e);
             soa_store_m(prefix, ld_pre, 0, t + (int64_t)slot * T, acc);
-            if (!fe_is_zero(z)) acc = fe_mul(acc, z);
+            if (!fe_is_zero(z)) acc = fe_mul_ilp(acc, z);
         }
     }
     if (slot == 0) return;
@@ -49,8 +49,8 @@ __device__ __forceinline__ void normalize_points(const uint32_t *in, int64_t ld_
             --slot;
             bool inf = fe_is_zero(P[pt].Z);
             fe pre = soa_load_m(prefix, ld_pre, 0, t + (int64_t)slot * T);
-            fe zinv = fe_mul(inv, pre);
-            if (!inf) inv = fe_mul(inv, P[pt].Z);
+            fe zinv = fe_mul_ilp(inv, pre);
+            if (!inf) inv = fe_mul_ilp(inv, P[pt].Z);
             A[pt] = jpt_to_affine_with(P[pt], zinv);
             if (inf) {
                 A[pt].x = fe_zero();

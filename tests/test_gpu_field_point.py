@@ -89,6 +89,18 @@ def test_point_ops_vs_oracle(dev, orc):
     Ps[4] = orc.INF
     Qs[4] = orc.INF
     Qs[5] = Ps[5]
+    # b is a square mod p, so (0, +-sqrt(b)) are curve points: an affine x of
+    # zero that is not the identity, as an operand and in P = Q and P = -Q
+    p_, b_ = orc.curve_params()[:2]
+    y0 = pow(b_, (p_ + 1) // 4, p_)
+    assert y0 * y0 % p_ == b_
+    X0 = bytes(32) + y0.to_bytes(32, "big")
+    X0n = bytes(32) + (p_ - y0).to_bytes(32, "big")
+    Ps[6] = X0
+    Qs[7] = X0
+    Ps[8], Qs[8] = X0, X0
+    Ps[9], Qs[9] = X0, X0n
+    Ps[10], Qs[10] = X0n, orc.INF
     PA, QA = _arr(Ps), _arr(Qs)
     for op in (0, 1):
         got = [_affine(j) for j in dev.diag_point(op, PA, QA)]

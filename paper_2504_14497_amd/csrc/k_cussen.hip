@@ -124,37 +124,45 @@ __device__ __forceinline__ void reg_store(uint32_t *regs, int rmax, int64_t n_la
 
 // One op of a group's straight-line program for output column j, point pt
 // and chain r: reads its operands (registers or the group's base points
-// B[k0 + t, j]) and writes its destination register.  Kept out of line so
-// that the kernel holds little state across it (higher occupancy).
-__device__ __noinline__ void run_op(const plan_op op, const uint32_t *__restrict__ B, int64_t ldb, int l, int k0,
-                                    int j, int pt, uint32_t *regs, int rmax, int64_t n_lanes, int r,
-                                    int64_t lane) {
+// B[k0 + t, j]) and writes its destination register.  The previous op's
+// result stays in VGPRs (`last`, register `last_reg`): a prefix sum's first
+// operand is the sum before it, so most operands need no reload.
+__device__ __forceinline__ jpt op_reg(const uint32_t *regs, int rmax, int64_t n_lanes, int r, int reg, int64_t lane,
+                                      const jpt &last, int last_reg) {
+    return reg == last_reg ? last : reg_load(regs, rmax, n_lanes, r, reg, lane);
+}
+
+__device__ __forceinline__ void run_op(const plan_op op, const uint32_t *__restrict__ B, int64_t ldb, int l, int k0,
+                                       int j, int pt, uint32_t *regs, int rmax, int64_t n_lanes, int r,
+                                       int64_t lane, jpt &last, int &last_reg) {
     jpt R;
     if (op.kind == OP_MUL) {
         const int s = op.s;
         const int bits = 32 - __builtin_clz((unsigned)s);
         R = ladder_small((uint32_t)s, bits, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
     } else if (op.a >= 0 && op.b >= 0) {
-        jpt Q = reg_load(regs, rmax, n_lanes, r, op.b, lane);
+        jpt Q = op_reg(regs, rmax, n_lanes, r, op.b, lane, last, last_reg);
         if (op.neg_b) Q = jpt_neg(Q);
-        R = jpt_add(reg_load(regs, rmax, n_lanes, r, op.a, lane), Q);
+        R = jpt_add(op_reg(regs, rmax, n_lanes, r, op.a, lane, last, last_reg), Q);
     } else if (op.b < 0) {
         apt Q = load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.b) * l + j);
         if (op.neg_b) Q = apt_neg(Q);
-        jpt P = op.a >= 0 ? reg_load(regs, rmax, n_lanes, r, op.a, lane)
+        jpt P = op.a >= 0 ? op_reg(regs, rmax, n_lanes, r, op.a, lane, last, last_reg)
                           : jpt_from_affine(load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
         R = jpt_add_affine(P, Q);
     } else {
         // a is a base point, b a register: a + (+-b) = (+-b) + a
-        jpt Q = reg_load(regs, rmax, n_lanes, r, op.b, lane);
+        jpt Q = op_reg(regs, rmax, n_lanes, r, op.b, lane, last, last_reg);
         if (op.neg_b) Q = jpt_neg(Q);
         R = jpt_add_affine(Q, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
     }
     reg_store(regs, rmax, n_lanes, r, op.dst, lane, R);
+    last = R;
+    last_reg = op.dst;
 }
 
 // Two wavefronts per SIMD (<= 256 VGPRs): the kernel waits on its register
-// scratch in HBM, and a second wavefront hides much of that latency.
+// file in HBM, and a second wavefront hides much of that latency.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) table_build_kernel(run_args a) {
     // the accumulation that follows on the stream starts its queue at zero
     if (blockIdx.x == 0 && threadIdx.x == 0) *at<int32_t>(a, a.ctr_off) = 0;
@@ -189,7 +197,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
         const int j = jslot + r * d.Lj;
         if (j >= l) break;
         last_r = r;
-        for (int o = ob; o < oe; ++o) run_op(ops[o], B, ldb, l, k0, j, pt, regs, rmax, n_lanes, r, lane);
+        jpt last = jpt_infinity();
+        int last_reg = -1;
+        for (int o = ob; o < oe; ++o)
+            run_op(ops[o], B, ldb, l, k0, j, pt, regs, rmax, n_lanes, r, lane, last, last_reg);
         // forward pass of the batched inversion over this table's register entries
         const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
         for (int e = 0; e < E; ++e) {

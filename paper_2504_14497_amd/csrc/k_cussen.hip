@@ -636,10 +636,10 @@ struct pcmm_plan_s {
     std::vector<stage_slot> ring;
     int ring_next = 0;
     ~pcmm_plan_s() {
-        if (pinned) hipHostFree(pinned);
+        if (pinned) (void)hipHostFree(pinned);  // destructors report nothing
         for (auto &r : ring) {
-            if (r.host) hipHostFree(r.host);
-            if (r.done) hipEventDestroy(r.done);
+            if (r.host) (void)hipHostFree(r.host);
+            if (r.done) (void)hipEventDestroy(r.done);
         }
     }
 };
@@ -972,7 +972,7 @@ struct stage_events {
     }
     ~stage_events() {
         for (auto &x : e)
-            if (x) hipEventDestroy(x);
+            if (x) (void)hipEventDestroy(x);
     }
 };
 
@@ -1071,7 +1071,7 @@ extern "C" pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t 
         (void)ws_bytes;
         if (sg.done) PCMM_HIP_TRY(hipEventSynchronize(sg.done));
         if (sg.bytes < bytes) {
-            if (sg.host) hipHostFree(sg.host);
+            if (sg.host) (void)hipHostFree(sg.host);
             sg.host = nullptr;
             sg.bytes = 0;
             PCMM_HIP_TRY(hipHostMalloc(&sg.host, bytes, hipHostMallocDefault));

@@ -11,6 +11,7 @@ derivation that both the library and the CPU reference implement.
 This module is shared by the tests, the benchmark and the CPU reference; it
 holds no curve, field or compression arithmetic.
 """
+import math
 from dataclasses import dataclass, field
 from typing import List
 
@@ -88,3 +89,68 @@ def batch_workload(count: int = 64, seed: int = 4, lo: int = 32, hi: int = 512,
         shapes.append(PCMMShape(m, n, l, bits, False, msg_bits, seed=seed * 1000003 + b,
                                 name=f"batch{b}"))
     return BatchWorkload(shapes=shapes, seed=seed)
+
+
+# ---------------------------------------------------------------------------
+# Paillier key material (inputs of the Paillier PC-MM; no PC-MM arithmetic)
+# ---------------------------------------------------------------------------
+_SMALL_PRIMES = [p for p in range(3, 2000, 2) if all(p % d for d in range(3, int(p ** 0.5) + 1, 2))]
+_KEY_CACHE = {}
+
+
+def _probable_prime(x: int, rng: np.random.Generator, rounds: int = 40) -> bool:
+    """Trial division by small primes, then Miller-Rabin with seeded bases."""
+    if x < 2 or x % 2 == 0:
+        return x == 2
+    for p in _SMALL_PRIMES:
+        if x % p == 0:
+            return x == p
+    d, s = x - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for _ in range(rounds):
+        a = 2 + int.from_bytes(rng.bytes((x.bit_length() + 7) // 8), "little") % (x - 3)
+        y = pow(a, d, x)
+        if y in (1, x - 1):
+            continue
+        for _ in range(s - 1):
+            y = y * y % x
+            if y == x - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def paillier_key(seed: int, bits: int = 3072):
+    """(n, p, q) for a Paillier key of `bits`-bit modulus n = p q: p and q are
+    distinct bits/2-bit primes with their top two bits set (so n has exactly
+    `bits` bits) and gcd(n, (p-1)(q-1)) = 1.  Candidates come from PCG64(seed);
+    cached per (seed, bits)."""
+    key = (seed, bits)
+    if key in _KEY_CACHE:
+        return _KEY_CACHE[key]
+    rng = rng_for(seed)
+    half = bits // 2
+
+    def prime():
+        while True:
+            x = int.from_bytes(rng.bytes(half // 8), "little")
+            x |= (3 << (half - 2)) | 1
+            x &= (1 << half) - 1
+            if _probable_prime(x, rng):
+                return x
+
+    while True:
+        p, q = prime(), prime()
+        n = p * q
+        if p != q and n.bit_length() == bits and math.gcd(n, (p - 1) * (q - 1)) == 1:
+            break
+    _KEY_CACHE[key] = (n, p, q)
+    return n, p, q
+
+
+def paillier_messages(rng: np.random.Generator, rows: int, cols: int, bits: int) -> np.ndarray:
+    """Uniform unsigned `bits`-bit messages (int32) for Paillier encryption."""
+    return rng.integers(0, 1 << bits, size=(rows, cols), dtype=np.int64).astype(np.int32)

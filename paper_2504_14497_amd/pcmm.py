@@ -156,6 +156,17 @@ _SIG = {
                           ctypes.c_char_p], _I32),
     "pcmm_diag_copy": ([_VP, _VP, _I64, _VP], _I32),
     "pcmm_diag_field_raw": ([_I32, _VP, _VP, _VP, _I64, _VP], _I32),
+    "pcmm_paillier_create": ([_VP, ctypes.POINTER(_VP)], _I32),
+    "pcmm_paillier_destroy": ([_VP], _I32),
+    "pcmm_paillier_encrypt": ([_VP, _VP, _I64, ctypes.c_uint64, _I64, _VP, _VP], _I32),
+    "pcmm_paillier_schoolbook_workspace": ([_I32, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "pcmm_paillier_schoolbook": ([_VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP], _I32),
+    "pcmm_paillier_cussen_workspace": ([_VP, _I32, _I32, _I32, _I32, ctypes.POINTER(CussenCfg),
+                                        ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "pcmm_paillier_cussen": ([_VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, ctypes.POINTER(CussenCfg), _VP,
+                              ctypes.c_size_t, ctypes.POINTER(CussenStats), _VP], _I32),
+    "pcmm_paillier_diag": ([_VP, _I32, _VP, _VP, _VP, _I64, _VP], _I32),
+    "pcmm_paillier_diag_constants": ([_VP, _VP, _VP, _VP, _VP], _I32),
 }
 
 EXPORTED = tuple(_SIG)

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_functions():
     names = set()
-    for h in ("pcmm.h", "pcmm_diag.h"):
+    for h in ("pcmm.h", "pcmm_diag.h", "pcmm_paillier.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         for mt in re.finditer(r"\b(pcmm_[a-z0-9_]+)\s*\(", text):

@@ -230,6 +230,70 @@ def vector_leg(ms, ts, l_batch, reps):
             "context": "paper (Raspberry Pi 5, m = 512, t = 4): schoolbook 59153.174 us, Cussen 399.094 us"}
 
 
+# algorithmic 32x32 multiply-adds of one 6144-bit Montgomery product (192
+# words: 192^2 for the product and 192^2 for the reduction, operand scanning)
+MADS_PAILLIER_MUL = 2 * 192 * 192
+
+
+def paillier_leg(m, n, l, bits, reps, school_reps):
+    """Paillier PC-MM (Sec. "Extension to Paillier Encryption"), 3072-bit n:
+    GPU encryption of the n x l ciphertexts (6148 products mod n^2 each,
+    which gives the per-product rate), then Cussen and schoolbook PC-MM of an
+    m x n unsigned bits-bit A on them."""
+    import numpy as np
+    import torch
+    from paper_2504_14497_amd import paillier, pcmm, workloads as W
+    stream = torch.cuda.current_stream()
+    key_seed = 41
+    t0 = time.time()
+    nmod, _, _ = W.paillier_key(key_seed)
+    key_s = time.time() - t0
+    rng = W.rng_for(key_seed + 1)
+    A = W.gen_plain_matrix(rng, m, n, bits, False)
+    msg = torch.from_numpy(W.paillier_messages(rng, n, l, 16)).cuda()
+    ctx = paillier.Paillier(nmod)
+    B = ctx.encrypt(msg, seed=key_seed)
+    torch.cuda.synchronize()
+    enc_ms = time_region(lambda: ctx.encrypt(msg, seed=key_seed), 1, stream)
+    products_per_ct = 2 * 3072 + 4
+    mul_per_s = n * l * products_per_ct / (enc_ms * 1e-3)
+    cfg = pcmm.cussen_cfg(4, 1)
+    wsc = torch.empty(ctx.cussen_workspace_bytes(A, bits, l, cfg), dtype=torch.uint8, device="cuda")
+    C = torch.empty((m, l, paillier.WORDS), dtype=torch.int32, device="cuda")
+    Cc, st = ctx.cussen(A, bits, B, cfg=cfg, workspace=wsc, out=C)
+    Cs = ctx.schoolbook(A, bits, B)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(Cc, Cs))
+    ms_c = time_region(lambda: ctx.cussen(A, bits, B, cfg=cfg, workspace=wsc, out=C), reps, stream)
+    ms_s = time_region(lambda: ctx.schoolbook(A, bits, B), school_reps, stream)
+    # executed products mod n^2 per PC-MM: Alg. 4 powers of `level_mults`
+    # (<= 2 bits products each), table products, accumulation products, plus
+    # the conversions of B in and C out
+    cussen_products = l * (st["table_adds"] + st["accum_adds"]) + n * l + m * l
+    power_products = l * st["level_mults"] * 2 * bits
+    nz = int(np.count_nonzero(A))
+    school_products = l * nz * (2 * bits + 1) + n * l + m * l
+    tops = mul_per_s * MADS_PAILLIER_MUL / 1e12
+    return {"what": f"Paillier PC-MM, 3072-bit n (6144-bit ciphertexts): A {m}x{n} uniform unsigned {bits}-bit x "
+                    f"B {n}x{l} GPU-encrypted uniform 16-bit messages; Cussen N=4, g=1 vs schoolbook (Alg. 4 "
+                    "powers); canonical ciphertexts out",
+            "cussen": {"pcmm_per_s": 1e3 / ms_c, "ms": ms_c,
+                       "products_mod_n2": cussen_products + power_products,
+                       "products_per_s": (cussen_products + power_products) / (ms_c * 1e-3)},
+            "schoolbook": {"pcmm_per_s": 1e3 / ms_s, "ms": ms_s, "products_mod_n2": school_products,
+                           "products_per_s": school_products / (ms_s * 1e-3)},
+            "speedup_cussen_vs_schoolbook": ms_s / ms_c, "same_output": same,
+            "encrypt": {"ciphertexts_per_s": n * l / (enc_ms * 1e-3), "ms": enc_ms,
+                        "products_per_ciphertext": products_per_ct},
+            "product_rate": {"products_mod_n2_per_s": mul_per_s,
+                             "mads_per_product": MADS_PAILLIER_MUL,
+                             "achieved_TOPs": tops, "peak_TOPs": PEAK_INT32_MAD / 1e12,
+                             "frac": tops * 1e12 / PEAK_INT32_MAD,
+                             "source": "encryption kernel (the r^n power: 2 products per exponent bit)"},
+            "key_generation_s": key_s,
+            "context": "the paper reports no Paillier timings; it expects speedups similar to EC-ElGamal's"}
+
+
 def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
     """Encrypted linear layers served by the continuous-batching scheduler:
     4 static layers W (256 x 1024, uniform signed 8-bit, resident plans),
@@ -353,6 +417,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-PC-MM batch comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--no-vector", action="store_true", help="skip the vector x ciphertext-scalar microbench")
+    ap.add_argument("--no-paillier", action="store_true", help="skip the Paillier PC-MM leg")
+    ap.add_argument("--paillier-shape", default="64,64,64,4", help="m,n,l,bits of the Paillier PC-MM leg")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--serve-fractions", default="0.25,0.5,0.75,1.0,1.25",
                     help="arrival rates as fractions of the measured capacity")
@@ -525,6 +591,10 @@ def main():
         out["batch"] = batch_leg(args.batch_reps)
     if not args.no_vector:
         out["vector"] = vector_leg((8, 64, 512), (4, 8, 16), 4096, 20)
+    if not args.no_paillier:
+        pm, pn, pl_, pb = (int(x) for x in args.paillier_shape.split(","))
+        log("paillier leg", pm, pn, pl_, pb)
+        out["paillier"] = paillier_leg(pm, pn, pl_, pb, 3, 1)
     if not args.no_serve:
         torch.cuda.empty_cache()
         out["serving"] = serve_leg(args.serve_requests, [float(x) for x in args.serve_fractions.split(",")],

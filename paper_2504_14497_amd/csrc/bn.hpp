@@ -13,11 +13,12 @@
 // for i = 0 .. K-1, T <- (T + a_i b + q N) / 2^26 with q = -T N^-1 mod 2^26,
 // R = 2^(26 K), K = 240.  Every limb position of T is a 64-bit accumulator:
 // with operand limbs <= 2^26 + 1 a position gains less than 2^53 per
-// iteration, so 240 iterations never overflow and no carry moves during the
-// loop.  Only the lowest position must be divided exactly, and the division
-// by 2^26 moves every position down by one: within a lane that is a renaming
-// of the 4 registers over 4 unrolled iterations, across lanes one 64-bit
-// shuffle per iteration.  Three carry rounds then leave limbs <= 2^26 + 1.
+// iteration and 240 iterations never overflow it.  The division by 2^26
+// moves every position down by one: within a lane that is a renaming of the
+// 4 registers over 4 unrolled iterations; across lanes only the low 26 bits
+// of each lane's lowest position move (one 32-bit shuffle), its high part
+// staying in the lane's next position, which also keeps the accumulators
+// near 2^55.  Three carry rounds then leave limbs <= 2^26 + 1.
 // Since R >= 4 N, inputs below 2N give an output below 2N ("lazy" form, no
 // final subtraction between products); only the conversion out of
 // Montgomery form reduces fully, with carries and the borrow of the final
@@ -75,11 +76,14 @@ __device__ __forceinline__ bn bn_mont(const bn &a, const bn &b, const bn &N, uin
             const uint32_t q = (t0 * n0) & BN_MASK;
 #pragma unroll
             for (int t = 0; t < BN_W; ++t) acc[(t + w) & 3] += (uint64_t)q * N.v[t];
-            // position 0 (lane 0) is now divisible by 2^26: its quotient
-            // joins position 1, and every position moves down by one
-            if (lane == 0) acc[(w + 1) & 3] += acc[w] >> BN_LB;
-            const uint64_t up = __shfl_down(acc[w], 1);
-            acc[w] = lane == 63 ? 0 : up;
+            // position 0 (lane 0) is now divisible by 2^26.  Every lane
+            // splits its lowest register: the part above 2^26 joins the
+            // lane's next position, the low 26 bits move one lane down (as
+            // the lane below's top position after the division by 2^26);
+            // lane 0's low part is zero and drops out.
+            acc[(w + 1) & 3] += acc[w] >> BN_LB;
+            const uint32_t down = (uint32_t)__shfl_down((uint32_t)acc[w] & BN_MASK, 1);
+            acc[w] = lane == 63 ? 0u : down;
         }
     }
 #pragma unroll

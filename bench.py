@@ -254,9 +254,14 @@ def paillier_leg(m, n, l, bits, reps, school_reps):
     ctx = paillier.Paillier(nmod)
     B = ctx.encrypt(msg, seed=key_seed)
     torch.cuda.synchronize()
-    enc_ms = time_region(lambda: ctx.encrypt(msg, seed=key_seed), 1, stream)
+    # the product rate: encryption of 16384 ciphertexts (16 wavefronts per
+    # SIMD), 6148 products mod n^2 each (2 per bit of the 3072-bit exponent n)
+    enc_count = 16384
+    msg_rate = torch.from_numpy(W.paillier_messages(rng, 128, enc_count // 128, 16)).cuda()
+    ctx.encrypt(msg_rate, seed=key_seed + 2)
+    enc_ms = time_region(lambda: ctx.encrypt(msg_rate, seed=key_seed + 2), 3, stream)
     products_per_ct = 2 * 3072 + 4
-    mul_per_s = n * l * products_per_ct / (enc_ms * 1e-3)
+    mul_per_s = enc_count * products_per_ct / (enc_ms * 1e-3)
     cfg = pcmm.cussen_cfg(4, 1)
     wsc = torch.empty(ctx.cussen_workspace_bytes(A, bits, l, cfg), dtype=torch.uint8, device="cuda")
     C = torch.empty((m, l, paillier.WORDS), dtype=torch.int32, device="cuda")
@@ -283,13 +288,14 @@ def paillier_leg(m, n, l, bits, reps, school_reps):
             "schoolbook": {"pcmm_per_s": 1e3 / ms_s, "ms": ms_s, "products_mod_n2": school_products,
                            "products_per_s": school_products / (ms_s * 1e-3)},
             "speedup_cussen_vs_schoolbook": ms_s / ms_c, "same_output": same,
-            "encrypt": {"ciphertexts_per_s": n * l / (enc_ms * 1e-3), "ms": enc_ms,
+            "encrypt": {"ciphertexts_per_s": enc_count / (enc_ms * 1e-3), "ms": enc_ms, "count": enc_count,
                         "products_per_ciphertext": products_per_ct},
             "product_rate": {"products_mod_n2_per_s": mul_per_s,
                              "mads_per_product": MADS_PAILLIER_MUL,
                              "achieved_TOPs": tops, "peak_TOPs": PEAK_INT32_MAD / 1e12,
                              "frac": tops * 1e12 / PEAK_INT32_MAD,
-                             "source": "encryption kernel (the r^n power: 2 products per exponent bit)"},
+                             "source": "encryption kernel over 16384 ciphertexts (the r^n power: 2 products "
+                                       "per exponent bit), 3 timed launches"},
             "key_generation_s": key_s,
             "context": "the paper reports no Paillier timings; it expects speedups similar to EC-ElGamal's"}
 

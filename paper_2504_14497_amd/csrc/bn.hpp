@@ -16,7 +16,7 @@
 // iteration and 240 iterations never overflow it.  The division by 2^26
 // moves every position down by one: within a lane that is a renaming of the
 // 4 registers over 4 unrolled iterations; across lanes only the low 26 bits
-// of each lane's lowest position move (one 32-bit shuffle), its high part
+// of each lane's lowest position move (one 32-bit DPP move), its high part
 // staying in the lane's next position, which also keeps the accumulators
 // near 2^55.  Three carry rounds then leave limbs <= 2^26 + 1.
 // Since R >= 4 N, inputs below 2N give an output below 2N ("lazy" form, no
@@ -44,6 +44,23 @@ struct bn {
 
 __device__ __forceinline__ int bn_lane() { return (int)(threadIdx.x & 63); }
 
+// One-lane moves across the whole wavefront as DPP moves: wave_shl1 (lane L
+// reads lane L + 1) and wave_shr1 (lane L reads lane L - 1); with bound_ctrl
+// the lane without a source (63, resp. 0) reads zero.
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
+__device__ __forceinline__ uint32_t lane_from_above(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_WAVE_SHL1, 0xF, 0xF, true);
+}
+
+__device__ __forceinline__ uint64_t lane_from_below(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, DPP_WAVE_SHR1, 0xF, 0xF, true);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), DPP_WAVE_SHR1, 0xF, 0xF, true);
+    return (uint64_t)hi << 32 | lo;
+}
+
 __device__ __forceinline__ bn bn_load(const uint32_t *__restrict__ p) {
     const uint4 x = ((const uint4 *)p)[bn_lane()];
     return bn{{x.x, x.y, x.z, x.w}};
@@ -63,7 +80,6 @@ __device__ __forceinline__ bn bn_select(bool c, const bn &a, const bn &b) {
 // Montgomery product a b R^-1 (mod N) for a, b < 2N with limbs <= 2^26 + 1;
 // the result is below 2N with limbs <= 2^26 + 1.  n0 = -N^-1 mod 2^32.
 __device__ __forceinline__ bn bn_mont(const bn &a, const bn &b, const bn &N, uint32_t n0) {
-    const int lane = bn_lane();
     uint64_t acc[BN_W] = {0, 0, 0, 0};
     for (int s = 0; s < BN_K / BN_W; ++s) {
 #pragma unroll
@@ -82,8 +98,7 @@ __device__ __forceinline__ bn bn_mont(const bn &a, const bn &b, const bn &N, uin
             // the lane below's top position after the division by 2^26);
             // lane 0's low part is zero and drops out.
             acc[(w + 1) & 3] += acc[w] >> BN_LB;
-            const uint32_t down = (uint32_t)__shfl_down((uint32_t)acc[w] & BN_MASK, 1);
-            acc[w] = lane == 63 ? 0u : down;
+            acc[w] = lane_from_above((uint32_t)acc[w] & BN_MASK);
         }
     }
 #pragma unroll
@@ -94,8 +109,7 @@ __device__ __forceinline__ bn bn_mont(const bn &a, const bn &b, const bn &N, uin
             c[t] = acc[t] >> BN_LB;
             acc[t] &= BN_MASK;
         }
-        const uint64_t in = __shfl_up(c[BN_W - 1], 1);
-        acc[0] += lane == 0 ? 0 : in;
+        acc[0] += lane_from_below(c[BN_W - 1]);
 #pragma unroll
         for (int t = 1; t < BN_W; ++t) acc[t] += c[t - 1];
     }

@@ -144,8 +144,7 @@ __global__ void __launch_bounds__(256) encrypt_kernel(const paillier_consts *__r
             c[t] = acc[t] >> BN_LB;
             acc[t] &= BN_MASK;
         }
-        const uint64_t in = __shfl_up(c[BN_W - 1], 1);
-        acc[0] += w.lane == 0 ? 0 : in;
+        acc[0] += lane_from_below(c[BN_W - 1]);
 #pragma unroll
         for (int t = 1; t < BN_W; ++t) acc[t] += c[t - 1];
     }

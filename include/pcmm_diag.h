@@ -70,7 +70,7 @@ pcmm_status pcmm_diag_device(int32_t *cus, int32_t *clock_khz, int64_t *lds_per_
 
 /* Paillier arithmetic mod n^2 of a context (pcmm_paillier.h), element-wise
  * over count residues given as canonical 192-word values (below n^2):
- * op 0 the raw Montgomery product a b R^-1 with R = 2^6240, 1 the product
+ * op 0 the raw Montgomery product a b R^-1 with R = 2^6148, 1 the product
  * a b, 2 the power a^k by Alg. 4 with k = word 0 of b (32-bit exponent),
  * 3 the power a^n (the encryption's 3072-bit exponent); all results
  * canonical (mod n^2). */
@@ -78,7 +78,7 @@ pcmm_status pcmm_paillier_diag(pcmm_paillier ctx, int32_t op, const uint32_t *a,
                                uint32_t *out, int64_t count, void *stream);
 
 /* The host-side constants of a Paillier modulus n (384 big-endian bytes), as
- * 256 limbs of 26 bits each: n^2, R mod n^2 and R^2 mod n^2 for R = 2^6240,
+ * 256 limbs of 29 bits each: n^2, R mod n^2 and R^2 mod n^2 for R = 2^6148,
  * and n0 = -(n^2)^-1 mod 2^32.  No device work; EINVAL unless n is odd with
  * 3072 bits. */
 pcmm_status pcmm_paillier_diag_constants(const uint8_t *n_be, uint32_t *N_limbs, uint32_t *one_limbs,

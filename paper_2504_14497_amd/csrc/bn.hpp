@@ -5,20 +5,21 @@
 // point addition by multiplication mod n^2 and scalar multiplication by
 // exponentiation (Alg. 4).  For a 3072-bit n, a residue mod n^2 has 6144
 // bits: far too many for one lane, so a wavefront of 64 lanes holds one
-// residue, lane L owning limbs 4L .. 4L + 3 of 26 bits each (256 limbs,
-// 6656 bits).  All 64 lanes of a wavefront call these functions together
+// residue, lane L owning limbs 4L .. 4L + 3 of 29 bits each (256 limbs,
+// 7424 bits; 212 of them carry a residue below 2^6148).  All 64 lanes of a wavefront call these functions together
 // with the same modulus; values and exponents are uniform per wavefront.
 //
 // Montgomery multiplication (operand scanning, the reduction interleaved):
-// for i = 0 .. K-1, T <- (T + a_i b + q N) / 2^26 with q = -T N^-1 mod 2^26,
-// R = 2^(26 K), K = 240.  Every limb position of T is a 64-bit accumulator:
-// with operand limbs <= 2^26 + 1 a position gains less than 2^53 per
-// iteration and 240 iterations never overflow it.  The division by 2^26
-// moves every position down by one: within a lane that is a renaming of the
-// 4 registers over 4 unrolled iterations; across lanes only the low 26 bits
-// of each lane's lowest position move (one 32-bit DPP move), its high part
-// staying in the lane's next position, which also keeps the accumulators
-// near 2^55.  Three carry rounds then leave limbs <= 2^26 + 1.
+// for i = 0 .. K-1, T <- (T + a_i b + q N) / 2^29 with q = -T N^-1 mod 2^29,
+// R = 2^(29 K), K = 212.  Every limb position of T is a 64-bit accumulator
+// that gains two products (each below 2^58 + 2^31 for operand limbs
+// <= 2^29 + 1) per iteration.  The division by 2^29 moves every position
+// down by one: within a lane that is a renaming of the 4 registers over 4
+// unrolled iterations; across lanes only the low 29 bits of each lane's
+// lowest position move (one 32-bit DPP move), its high part joining the
+// lane's next position.  So every register is split once per 4 iterations
+// and never holds more than about 8 products (below 2^62).  Three carry
+// rounds then leave limbs <= 2^29 + 1.
 // Since R >= 4 N, inputs below 2N give an output below 2N ("lazy" form, no
 // final subtraction between products); only the conversion out of
 // Montgomery form reduces fully, with carries and the borrow of the final
@@ -29,11 +30,11 @@
 
 namespace pcmm {
 
-constexpr int BN_LB = 26;
+constexpr int BN_LB = 29;
 constexpr uint32_t BN_MASK = (1u << BN_LB) - 1;
 constexpr int BN_W = 4;           // limbs per lane
 constexpr int BN_LIMBS = 256;     // limbs per residue (64 lanes)
-constexpr int BN_K = 240;         // Montgomery iterations: R = 2^(26 * 240)
+constexpr int BN_K = 212;         // Montgomery iterations: R = 2^(29 * 212) = 2^6148
 constexpr int BN_WORDS = 192;     // 32-bit words of a residue mod n^2
 constexpr int BN_NWORDS = 96;     // 32-bit words of n
 
@@ -77,8 +78,8 @@ __device__ __forceinline__ bn bn_select(bool c, const bn &a, const bn &b) {
     return r;
 }
 
-// Montgomery product a b R^-1 (mod N) for a, b < 2N with limbs <= 2^26 + 1;
-// the result is below 2N with limbs <= 2^26 + 1.  n0 = -N^-1 mod 2^32.
+// Montgomery product a b R^-1 (mod N) for a, b < 2N with limbs <= 2^29 + 1;
+// the result is below 2N with limbs <= 2^29 + 1.  n0 = -N^-1 mod 2^32.
 __device__ __forceinline__ bn bn_mont(const bn &a, const bn &b, const bn &N, uint32_t n0) {
     uint64_t acc[BN_W] = {0, 0, 0, 0};
     for (int s = 0; s < BN_K / BN_W; ++s) {
@@ -92,10 +93,10 @@ __device__ __forceinline__ bn bn_mont(const bn &a, const bn &b, const bn &N, uin
             const uint32_t q = (t0 * n0) & BN_MASK;
 #pragma unroll
             for (int t = 0; t < BN_W; ++t) acc[(t + w) & 3] += (uint64_t)q * N.v[t];
-            // position 0 (lane 0) is now divisible by 2^26.  Every lane
-            // splits its lowest register: the part above 2^26 joins the
-            // lane's next position, the low 26 bits move one lane down (as
-            // the lane below's top position after the division by 2^26);
+            // position 0 (lane 0) is now divisible by 2^29.  Every lane
+            // splits its lowest register: the part above 2^29 joins the
+            // lane's next position, the low 29 bits move one lane down (as
+            // the lane below's top position after the division by 2^29);
             // lane 0's low part is zero and drops out.
             acc[(w + 1) & 3] += acc[w] >> BN_LB;
             acc[w] = lane_from_above((uint32_t)acc[w] & BN_MASK);
@@ -129,7 +130,7 @@ __device__ __forceinline__ bool bn_lookahead(bool gen, bool prop, bool *out) {
     return ((S ^ X ^ G) >> bn_lane()) & 1;
 }
 
-// exact limbs (< 2^26) of a value with limbs <= 2^26 + 1 (below 2^6656)
+// exact limbs (< 2^29) of a value with limbs <= 2^29 + 1 (below 2^7424)
 __device__ __forceinline__ bn bn_carry_exact(const bn &x) {
     bn s0, s1;
     uint32_t c0 = 0, c1 = 1;
@@ -155,7 +156,7 @@ __device__ __forceinline__ bn bn_sub_if_ge(const bn &x, const bn &N, bool *ge) {
         const uint32_t v0 = x.v[t] - N.v[t] - b0, v1 = x.v[t] - N.v[t] - b1;
         d0.v[t] = v0 & BN_MASK;
         d1.v[t] = v1 & BN_MASK;
-        b0 = v0 >> 31;  // limbs < 2^26: a negative difference has its top bit set
+        b0 = v0 >> 31;  // limbs < 2^29: a negative difference has its top bit set
         b1 = v1 >> 31;
     }
     bool borrow_out;
@@ -164,7 +165,7 @@ __device__ __forceinline__ bn bn_sub_if_ge(const bn &x, const bn &N, bool *ge) {
     return borrow_out ? x : bn_select(bin, d0, d1);
 }
 
-// canonical residue (< N, exact limbs) of a value below 2N with limbs <= 2^26 + 1
+// canonical residue (< N, exact limbs) of a value below 2N with limbs <= 2^29 + 1
 __device__ __forceinline__ bn bn_canon(const bn &x, const bn &N) {
     bool ge;
     return bn_sub_if_ge(bn_carry_exact(x), N, &ge);

@@ -5,7 +5,7 @@
 // nonzero code), plus encryption c = (1 + m n) r^n mod n^2 (g = n + 1).
 //
 // One residue per wavefront (bn.hpp); blocks of 256 threads hold 4
-// independent wavefronts.  Internal residues are Montgomery limbs (256 x 26
+// independent wavefronts.  Internal residues are Montgomery limbs (256 x 29
 // bits, 1 KiB); at the boundary they are 192 canonical 32-bit words.
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -1,7 +1,7 @@
 """Paillier PC-MM on the GPU (Sec. "Extension to Paillier Encryption") against
 the Python-integer oracle, bit for bit:
 
-* the wavefront arithmetic mod n^2 (Montgomery product with R = 2^6240, the
+* the wavefront arithmetic mod n^2 (Montgomery product with R = 2^6148, the
   full product, Alg. 4 powers with 32-bit and 3072-bit exponents);
 * encryption with the counter-derived nonces;
 * schoolbook and Cussen PC-MM (N = 1..4 rounds, column groups 1..3, 4- to
@@ -32,7 +32,7 @@ def pl():
 def test_arithmetic_mod_n2(pl):
     paillier, ctx, (n, p, q) = pl
     N = n * n
-    R = 1 << 6240
+    R = 1 << 6148
     rnd = random.Random(5)
     a = [rnd.randrange(N) for _ in range(37)] + [0, 1, N - 1]
     b = [rnd.randrange(N) for _ in range(37)] + [N - 1, N - 1, N - 1]
@@ -121,3 +121,29 @@ def test_pcmm_degenerate_shapes(pl):
     with pytest.raises(paillier.PCMMError) as ei:
         ctx.cussen(np.array([[16]], dtype=np.uint8), 4, B[:1, :1].contiguous())
     assert ei.value.code == -2
+
+
+def test_pcmm_benchmark_shape_sampled(pl):
+    """The benchmark's 64 x 64 x 64 4-bit shape: Cussen equals schoolbook on
+    every output; sampled outputs equal the oracle's and decrypt to A msg."""
+    import torch
+    from oracle import paillier as P
+    from paper_2504_14497_amd import workloads as W
+    paillier, ctx, (n, p, q) = pl
+    n2 = n * n
+    rng = W.rng_for(43)
+    A = W.gen_plain_matrix(rng, 64, 64, 4, False)
+    msg = W.paillier_messages(rng, 64, 64, 16)
+    B = ctx.encrypt(torch.from_numpy(msg), seed=43)
+    log("paillier pcmm 64^3")
+    Cc, _ = ctx.cussen(A, 4, B)
+    Cs = ctx.schoolbook(A, 4, B)
+    torch.cuda.synchronize()
+    assert torch.equal(Cc, Cs)
+    Bi = paillier.download(B)
+    Ci = paillier.download(Cc)
+    for (i, j) in [(0, 0), (63, 63), (5, 40), (31, 7), (62, 1)]:
+        col = [[Bi[k * 64 + j]] for k in range(64)]
+        want = P.pcmm_schoolbook(A[i:i + 1].tolist(), col, n2, 4)[0][0]
+        assert Ci[i * 64 + j] == want
+        assert P.decrypt(p, q, want) == int(A[i].astype(np.int64) @ msg[:, j].astype(np.int64)) % n

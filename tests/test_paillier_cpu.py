@@ -1,6 +1,6 @@
 """Host-side checks of the Paillier PC-MM library (no GPU): the constants the
-library derives from a modulus n (n^2, R mod n^2, R^2 mod n^2 for R = 2^6240,
-and -(n^2)^-1 mod 2^32, as 26-bit limbs) equal those computed with Python
+library derives from a modulus n (n^2, R mod n^2, R^2 mod n^2 for R = 2^6148,
+and -(n^2)^-1 mod 2^32, as 29-bit limbs) equal those computed with Python
 integers, and bad moduli and arguments are rejected before any device work."""
 import ctypes
 
@@ -21,7 +21,7 @@ def _constants(n: int):
 
 
 def _value(limbs):
-    return sum(int(x) << (26 * i) for i, x in enumerate(limbs))
+    return sum(int(x) << (29 * i) for i, x in enumerate(limbs))
 
 
 @pytest.mark.parametrize("seed", [11, 12])
@@ -30,12 +30,12 @@ def test_modulus_constants(seed):
     N = n * n
     rc, (Nl, one, r2), n0 = _constants(n)
     assert rc == 0
-    R = 1 << 6240
+    R = 1 << 6148
     assert _value(Nl) == N
     assert _value(one) == R % N
     assert _value(r2) == R * R % N
     assert (N * n0 + 1) % (1 << 32) == 0
-    assert all(int(x) < (1 << 26) for a in (Nl, one, r2) for x in a)
+    assert all(int(x) < (1 << 29) for a in (Nl, one, r2) for x in a)
 
 
 def test_bad_moduli_rejected():

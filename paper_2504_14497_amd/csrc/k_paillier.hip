@@ -83,7 +83,7 @@ __device__ __forceinline__ void from_mont(const bn &x, uint32_t *__restrict__ wo
 // Kernels
 // --------------------------------------------------------------------------
 // canonical ciphertexts -> Montgomery limbs
-__global__ void __launch_bounds__(256) to_mont_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
+__global__ void __launch_bounds__(256) paillier_to_mont_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
                                                       const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                                                       int64_t count) {
     __shared__ uint32_t lds[WAVES_PER_BLOCK * BN_LIMBS];
@@ -102,7 +102,7 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 
 // c = (1 + m n) r^n mod n^2 for element e: r from 48 SplitMix64 words of
 // (seed, domain 2, idx0 + e), reduced mod n (0 -> 1)
-__global__ void __launch_bounds__(256) encrypt_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
+__global__ void __launch_bounds__(256) paillier_encrypt_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
                                                       const int32_t *__restrict__ msg, int64_t count,
                                                       uint64_t seed, int64_t idx0, uint32_t *__restrict__ ct) {
     __shared__ uint32_t lds[WAVES_PER_BLOCK * BN_LIMBS];
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256) encrypt_kernel(const paillier_consts *__r
 }
 
 // schoolbook: one wavefront per output (i, j), i fastest
-__global__ void __launch_bounds__(256) schoolbook_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
+__global__ void __launch_bounds__(256) paillier_schoolbook_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
                                                          const uint16_t *__restrict__ A, int m, int n, int l,
                                                          int bits, const uint32_t *__restrict__ Bm,
                                                          uint32_t *__restrict__ C) {
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) schoolbook_kernel(const paillier_consts *
 // Cussen table build: one wavefront per (group, output column j) runs the
 // group's straight-line program (MUL: an Alg. 4 power of a base; ADD: a
 // product of two operands) into its register file
-__global__ void __launch_bounds__(256) table_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
+__global__ void __launch_bounds__(256) paillier_table_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
                                                    const plan_op *__restrict__ ops,
                                                    const int32_t *__restrict__ op_begin, int ngroups, int g,
                                                    int l, int rmax, const uint32_t *__restrict__ Bm,
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(256) table_kernel(const paillier_consts *__res
 
 // Cussen accumulation: one wavefront per output (i, j), i fastest; the
 // product over the groups of the table entry each row segment's code names
-__global__ void __launch_bounds__(256) accumulate_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
+__global__ void __launch_bounds__(256) paillier_accumulate_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
                                                          const int16_t *__restrict__ codes,
                                                          const int32_t *__restrict__ entry_begin,
                                                          const int16_t *__restrict__ entries, int m, int ngroups,
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(256) accumulate_kernel(const paillier_consts *
 
 // diagnostics: 0 raw Montgomery product a b R^-1, 1 a b, 2 a^(b word 0) by
 // Alg. 4, 3 a^n (all mod n^2; canonical words in and out)
-__global__ void __launch_bounds__(256) diag_kernel(const paillier_consts *__restrict__ K, uint32_t n0, int op,
+__global__ void __launch_bounds__(256) paillier_diag_kernel(const paillier_consts *__restrict__ K, uint32_t n0, int op,
                                                    const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
                                                    uint32_t *__restrict__ out, int64_t count) {
     __shared__ uint32_t lds[WAVES_PER_BLOCK * BN_LIMBS];
@@ -475,7 +475,7 @@ pcmm_status pcmm_paillier_encrypt(pcmm_paillier ctx, const int32_t *msg_dev, int
     if (!ctx || count < 0 || (count > 0 && (!msg_dev || !ct_dev))) return PCMM_EINVAL;
     if (!count) return PCMM_OK;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(encrypt_kernel, dim3(blocks_for(count)), dim3(256), 0, s, ctx->d_consts, ctx->n0, msg_dev,
+    hipLaunchKernelGGL(paillier_encrypt_kernel, dim3(blocks_for(count)), dim3(256), 0, s, ctx->d_consts, ctx->n0, msg_dev,
                        count, seed, idx0, ct_dev);
     PCMM_LAUNCH_CHECK();
     return PCMM_OK;
@@ -505,10 +505,10 @@ pcmm_status pcmm_paillier_schoolbook(pcmm_paillier ctx, const void *A, int32_t m
     uint16_t *Ad = (uint16_t *)(ws + align256((size_t)n * l * BN_BYTES));
     st = upload(Ad, a16.data(), a16.size() * 2, s);
     if (st) return st;
-    hipLaunchKernelGGL(to_mont_kernel, dim3(blocks_for((int64_t)n * l)), dim3(256), 0, s, ctx->d_consts, ctx->n0, B,
+    hipLaunchKernelGGL(paillier_to_mont_kernel, dim3(blocks_for((int64_t)n * l)), dim3(256), 0, s, ctx->d_consts, ctx->n0, B,
                        Bm, (int64_t)n * l);
     PCMM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(schoolbook_kernel, dim3(blocks_for((int64_t)m * l)), dim3(256), 0, s, ctx->d_consts,
+    hipLaunchKernelGGL(paillier_schoolbook_kernel, dim3(blocks_for((int64_t)m * l)), dim3(256), 0, s, ctx->d_consts,
                        ctx->n0, Ad, m, n, l, bits, Bm, C);
     PCMM_LAUNCH_CHECK();
     return PCMM_OK;
@@ -563,16 +563,16 @@ pcmm_status pcmm_paillier_cussen(pcmm_paillier ctx, const void *A, int32_t m, in
     uint32_t *Bm = (uint32_t *)(ws + L.off_bm);
     uint32_t *regs = (uint32_t *)(ws + L.off_regs);
     const int rmax = std::max(P.max_regs, 1);
-    hipLaunchKernelGGL(to_mont_kernel, dim3(blocks_for((int64_t)n * l)), dim3(256), 0, s, ctx->d_consts, ctx->n0, B,
+    hipLaunchKernelGGL(paillier_to_mont_kernel, dim3(blocks_for((int64_t)n * l)), dim3(256), 0, s, ctx->d_consts, ctx->n0, B,
                        Bm, (int64_t)n * l);
     PCMM_LAUNCH_CHECK();
     if (!P.ops.empty()) {
-        hipLaunchKernelGGL(table_kernel, dim3(blocks_for((int64_t)P.ngroups * l)), dim3(256), 0, s, ctx->d_consts,
+        hipLaunchKernelGGL(paillier_table_kernel, dim3(blocks_for((int64_t)P.ngroups * l)), dim3(256), 0, s, ctx->d_consts,
                            ctx->n0, (const plan_op *)(ws + L.off_ops), (const int32_t *)(ws + L.off_opb),
                            P.ngroups, P.g, l, rmax, (const uint32_t *)Bm, regs);
         PCMM_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(accumulate_kernel, dim3(blocks_for((int64_t)m * l)), dim3(256), 0, s, ctx->d_consts, ctx->n0,
+    hipLaunchKernelGGL(paillier_accumulate_kernel, dim3(blocks_for((int64_t)m * l)), dim3(256), 0, s, ctx->d_consts, ctx->n0,
                        (const int16_t *)(ws + L.off_codes), (const int32_t *)(ws + L.off_entb),
                        (const int16_t *)(ws + L.off_ent), m, P.ngroups, P.g, l, rmax, (const uint32_t *)Bm,
                        (const uint32_t *)regs, C);
@@ -585,7 +585,7 @@ pcmm_status pcmm_paillier_diag(pcmm_paillier ctx, int32_t op, const uint32_t *a,
     if (!ctx || op < 0 || op > 3 || count < 0) return PCMM_EINVAL;
     if (count > 0 && (!a || !b || !out)) return PCMM_EINVAL;
     if (!count) return PCMM_OK;
-    hipLaunchKernelGGL(diag_kernel, dim3(blocks_for(count)), dim3(256), 0, (hipStream_t)stream, ctx->d_consts,
+    hipLaunchKernelGGL(paillier_diag_kernel, dim3(blocks_for(count)), dim3(256), 0, (hipStream_t)stream, ctx->d_consts,
                        ctx->n0, op, a, b, out, count);
     PCMM_LAUNCH_CHECK();
     return PCMM_OK;

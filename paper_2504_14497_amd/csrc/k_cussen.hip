@@ -290,8 +290,12 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
             const int chunk = bz * d.chunks_per_split + (gc - g_begin) / d.kc;
             const int len = chunk_len[chunk];
             const int32_t *lst = lists + chunk_off[chunk] * m + i;
+            // the next slot's code is loaded one addition ahead, so its
+            // memory latency overlaps the current point addition
+            int32_t v_next = len > 0 ? lst[0] : 0;
             for (int it = 0; it < len; ++it) {
-                const int32_t v = lst[(int64_t)it * m];
+                const int32_t v = v_next;
+                if (it + 1 < len) v_next = lst[(int64_t)(it + 1) * m];
                 const int code = (int16_t)(v & 0xFFFF);
                 if (code == 0) continue;
                 const int kk = v >> 16;

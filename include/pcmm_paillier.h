@@ -23,7 +23,8 @@
  *
  * Ownership: device buffers (messages, ciphertexts, workspace) belong to the
  * caller.  A context owns a small device block with the modulus constants
- * (allocated on the device current at creation) until it is destroyed.
+ * (allocated on the device current at creation) until it is destroyed; its
+ * calls must run with that device current (PCMM_EINVAL otherwise).
  * Calls enqueue their kernels on `stream` (a hipStream_t; NULL = default)
  * and return without waiting for them, except that the PC-MM calls copy their
  * host-side plan (and A) to the workspace first and wait for that copy.

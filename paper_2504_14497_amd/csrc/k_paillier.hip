@@ -93,6 +93,13 @@ __global__ void __launch_bounds__(256) paillier_to_mont_kernel(const paillier_co
     bn_store(out + w.inst * BN_LIMBS, to_mont(in + w.inst * BN_WORDS, *K, N, n0, w.lds));
 }
 
+// the identity ciphertext 1 (canonical words) in `count` elements
+__global__ void __launch_bounds__(256) paillier_identity_kernel(uint32_t *__restrict__ out, int64_t count) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= count * BN_WORDS) return;
+    out[x] = (x % BN_WORDS) == 0 ? 1u : 0u;
+}
+
 // SplitMix64 finaliser
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -338,6 +345,12 @@ pcmm_status plain_u16(const void *A, int m, int n, int bits, std::vector<uint16_
     return PCMM_OK;
 }
 
+// the context's constants live on the device it was created on
+bool on_ctx_device(const pcmm_paillier_s *ctx) {
+    int dev = -1;
+    return hipGetDevice(&dev) == hipSuccess && dev == ctx->device;
+}
+
 bool shapes_ok(const void *A, int m, int n, int l, int bits, const uint32_t *B, const uint32_t *C) {
     if (m < 0 || n < 0 || l < 0 || bits < 1 || bits > 16) return false;
     if ((int64_t)m * n > 0 && !A) return false;
@@ -361,11 +374,9 @@ pcmm_status upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
 // the identity ciphertext 1 into every element of C (canonical words)
 pcmm_status fill_identity(uint32_t *C, int64_t count, hipStream_t s) {
     if (!count) return PCMM_OK;
-    std::vector<uint32_t> one(BN_WORDS, 0u);
-    one[0] = 1;
-    for (int64_t e = 0; e < count; ++e)
-        PCMM_HIP_TRY(hipMemcpyAsync(C + e * BN_WORDS, one.data(), CT_BYTES, hipMemcpyHostToDevice, s));
-    PCMM_HIP_TRY(hipStreamSynchronize(s));
+    const int64_t words = count * BN_WORDS;
+    hipLaunchKernelGGL(paillier_identity_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, C, count);
+    PCMM_LAUNCH_CHECK();
     return PCMM_OK;
 }
 
@@ -473,6 +484,7 @@ pcmm_status pcmm_paillier_destroy(pcmm_paillier ctx) {
 pcmm_status pcmm_paillier_encrypt(pcmm_paillier ctx, const int32_t *msg_dev, int64_t count, uint64_t seed,
                                   int64_t idx0, uint32_t *ct_dev, void *stream) {
     if (!ctx || count < 0 || (count > 0 && (!msg_dev || !ct_dev))) return PCMM_EINVAL;
+    if (!on_ctx_device(ctx)) return PCMM_EINVAL;
     if (!count) return PCMM_OK;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(paillier_encrypt_kernel, dim3(blocks_for(count)), dim3(256), 0, s, ctx->d_consts, ctx->n0, msg_dev,
@@ -491,6 +503,7 @@ pcmm_status pcmm_paillier_schoolbook(pcmm_paillier ctx, const void *A, int32_t m
                                      int32_t bits, const uint32_t *B, uint32_t *C, void *workspace,
                                      size_t ws_bytes, void *stream) {
     if (!ctx || !shapes_ok(A, m, n, l, bits, B, C)) return PCMM_EINVAL;
+    if (!on_ctx_device(ctx)) return PCMM_EINVAL;
     std::vector<uint16_t> a16;
     pcmm_status st = plain_u16(A, m, n, bits, a16);
     if (st) return st;
@@ -528,6 +541,7 @@ pcmm_status pcmm_paillier_cussen(pcmm_paillier ctx, const void *A, int32_t m, in
                                  const uint32_t *B, uint32_t *C, const pcmm_cussen_cfg *cfg, void *workspace,
                                  size_t ws_bytes, pcmm_cussen_stats *stats, void *stream) {
     if (!ctx || !shapes_ok(A, m, n, l, bits, B, C)) return PCMM_EINVAL;
+    if (!on_ctx_device(ctx)) return PCMM_EINVAL;
     cussen_plan P;
     const int rc = build_cussen_plan(A, m, n, bits, false, cfg_rounds(cfg), cfg_group(cfg), &P);
     if (rc) return rc == -2 ? PCMM_ERANGE : PCMM_EINVAL;
@@ -583,6 +597,7 @@ pcmm_status pcmm_paillier_cussen(pcmm_paillier ctx, const void *A, int32_t m, in
 pcmm_status pcmm_paillier_diag(pcmm_paillier ctx, int32_t op, const uint32_t *a, const uint32_t *b,
                                uint32_t *out, int64_t count, void *stream) {
     if (!ctx || op < 0 || op > 3 || count < 0) return PCMM_EINVAL;
+    if (!on_ctx_device(ctx)) return PCMM_EINVAL;
     if (count > 0 && (!a || !b || !out)) return PCMM_EINVAL;
     if (!count) return PCMM_OK;
     hipLaunchKernelGGL(paillier_diag_kernel, dim3(blocks_for(count)), dim3(256), 0, (hipStream_t)stream, ctx->d_consts,

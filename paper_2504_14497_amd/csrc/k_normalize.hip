@@ -24,7 +24,10 @@ namespace pcmm {
 
 // number of threads and batch length for n_elem elements
 void normalize_geometry(int64_t n_elem, int64_t *threads, int *per_thread) {
-    const int64_t target_batch = 24;  // points per thread (inversion amortised over them)
+    // elements per thread: one inversion is amortised over them, but each
+    // thread is one serial chain (prefix products, the inversion, the way
+    // back), so the batch stays small enough to give the GPU many chains
+    const int64_t target_batch = 4;
     int64_t th = (n_elem + target_batch - 1) / target_batch;
     if (th < 1) th = 1;
     th = (th + 255) / 256 * 256;

@@ -162,3 +162,23 @@ def test_null_and_shape_errors_are_host_side():
     rc = L.pcmm_decrypt_to_points(bytes(32), ctypes.byref(B), ctypes.byref(M), None)
     assert rc == -1
     assert L.pcmm_normalize_workspace(1000, 2) >= 1000 * 2 * 32
+
+
+# property-based: random shapes, bit-widths, signedness and rounds
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(m=st.integers(1, 70), n=st.integers(1, 9), bits=st.integers(1, 16), signed=st.booleans(),
+       N=st.integers(1, 6), seed=st.integers(0, 2**31 - 1), zero_frac=st.floats(0.0, 0.9))
+def test_plan_counts_property(orc, m, n, bits, signed, N, seed, zero_frac):
+    rng = np.random.default_rng(seed)
+    A = W.gen_plain_matrix(rng, m, n, bits, signed)
+    A[rng.random(A.shape) < zero_frac] = 0
+    st_ = pcmm.cussen_plan_stats(A, bits, pcmm.CussenCfg(N, 1, 0, 0))
+    muls, adds = _oracle_column_counts(orc, A, N)
+    assert st_["level_mults"] == muls
+    assert st_["level_adds"] == adds
+    assert st_["accum_adds"] == int(np.count_nonzero(A))
+    distinct = sum(len(set(np.abs(A[:, k].astype(int))) - {0}) for k in range(n))
+    assert st_["table_entries"] == distinct

@@ -4,8 +4,8 @@ the Python-integer oracle, bit for bit:
 * the wavefront arithmetic mod n^2 (Montgomery product with R = 2^6148, the
   full product, Alg. 4 powers with 32-bit and 3072-bit exponents);
 * encryption with the counter-derived nonces;
-* schoolbook and Cussen PC-MM (N = 1..4 rounds, column groups 1..3, 4- to
-  12-bit plaintexts, zero rows and columns, an empty inner dimension) equal
+* schoolbook and Cussen PC-MM (N = 1..4 rounds, column groups 1..4, 2- to
+  16-bit plaintexts, zero rows and columns, an empty inner dimension) equal
   the oracle's schoolbook result, and decrypt to A msg mod n.
 """
 import random
@@ -71,7 +71,8 @@ def _case(rng, m, k, l, bits, zero_row=False, zero_col=False):
 
 
 @pytest.mark.parametrize("m,k,l,bits,N,g", [(3, 5, 2, 4, 4, 1), (7, 6, 3, 8, 4, 1), (5, 9, 2, 4, 2, 2),
-                                            (4, 7, 2, 2, 1, 3), (6, 4, 2, 12, 3, 1), (9, 11, 1, 4, 4, 2)])
+                                            (4, 7, 2, 2, 1, 3), (6, 4, 2, 12, 3, 1), (9, 11, 1, 4, 4, 2),
+                                            (5, 6, 2, 16, 4, 1), (6, 5, 2, 3, 4, 4)])
 def test_pcmm_vs_oracle(pl, m, k, l, bits, N, g):
     import torch
     from oracle import paillier as P

@@ -9,8 +9,8 @@ table build with batched inversion, the gather-and-add accumulation and the
 affine normalisation of C, with A on the host and B already resident in HBM.
 The schoolbook method (Sec. 3.1) runs on the same inputs for the speedup.
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
-one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the benchmark runs
+on one GPU (the design of a sharded run is documented separately).
 """
 import argparse
 import hashlib
@@ -435,7 +435,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

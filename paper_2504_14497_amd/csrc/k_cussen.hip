@@ -489,6 +489,9 @@ struct job {
     bool fits = true;  // one column group's tables for one pair fit the LDS budget
 };
 
+// padded table-build lanes allowed (4 wavefronts per SIMD of a 256-CU device)
+constexpr int64_t PAD_LANES_MAX = 4 * 1024 * 64;
+
 void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     const cussen_plan &P = G.P;
     const int m = P.m, l = G.l;
@@ -501,8 +504,14 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     while (J > 1 && (int64_t)P.ngroups * 2 * ((l + J - 1) / J) < 16384) J /= 2;
     G.J = J;
     G.Lj = (l + J - 1) / J;
-    // lanes of one group fill whole wavefronts (uniform control flow) when possible
+    // lanes of one group fill whole wavefronts (uniform control flow) when
+    // possible.  With few output columns a group's chains fill less than a
+    // wavefront; packing several groups into one wavefront would run their
+    // different programs divergently, so each group is padded to a whole
+    // wavefront as long as that keeps the grid small (the build is then
+    // bound by its chains' latency, not by lanes).
     if (2 * G.Lj >= 64) G.Lj = (G.Lj + 31) / 32 * 32;
+    else if ((int64_t)P.ngroups * 64 <= PAD_LANES_MAX) G.Lj = 32;
     G.n_lanes = (int64_t)P.ngroups * 2 * G.Lj;
     // accumulation tile
     const int npairs = 2 * l;

@@ -127,13 +127,14 @@ constexpr int JAC2_PLANES = 2 * 3 * NL;
 // Alg. 1 (Montgomery ladder) over the low t bits of k, most significant
 // first: R0 <- inf, R1 <- P; per bit b: R_{1-b} <- R0 + R1, R_b <- 2 R_b.
 // Branch-free per lane (lanes may hold different k; t is uniform).
+template <bool CHAIN = true>
 __device__ __forceinline__ jpt ladder_small(uint32_t k, int t, const apt &P) {
     jpt R0 = jpt_infinity();
     jpt R1 = jpt_from_affine(P);
     for (int i = t - 1; i >= 0; --i) {
         bool b = (k >> i) & 1u;
-        jpt S = jpt_add(R1, R0);
-        jpt D = jpt_dbl(jpt_select(b, R0, R1));
+        jpt S = jpt_add<CHAIN>(R1, R0);
+        jpt D = jpt_dbl<CHAIN>(jpt_select(b, R0, R1));
         R0 = jpt_select(b, D, S);
         R1 = jpt_select(b, S, D);
     }

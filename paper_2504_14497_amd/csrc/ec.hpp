@@ -81,30 +81,37 @@ __device__ __forceinline__ jpt jpt_neg(const jpt &P) {
     return r;
 }
 
+// The template parameter CHAIN of the point operations selects the product
+// form of fp.hpp: one multiply-add chain per column (the default, for the
+// accumulation, whose independent products hide the chains' latency) or the
+// split form (for latency-bound callers such as the table build).
+
 // 2P, a = -3 (dbl-2001-b).  Z = 0 stays Z = 0.  Lazy reduction as in
 // jpt_add_affine: X1 -+ delta stay carry-only (their product is below
 // 16 p^2), X3 = alpha^2 - 8 beta and Y3 = alpha (4 beta - X3) - 8 gamma^2 are
 // one limb pass plus one normalisation each, and Z3 = (Y1 + Z1)^2 - gamma -
 // delta is computed as the equal 2 Y1 Z1.
+template <bool CHAIN = true>
 __device__ __forceinline__ jpt jpt_dbl(const jpt &P) {
-    fe delta = fe_sqr(P.Z);
-    fe gamma = fe_sqr(P.Y);
-    fe beta = fe_mul(P.X, gamma);
-    fe alpha = fe_mul3(fe_mul(fe_sub_w(P.X, delta), fe_add_w(P.X, delta)));  // 3 (X - delta)(X + delta)
+    fe delta = fe_sqr_t<CHAIN>(P.Z);
+    fe gamma = fe_sqr_t<CHAIN>(P.Y);
+    fe beta = fe_mul_t<CHAIN>(P.X, gamma);
+    fe alpha = fe_mul3(fe_mul_t<CHAIN>(fe_sub_w(P.X, delta), fe_add_w(P.X, delta)));  // 3 (X - delta)(X + delta)
     jpt R;
     fe beta4 = fe_mul4(beta);
-    R.X = fe_sub2x(fe_sqr(alpha), beta4);
-    R.Z = fe_dbl(fe_mul(P.Y, P.Z));
-    R.Y = fe_sub2x(fe_mul(alpha, fe_sub_w(beta4, R.X)), fe_mul4(fe_sqr(gamma)));
+    R.X = fe_sub2x(fe_sqr_t<CHAIN>(alpha), beta4);
+    R.Z = fe_dbl(fe_mul_t<CHAIN>(P.Y, P.Z));
+    R.Y = fe_sub2x(fe_mul_t<CHAIN>(alpha, fe_sub_w(beta4, R.X)), fe_mul4(fe_sqr_t<CHAIN>(gamma)));
     return R;
 }
 
 // R <- 2P on the lanes where `same` holds.  The doubling runs only when some
 // lane of the wavefront needs it, and then on the whole wavefront (a uniform
 // branch) followed by a per-lane select.
+template <bool CHAIN = true>
 __device__ __forceinline__ jpt fix_equal_operands(bool same, const jpt &R, const jpt &P) {
     if (__ballot(same)) {
-        jpt D = jpt_dbl(P);
+        jpt D = jpt_dbl<CHAIN>(P);
         return jpt_select(same, R, D);
     }
     return R;
@@ -115,24 +122,25 @@ __device__ __forceinline__ jpt fix_equal_operands(bool same, const jpt &R, const
 // 32 p^2), X3 = r^2 - J - 2V and Y3 = r (V - X3) - 2 Y1 J are each one limb
 // pass plus one normalisation, and Z3 = (Z1 + H)^2 - Z1Z1 - HH is computed as
 // the equal 2 Z1 H.
+template <bool CHAIN = true>
 __device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
-    fe z1z1 = fe_sqr(P.Z);
-    fe u2 = fe_mul(Q.x, z1z1);
-    fe s2 = fe_mul(fe_mul(Q.y, P.Z), z1z1);
+    fe z1z1 = fe_sqr_t<CHAIN>(P.Z);
+    fe u2 = fe_mul_t<CHAIN>(Q.x, z1z1);
+    fe s2 = fe_mul_t<CHAIN>(fe_mul_t<CHAIN>(Q.y, P.Z), z1z1);
     fe h = fe_sub_w(u2, P.X);           // (0, 4p)
-    fe hh = fe_sqr(h);
+    fe hh = fe_sqr_t<CHAIN>(h);
     fe i4 = fe_mul4_w(hh);              // [0, 8p)
-    fe j = fe_mul(h, i4);
+    fe j = fe_mul_t<CHAIN>(h, i4);
     fe r = fe_sub2(s2, P.Y);
-    fe v = fe_mul(P.X, i4);
+    fe v = fe_mul_t<CHAIN>(P.X, i4);
     jpt R;
-    R.X = fe_sub_sub2(fe_sqr(r), j, v);
-    R.Y = fe_sub2x(fe_mul(r, fe_sub_w(v, R.X)), fe_mul(P.Y, j));
-    R.Z = fe_dbl(fe_mul(P.Z, h));
+    R.X = fe_sub_sub2(fe_sqr_t<CHAIN>(r), j, v);
+    R.Y = fe_sub2x(fe_mul_t<CHAIN>(r, fe_sub_w(v, R.X)), fe_mul_t<CHAIN>(P.Y, j));
+    R.Z = fe_dbl(fe_mul_t<CHAIN>(P.Z, h));
     bool p_inf = jpt_is_inf(P);
     bool q_inf = apt_is_inf(Q);
     bool same = fe_is_zero(hh) && fe_is_zero(r) && !p_inf && !q_inf;
-    R = fix_equal_operands(same, R, P);
+    R = fix_equal_operands<CHAIN>(same, R, P);
     // infinity operands are rare: the selects run only when some lane of the
     // wavefront has one (uniform branches, then per-lane selects)
     if (__ballot(p_inf)) R = jpt_select(p_inf, R, jpt_from_affine(Q));
@@ -143,27 +151,28 @@ __device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
 // P + Q, both Jacobian (add-2007-bl), complete.  Lazy reduction as in
 // jpt_add_affine; I = (2H)^2 is computed as 4 H^2 and Z3 =
 // ((Z1 + Z2)^2 - Z1Z1 - Z2Z2) H as the equal 2 Z1 Z2 H.
+template <bool CHAIN = true>
 __device__ __forceinline__ jpt jpt_add(const jpt &P, const jpt &Q) {
-    fe z1z1 = fe_sqr(P.Z);
-    fe z2z2 = fe_sqr(Q.Z);
-    fe u1 = fe_mul(P.X, z2z2);
-    fe u2 = fe_mul(Q.X, z1z1);
-    fe s1 = fe_mul(fe_mul(P.Y, Q.Z), z2z2);
-    fe s2 = fe_mul(fe_mul(Q.Y, P.Z), z1z1);
+    fe z1z1 = fe_sqr_t<CHAIN>(P.Z);
+    fe z2z2 = fe_sqr_t<CHAIN>(Q.Z);
+    fe u1 = fe_mul_t<CHAIN>(P.X, z2z2);
+    fe u2 = fe_mul_t<CHAIN>(Q.X, z1z1);
+    fe s1 = fe_mul_t<CHAIN>(fe_mul_t<CHAIN>(P.Y, Q.Z), z2z2);
+    fe s2 = fe_mul_t<CHAIN>(fe_mul_t<CHAIN>(Q.Y, P.Z), z1z1);
     fe h = fe_sub_w(u2, u1);           // (0, 4p)
-    fe hh = fe_sqr(h);
+    fe hh = fe_sqr_t<CHAIN>(h);
     fe i = fe_mul4_w(hh);              // [0, 8p)
-    fe j = fe_mul(h, i);
+    fe j = fe_mul_t<CHAIN>(h, i);
     fe r = fe_sub2(s2, s1);
-    fe v = fe_mul(u1, i);
+    fe v = fe_mul_t<CHAIN>(u1, i);
     jpt R;
-    R.X = fe_sub_sub2(fe_sqr(r), j, v);
-    R.Y = fe_sub2x(fe_mul(r, fe_sub_w(v, R.X)), fe_mul(s1, j));
-    R.Z = fe_dbl(fe_mul(fe_mul(P.Z, Q.Z), h));
+    R.X = fe_sub_sub2(fe_sqr_t<CHAIN>(r), j, v);
+    R.Y = fe_sub2x(fe_mul_t<CHAIN>(r, fe_sub_w(v, R.X)), fe_mul_t<CHAIN>(s1, j));
+    R.Z = fe_dbl(fe_mul_t<CHAIN>(fe_mul_t<CHAIN>(P.Z, Q.Z), h));
     bool p_inf = jpt_is_inf(P);
     bool q_inf = jpt_is_inf(Q);
     bool same = fe_is_zero(hh) && fe_is_zero(r) && !p_inf && !q_inf;
-    R = fix_equal_operands(same, R, P);
+    R = fix_equal_operands<CHAIN>(same, R, P);
     if (__ballot(p_inf)) R = jpt_select(p_inf, R, Q);
     if (__ballot(q_inf)) R = jpt_select(q_inf, R, P);
     return R;

@@ -139,22 +139,22 @@ __device__ __forceinline__ void run_op(const plan_op op, const uint32_t *__restr
     if (op.kind == OP_MUL) {
         const int s = op.s;
         const int bits = 32 - __builtin_clz((unsigned)s);
-        R = ladder_small((uint32_t)s, bits, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
+        R = ladder_small<false>((uint32_t)s, bits, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
     } else if (op.a >= 0 && op.b >= 0) {
         jpt Q = op_reg(regs, rmax, n_lanes, r, op.b, lane, last, last_reg);
         if (op.neg_b) Q = jpt_neg(Q);
-        R = jpt_add(op_reg(regs, rmax, n_lanes, r, op.a, lane, last, last_reg), Q);
+        R = jpt_add<false>(op_reg(regs, rmax, n_lanes, r, op.a, lane, last, last_reg), Q);
     } else if (op.b < 0) {
         apt Q = load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.b) * l + j);
         if (op.neg_b) Q = apt_neg(Q);
         jpt P = op.a >= 0 ? op_reg(regs, rmax, n_lanes, r, op.a, lane, last, last_reg)
                           : jpt_from_affine(load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
-        R = jpt_add_affine(P, Q);
+        R = jpt_add_affine<false>(P, Q);
     } else {
         // a is a base point, b a register: a + (+-b) = (+-b) + a
         jpt Q = op_reg(regs, rmax, n_lanes, r, op.b, lane, last, last_reg);
         if (op.neg_b) Q = jpt_neg(Q);
-        R = jpt_add_affine(Q, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
+        R = jpt_add_affine<false>(Q, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
     }
     reg_store(regs, rmax, n_lanes, r, op.dst, lane, R);
     last = R;
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
             uint32_t *slot = table + (T * emax + e) * ENTRY_WORDS;
 #pragma unroll
             for (int w = 0; w < NL; ++w) slot[w] = prod.v[w];
-            if (!fe_is_zero(z)) prod = fe_mul(prod, z);
+            if (!fe_is_zero(z)) prod = fe_mul_ilp(prod, z);
         }
     }
     if (last_r < 0) return;
@@ -233,8 +233,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
                     A.x = fe_zero();
                     A.y = fe_zero();
                 } else {
-                    fe zinv = fe_mul(inv, pre);
-                    inv = fe_mul(inv, P.Z);
+                    fe zinv = fe_mul_ilp(inv, pre);
+                    inv = fe_mul_ilp(inv, P.Z);
                     A = jpt_to_affine_with(P, zinv);
                 }
             }

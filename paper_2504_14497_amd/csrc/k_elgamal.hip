@@ -192,11 +192,13 @@ __global__ void __launch_bounds__(256) decrypt_kernel(scalar8 x, const uint32_t 
     jpt acc = jpt_infinity();
     int top = 255;
     while (top >= 0 && !((x.w[top >> 5] >> (top & 31)) & 1u)) --top;
+    // few lanes per call and one long dependent chain each: the split
+    // product form (lower latency per product) suits this kernel
     for (int i = top; i >= 0; --i) {
-        acc = jpt_dbl(acc);
-        if ((x.w[i >> 5] >> (i & 31)) & 1u) acc = jpt_add_affine(acc, c1);
+        acc = jpt_dbl<false>(acc);
+        if ((x.w[i >> 5] >> (i & 31)) & 1u) acc = jpt_add_affine<false>(acc, c1);
     }
-    jpt R = jpt_add(jpt_from_affine(c2), jpt_neg(acc));
+    jpt R = jpt_add<false>(jpt_from_affine(c2), jpt_neg(acc));
     apt A;
     if (jpt_is_inf(R)) {
         A.x = A.y = fe_zero();

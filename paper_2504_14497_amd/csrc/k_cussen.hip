@@ -476,6 +476,9 @@ struct job {
     int l = 0, c_form = PCMM_AFFINE;
     int J = 1, Lj = 1;
     int64_t n_lanes = 0;
+    int Lj_pad = 0;           // table-build lanes with each group padded to a
+    int64_t n_lanes_pad = 0;  // whole wavefront (0: not applicable), chosen per run
+    size_t regs_bytes_pad = 0;
     int tm = 256, pp = 1, kc = 1, S = 1, gps = 0, tiles_x = 1, tiles_y = 1;
     size_t lds_bytes = 0;
     int64_t ldj = 64, norm_threads = 0, ld_pre = 0;
@@ -492,6 +495,18 @@ struct job {
 // padded table-build lanes allowed (4 wavefronts per SIMD of a 256-CU device)
 constexpr int64_t PAD_LANES_MAX = 4 * 1024 * 64;
 
+// whether a run pads its groups' table-build lanes: only if the padded grid
+// of all its problems stays within PAD_LANES_MAX
+template <typename JobOf>
+bool pad_run(size_t count, JobOf job_at) {
+    int64_t lanes = 0;
+    for (size_t q = 0; q < count; ++q) {
+        const auto &G = job_at(q);
+        lanes += G.n_lanes_pad ? G.n_lanes_pad : G.n_lanes;
+    }
+    return lanes <= PAD_LANES_MAX;
+}
+
 void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     const cussen_plan &P = G.P;
     const int m = P.m, l = G.l;
@@ -506,13 +521,14 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     G.Lj = (l + J - 1) / J;
     // lanes of one group fill whole wavefronts (uniform control flow) when
     // possible.  With few output columns a group's chains fill less than a
-    // wavefront; packing several groups into one wavefront would run their
-    // different programs divergently, so each group is padded to a whole
-    // wavefront as long as that keeps the grid small (the build is then
-    // bound by its chains' latency, not by lanes).
+    // wavefront; packing several groups into one wavefront runs their
+    // different programs divergently, so a run pads each group to a whole
+    // wavefront when its padded grid stays small (pad_run): the build is then
+    // bound by its chains' latency, not by lanes.
     if (2 * G.Lj >= 64) G.Lj = (G.Lj + 31) / 32 * 32;
-    else if ((int64_t)P.ngroups * 64 <= PAD_LANES_MAX) G.Lj = 32;
+    else G.Lj_pad = 32;
     G.n_lanes = (int64_t)P.ngroups * 2 * G.Lj;
+    G.n_lanes_pad = G.Lj_pad ? (int64_t)P.ngroups * 2 * G.Lj_pad : 0;
     // accumulation tile
     const int npairs = 2 * l;
     // rows per tile: the fewest padded rows, the larger tile on ties (each
@@ -548,6 +564,7 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     const int64_t n_out = (int64_t)m * l;
     G.ldj = std::max<int64_t>(64, (n_out + 63) / 64 * 64);
     G.regs_bytes = (size_t)G.J * std::max(P.max_regs, 1) * JAC_WORDS * 4 * (size_t)G.n_lanes;
+    G.regs_bytes_pad = (size_t)G.J * std::max(P.max_regs, 1) * JAC_WORDS * 4 * (size_t)G.n_lanes_pad;
     G.table_bytes = (size_t)P.ngroups * npairs * emax * ENTRY_WORDS * 4;
     G.part_bytes = S > 1 ? (size_t)S * JAC2_PLANES * G.ldj * 4 : 0;
     const bool affine = G.c_form == PCMM_AFFINE;
@@ -557,7 +574,7 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
         G.ld_pre = G.norm_threads * G.norm_per * 2;
         G.norm_bytes = normalize_scratch_bytes(n_out, 2);
     }
-    G.footprint = align256(G.regs_bytes) + align256(G.table_bytes) + align256(G.part_bytes) +
+    G.footprint = align256(std::max(G.regs_bytes, G.regs_bytes_pad)) + align256(G.table_bytes) + align256(G.part_bytes) +
                   align256(G.cjac_bytes) + align256(G.norm_bytes);
 }
 
@@ -708,9 +725,11 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
     size_t ws = img + 256;
     int64_t tb = 0, tiles = 0, red = 0, norm = 0;
     L.max_lds = 0;
+    const bool pad = pad_run(nd, [&](size_t q) -> const job & { return pl.jobs[q]; });
     for (size_t k = 0; k < nd; ++k) {
         const job &G = pl.jobs[k];
         prob_desc &d = D[k];
+        const bool pad_k = pad && G.Lj_pad;
         d.m = G.P.m;
         d.n = G.P.n;
         d.l = G.l;
@@ -720,7 +739,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         d.rmax = std::max(G.P.max_regs, 1);
         d.c_form = G.c_form;
         d.J = G.J;
-        d.Lj = G.Lj;
+        d.Lj = pad_k ? G.Lj_pad : G.Lj;
         d.tm = G.tm;
         d.pp = G.pp;
         d.kc = G.kc;
@@ -731,9 +750,9 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         d.tiles_y = G.tiles_y;
         d.norm_per = G.norm_per;
         d.chunks_per_split = G.chunks_per_split;
-        d.n_lanes = G.n_lanes;
+        d.n_lanes = pad_k ? G.n_lanes_pad : G.n_lanes;
         d.tb_block0 = tb;
-        tb += (G.n_lanes + 255) / 256;
+        tb += (d.n_lanes + 255) / 256;
         d.tile0 = tiles;
         tiles += (int64_t)G.tiles_x * G.tiles_y * G.S;
         d.red_block0 = red;
@@ -745,7 +764,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         d.ldj = G.ldj;
         d.ld_pre = G.ld_pre;
         d.w_regs = (int64_t)ws;
-        ws += align256(G.regs_bytes);
+        ws += align256(pad_k ? G.regs_bytes_pad : G.regs_bytes);
         d.w_table = (int64_t)ws;
         ws += align256(G.table_bytes);
         d.w_part = (int64_t)ws;
@@ -1198,14 +1217,18 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
     size_t ws = L.ctr_off + 256;
     D.resize(nd);
     int64_t tb = 0, tiles = 0, red = 0, norm = 0;
+    const bool pad = pad_run(nd, [&](size_t q) -> const job & { return pl.jobs[pl.job_of[which[order[q]]]]; });
     for (size_t q = 0; q < nd; ++q) {
         const int r = order[q];
         const int jk = pl.job_of[which[r]];
         const job &G = pl.jobs[jk];
         prob_desc d = pl.desc[jk];
+        const bool pad_k = pad && G.Lj_pad;
+        d.Lj = pad_k ? G.Lj_pad : G.Lj;
+        d.n_lanes = pad_k ? G.n_lanes_pad : G.n_lanes;
         d.io = r;
         d.tb_block0 = tb;
-        tb += (G.n_lanes + 255) / 256;
+        tb += (d.n_lanes + 255) / 256;
         d.tile0 = tiles;
         tiles += (int64_t)G.tiles_x * G.tiles_y * G.S;
         d.red_block0 = red;
@@ -1213,7 +1236,7 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         d.norm_block0 = norm;
         norm += d.norm_threads / 256;
         d.w_regs = (int64_t)ws;
-        ws += align256(G.regs_bytes);
+        ws += align256(pad_k ? G.regs_bytes_pad : G.regs_bytes);
         d.w_table = (int64_t)ws;
         ws += align256(G.table_bytes);
         d.w_part = (int64_t)ws;

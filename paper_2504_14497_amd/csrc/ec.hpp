@@ -117,26 +117,41 @@ __device__ __forceinline__ jpt fix_equal_operands(bool same, const jpt &R, const
     return R;
 }
 
-// P + Q with Q affine (madd-2007-bl, 7M + 4S), complete.  Lazy reduction:
-// H (< 4p) and I = 4 H^2 (< 8p) stay carry-only (their products are below
-// 32 p^2), X3 = r^2 - J - 2V and Y3 = r (V - X3) - 2 Y1 J are each one limb
-// pass plus one normalisation, and Z3 = (Z1 + H)^2 - Z1Z1 - HH is computed as
-// the equal 2 Z1 H.
-template <bool CHAIN = true>
-__device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
+// The formulas of madd-2007-bl (7M + 4S) for P + Q with Q affine, without
+// the exceptional cases; hh = H^2 and r are returned for their tests.  Lazy
+// reduction: H (< 4p) and I = 4 H^2 (< 8p) stay carry-only (their products
+// are below 32 p^2), X3 = r^2 - J - 2V and Y3 = r (V - X3) - 2 Y1 J are each
+// one limb pass plus one normalisation, and Z3 = (Z1 + H)^2 - Z1Z1 - HH is
+// computed as the equal 2 Z1 H: with Z3_X2, as Z1 (2H) with the doubling in
+// the operand's limbs (fe_x2; 2H < 8p, product below 16 p^2), else as a
+// normalised doubling of Z1 H (which keeps fewer registers live in the
+// latency-bound callers).
+template <bool CHAIN, bool Z3_X2>
+__device__ __forceinline__ jpt madd_formulas(const jpt &P, const apt &Q, fe &hh, fe &r) {
     fe z1z1 = fe_sqr_t<CHAIN>(P.Z);
     fe u2 = fe_mul_t<CHAIN>(Q.x, z1z1);
     fe s2 = fe_mul_t<CHAIN>(fe_mul_t<CHAIN>(Q.y, P.Z), z1z1);
     fe h = fe_sub_w(u2, P.X);           // (0, 4p)
-    fe hh = fe_sqr_t<CHAIN>(h);
+    hh = fe_sqr_t<CHAIN>(h);
     fe i4 = fe_mul4_w(hh);              // [0, 8p)
     fe j = fe_mul_t<CHAIN>(h, i4);
-    fe r = fe_sub2(s2, P.Y);
+    r = fe_sub2(s2, P.Y);
     fe v = fe_mul_t<CHAIN>(P.X, i4);
     jpt R;
     R.X = fe_sub_sub2(fe_sqr_t<CHAIN>(r), j, v);
     R.Y = fe_sub2x(fe_mul_t<CHAIN>(r, fe_sub_w(v, R.X)), fe_mul_t<CHAIN>(P.Y, j));
-    R.Z = fe_dbl(fe_mul_t<CHAIN>(P.Z, h));
+    if constexpr (Z3_X2)
+        R.Z = fe_mul_t<CHAIN>(P.Z, fe_x2(h));
+    else
+        R.Z = fe_dbl(fe_mul_t<CHAIN>(P.Z, h));
+    return R;
+}
+
+// P + Q with Q affine, complete.
+template <bool CHAIN = true>
+__device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
+    fe hh, r;
+    jpt R = madd_formulas<CHAIN, false>(P, Q, hh, r);
     bool p_inf = jpt_is_inf(P);
     bool q_inf = apt_is_inf(Q);
     bool same = fe_is_zero(hh) && fe_is_zero(r) && !p_inf && !q_inf;
@@ -145,6 +160,39 @@ __device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
     // wavefront has one (uniform branches, then per-lane selects)
     if (__ballot(p_inf)) R = jpt_select(p_inf, R, jpt_from_affine(Q));
     if (__ballot(q_inf)) R = jpt_select(q_inf, R, P);
+    return R;
+}
+
+// P + Q with Q affine, complete, for an accumulation that knows which
+// operands are the identity: p_inf (Z1 = 0) and q_inf (Q is the affine
+// identity) are given, and r_inf receives whether the result is the
+// identity (its Z is then 0), so the caller carries the flag instead of
+// testing Z1's limbs at every addition.  Exceptional cases: with neither
+// operand the identity, H = 0 means P = +-Q; P = Q (r = 0) needs the
+// doubling, P = -Q gives Z3 = 0, the identity.  The test of r runs only
+// when some lane of the wavefront has H = 0.  A P-256 point is never of
+// order 2, so 2P is not the identity.
+template <bool CHAIN = true>
+__device__ __forceinline__ jpt jpt_add_affine_known(const jpt &P, bool p_inf, const apt &Q, bool q_inf,
+                                                    bool &r_inf) {
+    fe hh, r;
+    jpt R = madd_formulas<CHAIN, true>(P, Q, hh, r);
+    const bool h_zero = fe_is_zero(hh) && !p_inf && !q_inf;
+    bool inf = p_inf && q_inf;
+    if (__ballot(h_zero)) {
+        const bool r_zero = fe_is_zero(r);
+        R = fix_equal_operands<CHAIN>(h_zero && r_zero, R, P);
+        inf = inf || (h_zero && !r_zero);
+    }
+    if (__ballot(p_inf)) {
+        jpt Qj;
+        Qj.X = Q.x;
+        Qj.Y = Q.y;
+        Qj.Z = q_inf ? fe_zero() : fe_one_mont();
+        R = jpt_select(p_inf, R, Qj);
+    }
+    if (__ballot(q_inf)) R = jpt_select(q_inf, R, P);
+    r_inf = inf;
     return R;
 }
 

@@ -292,6 +292,18 @@ __device__ __forceinline__ bool fe_eq(const fe &a, const fe &b) { return fe_is_z
 // below 2p, in normal form), with limb 8 below 2^27 (column sums stay below
 // 2^63).
 // ---------------------------------------------------------------------------
+// 2a with its limbs doubled and no carries (limbs 0..7 < 2^30, limb 8 <
+// 2^27 for a weak or normal a, value < 8p).  Only as ONE operand of a
+// product whose other operand has limbs 0..7 < 2^29: a column then holds
+// at most 8 products below 2^59, the carry and 4 reduction terms below 2^55,
+// so it stays below 2^63; the value bound a b <= 32 p^2 still applies.
+__device__ __forceinline__ fe fe_x2(const fe &a) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] << 1;
+    return x;
+}
+
 // a - b + 2p in (0, 4p) for a, b normal; weak
 __device__ __forceinline__ fe fe_sub_w(const fe &a, const fe &b) {
     fe x;

@@ -40,7 +40,10 @@ using namespace pcmm;
 
 namespace {
 
-constexpr int ENTRY_WORDS = 20;  // affine entry: x (9 limbs), y (9 limbs), 2 pad words; Montgomery form
+// affine table entry, Montgomery form: x (9 limbs), y (9 limbs), a word that
+// is 1 for the identity and 0 otherwise, 1 pad word
+constexpr int ENTRY_WORDS = 20;
+constexpr int ENTRY_INF = 2 * NL;
 constexpr int JAC_WORDS = 3 * NL;
 constexpr int MAX_PROBLEMS = PCMM_PLAN_MAX_PROBLEMS;
 constexpr size_t LDS_BUDGET = 150 * 1024;  // per workgroup, of the 160 KB of a CU
@@ -243,6 +246,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
                 slot[w] = A.x.v[w];
                 slot[NL + w] = A.y.v[w];
             }
+            slot[ENTRY_INF] = apt_is_inf(A) ? 1u : 0u;
         }
     }
 }
@@ -274,6 +278,7 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
     const int32_t *chunk_len = plan_at<int32_t>(a, d.o_chunk_len);
 
     jpt acc = jpt_infinity();
+    bool acc_inf = true;  // whether acc is the identity, kept by the additions
     for (int gc = g_begin; gc < g_end; gc += d.kc) {
         const int kn = min(d.kc, g_end - gc);
         // stage the tables of groups gc .. gc+kn-1 for pairs p0 .. p0+pairs_here-1
@@ -308,8 +313,9 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
                     Q.x.v[w] = ent[w];
                     Q.y.v[w] = ent[NL + w];
                 }
+                const bool q_inf = ent[ENTRY_INF] != 0;
                 if (code < 0) Q.y = fe_neg(Q.y);
-                acc = jpt_add_affine(acc, Q);
+                acc = jpt_add_affine_known(acc, acc_inf, Q, q_inf, acc_inf);
             }
         }
     }

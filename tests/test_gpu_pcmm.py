@@ -136,7 +136,8 @@ def test_wide_plaintexts_vs_oracle(dev, orc, bits, signed):
 
 def test_exceptional_cases_vs_oracle(dev, orc):
     # equal ciphertexts down a column (accumulator meets P = Q, tables meet
-    # P = Q through repeated differences) and opposite ones (P = -Q)
+    # P = Q through repeated differences), opposite ones (P = -Q) and an
+    # identity point in B
     B = random_cts(orc, 6, 3, 300)
     B[1] = B[0]
     B[3] = B[0]
@@ -146,7 +147,10 @@ def test_exceptional_cases_vs_oracle(dev, orc):
             B[2, j, 64 * h:64 * h + 64] = np.frombuffer(orc.pt_neg(P_), dtype=np.uint8)
     B[5, 1] = 0  # an infinity point inside B
     A = np.array([[1, 1, 0, 0, 0, 2], [1, 0, 1, 0, 3, 0], [3, 3, 6, 1, 0, 1], [2, 0, 2, 5, 1, 1],
-                  [1, 2, 3, 4, 5, 6], [7, 7, 7, 7, 7, 7], [-1, 1, 1, -1, 2, -2], [0, 0, 0, 0, 0, 0]],
+                  [1, 2, 3, 4, 5, 6], [7, 7, 7, 7, 7, 7], [-1, 1, 1, -1, 2, -2], [0, 0, 0, 0, 0, 0],
+                  # an identity accumulator meets an identity entry (column 1: 3 B[5] is
+                  # the identity), first from the start, then after P + (-P)
+                  [0, 0, 0, 0, 0, 3], [1, 0, 1, 0, 0, 1], [1, 0, 1, 0, 0, -2]],
                  dtype=np.int8)
     want = orc.pcmm_cussen(A, B)
     Bd = _upload(dev, B)
@@ -158,6 +162,7 @@ def test_exceptional_cases_vs_oracle(dev, orc):
         C, _ = dev.cussen(A, 4, Bd, cfg=dev.CussenCfg(4, g, 2, 0))
         assert (C.to_host() == want).all()
     assert (want[7] == 0).all()
+    assert (want[8:11, 1] == 0).all()
 
 
 def test_degenerate_sizes(dev, orc):

@@ -118,15 +118,18 @@ __device__ __forceinline__ jpt fix_equal_operands(bool same, const jpt &R, const
 }
 
 // The formulas of madd-2007-bl (7M + 4S) for P + Q with Q affine, without
-// the exceptional cases; hh = H^2 and r are returned for their tests.  Lazy
-// reduction: H (< 4p) and I = 4 H^2 (< 8p) stay carry-only (their products
-// are below 32 p^2), X3 = r^2 - J - 2V and Y3 = r (V - X3) - 2 Y1 J are each
-// one limb pass plus one normalisation, and Z3 = (Z1 + H)^2 - Z1Z1 - HH is
-// computed as the equal 2 Z1 H: with Z3_X2, as Z1 (2H) with the doubling in
-// the operand's limbs (fe_x2; 2H < 8p, product below 16 p^2), else as a
-// normalised doubling of Z1 H (which keeps fewer registers live in the
-// latency-bound callers).
-template <bool CHAIN, bool Z3_X2>
+// the exceptional cases; hh = H^2 and r (r / 2 with LEAN) are returned for
+// their tests.  Lazy reduction: H (< 4p) and I = 4 H^2 (< 8p) stay
+// carry-only (their products are below 32 p^2), X3 = r^2 - J - 2V and
+// Y3 = r (V - X3) - 2 Y1 J are each one limb pass plus one normalisation,
+// and Z3 = (Z1 + H)^2 - Z1Z1 - HH is computed as the equal 2 Z1 H.
+// LEAN (the accumulation) saves normalisations by doubling in an operand's
+// limbs (fe_x2: below 2^30, valid for one operand of a product):
+// r' = S2 - Y1 stays carry-only (< 4p), r^2 = 4 r'^2 enters the X3 limb pass,
+// r (V - X3) = (2 r') (V - X3) (below 32 p^2), Z3 = Z1 (2H) (below 16 p^2).
+// Otherwise r is normalised and Z3 is the normalised doubling of Z1 H, which
+// keeps fewer registers live in the latency-bound callers.
+template <bool CHAIN, bool LEAN>
 __device__ __forceinline__ jpt madd_formulas(const jpt &P, const apt &Q, fe &hh, fe &r) {
     fe z1z1 = fe_sqr_t<CHAIN>(P.Z);
     fe u2 = fe_mul_t<CHAIN>(Q.x, z1z1);
@@ -135,15 +138,20 @@ __device__ __forceinline__ jpt madd_formulas(const jpt &P, const apt &Q, fe &hh,
     hh = fe_sqr_t<CHAIN>(h);
     fe i4 = fe_mul4_w(hh);              // [0, 8p)
     fe j = fe_mul_t<CHAIN>(h, i4);
-    r = fe_sub2(s2, P.Y);
-    fe v = fe_mul_t<CHAIN>(P.X, i4);
     jpt R;
-    R.X = fe_sub_sub2(fe_sqr_t<CHAIN>(r), j, v);
-    R.Y = fe_sub2x(fe_mul_t<CHAIN>(r, fe_sub_w(v, R.X)), fe_mul_t<CHAIN>(P.Y, j));
-    if constexpr (Z3_X2)
+    if constexpr (LEAN) {
+        r = fe_sub_w(s2, P.Y);          // r / 2, (0, 4p), carry-only
+        fe v = fe_mul_t<CHAIN>(P.X, i4);
+        R.X = fe_4sub_sub2(fe_sqr_t<CHAIN>(r), j, v);
+        R.Y = fe_sub2x(fe_mul_t<CHAIN>(fe_x2(r), fe_sub_w(v, R.X)), fe_mul_t<CHAIN>(P.Y, j));
         R.Z = fe_mul_t<CHAIN>(P.Z, fe_x2(h));
-    else
+    } else {
+        r = fe_sub2(s2, P.Y);
+        fe v = fe_mul_t<CHAIN>(P.X, i4);
+        R.X = fe_sub_sub2(fe_sqr_t<CHAIN>(r), j, v);
+        R.Y = fe_sub2x(fe_mul_t<CHAIN>(r, fe_sub_w(v, R.X)), fe_mul_t<CHAIN>(P.Y, j));
         R.Z = fe_dbl(fe_mul_t<CHAIN>(P.Z, h));
+    }
     return R;
 }
 
@@ -180,18 +188,18 @@ __device__ __forceinline__ jpt jpt_add_affine_known(const jpt &P, bool p_inf, co
     const bool h_zero = fe_is_zero(hh) && !p_inf && !q_inf;
     bool inf = p_inf && q_inf;
     if (__ballot(h_zero)) {
-        const bool r_zero = fe_is_zero(r);
+        const bool r_zero = fe_is_zero(fe_norm(r));  // r / 2 is carry-only
         R = fix_equal_operands<CHAIN>(h_zero && r_zero, R, P);
         inf = inf || (h_zero && !r_zero);
     }
-    if (__ballot(p_inf)) {
+    if (__ballot(p_inf || q_inf)) {
         jpt Qj;
         Qj.X = Q.x;
         Qj.Y = Q.y;
         Qj.Z = q_inf ? fe_zero() : fe_one_mont();
         R = jpt_select(p_inf, R, Qj);
+        R = jpt_select(q_inf, R, P);
     }
-    if (__ballot(q_inf)) R = jpt_select(q_inf, R, P);
     r_inf = inf;
     return R;
 }

@@ -160,6 +160,34 @@ constexpr fe29w c_kp(int K) {
 
 constexpr fe29w KP4 = c_kp(4), KP6 = c_kp(6);
 
+// K p as digits with limbs 0..7 in (-2^29, 0] (each positive digit lends
+// 2^29 to the next limb) and limb 8 the rest
+constexpr fe29w c_kp_nonpos(int K) {
+    fe29w r = c_kp(K);
+    for (int i = 0; i < NL - 1; ++i)
+        if (r.v[i] > 0) {
+            r.v[i] -= (int64_t)1 << LB;
+            r.v[i + 1] += 1;
+        }
+    return r;
+}
+
+constexpr fe29w KN6 = c_kp_nonpos(6);
+
+constexpr bool c_check_kn6() {
+    int64_t carry = 0;
+    for (int i = 0; i < NL; ++i) {
+        if (i < NL - 1 && (KN6.v[i] > 0 || KN6.v[i] <= -((int64_t)1 << LB))) return false;
+        const int64_t t = KN6.v[i] + carry;
+        if (i == NL - 1) return t == KP6.v[i];
+        const int64_t d = t & LMASK;  // the same value in radix-2^29 digits
+        carry = (t - d) >> LB;
+        if (d != KP6.v[i]) return false;
+    }
+    return false;
+}
+static_assert(c_check_kn6(), "6p with non-positive limbs");
+
 // ---------------------------------------------------------------------------
 // Limb helpers
 // ---------------------------------------------------------------------------
@@ -338,6 +366,16 @@ __device__ __forceinline__ fe fe_sub_sub2(const fe &a, const fe &b, const fe &c)
     fe x;
 #pragma unroll
     for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] - b.v[i] - (c.v[i] << 1) + (uint32_t)KP6.v[i];
+    return fe_norm(x);
+}
+
+// 4a - b - 2c (mod p) for a, b, c normal: one limb pass adding the digits of
+// 6p with limbs 0..7 in (-2^29, 0] (signed limb sums in (-2^31, 2^31), value
+// in (0, 14p)), then normalised
+__device__ __forceinline__ fe fe_4sub_sub2(const fe &a, const fe &b, const fe &c) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = (a.v[i] << 2) - b.v[i] - (c.v[i] << 1) + (uint32_t)KN6.v[i];
     return fe_norm(x);
 }
 

@@ -38,7 +38,11 @@ pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint32_t *b, ui
  * lazy forms (carry-only results: limbs 0..7 < 2^29, the rest in limb 8):
  * 13 a-b+2p in (0, 4p), 14 4a in [0, 8p), 15 a-3b (mod p, normal form, one
  * limb pass adding 6p), 16 a-2b (likewise, adding 4p),
- * 17 (a-b+2p) * 4b with both operands carry-only (normal form). */
+ * 17 (a-b+2p) * 4b with both operands carry-only (normal form);
+ * products that absorb an addition: 18 a*b + (2p - b) with the addend above
+ * R (carry-only, in (0, 4p)), 20 (2a)*b - 2 b'*b' with one reduction, for a
+ * and b carry-only (value < 4p) and b' the normal form of b (normal form);
+ * 19 4a-3b (mod p, normal form, one limb pass adding 6p). */
 pcmm_status pcmm_diag_field_raw(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
                                 int64_t count, void *stream);
 

@@ -123,29 +123,36 @@ __device__ __forceinline__ jpt fix_equal_operands(bool same, const jpt &R, const
 // carry-only (their products are below 32 p^2), X3 = r^2 - J - 2V and
 // Y3 = r (V - X3) - 2 Y1 J are each one limb pass plus one normalisation,
 // and Z3 = (Z1 + H)^2 - Z1Z1 - HH is computed as the equal 2 Z1 H.
-// LEAN (the accumulation) saves normalisations by doubling in an operand's
-// limbs (fe_x2: below 2^30, valid for one operand of a product):
-// r' = S2 - Y1 stays carry-only (< 4p), r^2 = 4 r'^2 enters the X3 limb pass,
-// r (V - X3) = (2 r') (V - X3) (below 32 p^2), Z3 = Z1 (2H) (below 16 p^2).
-// Otherwise r is normalised and Z3 is the normalised doubling of Z1 H, which
-// keeps fewer registers live in the latency-bound callers.
+// LEAN (the accumulation) folds additions into the products and doubles in
+// an operand's limbs (fe_x2: below 2^30, valid for one operand of a
+// product): H = U2 - X1 and r' = S2 - Y1 (= r / 2) come out of the products
+// U2 and S2 with 2p - X1, 2p - Y1 added above R (carry-only, < 4p); r^2 =
+// 4 r'^2 enters the X3 limb pass; Y3 = (2 r') (V - X3) - 2 Y1 J is one
+// reduction of both products (fe_mul_sub2); Z3 = Z1 (2H) (below 16 p^2).
+// Otherwise H and r are formed by limb passes, r is normalised and Z3 is the
+// normalised doubling of Z1 H, which keeps fewer registers live in the
+// latency-bound callers.
 template <bool CHAIN, bool LEAN>
 __device__ __forceinline__ jpt madd_formulas(const jpt &P, const apt &Q, fe &hh, fe &r) {
-    fe z1z1 = fe_sqr_t<CHAIN>(P.Z);
-    fe u2 = fe_mul_t<CHAIN>(Q.x, z1z1);
-    fe s2 = fe_mul_t<CHAIN>(fe_mul_t<CHAIN>(Q.y, P.Z), z1z1);
-    fe h = fe_sub_w(u2, P.X);           // (0, 4p)
-    hh = fe_sqr_t<CHAIN>(h);
-    fe i4 = fe_mul4_w(hh);              // [0, 8p)
-    fe j = fe_mul_t<CHAIN>(h, i4);
     jpt R;
+    fe z1z1 = fe_sqr_t<CHAIN>(P.Z);
     if constexpr (LEAN) {
-        r = fe_sub_w(s2, P.Y);          // r / 2, (0, 4p), carry-only
+        fe h = fe_mul_plus_t<CHAIN>(Q.x, z1z1, fe_2p_minus(P.X));                        // (0, 4p)
+        r = fe_mul_plus_t<CHAIN>(fe_mul_t<CHAIN>(Q.y, P.Z), z1z1, fe_2p_minus(P.Y));  // r / 2, (0, 4p)
+        hh = fe_sqr_t<CHAIN>(h);
+        fe i4 = fe_mul4_w(hh);              // [0, 8p)
+        fe j = fe_mul_t<CHAIN>(h, i4);
         fe v = fe_mul_t<CHAIN>(P.X, i4);
         R.X = fe_4sub_sub2(fe_sqr_t<CHAIN>(r), j, v);
-        R.Y = fe_sub2x(fe_mul_t<CHAIN>(fe_x2(r), fe_sub_w(v, R.X)), fe_mul_t<CHAIN>(P.Y, j));
+        R.Y = fe_mul_sub2_t<CHAIN>(fe_x2(r), fe_sub_w(v, R.X), P.Y, j);
         R.Z = fe_mul_t<CHAIN>(P.Z, fe_x2(h));
     } else {
+        fe u2 = fe_mul_t<CHAIN>(Q.x, z1z1);
+        fe s2 = fe_mul_t<CHAIN>(fe_mul_t<CHAIN>(Q.y, P.Z), z1z1);
+        fe h = fe_sub_w(u2, P.X);           // (0, 4p)
+        hh = fe_sqr_t<CHAIN>(h);
+        fe i4 = fe_mul4_w(hh);              // [0, 8p)
+        fe j = fe_mul_t<CHAIN>(h, i4);
         r = fe_sub2(s2, P.Y);
         fe v = fe_mul_t<CHAIN>(P.X, i4);
         R.X = fe_sub_sub2(fe_sqr_t<CHAIN>(r), j, v);

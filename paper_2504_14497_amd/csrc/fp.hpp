@@ -485,6 +485,107 @@ __device__ __forceinline__ fe fe_sqr_t(const fe &a) {
 }
 
 // one-chain forms for the point formulas, split forms for serial chains
+// ---------------------------------------------------------------------------
+// Products that absorb an addition.  Above column 8 the column sums are the
+// result's limbs (the division by R = 2^261 keeps them), so a value e added
+// there appears in the output unreduced: the column algorithm returns the
+// exact integer (a b + M p) / R + e.  Outputs are carry-only (limbs 0..7 in
+// [0, 2^29), limb 8 the rest); each caller bounds the value.
+// ---------------------------------------------------------------------------
+
+// 2p - x as signed limbs (each in (-2^29, 2^30)), value in (0, 2p], for x normal
+__device__ __forceinline__ fe fe_2p_minus(const fe &x) {
+    fe e;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) e.v[i] = TWO_P29.v[i] - x.v[i];
+    return e;
+}
+
+// REDC(a b) + e for e as signed limbs (|e_i| < 2^31): with a b < 4 p^2 and
+// e = 2p - x, the result is a b / R - x (mod p), carry-only, in (0, 4p)
+template <bool CHAIN>
+__device__ __forceinline__ fe fe_mul_plus_t(const fe &a, const fe &b, const fe &e) {
+    const red_consts k = red_consts_make();
+    int64_t acc = 0;
+    uint32_t m[NL];
+    fe r;
+#pragma unroll
+    for (int c = 0; c < 2 * NL - 1; ++c) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int j = c - i;
+            if (j >= 0 && j < NL) { acc += (int64_t)((uint64_t)a.v[i] * b.v[j]); chain<CHAIN>(acc); }
+        }
+        red_terms<CHAIN>(acc, m, c, k);
+        if (c < NL) {
+            m[c] = (uint32_t)acc & LMASK;
+        } else {
+            acc += (int64_t)(int32_t)e.v[c - NL];
+            r.v[c - NL] = (uint32_t)acc & LMASK;
+        }
+        acc >>= LB;
+    }
+    r.v[NL - 1] = (uint32_t)acc + e.v[NL - 1];
+    return r;
+}
+
+// fe_norm without its first carry pass, for a carry-only value below 2^260
+__device__ __forceinline__ fe fe_fold(fe x) {
+    const uint32_t h = x.v[8] >> 24;
+    x.v[8] &= (1u << 24) - 1;
+    x.v[0] += h;
+    x.v[3] -= h << 9;
+    x.v[6] -= h << 18;
+    x.v[7] += h << 21;
+    fe_carry(x);
+    return x;
+}
+
+// (a b - 2 c d) / R (mod p) in normal form, with one reduction: the column
+// sums take a_i b_j and (-c_i)(2 d_j) (signed multiply-adds), p R is added
+// above column 8, and the result is folded into [0, 2p).  For a with limbs
+// < 2^30 (fe_x2 of a carry-only value), b carry-only, c and d normal: each
+// part of a column is below 9 2^59 in magnitude, so partial sums stay within
+// 2^62.2; a b < 32 p^2 and 2 c d < 8 p^2 give a b - 2 c d + p R > 0 and a
+// reduced value in (0, 3p) before the fold.
+template <bool CHAIN>
+__device__ __forceinline__ fe fe_mul_sub2_t(const fe &a, const fe &b, const fe &c, const fe &d) {
+    const red_consts k = red_consts_make();
+    int32_t nc[NL];
+    int32_t d2[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        nc[i] = -(int32_t)c.v[i];
+        d2[i] = (int32_t)(d.v[i] << 1);
+    }
+    int64_t acc = 0;
+    uint32_t m[NL];
+    fe r;
+#pragma unroll
+    for (int col = 0; col < 2 * NL - 1; ++col) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int j = col - i;
+            if (j >= 0 && j < NL) {
+                acc += (int64_t)((uint64_t)a.v[i] * b.v[j]);
+                chain<CHAIN>(acc);
+                acc += (int64_t)nc[i] * (int64_t)d2[j];
+                chain<CHAIN>(acc);
+            }
+        }
+        red_terms<CHAIN>(acc, m, col, k);
+        if (col < NL) {
+            m[col] = (uint32_t)acc & LMASK;
+        } else {
+            acc += (int64_t)P29.v[col - NL];
+            r.v[col - NL] = (uint32_t)acc & LMASK;
+        }
+        acc >>= LB;
+    }
+    r.v[NL - 1] = (uint32_t)acc + P29.v[NL - 1];
+    return fe_fold(r);
+}
+
 __device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) { return fe_mul_t<true>(a, b); }
 __device__ __forceinline__ fe fe_sqr(const fe &a) { return fe_sqr_t<true>(a); }
 __device__ __forceinline__ fe fe_mul_ilp(const fe &a, const fe &b) { return fe_mul_t<false>(a, b); }

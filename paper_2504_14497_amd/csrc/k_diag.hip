@@ -52,7 +52,10 @@ __global__ void __launch_bounds__(256) field_raw_kernel(int op, const uint32_t *
         case 14: r = fe_mul4_w(x); break;
         case 15: r = fe_sub_sub2(x, y, y); break;
         case 16: r = fe_sub2x(x, y); break;
-        default: r = fe_mul(fe_sub_w(x, y), fe_mul4_w(y)); break;
+        case 17: r = fe_mul(fe_sub_w(x, y), fe_mul4_w(y)); break;
+        case 18: r = fe_mul_plus_t<true>(x, y, fe_2p_minus(y)); break;
+        case 19: r = fe_4sub_sub2(x, y, y); break;
+        default: r = fe_mul_sub2_t<true>(fe_x2(x), y, fe_norm(y), fe_norm(y)); break;
     }
     soa_store_m(out, n, 0, e, r);
 }
@@ -225,7 +228,7 @@ extern "C" pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint
 
 extern "C" pcmm_status pcmm_diag_field_raw(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
                                            int64_t count, void *stream) {
-    if (op < 0 || op > 17 || count < 0) return PCMM_EINVAL;
+    if (op < 0 || op > 20 || count < 0) return PCMM_EINVAL;
     if (count == 0) return PCMM_OK;
     if (!a || !b || !out) return PCMM_EINVAL;
     int64_t blocks = (count + 255) / 256;

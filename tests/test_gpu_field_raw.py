@@ -91,6 +91,9 @@ def test_raw_field_ops_vs_integers(dev):
         15: (lambda x, y: (x - 3 * y) % P, 2 * P, 25),
         16: (lambda x, y: (x - 2 * y) % P, 2 * P, 25),
         17: (lambda x, y: ((x - y) * 4 * y * RINV) % P, 2 * P, 25),
+        18: (lambda x, y: (x * y * RINV - y) % P, 4 * P, 26),
+        19: (lambda x, y: (4 * x - 3 * y) % P, 2 * P, 25),
+        20: (lambda x, y: (2 * (x - y) * y * RINV) % P, 2 * P, 25),
     }
     for op, (f, bound, top) in lazy.items():
         out = dev.diag_field_raw(op, A, B)
@@ -103,6 +106,41 @@ def test_raw_field_ops_vs_integers(dev):
     assert all(bool(eq[i]) == ((a[i] - b[i]) % P == 0) for i in range(len(a)))
     z = dev.diag_field_raw(12, A, B)[:, 0]
     assert all(bool(z[i]) == (a[i] % P == 0) for i in range(len(a)))
+
+
+def test_raw_products_of_extreme_carry_only_operands(dev):
+    """The products that take a doubled operand (limbs < 2^30) and a
+    subtracted product: operands carry-only below 4p with limbs 0..7 at or
+    near 2^29 - 1, the largest column sums their bounds allow."""
+    rnd = random.Random(8)
+    rows, vals = [], []
+    top = (4 * P - 1) >> (LB * 8)
+    while len(rows) < 3000:
+        mode = len(rows) % 3
+        low = [MASK if mode == 0 else MASK - rnd.randrange(1 << (8 * mode)) for _ in range(8)]
+        if mode == 2 and rnd.random() < 0.5:
+            low = [rnd.randrange(1 << LB) for _ in range(8)]
+        row = low + [rnd.randrange(top + 1)]
+        v = value(row)
+        if v < 4 * P:
+            rows.append(row)
+            vals.append(v)
+    A = np.array(rows, dtype=np.int64)
+    B = A[::-1].copy()
+    vb = vals[::-1]
+    out = dev.diag_field_raw(20, A, B)
+    _check_normal(out)
+    bad = [i for i in range(len(vals)) if value(out[i]) % P != (2 * (vals[i] - vb[i]) * vb[i] * RINV) % P]
+    assert not bad, bad[:5]
+    # the addend form with normal operands at their largest limbs
+    nrows = [r for r, v in zip(rows, vals) if v < 2 * P and r[8] < (1 << 25)][:1000]
+    N = np.array(nrows, dtype=np.int64)
+    M = N[::-1].copy()
+    out = dev.diag_field_raw(18, N, M)
+    _check_normal(out, 4 * P, 26)
+    for i in range(len(nrows)):
+        x, y = value(nrows[i]), value(nrows[-1 - i])
+        assert value(out[i]) % P == (x * y * RINV - y) % P
 
 
 def test_raw_normalisation_of_signed_limbs(dev):

@@ -414,7 +414,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large512_t4")
     ap.add_argument("--group", type=int, default=0, help="Cussen column group g (0 = library default)")
-    ap.add_argument("--k-chunk", type=int, default=0, help="column groups staged in LDS at once (0 = library default)")
+    ap.add_argument("--k-chunk", type=int, default=0, help="column groups per code list of the accumulation (0 = library default)")
     ap.add_argument("--k-split", type=int, default=0, help="split of the inner dimension (0 = library default)")
     ap.add_argument("--school-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

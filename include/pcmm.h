@@ -94,7 +94,8 @@ typedef struct {
  *           shape (m, n, l, bits, signedness, rounds) for the process)
  *   k_split split of the n (inner) dimension over independent partial sums that
  *           are then added (0 = chosen from the shape)
- *   k_chunk columns of A whose tables are staged in LDS at once (0 = auto)
+ *   k_chunk column groups per code list of the accumulation; each list is
+ *           padded to its longest row (0 = one list per split of n)
  *   profile nonzero: record HIP events around every launch of the call on
  *           its stream, wait for them, and return per-stage durations in the
  *           stats (the call then returns after its GPU work has finished)

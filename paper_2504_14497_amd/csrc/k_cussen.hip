@@ -12,11 +12,12 @@
 //                 tables to affine with one inversion for all of its J tables.
 //   accumulate    persistent: workgroups take tiles (problem, row tile, pair
 //                 tile, split) from a device queue, the most expensive tiles
-//                 first.  For a tile, C_ij += sign * T_kj[code_ik]: the
-//                 workgroup stages the tables of a chunk of column groups for
-//                 its (j, point) pairs in LDS; every lane owns one accumulator
-//                 (row i, pair) in VGPRs and walks the chunk with mixed
-//                 additions.  The inner dimension may be split over
+//                 first.  For a tile, C_ij += sign * T_kj[code_ik]: every
+//                 lane owns one accumulator (row i, pair) in VGPRs and walks
+//                 its row's nonzero codes with mixed additions, gathering
+//                 the entries from the tables in global memory (a
+//                 wavefront's lanes share the pair, so L1 and L2 serve
+//                 them).  The inner dimension may be split over
 //                 independent partial sums.
 //   reduce        adds the split-k partial sums of one output with a tree of
 //                 point additions across the lanes of a wavefront (shuffles).
@@ -46,8 +47,9 @@ constexpr int ENTRY_WORDS = 20;
 constexpr int ENTRY_INF = 2 * NL;
 constexpr int JAC_WORDS = 3 * NL;
 constexpr int MAX_PROBLEMS = PCMM_PLAN_MAX_PROBLEMS;
-constexpr size_t LDS_BUDGET = 150 * 1024;  // per workgroup, of the 160 KB of a CU
-constexpr size_t LDS_CHUNK = 64 * 1024;    // default tables staged at once
+// the autotuner skips column groups g > 1 whose single (group, pair) table is
+// larger than this: such a table's build would outweigh what it saves
+constexpr size_t GROUP_TABLE_CAP = 150 * 1024;
 
 // One problem of a run, as the kernels see it.  Offsets o_* are bytes into
 // the plan image, w_* bytes into the workspace; the image sits at the start
@@ -65,7 +67,7 @@ struct prob_desc {
     int64_t ldj;     // ld of the internal Jacobian buffers (partials, C before normalisation)
     int64_t ld_pre;  // ld of the normalisation prefixes
     int64_t o_ops, o_op_begin, o_entry_begin, o_entries;
-    int64_t o_lists, o_chunk_off, o_chunk_len;  // nonzero codes per (split, LDS chunk), see pack_codes
+    int64_t o_lists, o_chunk_off, o_chunk_len;  // nonzero codes per (split, chunk), see pack_codes
     int32_t chunks_per_split, pad2;
     int64_t w_regs, w_table, w_part, w_cjac, w_norm;
 };
@@ -254,72 +256,82 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
 // --------------------------------------------------------------------------
 // Accumulation (persistent)
 // --------------------------------------------------------------------------
+// Affine table entry e of group k for pair p, read from global memory (the
+// lanes of a wavefront share the pair, so they gather from one small table
+// that L1 and L2 serve): five 16-byte loads.
+__device__ __forceinline__ void load_entry(const uint32_t *tp, int64_t gstride, int32_t v, uint4 (&en)[5]) {
+    const int c = (int16_t)(v & 0xFFFF);
+    const int e = (c < 0 ? -c : c) - 1;
+    const uint4 *ep = (const uint4 *)(tp + (int64_t)(v >> 16) * gstride + (int64_t)e * ENTRY_WORDS);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) en[q] = ep[q];
+}
+
 // One tile: rows bx * tm .. + tm, (j, point) pairs by * pp .. + pp, column
-// groups of split bz.  Every thread of the workgroup calls this with the same
-// tile (the LDS staging has barriers).
-__device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_desc &d, int bx, int by, int bz,
-                                                uint32_t *lds) {
+// groups of split bz.  Each lane walks its row's nonzero codes and adds the
+// entries T[k][j, pt][|code|] (negated for negative codes) into its
+// accumulator; entries come straight from the tables in global memory, so
+// one code list per split covers all of the split's groups and a wavefront
+// runs as many additions as its rows' largest count of nonzero codes.
+__device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_desc &d, int bx, int by, int bz) {
     const int tid = threadIdx.x;
-    const int tm = d.tm, pp = d.pp, emax = d.emax, m = d.m, l = d.l;
+    const int tm = d.tm, emax = d.emax, m = d.m, l = d.l;
     const int row_l = tid % tm;
     const int pair_l = tid / tm;
     const int i = bx * tm + row_l;
-    const int p0 = by * pp;
-    const int p = p0 + pair_l;
+    const int p = by * d.pp + pair_l;
     const int npairs = 2 * l;
-    const bool active = i < m && p < npairs;
+    if (i >= m || p >= npairs) return;
     const int g_begin = bz * d.gps;
     const int g_end = min(d.ngroups, g_begin + d.gps);
-    const int pairs_here = min(pp, npairs - p0);
-    const int chunk_words_per_group = pp * emax * ENTRY_WORDS;
     const uint32_t *table = at<const uint32_t>(a, d.w_table);
     const int32_t *lists = plan_at<int32_t>(a, d.o_lists);
     const int64_t *chunk_off = plan_at<int64_t>(a, d.o_chunk_off);
     const int32_t *chunk_len = plan_at<int32_t>(a, d.o_chunk_len);
+    const int64_t gstride = (int64_t)npairs * emax * ENTRY_WORDS;  // words from one group's tables to the next
 
     jpt acc = jpt_infinity();
     bool acc_inf = true;  // whether acc is the identity, kept by the additions
     for (int gc = g_begin; gc < g_end; gc += d.kc) {
-        const int kn = min(d.kc, g_end - gc);
-        // stage the tables of groups gc .. gc+kn-1 for pairs p0 .. p0+pairs_here-1
-        __syncthreads();
-        for (int kk = 0; kk < kn; ++kk) {
-            const uint4 *src = (const uint4 *)(table + ((int64_t)(gc + kk) * npairs + p0) * emax * ENTRY_WORDS);
-            uint4 *dst = (uint4 *)(lds + (int64_t)kk * chunk_words_per_group);
-            const int n4 = pairs_here * emax * ENTRY_WORDS / 4;
-            for (int x = tid; x < n4; x += blockDim.x) dst[x] = src[x];
-        }
-        __syncthreads();
-        if (active) {
-            // this row's nonzero codes of the chunk, as (group in chunk, code)
-            const int chunk = bz * d.chunks_per_split + (gc - g_begin) / d.kc;
-            const int len = chunk_len[chunk];
-            const int32_t *lst = lists + chunk_off[chunk] * m + i;
-            // the next slot's code is loaded one addition ahead, so its
-            // memory latency overlaps the current point addition
-            int32_t v_next = len > 0 ? lst[0] : 0;
-            for (int it = 0; it < len; ++it) {
-                const int32_t v = v_next;
-                if (it + 1 < len) v_next = lst[(int64_t)(it + 1) * m];
-                const int code = (int16_t)(v & 0xFFFF);
-                if (code == 0) continue;
-                const int kk = v >> 16;
-                const int e = (code < 0 ? -code : code) - 1;
-                const uint32_t *ent =
-                    lds + (int64_t)kk * chunk_words_per_group + ((int64_t)pair_l * emax + e) * ENTRY_WORDS;
-                apt Q;
+        const int chunk = bz * d.chunks_per_split + (gc - g_begin) / d.kc;
+        const int len = chunk_len[chunk];
+        const int32_t *lst = lists + chunk_off[chunk] * m + i;
+        const uint32_t *tp = table + ((int64_t)gc * npairs + p) * emax * ENTRY_WORDS;
+        // software pipeline: codes three slots ahead, the entry one slot
+        // ahead, so that their memory latency overlaps the point additions
+        int32_t v_cur = len > 0 ? lst[0] : 0;
+        int32_t v_nxt = len > 1 ? lst[m] : 0;
+        int32_t v_nx2 = len > 2 ? lst[2 * (int64_t)m] : 0;
+        uint4 en[5];
+        if ((int16_t)(v_cur & 0xFFFF) != 0) {
+            load_entry(tp, gstride, v_cur, en);
+        } else {
 #pragma unroll
-                for (int w = 0; w < NL; ++w) {
-                    Q.x.v[w] = ent[w];
-                    Q.y.v[w] = ent[NL + w];
-                }
-                const bool q_inf = ent[ENTRY_INF] != 0;
-                if (code < 0) Q.y = fe_neg(Q.y);
-                acc = jpt_add_affine_known(acc, acc_inf, Q, q_inf, acc_inf);
+            for (int q = 0; q < 5; ++q) en[q] = make_uint4(0, 0, 0, 0);
+        }
+        for (int it = 0; it < len; ++it) {
+            const int32_t v = v_cur;
+            uint4 ec[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) ec[q] = en[q];
+            v_cur = v_nxt;
+            v_nxt = v_nx2;
+            if (it + 3 < len) v_nx2 = lst[(int64_t)(it + 3) * m];
+            if (it + 1 < len && (int16_t)(v_cur & 0xFFFF) != 0) load_entry(tp, gstride, v_cur, en);
+            const int code = (int16_t)(v & 0xFFFF);
+            if (code == 0) continue;  // padding after the row's last nonzero code
+            const uint32_t *w = (const uint32_t *)ec;
+            apt Q;
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                Q.x.v[k] = w[k];
+                Q.y.v[k] = w[NL + k];
             }
+            const bool q_inf = w[ENTRY_INF] != 0;
+            if (code < 0) Q.y = fe_neg(Q.y);
+            acc = jpt_add_affine_known(acc, acc_inf, Q, q_inf, acc_inf);
         }
     }
-    if (!active) return;
     const int j = p >> 1, pt = p & 1;
     const int64_t e_out = (int64_t)i * l + j;
     if (d.S > 1) {
@@ -332,11 +344,10 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
 }
 
 __global__ void __launch_bounds__(256) accumulate_kernel(run_args a) {
-    extern __shared__ uint32_t lds[];
     __shared__ int32_t s_tile;
     int32_t *ctr = at<int32_t>(a, a.ctr_off);
     for (;;) {
-        __syncthreads();  // every thread has read s_tile and finished with the LDS tables
+        __syncthreads();  // every thread has read s_tile
         if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1);
         __syncthreads();
         const int64_t tile = __builtin_amdgcn_readfirstlane(s_tile);  // uniform over the workgroup
@@ -349,7 +360,7 @@ __global__ void __launch_bounds__(256) accumulate_kernel(run_args a) {
         const int64_t r = u - (int64_t)bz * txy;
         const int by = (int)(r / d.tiles_x);
         const int bx = (int)(r - (int64_t)by * d.tiles_x);
-        accumulate_tile(a, d, bx, by, bz, lds);
+        accumulate_tile(a, d, bx, by, bz);
     }
 }
 
@@ -462,7 +473,7 @@ int build_plan_cfg(const void *A, int m, int n, int bits, bool sgn, const pcmm_c
         cussen_plan P;
         int rc = build_cussen_plan(A, m, n, bits, sgn, N, g, &P);
         if (rc) return rc;
-        if (g > 1 && (size_t)std::max(P.max_entries, 1) * ENTRY_WORDS * 4 > LDS_BUDGET) continue;
+        if (g > 1 && (size_t)std::max(P.max_entries, 1) * ENTRY_WORDS * 4 > GROUP_TABLE_CAP) continue;
         const double c = predicted_cost(P);
         if (g == 1 || c < best) {
             best = c;
@@ -486,7 +497,6 @@ struct job {
     int64_t n_lanes_pad = 0;  // whole wavefront (0: not applicable), chosen per run
     size_t regs_bytes_pad = 0;
     int tm = 256, pp = 1, kc = 1, S = 1, gps = 0, tiles_x = 1, tiles_y = 1;
-    size_t lds_bytes = 0;
     int64_t ldj = 64, norm_threads = 0, ld_pre = 0;
     int norm_per = 0;
     size_t regs_bytes = 0, table_bytes = 0, part_bytes = 0, cjac_bytes = 0, norm_bytes = 0;
@@ -495,7 +505,6 @@ struct job {
     int chunks_per_split = 0;
     std::vector<int32_t> lists, chunk_len;
     std::vector<int64_t> chunk_off;
-    bool fits = true;  // one column group's tables for one pair fit the LDS budget
 };
 
 // padded table-build lanes allowed (4 wavefronts per SIMD of a 256-CU device)
@@ -537,27 +546,15 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     G.n_lanes_pad = G.Lj_pad ? (int64_t)P.ngroups * 2 * G.Lj_pad : 0;
     // accumulation tile
     const int npairs = 2 * l;
-    // rows per tile: the fewest padded rows, the larger tile on ties (each
-    // staged table entry then serves more rows), among the tiles whose pairs'
-    // tables of one column group fit the default LDS chunk (the persistent
-    // kernel reserves the largest chunk of all problems of a run, and two
-    // workgroups per CU, which the registers allow, need <= 80 KB each)
+    // rows per tile: the fewest padded rows, the larger tile on ties (the
+    // wavefronts of a workgroup then gather from the same pairs' tables)
     G.tm = 256;
-    for (int tm : {128, 64, 32}) {
-        if ((size_t)(256 / tm) * emax * ENTRY_WORDS * 4 > LDS_CHUNK) break;
+    for (int tm : {128, 64, 32})
         if ((int64_t)(m + tm - 1) / tm * tm < (int64_t)(m + G.tm - 1) / G.tm * G.tm) G.tm = tm;
-    }
     G.pp = 256 / G.tm;
     G.tiles_x = (m + G.tm - 1) / G.tm;
     G.tiles_y = (npairs + G.pp - 1) / G.pp;
     const int64_t wg_base = (int64_t)G.tiles_x * G.tiles_y;
-    const size_t group_bytes = (size_t)G.pp * emax * ENTRY_WORDS * 4;
-    int kc = cfg && cfg->k_chunk > 0 ? cfg->k_chunk : (int)std::max<size_t>(1, LDS_CHUNK / group_bytes);
-    kc = std::max(1, std::min(kc, std::max(P.ngroups, 1)));
-    while (kc > 1 && (size_t)kc * group_bytes > LDS_BUDGET) --kc;
-    G.kc = kc;
-    G.fits = group_bytes <= LDS_BUDGET;
-    G.lds_bytes = (size_t)kc * group_bytes;
     int S = cfg && cfg->k_split > 0 ? cfg->k_split : 1;
     if (!(cfg && cfg->k_split > 0)) {
         while (S < 64 && wg_base * S * 2 <= 2048 && (P.ngroups / (S * 2)) >= 4) S *= 2;
@@ -565,6 +562,9 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     while (S > 1 && (P.ngroups + S - 1) / S < 1) S /= 2;
     G.S = S;
     G.gps = P.ngroups > 0 ? (P.ngroups + S - 1) / S : 0;
+    // column groups per code list: a split's groups in one list, unless the
+    // caller asks for shorter lists (each list is padded to its longest row)
+    G.kc = std::max(1, std::min(cfg && cfg->k_chunk > 0 ? cfg->k_chunk : G.gps, std::max(G.gps, 1)));
     G.tile_cost = (double)G.tm * G.pp * G.gps;
     // workspace regions
     const int64_t n_out = (int64_t)m * l;
@@ -584,8 +584,8 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
                   align256(G.cjac_bytes) + align256(G.norm_bytes);
 }
 
-// The accumulation walks, per (split, LDS chunk of kc column groups), only
-// the nonzero codes of each row: slot-major lists lists[(chunk_off + slot) * m
+// The accumulation walks, per (split, chunk of kc column groups), only the
+// nonzero codes of each row: slot-major lists lists[(chunk_off + slot) * m
 // + i] = (group in chunk) << 16 | (code & 0xffff), padded with 0 (no
 // operation) up to the chunk's longest row.  A wavefront then runs as many
 // mixed additions as its rows' largest count of nonzero codes rather than
@@ -641,7 +641,6 @@ struct run_layout {
     int32_t count = 0;  // descriptors
     size_t copy_bytes = 0, ctr_off = 0, ws_bytes = 256;
     int64_t tb_blocks = 0, tiles = 0, red_blocks = 0, norm_blocks = 0;
-    size_t max_lds = 0;
     int acc_grid = 0;
     std::vector<int> fills;  // run indices whose inner dimension is empty (identity outputs)
 };
@@ -730,7 +729,6 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
     L.ctr_off = img;
     size_t ws = img + 256;
     int64_t tb = 0, tiles = 0, red = 0, norm = 0;
-    L.max_lds = 0;
     const bool pad = pad_run(nd, [&](size_t q) -> const job & { return pl.jobs[q]; });
     for (size_t k = 0; k < nd; ++k) {
         const job &G = pl.jobs[k];
@@ -779,7 +777,6 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         ws += align256(G.cjac_bytes);
         d.w_norm = (int64_t)ws;
         ws += align256(G.norm_bytes);
-        L.max_lds = std::max(L.max_lds, G.lds_bytes);
     }
     L.ws_bytes = ws + 256;
     L.tb_blocks = tb;
@@ -811,17 +808,14 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
 }
 
 std::mutex g_occ_lock;
-std::map<std::pair<int, size_t>, int64_t> g_occ_cache;  // (device, LDS bytes) -> resident workgroups
+std::map<int, int64_t> g_occ_cache;  // device -> resident workgroups
 
 // Sizes the persistent accumulation grid of L on `device` (current): the
 // workgroups that fit on the device at once, or the tiles if fewer.
 pcmm_status size_acc_grid(int device, run_layout &L) {
     L.acc_grid = 0;
     if (L.tiles == 0) return PCMM_OK;
-    if (L.max_lds > 64 * 1024)
-        PCMM_HIP_TRY(hipFuncSetAttribute((const void *)accumulate_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)L.max_lds));
-    const auto key = std::make_pair(device, L.max_lds);
+    const int key = device;
     int64_t cap = 0;
     {
         std::lock_guard<std::mutex> guard(g_occ_lock);
@@ -830,7 +824,7 @@ pcmm_status size_acc_grid(int device, run_layout &L) {
     }
     if (cap == 0) {
         int per_cu = 0, cus = 0;
-        PCMM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, accumulate_kernel, 256, L.max_lds));
+        PCMM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, accumulate_kernel, 256, 0));
         PCMM_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
         cap = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
         std::lock_guard<std::mutex> guard(g_occ_lock);
@@ -873,7 +867,7 @@ pcmm_status build_plan(const pcmm_problem *probs, int count, pcmm_plan_s &pl) {
         G.l = q.l;
         G.c_form = q.c_form;
         make_geometry(G, &q.cfg);
-        if (G.fits && (int64_t)q.m * q.l > 0 && q.n > 0) pack_codes(G);
+        if ((int64_t)q.m * q.l > 0 && q.n > 0) pack_codes(G);
     };
     const int nthreads = std::min(count, std::max(1, std::min(16, (int)std::thread::hardware_concurrency())));
     if (nthreads <= 1) {
@@ -890,9 +884,6 @@ pcmm_status build_plan(const pcmm_problem *probs, int count, pcmm_plan_s &pl) {
     for (int i = 0; i < count; ++i) {
         if (rcs[i] == -2) return PCMM_ERANGE;
         if (rcs[i]) return PCMM_EINVAL;
-        // a table larger than the LDS budget (g > 1 with very many distinct
-        // row segments) has no accumulation geometry
-        if (!built[i].fits && (int64_t)probs[i].m * probs[i].l > 0 && probs[i].n > 0) return PCMM_EINVAL;
     }
     for (int i = 0; i < count; ++i) {
         const pcmm_problem &q = probs[i];
@@ -957,10 +948,7 @@ pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *p
     }
     PCMM_REC(2);
     if (gpu_work) {
-        if (L.max_lds > 64 * 1024)
-            PCMM_HIP_TRY(hipFuncSetAttribute((const void *)accumulate_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.max_lds));
-        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)L.acc_grid), dim3(256), L.max_lds, s, ra);
+        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)L.acc_grid), dim3(256), 0, s, ra);
         PCMM_LAUNCH_CHECK();
     }
     PCMM_REC(3);
@@ -1251,7 +1239,6 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         ws += align256(G.cjac_bytes);
         d.w_norm = (int64_t)ws;
         ws += align256(G.norm_bytes);
-        L.max_lds = std::max(L.max_lds, G.lds_bytes);
         D[q] = d;
     }
     L.ws_bytes = ws + 256;

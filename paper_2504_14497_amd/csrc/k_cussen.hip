@@ -454,24 +454,29 @@ double predicted_cost(const cussen_plan &P) {
 std::mutex g_tune_lock;
 std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;  // (m, n, bits, signed, N) -> g
 
-// Builds the plan for cfg's group, or for the autotuned one.
+// host threads for planning: the CPU share of one GPU
+int host_threads() { return std::max(1, std::min(16, (int)std::thread::hardware_concurrency())); }
+
+// Builds the plan for cfg's group, or for the autotuned one, on up to
+// `threads` host threads.
 int build_plan_cfg(const void *A, int m, int n, int bits, bool sgn, const pcmm_cussen_cfg *cfg,
-                   cussen_plan *out) {
+                   cussen_plan *out, int threads) {
     const int N = cfg_rounds(cfg);
     const int group = cfg ? cfg->group : 0;
-    if (group != PCMM_GROUP_AUTO) return build_cussen_plan(A, m, n, bits, sgn, N, group > 0 ? group : 1, out);
+    if (group != PCMM_GROUP_AUTO)
+        return build_cussen_plan(A, m, n, bits, sgn, N, group > 0 ? group : 1, out, threads);
     const auto key = std::make_tuple(m, n, bits, (int)sgn, N);
     {
         std::lock_guard<std::mutex> guard(g_tune_lock);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) return build_cussen_plan(A, m, n, bits, sgn, N, it->second, out);
+        if (it != g_tune_cache.end()) return build_cussen_plan(A, m, n, bits, sgn, N, it->second, out, threads);
     }
     int best_g = 1;
     double best = 0;
     const int gmax = std::max(1, std::min(4, n));
     for (int g = 1; g <= gmax; ++g) {
         cussen_plan P;
-        int rc = build_cussen_plan(A, m, n, bits, sgn, N, g, &P);
+        int rc = build_cussen_plan(A, m, n, bits, sgn, N, g, &P, threads);
         if (rc) return rc;
         if (g > 1 && (size_t)std::max(P.max_entries, 1) * ENTRY_WORDS * 4 > GROUP_TABLE_CAP) continue;
         const double c = predicted_cost(P);
@@ -591,44 +596,70 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
 // mixed additions as its rows' largest count of nonzero codes rather than
 // one per column group, which matters where many codes are zero (small
 // bit-widths).
-void pack_codes(job &G) {
+void pack_codes(job &G, int threads) {
     const cussen_plan &P = G.P;
     const int m = P.m;
     G.chunks_per_split = G.gps > 0 ? (G.gps + G.kc - 1) / G.kc : 0;
     const int nchunks = G.S * G.chunks_per_split;
     G.chunk_off.assign(nchunks, 0);
     G.chunk_len.assign(nchunks, 0);
-    std::vector<int32_t> cnt(m);
+    auto chunk_groups = [&](int c, int &g0, int &g1) {
+        const int bz = c / std::max(G.chunks_per_split, 1);
+        g0 = bz * G.gps + (c % std::max(G.chunks_per_split, 1)) * G.kc;
+        g1 = std::min({P.ngroups, bz * G.gps + G.gps, g0 + G.kc});
+    };
+    // rows are independent (each owns one column of every list): ranges of
+    // rows on up to `threads` threads, first for the lists' lengths, then to
+    // fill them
+    const int nthreads = std::max(1, std::min(threads, m / 64));
+    auto run = [&](auto &&body) {
+        if (nthreads <= 1) {
+            body(0, m, 0);
+            return;
+        }
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthreads; ++t)
+            pool.emplace_back(body, (int)((int64_t)m * t / nthreads), (int)((int64_t)m * (t + 1) / nthreads), t);
+        for (auto &th : pool) th.join();
+    };
+    std::vector<int> part_len((size_t)nthreads * std::max(nchunks, 1), 0);
+    run([&](int r0, int r1, int t) {
+        for (int c = 0; c < nchunks; ++c) {
+            int g0, g1, len = 0;
+            chunk_groups(c, g0, g1);
+            for (int i = r0; i < r1; ++i) {
+                int k = 0;
+                for (int g = g0; g < g1; ++g) k += P.codes[(size_t)g * m + i] != 0;
+                len = std::max(len, k);
+            }
+            part_len[(size_t)t * nchunks + c] = len;
+        }
+    });
     int64_t total = 0;
     for (int c = 0; c < nchunks; ++c) {
-        const int bz = c / std::max(G.chunks_per_split, 1);
-        const int g0 = bz * G.gps + (c % std::max(G.chunks_per_split, 1)) * G.kc;
-        const int g1 = std::min({P.ngroups, bz * G.gps + G.gps, g0 + G.kc});
         int len = 0;
-        for (int i = 0; i < m; ++i) {
-            int k = 0;
-            for (int g = g0; g < g1; ++g) k += P.codes[(size_t)g * m + i] != 0;
-            len = std::max(len, k);
-        }
+        for (int t = 0; t < nthreads; ++t) len = std::max(len, part_len[(size_t)t * nchunks + c]);
         G.chunk_off[c] = total;
         G.chunk_len[c] = len;
         total += len;
     }
     G.lists.assign((size_t)total * m, 0);
-    for (int c = 0; c < nchunks; ++c) {
-        const int bz = c / std::max(G.chunks_per_split, 1);
-        const int g0 = bz * G.gps + (c % std::max(G.chunks_per_split, 1)) * G.kc;
-        const int g1 = std::min({P.ngroups, bz * G.gps + G.gps, g0 + G.kc});
-        std::fill(cnt.begin(), cnt.end(), 0);
-        for (int g = g0; g < g1; ++g) {
-            const int16_t *row = &P.codes[(size_t)g * m];
-            for (int i = 0; i < m; ++i) {
-                if (!row[i]) continue;
-                G.lists[(size_t)(G.chunk_off[c] + cnt[i]++) * m + i] =
-                    (int32_t)(((uint32_t)(g - g0) << 16) | (uint16_t)row[i]);
+    run([&](int r0, int r1, int) {
+        std::vector<int32_t> cnt(std::max(r1 - r0, 0));
+        for (int c = 0; c < nchunks; ++c) {
+            int g0, g1;
+            chunk_groups(c, g0, g1);
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int g = g0; g < g1; ++g) {
+                const int16_t *row = &P.codes[(size_t)g * m];
+                for (int i = r0; i < r1; ++i) {
+                    if (!row[i]) continue;
+                    G.lists[(size_t)(G.chunk_off[c] + cnt[i - r0]++) * m + i] =
+                        (int32_t)(((uint32_t)(g - g0) << 16) | (uint16_t)row[i]);
+                }
             }
         }
-    }
+    });
 }
 
 }  // namespace
@@ -858,18 +889,21 @@ pcmm_status build_plan(const pcmm_problem *probs, int count, pcmm_plan_s &pl) {
     pl.stats.assign(count, pcmm_cussen_stats{});
     std::vector<job> built(count);
     std::vector<int> rcs(count, 0);
+    // problems on up to host_threads() threads; a problem's column groups
+    // share the threads left over (all of them for a single problem)
+    const int nthreads = std::min(count, host_threads());
+    const int inner = std::max(1, host_threads() / std::max(nthreads, 1));
     auto work = [&](int i) {
         const pcmm_problem &q = probs[i];
         job &G = built[i];
-        rcs[i] = build_plan_cfg(q.A, q.m, q.n, q.bits, q.is_signed != 0, &q.cfg, &G.P);
+        rcs[i] = build_plan_cfg(q.A, q.m, q.n, q.bits, q.is_signed != 0, &q.cfg, &G.P, inner);
         if (rcs[i]) return;
         G.index = i;
         G.l = q.l;
         G.c_form = q.c_form;
         make_geometry(G, &q.cfg);
-        if ((int64_t)q.m * q.l > 0 && q.n > 0) pack_codes(G);
+        if ((int64_t)q.m * q.l > 0 && q.n > 0) pack_codes(G, inner);
     };
-    const int nthreads = std::min(count, std::max(1, std::min(16, (int)std::thread::hardware_concurrency())));
     if (nthreads <= 1) {
         for (int i = 0; i < count; ++i) work(i);
     } else {
@@ -919,7 +953,8 @@ pcmm_status check_mats(int m, int n, int l, int c_form, const pcmm_mat *B, const
 // workspace itself.  B, C: the run's n_io matrices.  ev: PCMM_STAGE_EVENTS
 // events or null.
 pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *plan_base, const pcmm_mat *B,
-                        pcmm_mat *C, int n_io, void *workspace, hipEvent_t *ev, hipStream_t s) {
+                        pcmm_mat *C, int n_io, void *workspace, hipEvent_t *ev, hipStream_t s,
+                        hipEvent_t copied) {
     auto rec = [&](int i) -> pcmm_status {
         if (ev) PCMM_HIP_TRY(hipEventRecord(ev[i], s));
         return PCMM_OK;
@@ -941,6 +976,9 @@ pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *p
         for (int i = 0; i < n_io; ++i) ra.io[i] = io_ptrs{B[i].d, C[i].d, B[i].ld, C[i].ld};
         PCMM_HIP_TRY(hipMemcpyAsync(workspace, copy_src, L.copy_bytes, hipMemcpyHostToDevice, s));
     }
+    // the host buffer may be refilled once its copy has executed, while the
+    // kernels below still run
+    if (copied) PCMM_HIP_TRY(hipEventRecord(copied, s));
     PCMM_REC(1);
     if (gpu_work) {
         hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)L.tb_blocks), dim3(256), 0, s, ra);
@@ -1035,7 +1073,7 @@ extern "C" pcmm_status pcmm_cussen_plan_stats(const void *A, int32_t m, int32_t 
                                               pcmm_cussen_stats *stats) {
     if (!stats || !valid_cfg(cfg) || m < 0 || n < 0) return PCMM_EINVAL;
     job G;
-    int rc = build_plan_cfg(A, m, n, bits, is_signed != 0, cfg, &G.P);
+    int rc = build_plan_cfg(A, m, n, bits, is_signed != 0, cfg, &G.P, host_threads());
     if (rc == -2) return PCMM_ERANGE;
     if (rc) return PCMM_EINVAL;
     G.l = 1;
@@ -1089,7 +1127,8 @@ extern "C" pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t 
     }
     const bool prof = wait_prof || caller_events;
     {
-        // stage the image in the device's pinned buffer, once its previous copy has executed
+        // stage the image in the device's pinned buffer, once its previous copy
+        // has executed (the previous run's kernels may still be running)
         std::lock_guard<std::mutex> guard(g_stage_lock);
         if (pl.device < 0 || pl.device >= 64) return PCMM_EDEVICE;
         staging &sg = g_stage[pl.device];
@@ -1105,9 +1144,8 @@ extern "C" pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t 
         }
         if (!sg.done) PCMM_HIP_TRY(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
         if (!pl.image.empty()) memcpy(sg.host, pl.image.data(), pl.image.size());
-        st = enqueue_run(pl.full, sg.host, nullptr, B, C, 1, workspace, prof ? ev : nullptr, s);
+        st = enqueue_run(pl.full, sg.host, nullptr, B, C, 1, workspace, prof ? ev : nullptr, s, sg.done);
         if (st != PCMM_OK) return st;
-        PCMM_HIP_TRY(hipEventRecord(sg.done, s));
     }
     if (wait_prof) {
         PCMM_HIP_TRY(hipEventSynchronize(ev[5]));
@@ -1183,7 +1221,7 @@ extern "C" pcmm_status pcmm_plan_run(pcmm_plan plan, const pcmm_mat *B, pcmm_mat
         }
     }
     return enqueue_run(plan->full, plan->pinned, nullptr, B, C, plan->count, workspace, stage_events ? ev : nullptr,
-                       (hipStream_t)stream);
+                       (hipStream_t)stream, nullptr);  // the pinned image is immutable
 }
 
 namespace {
@@ -1316,8 +1354,5 @@ extern "C" pcmm_status pcmm_plan_run_selected(pcmm_plan plan, const int32_t *whi
         PCMM_HIP_TRY(hipEventSynchronize(slot.done));
     }
     if (!D.empty()) memcpy(slot.host, D.data(), D.size() * sizeof(prob_desc));
-    st = enqueue_run(L, slot.host, plan->resident, B, C, k, workspace, stage_events ? ev : nullptr, s);
-    if (st != PCMM_OK) return st;
-    PCMM_HIP_TRY(hipEventRecord(slot.done, s));
-    return PCMM_OK;
+    return enqueue_run(L, slot.host, plan->resident, B, C, k, workspace, stage_events ? ev : nullptr, s, slot.done);
 }

@@ -3,6 +3,8 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <unordered_map>
 
 namespace pcmm {
@@ -123,8 +125,136 @@ column_result compress_column(const std::vector<int> &vals, int N, int t, std::v
 
 }  // namespace
 
-int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int N, int g,
-                      cussen_plan *out) {
+namespace {
+
+// One column group's share of the plan: its program, its table entries and
+// (written in place) its row codes.
+struct group_plan {
+    std::vector<plan_op> ops;
+    std::vector<int16_t> entries;
+    int nreg = 0;
+    int64_t level_mults = 0, level_adds = 0, mul_bits = 0, accum_adds = 0;
+    int err = 0;  // 0, -1 (too many registers or entries), -2 (entry outside the bit-width)
+};
+
+// Per-thread scratch: direct-mapped lookup of row segments (g <= 2, entries
+// up to 8 bits), stamped with the group so it needs no clearing.
+struct group_scratch {
+    std::vector<int> stamp, slot, vals;
+    std::vector<int32_t> col[4];
+};
+
+void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, int g, int key_bits, int grp,
+                 int16_t *codes, group_plan &gp, group_scratch &sc) {
+    const int lo = is_signed ? -(1 << (bits - 1)) : 0;
+    const int hi = is_signed ? (1 << (bits - 1)) - 1 : (1 << bits) - 1;
+    const int k0 = grp * g;
+    const int gg = std::min(g, n - k0);
+    // the group's columns of A, validated against the declared bit-width
+    for (int t = 0; t < gg; ++t) {
+        sc.col[t].resize(m);
+        for (int i = 0; i < m; ++i) {
+            const int v = plain_at(A, (int64_t)i * n + k0 + t, bits, is_signed);
+            if (v < lo || v > hi) {
+                gp.err = -2;
+                return;
+            }
+            sc.col[t][i] = v;
+        }
+    }
+    int nreg = 0;
+    // per-digit tables
+    std::vector<std::vector<int16_t>> digit_operand(gg);
+    sc.vals.resize(m);
+    for (int t = 0; t < gg; ++t) {
+        const int32_t *col = sc.col[t].data();
+        for (int i = 0; i < m; ++i) sc.vals[i] = std::abs((int)col[i]);
+        column_result cr = compress_column(sc.vals, N, t, gp.ops, &nreg, &gp.mul_bits);
+        gp.level_mults += cr.nN;
+        gp.level_adds += cr.adds_counted;
+        if (gg == 1) {
+            // one column: the table is the level-1 reconstruction itself,
+            // entry e = the e-th smallest distinct |a|; code = sign (e + 1)
+            for (int i = 0; i < m; ++i) {
+                if (cr.row_rank[i] < 0) continue;
+                codes[i] = (int16_t)(col[i] < 0 ? -(cr.row_rank[i] + 1) : cr.row_rank[i] + 1);
+                ++gp.accum_adds;
+            }
+            gp.entries = std::move(cr.level1);
+            gp.nreg = nreg;
+            if (nreg > 32000) gp.err = -1;
+            return;
+        }
+        digit_operand[t] = std::move(cr.row_operand);
+    }
+    // distinct row segments up to sign (first nonzero digit made positive);
+    // a segment is keyed by its digits, key_bits each
+    const bool direct = gg <= 2 && key_bits == 9;
+    if (direct && sc.stamp.empty()) {
+        sc.stamp.assign((size_t)1 << 18, -1);
+        sc.slot.assign((size_t)1 << 18, 0);
+    }
+    std::unordered_map<uint64_t, int> entry_of;
+    for (int i = 0; i < m; ++i) {
+        int seg[4] = {0, 0, 0, 0};
+        int first = -1;
+        for (int t = 0; t < gg; ++t) {
+            seg[t] = sc.col[t][i];
+            if (first < 0 && seg[t] != 0) first = t;
+        }
+        if (first < 0) continue;  // code 0: all-zero segment
+        int sigma = seg[first] < 0 ? -1 : 1;
+        uint64_t key = 0;
+        for (int t = 0; t < gg; ++t) {
+            seg[t] *= sigma;
+            key |= (uint64_t)(seg[t] + (1 << (key_bits - 1))) << (key_bits * t);
+        }
+        int e = -1;
+        if (direct) {
+            if (sc.stamp[key] == grp) e = sc.slot[key];
+        } else {
+            auto it = entry_of.find(key);
+            if (it != entry_of.end()) e = it->second;
+        }
+        if (e < 0) {
+            // entry = sum_t seg_t B_t from the digit tables
+            int16_t acc = INT16_MIN;
+            for (int t = 0; t < gg; ++t) {
+                if (seg[t] == 0) continue;
+                int16_t d = digit_operand[t][i];
+                if (acc == INT16_MIN) {
+                    acc = d;  // first nonzero digit is positive
+                } else {
+                    plan_op op{};
+                    op.kind = OP_ADD;
+                    op.dst = (int16_t)nreg++;
+                    op.a = acc;
+                    op.b = d;
+                    op.neg_b = seg[t] < 0 ? 1 : 0;
+                    gp.ops.push_back(op);
+                    acc = op.dst;
+                }
+            }
+            e = (int)gp.entries.size();
+            gp.entries.push_back(acc);
+            if (direct) {
+                sc.stamp[key] = grp;
+                sc.slot[key] = e;
+            } else {
+                entry_of.emplace(key, e);
+            }
+        }
+        codes[i] = (int16_t)(sigma * (e + 1));
+        ++gp.accum_adds;
+    }
+    gp.nreg = nreg;
+    if (nreg > 32000 || gp.entries.size() > 32000) gp.err = -1;
+}
+
+}  // namespace
+
+int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int N, int g, cussen_plan *out,
+                      int threads) {
     if (!out || m < 0 || n < 0 || bits < 1 || bits > 16 || N < 1 || N > 8 || g < 1 || g > 4) return -1;
     if ((int64_t)m * n > 0 && !A) return -1;
     if (m > 32767) return -1;
@@ -132,135 +262,58 @@ int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int
     // entries and 17 bits beyond (so at most 3 digits fit the 64-bit key)
     const int key_bits = bits <= 8 ? 9 : 17;
     if (g * key_bits > 64) return -1;
-    // validate A against the declared bit-width
-    const int lo = is_signed ? -(1 << (bits - 1)) : 0;
-    const int hi = is_signed ? (1 << (bits - 1)) - 1 : (1 << bits) - 1;
-    // validate and transpose to column-major (columns are what gets compressed)
-    std::vector<int32_t> At((size_t)m * n);
-    for (int i = 0; i < m; ++i) {
-        for (int k = 0; k < n; ++k) {
-            const int64_t x = (int64_t)i * n + k;
-            const int v = plain_at(A, x, bits, is_signed);
-            if (v < lo || v > hi) return -2;
-            At[(size_t)k * m + i] = v;
-        }
-    }
-    auto at = [&](int i, int k) -> int { return At[(size_t)k * m + i]; };
     cussen_plan P;
     P.m = m;
     P.n = n;
     P.g = g;
     P.N = N;
     P.ngroups = (n + g - 1) / g;
+    P.codes.assign((size_t)P.ngroups * m, 0);
+    // the groups are independent: built on up to `threads` threads (at least
+    // 16 groups each), then concatenated in group order
+    std::vector<group_plan> parts(P.ngroups);
+    const int nthreads = std::max(1, std::min(threads, P.ngroups / 16));
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        group_scratch sc;
+        for (int grp = next++; grp < P.ngroups; grp = next++)
+            build_group(A, m, n, bits, is_signed, N, g, key_bits, grp, &P.codes[(size_t)grp * m], parts[grp], sc);
+    };
+    if (nthreads <= 1) {
+        worker();
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
+        for (auto &th : pool) th.join();
+    }
+    for (const group_plan &gp : parts)
+        if (gp.err == -2) return -2;
+    for (const group_plan &gp : parts)
+        if (gp.err) return gp.err;
+    size_t nops = 0, nent = 0;
+    for (const group_plan &gp : parts) {
+        nops += gp.ops.size();
+        nent += gp.entries.size();
+    }
+    P.ops.reserve(nops);
+    P.entries.reserve(nent);
+    P.op_begin.reserve(P.ngroups + 1);
+    P.entry_begin.reserve(P.ngroups + 1);
     P.op_begin.push_back(0);
     P.entry_begin.push_back(0);
-    P.codes.assign((size_t)P.ngroups * m, 0);
-    std::vector<int> stamp, slot;  // direct-mapped segment lookup for g <= 2
-    for (int grp = 0; grp < P.ngroups; ++grp) {
-        const int k0 = grp * g;
-        const int gg = std::min(g, n - k0);
-        int nreg = 0;
-        // per-digit tables
-        std::vector<std::vector<int16_t>> digit_operand(gg);
-        std::vector<int> vals(m);
-        for (int t = 0; t < gg; ++t) {
-            const int32_t *col = &At[(size_t)(k0 + t) * m];
-            for (int i = 0; i < m; ++i) vals[i] = std::abs((int)col[i]);
-            column_result cr = compress_column(vals, N, t, P.ops, &nreg, &P.table_mul_bits);
-            P.level_mults += cr.nN;
-            P.level_adds += cr.adds_counted;
-            if (gg == 1) {
-                // one column: the table is the level-1 reconstruction itself,
-                // entry e = the e-th smallest distinct |a|; code = sign (e + 1)
-                for (int i = 0; i < m; ++i) {
-                    if (cr.row_rank[i] < 0) continue;
-                    P.codes[(size_t)grp * m + i] = (int16_t)(col[i] < 0 ? -(cr.row_rank[i] + 1) : cr.row_rank[i] + 1);
-                    ++P.accum_adds;
-                }
-                P.entries.insert(P.entries.end(), cr.level1.begin(), cr.level1.end());
-                P.max_entries = std::max(P.max_entries, (int)cr.level1.size());
-                P.table_entries += (int64_t)cr.level1.size();
-                break;
-            }
-            digit_operand[t] = std::move(cr.row_operand);
-        }
-        if (gg == 1) {
-            if (nreg > 32000) return -1;
-            P.entry_begin.push_back((int32_t)P.entries.size());
-            P.op_begin.push_back((int32_t)P.ops.size());
-            P.nregs.push_back(nreg);
-            P.max_regs = std::max(P.max_regs, nreg);
-            continue;
-        }
-        // distinct row segments up to sign (first nonzero digit made positive);
-        // a segment is keyed by its digits, key_bits each
-        std::vector<int16_t> entry_operands;
-        const bool direct = gg <= 2 && key_bits == 9;
-        if (direct && (int)stamp.size() < (1 << (9 * gg))) {
-            stamp.assign((size_t)1 << 18, -1);
-            slot.assign((size_t)1 << 18, 0);
-        }
-        std::unordered_map<uint64_t, int> entry_of;
-        for (int i = 0; i < m; ++i) {
-            int seg[4] = {0, 0, 0, 0};
-            int first = -1;
-            for (int t = 0; t < gg; ++t) {
-                seg[t] = at(i, k0 + t);
-                if (first < 0 && seg[t] != 0) first = t;
-            }
-            if (first < 0) continue;  // code 0: all-zero segment
-            int sigma = seg[first] < 0 ? -1 : 1;
-            uint64_t key = 0;
-            for (int t = 0; t < gg; ++t) {
-                seg[t] *= sigma;
-                key |= (uint64_t)(seg[t] + (1 << (key_bits - 1))) << (key_bits * t);
-            }
-            int e = -1;
-            if (direct) {
-                if (stamp[key] == grp) e = slot[key];
-            } else {
-                auto it = entry_of.find(key);
-                if (it != entry_of.end()) e = it->second;
-            }
-            if (e < 0) {
-                // entry = sum_t seg_t B_t from the digit tables
-                int16_t acc = INT16_MIN;
-                for (int t = 0; t < gg; ++t) {
-                    if (seg[t] == 0) continue;
-                    int16_t d = digit_operand[t][i];
-                    if (acc == INT16_MIN) {
-                        acc = d;  // first nonzero digit is positive
-                    } else {
-                        plan_op op{};
-                        op.kind = OP_ADD;
-                        op.dst = (int16_t)nreg++;
-                        op.a = acc;
-                        op.b = d;
-                        op.neg_b = seg[t] < 0 ? 1 : 0;
-                        P.ops.push_back(op);
-                        acc = op.dst;
-                    }
-                }
-                e = (int)entry_operands.size();
-                entry_operands.push_back(acc);
-                if (direct) {
-                    stamp[key] = grp;
-                    slot[key] = e;
-                } else {
-                    entry_of.emplace(key, e);
-                }
-            }
-            P.codes[(size_t)grp * m + i] = (int16_t)(sigma * (e + 1));
-            ++P.accum_adds;
-        }
-        if (nreg > 32000 || entry_operands.size() > 32000) return -1;
-        P.entries.insert(P.entries.end(), entry_operands.begin(), entry_operands.end());
-        P.entry_begin.push_back((int32_t)P.entries.size());
+    for (group_plan &gp : parts) {
+        P.ops.insert(P.ops.end(), gp.ops.begin(), gp.ops.end());
+        P.entries.insert(P.entries.end(), gp.entries.begin(), gp.entries.end());
         P.op_begin.push_back((int32_t)P.ops.size());
-        P.nregs.push_back(nreg);
-        P.max_regs = std::max(P.max_regs, nreg);
-        P.max_entries = std::max(P.max_entries, (int)entry_operands.size());
-        P.table_entries += (int64_t)entry_operands.size();
+        P.entry_begin.push_back((int32_t)P.entries.size());
+        P.nregs.push_back(gp.nreg);
+        P.max_regs = std::max(P.max_regs, gp.nreg);
+        P.max_entries = std::max(P.max_entries, (int)gp.entries.size());
+        P.table_entries += (int64_t)gp.entries.size();
+        P.level_mults += gp.level_mults;
+        P.level_adds += gp.level_adds;
+        P.table_mul_bits += gp.mul_bits;
+        P.accum_adds += gp.accum_adds;
     }
     for (const plan_op &op : P.ops)
         if (op.kind == OP_ADD) ++P.table_adds;

@@ -59,10 +59,11 @@ inline int plain_at(const void *A, int64_t x, int bits, bool is_signed) {
 }
 
 // Validates A (m x n row-major, elements as plain_at reads them) against its
-// declared bit-width (1..16) and builds the plan.  Returns 0, or -1 (bad
+// declared bit-width (1..16) and builds the plan, on up to `threads` host
+// threads (column groups are independent).  Returns 0, or -1 (bad
 // arguments, including g > 3 with entries wider than 8 bits) / -2 (an entry
 // outside the bit-width).
-int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int N, int g,
-                      cussen_plan *out);
+int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int N, int g, cussen_plan *out,
+                      int threads = 1);
 
 }  // namespace pcmm

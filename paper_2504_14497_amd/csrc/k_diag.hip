@@ -264,26 +264,31 @@ extern "C" pcmm_status pcmm_diag_probe(int32_t kind, int64_t iters, int32_t bloc
     if (kind < 0 || kind > 4 || iters <= 0 || blocks <= 0 || !seconds || !ops) return PCMM_EINVAL;
     uint32_t *scratch = nullptr;
     PCMM_HIP_TRY(hipMalloc(&scratch, (size_t)blocks * 256 * sizeof(uint32_t)));
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
-    hipEventRecord(e0, 0);
-    switch (kind) {
-        case 0: hipLaunchKernelGGL(probe_mad_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
-        case 1: hipLaunchKernelGGL(probe_add3_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
-        case 2: hipLaunchKernelGGL(probe_femul_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
-        case 3: hipLaunchKernelGGL(probe_madd_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
-        default: hipLaunchKernelGGL(probe_fma64_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
-    }
-    hipError_t le = hipGetLastError();
-    hipEventRecord(e1, 0);
-    hipError_t se = hipEventSynchronize(e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    auto keep = [&](hipError_t e) {  // the first error is the one reported
+        if (err == hipSuccess) err = e;
+    };
+    keep(hipEventCreate(&e1));
     float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(scratch);
-    if (le != hipSuccess || se != hipSuccess) return PCMM_EDEVICE;
+    if (err == hipSuccess) {
+        keep(hipEventRecord(e0, 0));
+        switch (kind) {
+            case 0: hipLaunchKernelGGL(probe_mad_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
+            case 1: hipLaunchKernelGGL(probe_add3_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
+            case 2: hipLaunchKernelGGL(probe_femul_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
+            case 3: hipLaunchKernelGGL(probe_madd_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
+            default: hipLaunchKernelGGL(probe_fma64_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
+        }
+        keep(hipGetLastError());
+        keep(hipEventRecord(e1, 0));
+        keep(hipEventSynchronize(e1));
+        keep(hipEventElapsedTime(&ms, e0, e1));
+    }
+    if (e0) keep(hipEventDestroy(e0));
+    if (e1) keep(hipEventDestroy(e1));
+    keep(hipFree(scratch));
+    if (err != hipSuccess) return PCMM_EDEVICE;
     double per_thread = (kind <= 1 || kind == 4) ? 8.0 * (double)iters : (double)iters;
     *seconds = ms * 1e-3;
     *ops = per_thread * (double)blocks * 256.0;

@@ -279,22 +279,25 @@ pcmm_status generator_table(const uint32_t **out) {
         uint32_t *tab = nullptr;
         void *tmp = nullptr;
         PCMM_HIP_TRY(hipMalloc(&tab, table_bytes()));
+        // on the error paths the frees' own status adds nothing: PCMM_EDEVICE either way
         if (hipMalloc(&tmp, table_tmp_bytes()) != hipSuccess) {
-            hipFree(tab);
+            (void)hipFree(tab);
             return PCMM_EDEVICE;
         }
         hipStream_t s;
         if (hipStreamCreate(&s) != hipSuccess) {
-            hipFree(tab);
-            hipFree(tmp);
+            (void)hipFree(tab);
+            (void)hipFree(tmp);
             return PCMM_EDEVICE;
         }
         pcmm_status st = build_table(base, tab, tmp, table_tmp_bytes(), s);
         hipError_t e = hipStreamSynchronize(s);
-        hipStreamDestroy(s);
-        hipFree(tmp);
+        if (e == hipSuccess) e = hipStreamDestroy(s);
+        else (void)hipStreamDestroy(s);
+        if (e == hipSuccess) e = hipFree(tmp);
+        else (void)hipFree(tmp);
         if (st != PCMM_OK || e != hipSuccess) {
-            hipFree(tab);
+            (void)hipFree(tab);
             return st != PCMM_OK ? st : PCMM_EDEVICE;
         }
         g_table[dev] = tab;
@@ -320,8 +323,8 @@ extern "C" pcmm_status pcmm_keygen(uint64_t seed, uint8_t sk_be[32], pcmm_point_
     uint32_t h[24];
     hipError_t le = hipGetLastError();
     hipError_t ce = hipMemcpy(h, dout, sizeof h, hipMemcpyDeviceToHost);
-    hipFree(dout);
-    if (le != hipSuccess || ce != hipSuccess) return PCMM_EDEVICE;
+    hipError_t fe = hipFree(dout);
+    if (le != hipSuccess || ce != hipSuccess || fe != hipSuccess) return PCMM_EDEVICE;
     words_to_be32(h, sk_be);
     words_to_be32(h + 8, pk->x);
     words_to_be32(h + 16, pk->y);

@@ -36,7 +36,6 @@ namespace {
 
 constexpr int WAVES_PER_BLOCK = 4;
 constexpr size_t BN_BYTES = BN_LIMBS * 4;   // one residue in limb form
-constexpr size_t CT_BYTES = BN_WORDS * 4;   // one residue in canonical words
 
 // device constants of one modulus (limb arrays are BN_LIMBS long)
 struct paillier_consts {

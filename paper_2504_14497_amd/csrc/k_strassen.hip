@@ -375,7 +375,7 @@ extern "C" pcmm_status pcmm_strassen(const void *A, int32_t m, int32_t n, int32_
         const size_t need = G.a_bytes + leafbits.size();
         if (sg.done) PCMM_HIP_TRY(hipEventSynchronize(sg.done));
         if (sg.bytes < need) {
-            if (sg.host) hipHostFree(sg.host);
+            if (sg.host) (void)hipHostFree(sg.host);  // replaced by a larger buffer
             sg.host = nullptr;
             sg.bytes = 0;
             PCMM_HIP_TRY(hipHostMalloc(&sg.host, need, hipHostMallocDefault));

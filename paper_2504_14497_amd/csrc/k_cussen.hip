@@ -204,18 +204,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
         last_r = r;
         jpt last = jpt_infinity();
         int last_reg = -1;
-        for (int o = ob; o < oe; ++o)
-            run_op(ops[o], B, ldb, l, k0, j, pt, regs, rmax, n_lanes, r, lane, last, last_reg);
-        // forward pass of the batched inversion over this table's register entries
         const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
-        for (int e = 0; e < E; ++e) {
-            const int16_t opd = entries[eb + e];
-            if (opd < 0) continue;
-            fe z = reg_load(regs, rmax, n_lanes, r, opd, lane).Z;
-            uint32_t *slot = table + (T * emax + e) * ENTRY_WORDS;
+        // forward pass of the batched inversion, folded into the program: the
+        // plan orders a group's entries by their producing ops, so the next
+        // register entry is always the next one an op produces, and its Z
+        // joins the running product while it is still in registers (entry
+        // slots hold the products before them)
+        int ne = 0;
+        while (ne < E && entries[eb + ne] < 0) ++ne;
+        for (int o = ob; o < oe; ++o) {
+            const plan_op op = ops[o];
+            run_op(op, B, ldb, l, k0, j, pt, regs, rmax, n_lanes, r, lane, last, last_reg);
+            if (ne < E && op.dst == entries[eb + ne]) {
+                uint32_t *slot = table + (T * emax + ne) * ENTRY_WORDS;
 #pragma unroll
-            for (int w = 0; w < NL; ++w) slot[w] = prod.v[w];
-            if (!fe_is_zero(z)) prod = fe_mul_ilp(prod, z);
+                for (int w = 0; w < NL; ++w) slot[w] = prod.v[w];
+                if (!fe_is_zero(last.Z)) prod = fe_mul_ilp(prod, last.Z);
+                ++ne;
+                while (ne < E && entries[eb + ne] < 0) ++ne;
+            }
         }
     }
     if (last_r < 0) return;

@@ -144,6 +144,42 @@ struct group_scratch {
     std::vector<int32_t> col[4];
 };
 
+// The table build folds each entry's Z into its batched inversion as soon as
+// the op producing the entry ends, so a group's entries must be in the order
+// of their producing ops (entries that are base points, which need no
+// inversion, may sit anywhere).  Reorders the entries stably by that op and
+// renumbers the group's row codes to match.
+void order_entries(group_plan &gp, int16_t *codes, int m) {
+    const size_t E = gp.entries.size();
+    std::vector<int> made_by(std::max(gp.nreg, 1), -1);
+    for (size_t o = 0; o < gp.ops.size(); ++o) made_by[gp.ops[o].dst] = (int)o;
+    auto key = [&](size_t e) { return gp.entries[e] < 0 ? -1 : made_by[gp.entries[e]]; };
+    // already in order (always for single columns): the producing ops of the
+    // register entries increase
+    bool sorted = true;
+    int last = -1;
+    for (size_t e = 0; e < E && sorted; ++e) {
+        if (key(e) < 0) continue;
+        sorted = key(e) > last;
+        last = key(e);
+    }
+    if (sorted) return;
+    std::vector<int> order(E);
+    for (size_t e = 0; e < E; ++e) order[e] = (int)e;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
+    std::vector<int16_t> entries(E);
+    std::vector<int> renum(E);
+    for (size_t k = 0; k < E; ++k) {
+        entries[k] = gp.entries[order[k]];
+        renum[order[k]] = (int)k;
+    }
+    gp.entries = std::move(entries);
+    for (int i = 0; i < m; ++i) {
+        const int c = codes[i];
+        if (c != 0) codes[i] = (int16_t)(c < 0 ? -(renum[-c - 1] + 1) : renum[c - 1] + 1);
+    }
+}
+
 void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, int g, int key_bits, int grp,
                  int16_t *codes, group_plan &gp, group_scratch &sc) {
     const int lo = is_signed ? -(1 << (bits - 1)) : 0;
@@ -183,6 +219,7 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
             gp.entries = std::move(cr.level1);
             gp.nreg = nreg;
             if (nreg > 32000) gp.err = -1;
+            else order_entries(gp, codes, m);
             return;
         }
         digit_operand[t] = std::move(cr.row_operand);
@@ -249,6 +286,7 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
     }
     gp.nreg = nreg;
     if (nreg > 32000 || gp.entries.size() > 32000) gp.err = -1;
+    else order_entries(gp, codes, m);
 }
 
 }  // namespace

@@ -46,6 +46,19 @@ pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint32_t *b, ui
 pcmm_status pcmm_diag_field_raw(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
                                 int64_t count, void *stream);
 
+/* Host-only check of the compression plan of A (m x n, row-major, elements as
+ * for pcmm_cussen, bits 1..16) with `rounds` rounds (1..8) and column group
+ * `group` (1..4): each group's table-build program is run on integer
+ * coefficient vectors over its base points B_t (Alg. 2 reconstruction as
+ * exact integer arithmetic, no GPU), and *result receives 0 when every row's
+ * code names the table entry equal to its signed row segment and the table's
+ * register entries follow the order of their producing ops, else 1 (entry
+ * order), 2 (code outside its table), 3 (entry and row segment differ) or 4
+ * (malformed program).  Errors: PCMM_EINVAL (arguments, unsupported shape),
+ * PCMM_ERANGE (an entry of A outside the bit-width). */
+pcmm_status pcmm_diag_plan_check(const void *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
+                                 int32_t rounds, int32_t group, int32_t *result);
+
 /* Point operations, element-wise over count = P->rows * P->cols elements.
  * P, Q: affine npts 1.  k: device uint32 scalars (op 3).  R: Jacobian npts 1.
  * op: 0 P + Q by the mixed addition (P lifted to Z = 1);

@@ -2,7 +2,10 @@
 // programs and row codes (host side of Cussen PC-MM).
 #include "plan.hpp"
 
+#include "../../include/pcmm_diag.h"
+
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <thread>
 #include <unordered_map>
@@ -359,4 +362,97 @@ int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int
     return 0;
 }
 
+// Verifies a plan by running every group's program on integer coefficient
+// vectors over the group's base points (B_t -> the t-th unit vector).  0 when
+// the plan is sound, else the first failure: 1 register entries out of the
+// order of their producing ops, 2 a code outside its group's table, 3 an
+// entry that is not the row segment its code stands for, 4 a malformed
+// program (operand undefined or out of range, a register written twice).
+int check_cussen_plan(const cussen_plan &P, const void *A, int bits, bool is_signed) {
+    const int m = P.m, n = P.n, g = P.g;
+    if ((int)P.op_begin.size() != P.ngroups + 1 || (int)P.entry_begin.size() != P.ngroups + 1 ||
+        (int)P.nregs.size() != P.ngroups || P.codes.size() != (size_t)P.ngroups * m)
+        return 4;
+    using vec = std::array<int64_t, 4>;
+    for (int grp = 0; grp < P.ngroups; ++grp) {
+        const int k0 = grp * g;
+        const int gg = std::min(g, n - k0);
+        const int nreg = P.nregs[grp];
+        std::vector<vec> reg(std::max(nreg, 1));
+        std::vector<int> made_by(std::max(nreg, 1), -1);
+        bool bad = false;
+        auto value = [&](int16_t opd) -> vec {
+            vec v{0, 0, 0, 0};
+            if (opd < 0) {
+                const int t = -1 - opd;
+                if (t >= gg) bad = true;
+                else v[t] = 1;
+            } else if (opd >= nreg || made_by[opd] < 0) {
+                bad = true;
+            } else {
+                v = reg[opd];
+            }
+            return v;
+        };
+        for (int o = P.op_begin[grp]; o < P.op_begin[grp + 1]; ++o) {
+            const plan_op &op = P.ops[o];
+            if (op.dst < 0 || op.dst >= nreg || made_by[op.dst] >= 0) return 4;
+            vec r{0, 0, 0, 0};
+            if (op.kind == OP_MUL) {
+                if (op.a >= 0 || op.s < 1) return 4;
+                const vec b = value(op.a);
+                for (int t = 0; t < 4; ++t) r[t] = (int64_t)op.s * b[t];
+            } else if (op.kind == OP_ADD) {
+                const vec x = value(op.a), y = value(op.b);
+                for (int t = 0; t < 4; ++t) r[t] = x[t] + (op.neg_b ? -y[t] : y[t]);
+            } else {
+                return 4;
+            }
+            if (bad) return 4;
+            reg[op.dst] = r;
+            made_by[op.dst] = o;
+        }
+        const int eb = P.entry_begin[grp], E = P.entry_begin[grp + 1] - eb;
+        std::vector<vec> ent(E);
+        int last = -1;
+        for (int e = 0; e < E; ++e) {
+            const int16_t opd = P.entries[eb + e];
+            ent[e] = value(opd);
+            if (bad) return 4;
+            if (opd >= 0) {
+                if (made_by[opd] <= last) return 1;
+                last = made_by[opd];
+            }
+        }
+        for (int i = 0; i < m; ++i) {
+            vec seg{0, 0, 0, 0};
+            bool zero = true;
+            for (int t = 0; t < gg; ++t) {
+                seg[t] = plain_at(A, (int64_t)i * n + k0 + t, bits, is_signed);
+                zero = zero && seg[t] == 0;
+            }
+            const int c = P.codes[(size_t)grp * m + i];
+            if (zero != (c == 0)) return 3;
+            if (c == 0) continue;
+            const int e = (c < 0 ? -c : c) - 1;
+            if (e >= E) return 2;
+            for (int t = 0; t < 4; ++t)
+                if ((c < 0 ? -ent[e][t] : ent[e][t]) != seg[t]) return 3;
+        }
+    }
+    return 0;
+}
+
 }  // namespace pcmm
+
+extern "C" pcmm_status pcmm_diag_plan_check(const void *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
+                                            int32_t rounds, int32_t group, int32_t *result) {
+    if (!result || m < 0 || n < 0 || bits < 1 || bits > 16 || rounds < 1 || rounds > 8 || group < 1 || group > 4)
+        return PCMM_EINVAL;
+    pcmm::cussen_plan P;
+    const int rc = pcmm::build_cussen_plan(A, m, n, bits, is_signed != 0, rounds, group, &P, 4);
+    if (rc == -2) return PCMM_ERANGE;
+    if (rc) return PCMM_EINVAL;
+    *result = pcmm::check_cussen_plan(P, A, bits, is_signed != 0);
+    return PCMM_OK;
+}

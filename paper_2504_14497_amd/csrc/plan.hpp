@@ -66,4 +66,8 @@ inline int plain_at(const void *A, int64_t x, int bits, bool is_signed) {
 int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int N, int g, cussen_plan *out,
                       int threads = 1);
 
+// Runs each group's program on integer coefficient vectors and checks the
+// plan against A (see plan.cpp): 0 when sound, else the failed check.
+int check_cussen_plan(const cussen_plan &P, const void *A, int bits, bool is_signed);
+
 }  // namespace pcmm

@@ -156,6 +156,7 @@ _SIG = {
                           ctypes.c_char_p], _I32),
     "pcmm_diag_copy": ([_VP, _VP, _I64, _VP], _I32),
     "pcmm_diag_field_raw": ([_I32, _VP, _VP, _VP, _I64, _VP], _I32),
+    "pcmm_diag_plan_check": ([_VP, _I32, _I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_I32)], _I32),
     "pcmm_paillier_create": ([_VP, ctypes.POINTER(_VP)], _I32),
     "pcmm_paillier_destroy": ([_VP], _I32),
     "pcmm_paillier_encrypt": ([_VP, _VP, _I64, ctypes.c_uint64, _I64, _VP, _VP], _I32),
@@ -346,6 +347,15 @@ def diag_point(op: int, P: np.ndarray, Q: np.ndarray = None, k=None, t: int = 0,
     Y = limbs_to_ints(planes[8:16, :count])
     Z = limbs_to_ints(planes[16:24, :count])
     return list(zip(X, Y, Z))
+
+
+def diag_plan_check(A, bits: int, rounds: int = 4, group: int = 1) -> int:
+    """Host-only symbolic check of the compression plan (0 = sound)."""
+    A, signed = _host_A(A, bits)
+    m, n = A.shape
+    r = _I32(-1)
+    _call("pcmm_diag_plan_check", A.ctypes.data_as(_VP), m, n, bits, signed, rounds, group, ctypes.byref(r))
+    return r.value
 
 
 def diag_probe(kind: int, iters: int, blocks: int):

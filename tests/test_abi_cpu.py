@@ -182,3 +182,37 @@ def test_plan_counts_property(orc, m, n, bits, signed, N, seed, zero_frac):
     assert st_["accum_adds"] == int(np.count_nonzero(A))
     distinct = sum(len(set(np.abs(A[:, k].astype(int))) - {0}) for k in range(n))
     assert st_["table_entries"] == distinct
+
+
+def _plan_case(rng, m, n, bits, signed, zero_frac):
+    lo, hi = (-(1 << (bits - 1)), (1 << (bits - 1)) - 1) if signed else (0, (1 << bits) - 1)
+    A = rng.integers(lo, hi + 1, size=(m, n))
+    A[rng.random((m, n)) < zero_frac] = 0
+    if m > 2 and n > 1:
+        A[1] = 0          # an all-zero row
+        A[:, 0] = 0       # an all-zero column
+        A[2, 1] = lo      # extreme values
+        A[0, 1] = hi
+    dt = {(True, False): np.int8, (False, False): np.uint8, (True, True): np.int16, (False, True): np.uint16}
+    return A.astype(dt[(signed, bits > 8)])
+
+
+@pytest.mark.parametrize("group", [1, 2, 3, 4])
+@pytest.mark.parametrize("bits,signed", [(1, False), (2, True), (4, False), (4, True), (8, True), (8, False),
+                                         (12, True), (16, False)])
+def test_plan_programs_reconstruct_every_row(group, bits, signed):
+    """Each group's table-build program, run on integer coefficient vectors
+    over its base points (Alg. 2 reconstruction as exact integer arithmetic),
+    gives for every row the signed segment its code names, and the table's
+    register entries follow their producing ops (the order the table build's
+    batched inversion relies on)."""
+    if bits > 8 and group > 3:
+        pytest.skip("segments of more than 3 wide entries do not fit the 64-bit key")
+    rng = np.random.default_rng(bits * 10 + group)
+    for (m, n, N, zf) in [(37, 11, 4, 0.2), (130, 9, 1, 0.0), (64, 17, 2, 0.5), (300, 5, 3, 0.05), (1, 7, 4, 0.0)]:
+        A = _plan_case(rng, m, n, bits, signed, zf)
+        assert pcmm.diag_plan_check(A, bits, N, group) == 0, (m, n, N)
+    # degenerate shapes: no columns, no rows
+    for shape in [(5, 0), (0, 6)]:
+        A = np.zeros(shape, dtype=np.int16 if bits > 8 else np.int8)
+        assert pcmm.diag_plan_check(A, bits, 4, group) == 0

@@ -575,8 +575,12 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     G.S = S;
     G.gps = P.ngroups > 0 ? (P.ngroups + S - 1) / S : 0;
     // column groups per code list: a split's groups in one list, unless the
-    // caller asks for shorter lists (each list is padded to its longest row)
-    G.kc = std::max(1, std::min(cfg && cfg->k_chunk > 0 ? cfg->k_chunk : G.gps, std::max(G.gps, 1)));
+    // caller asks for shorter lists (each list is padded to its longest row);
+    // a code word keeps the group's index inside its list in the top 16 bits,
+    // which the kernel reads back signed, so a list covers < 2^15 groups
+    constexpr int MAX_LIST_GROUPS = 32767;
+    G.kc = std::max(1, std::min({cfg && cfg->k_chunk > 0 ? cfg->k_chunk : G.gps, std::max(G.gps, 1),
+                                 MAX_LIST_GROUPS}));
     G.tile_cost = (double)G.tm * G.pp * G.gps;
     // workspace regions
     const int64_t n_out = (int64_t)m * l;

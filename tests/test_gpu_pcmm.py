@@ -283,3 +283,13 @@ def test_full_size_signed128(dev, orc):
 def test_full_size_serve_layer(dev, orc):
     # 256 x 1024 times 1024 x 8: the split-k path with the wavefront reduction
     _full_size(dev, orc, W.SERVE_LAYER, n_samples=12, check_schoolbook=False)
+
+
+def test_long_inner_dimension_in_one_split(dev, orc):
+    """n = 40000 columns with the inner dimension unsplit: one split holds more
+    column groups than a code list may (its group index is kept in 15 bits),
+    so the accumulation walks two lists; Cussen equals schoolbook and the
+    closed form on every output."""
+    from paper_2504_14497_amd import pcmm
+    sh = W.PCMMShape(m=3, n=40000, l=2, bits=2, signed=False, msg_bits=4, seed=57, name="long_n")
+    _full_size(dev, orc, sh, cfg=pcmm.CussenCfg(4, 1, 1, 0), n_samples=6)

@@ -59,7 +59,7 @@ struct prob_desc {
     int32_t ngroups, emax, rmax, c_form;
     int32_t J, Lj, tm, pp;
     int32_t kc, S, gps, io;  // io: index of the problem's matrices in the run
-    int32_t tiles_x, tiles_y, norm_per, pad;
+    int32_t tiles_x, tiles_y, norm_per, coop_w;  // coop_w: lanes per level-1 chain (0: one lane per chain)
     int64_t n_lanes, tb_block0;
     int64_t tile0;
     int64_t red_block0, red_threads;
@@ -166,6 +166,137 @@ __device__ __forceinline__ void run_op(const plan_op op, const uint32_t *__restr
     last_reg = op.dst;
 }
 
+// Operand of a single-column program (a register, or the base point B_kj)
+// as a Jacobian point.
+__device__ __forceinline__ jpt operand_point(int16_t opd, const uint32_t *B, int64_t ldb, int l, int k0, int j,
+                                             int pt, const uint32_t *regs, int rmax, int64_t n_lanes, int64_t lane) {
+    if (opd < 0) return jpt_from_affine(load_affine(B, ldb, pt, (int64_t)(k0 - 1 - opd) * l + j));
+    return reg_load(regs, rmax, n_lanes, 0, opd, lane);
+}
+
+__device__ __forceinline__ jpt shfl_up_jpt(const jpt &P, int delta, int width) {
+    jpt R;
+#pragma unroll
+    for (int w = 0; w < NL; ++w) {
+        R.X.v[w] = (uint32_t)__shfl_up((int)P.X.v[w], delta, width);
+        R.Y.v[w] = (uint32_t)__shfl_up((int)P.Y.v[w], delta, width);
+        R.Z.v[w] = (uint32_t)__shfl_up((int)P.Z.v[w], delta, width);
+    }
+    return R;
+}
+
+// Table of one (group, j, point) built by W lanes (a padded run of
+// single-column groups; 64 lanes per group, 2 l chains of W lanes).  The
+// program's last E - 1 ops are the level-1 prefix sums S_i = S_{i-1} + b_i
+// (S_0 = b_0); every lane runs the ops before them (levels >= 2, a few
+// short chains), sums its block of b_i, the block totals are scanned across
+// the W lanes (shuffles, log2 W additions), each lane adds the sum of the
+// blocks before it to its block's partial sums, then converts its block's
+// entries to affine with one inversion.  Chain depth ~ 2 E / W + log2 W
+// additions instead of E.
+__device__ __forceinline__ void coop_table_build(const run_args &a, const prob_desc &d, int64_t lane) {
+    const int W = d.coop_w, l = d.l;
+    const int grp = (int)(lane / 64);
+    const int rem = (int)(lane % 64);
+    const int chain = rem / W, w = rem % W;
+    if (chain >= 2 * l) return;  // whole W-lane segments idle
+    const int j = chain >> 1, pt = chain & 1;
+    const plan_op *ops = plan_at<plan_op>(a, d.o_ops);
+    const int32_t *op_begin = plan_at<int32_t>(a, d.o_op_begin);
+    const int32_t *entry_begin = plan_at<int32_t>(a, d.o_entry_begin);
+    const int16_t *entries = plan_at<int16_t>(a, d.o_entries);
+    uint32_t *regs = at<uint32_t>(a, d.w_regs);
+    uint32_t *table = at<uint32_t>(a, d.w_table);
+    const uint32_t *B = a.io[d.io].B;
+    const int64_t ldb = a.io[d.io].ldb;
+    const int rmax = d.rmax, emax = d.emax;
+    const int64_t n_lanes = d.n_lanes;
+    const int k0 = grp;
+    const int ob = op_begin[grp], oe = op_begin[grp + 1];
+    const int eb = entry_begin[grp], E = entry_begin[grp + 1] - eb;
+    if (E == 0) return;  // uniform over the chain's lanes
+    const int ofirst = oe - (E - 1);
+    // levels >= 2, on every lane (each keeps its own register column)
+    jpt last = jpt_infinity();
+    int last_reg = -1;
+    for (int o = ob; o < ofirst; ++o) run_op(ops[o], B, ldb, l, k0, j, pt, regs, rmax, n_lanes, 0, lane, last, last_reg);
+    auto opd_of = [&](int i) -> int16_t { return i == 0 ? entries[eb] : ops[ofirst + i - 1].b; };
+    // this lane's block of the chain and its partial sums (stored in the
+    // registers of S_i, i >= 1)
+    const int bs = (E + W - 1) / W;
+    const int i0 = min(E, w * bs), i1 = min(E, i0 + bs);
+    jpt acc = jpt_infinity();
+    for (int i = i0; i < i1; ++i) {
+        const jpt bi = operand_point(opd_of(i), B, ldb, l, k0, j, pt, regs, rmax, n_lanes, lane);
+        acc = i == i0 ? bi : jpt_add<false>(acc, bi);
+        if (i > 0) reg_store(regs, rmax, n_lanes, 0, entries[eb + i], lane, acc);
+    }
+    // inclusive scan of the block totals over the chain's W lanes, then the
+    // sum of the blocks before this one
+    jpt incl = acc;
+    for (int delta = 1; delta < W; delta <<= 1) {
+        const jpt o = shfl_up_jpt(incl, delta, W);
+        const jpt s = jpt_add<false>(o, incl);
+        if (w >= delta) incl = s;
+    }
+    jpt excl = shfl_up_jpt(incl, 1, W);
+    if (w == 0) excl = jpt_infinity();
+    // S_i = (blocks before) + partial sum; forward pass of the inversion
+    const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
+    fe prod = fe_one_mont();
+    for (int i = i0; i < i1; ++i) {
+        const int16_t opd = entries[eb + i];
+        if (opd < 0) continue;  // S_0 = B_kj: affine already
+        jpt S = reg_load(regs, rmax, n_lanes, 0, opd, lane);
+        if (w > 0) {
+            S = jpt_add<false>(excl, S);
+            reg_store(regs, rmax, n_lanes, 0, opd, lane, S);
+        }
+        uint32_t *slot = table + (T * emax + i) * ENTRY_WORDS;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) slot[q] = prod.v[q];
+        if (!fe_is_zero(S.Z)) prod = fe_mul_ilp(prod, S.Z);
+    }
+    fe inv = fe_inv(prod);
+    for (int i = i1 - 1; i >= i0; --i) {
+        const int16_t opd = entries[eb + i];
+        uint32_t *slot = table + (T * emax + i) * ENTRY_WORDS;
+        apt A;
+        if (opd < 0) {
+            A = load_affine(B, ldb, pt, (int64_t)(k0 + (-1 - opd)) * l + j);
+        } else {
+            const jpt P = reg_load(regs, rmax, n_lanes, 0, opd, lane);
+            fe pre;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) pre.v[q] = slot[q];
+            if (fe_is_zero(P.Z)) {
+                A.x = fe_zero();
+                A.y = fe_zero();
+            } else {
+                const fe zinv = fe_mul_ilp(inv, pre);
+                inv = fe_mul_ilp(inv, P.Z);
+                A = jpt_to_affine_with(P, zinv);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            slot[q] = A.x.v[q];
+            slot[NL + q] = A.y.v[q];
+        }
+        slot[ENTRY_INF] = apt_is_inf(A) ? 1u : 0u;
+    }
+}
+
+// The tables of the run's problems with coop_w > 1 (launched over the same
+// blocks as table_build_kernel, which skips those problems).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) coop_table_kernel(run_args a) {
+    const int b = find_problem(a, offsetof(prob_desc, tb_block0), blockIdx.x);
+    const prob_desc &d = descs(a)[b];
+    const int64_t lane = ((int64_t)blockIdx.x - d.tb_block0) * blockDim.x + threadIdx.x;
+    if (d.coop_w <= 1 || lane >= d.n_lanes) return;
+    coop_table_build(a, d, lane);
+}
+
 // Two wavefronts per SIMD (<= 256 VGPRs): the kernel waits on its register
 // file in HBM, and a second wavefront hides much of that latency.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) table_build_kernel(run_args a) {
@@ -175,6 +306,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
     const prob_desc &d = descs(a)[b];
     const int64_t lane = ((int64_t)blockIdx.x - d.tb_block0) * blockDim.x + threadIdx.x;
     if (lane >= d.n_lanes) return;
+    if (d.coop_w > 1) return;  // coop_table_kernel builds this problem's tables
     const plan_op *ops = plan_at<plan_op>(a, d.o_ops);
     const int32_t *op_begin = plan_at<int32_t>(a, d.o_op_begin);
     const int32_t *entry_begin = plan_at<int32_t>(a, d.o_entry_begin);
@@ -508,6 +640,7 @@ struct job {
     int Lj_pad = 0;           // table-build lanes with each group padded to a
     int64_t n_lanes_pad = 0;  // whole wavefront (0: not applicable), chosen per run
     size_t regs_bytes_pad = 0;
+    int coop_w = 0;           // padded runs: lanes sharing each level-1 chain (0: none)
     int tm = 256, pp = 1, kc = 1, S = 1, gps = 0, tiles_x = 1, tiles_y = 1;
     int64_t ldj = 64, norm_threads = 0, ld_pre = 0;
     int norm_per = 0;
@@ -534,6 +667,25 @@ bool pad_run(size_t count, JobOf job_at) {
     return lanes <= PAD_LANES_MAX;
 }
 
+// Whether every group of a single-column plan ends its program with its
+// level-1 reconstruction, the prefix sums S_i = S_{i-1} + b_i (S_0 = b_0,
+// the table's entry 0): then lanes of a padded group can share that chain.
+bool level1_chains(const cussen_plan &P) {
+    if (P.g != 1) return false;
+    for (int grp = 0; grp < P.ngroups; ++grp) {
+        const int eb = P.entry_begin[grp], E = P.entry_begin[grp + 1] - eb;
+        const int ob = P.op_begin[grp], oe = P.op_begin[grp + 1];
+        if (E == 0) continue;  // an all-zero column: no table
+        if (oe - ob < E - 1) return false;
+        for (int i = 1; i < E; ++i) {
+            const plan_op &op = P.ops[oe - (E - 1) + (i - 1)];
+            if (op.kind != OP_ADD || op.neg_b || op.a != P.entries[eb + i - 1] || op.dst != P.entries[eb + i])
+                return false;
+        }
+    }
+    return true;
+}
+
 void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     const cussen_plan &P = G.P;
     const int m = P.m, l = G.l;
@@ -556,6 +708,15 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     else G.Lj_pad = 32;
     G.n_lanes = (int64_t)P.ngroups * 2 * G.Lj;
     G.n_lanes_pad = G.Lj_pad ? (int64_t)P.ngroups * 2 * G.Lj_pad : 0;
+    // a padded group has 64 lanes for its 2 l chains: with single columns,
+    // W = 64 / (2 l) lanes (a power of two, blocks of >= 4 entries on
+    // average) split each level-1 chain as a parallel scan instead of idling
+    G.coop_w = 0;
+    if (G.Lj_pad && l >= 1 && level1_chains(P)) {
+        int W = 1;
+        while (W * 2 * 2 * l <= 64 && W * 2 * 4 <= avg_e) W *= 2;
+        if (W >= 2) G.coop_w = W;
+    }
     // accumulation tile
     const int npairs = 2 * l;
     // rows per tile: the fewest padded rows, the larger tile on ties (the
@@ -684,6 +845,7 @@ struct run_layout {
     size_t copy_bytes = 0, ctr_off = 0, ws_bytes = 256;
     int64_t tb_blocks = 0, tiles = 0, red_blocks = 0, norm_blocks = 0;
     int acc_grid = 0;
+    bool coop = false;  // some problem's tables are built by coop_table_kernel
     std::vector<int> fills;  // run indices whose inner dimension is empty (identity outputs)
 };
 
@@ -767,6 +929,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
     }
     run_layout &L = pl.full;
     L.count = (int32_t)nd;
+    L.coop = false;
     L.copy_bytes = img;
     L.ctr_off = img;
     size_t ws = img + 256;
@@ -786,6 +949,8 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         d.c_form = G.c_form;
         d.J = G.J;
         d.Lj = pad_k ? G.Lj_pad : G.Lj;
+        d.coop_w = pad_k ? G.coop_w : 0;
+        if (d.coop_w > 1) L.coop = true;
         d.tm = G.tm;
         d.pp = G.pp;
         d.kc = G.kc;
@@ -994,6 +1159,10 @@ pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *p
     if (gpu_work) {
         hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)L.tb_blocks), dim3(256), 0, s, ra);
         PCMM_LAUNCH_CHECK();
+        if (L.coop) {
+            hipLaunchKernelGGL(coop_table_kernel, dim3((unsigned)L.tb_blocks), dim3(256), 0, s, ra);
+            PCMM_LAUNCH_CHECK();
+        }
     }
     PCMM_REC(2);
     if (gpu_work) {
@@ -1268,6 +1437,8 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         prob_desc d = pl.desc[jk];
         const bool pad_k = pad && G.Lj_pad;
         d.Lj = pad_k ? G.Lj_pad : G.Lj;
+        d.coop_w = pad_k ? G.coop_w : 0;
+        if (d.coop_w > 1) L.coop = true;
         d.n_lanes = pad_k ? G.n_lanes_pad : G.n_lanes;
         d.io = r;
         d.tb_block0 = tb;

@@ -293,3 +293,14 @@ def test_long_inner_dimension_in_one_split(dev, orc):
     from paper_2504_14497_amd import pcmm
     sh = W.PCMMShape(m=3, n=40000, l=2, bits=2, signed=False, msg_bits=4, seed=57, name="long_n")
     _full_size(dev, orc, sh, cfg=pcmm.CussenCfg(4, 1, 1, 0), n_samples=6)
+
+
+@pytest.mark.parametrize("m,l,bits,signed", [(300, 1, 8, False), (257, 2, 12, True), (200, 1, 16, False),
+                                             (130, 4, 8, True), (97, 1, 4, False)])
+def test_narrow_tables_built_cooperatively(dev, orc, m, l, bits, signed):
+    """Few output columns: the run pads its groups to whole wavefronts and W =
+    64 / (2 l) lanes share each level-1 chain (ragged blocks, a scan across
+    lanes).  Cussen equals schoolbook and the closed form on every output."""
+    from paper_2504_14497_amd import pcmm
+    sh = W.PCMMShape(m=m, n=3, l=l, bits=bits, signed=signed, msg_bits=8, seed=61 + m, name="narrow")
+    _full_size(dev, orc, sh, cfg=pcmm.CussenCfg(4, 1, 0, 0), n_samples=m * l)

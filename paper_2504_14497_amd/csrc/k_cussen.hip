@@ -190,10 +190,10 @@ __device__ __forceinline__ jpt shfl_up_jpt(const jpt &P, int delta, int width) {
 // program's last E - 1 ops are the level-1 prefix sums S_i = S_{i-1} + b_i
 // (S_0 = b_0); every lane runs the ops before them (levels >= 2, a few
 // short chains), sums its block of b_i, the block totals are scanned across
-// the W lanes (shuffles, log2 W additions), each lane adds the sum of the
-// blocks before it to its block's partial sums, then converts its block's
-// entries to affine with one inversion.  Chain depth ~ 2 E / W + log2 W
-// additions instead of E.
+// the W lanes (shuffles, log2 W additions), each lane runs its block's
+// prefix sums again from the sum of the blocks before it (storing each S_i
+// once), then converts its block's entries to affine with one inversion.
+// Chain depth ~ 2 E / W + log2 W additions instead of E.
 __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_desc &d, int64_t lane) {
     const int W = d.coop_w, l = d.l;
     const int grp = (int)(lane / 64);
@@ -221,15 +221,13 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
     int last_reg = -1;
     for (int o = ob; o < ofirst; ++o) run_op(ops[o], B, ldb, l, k0, j, pt, regs, rmax, n_lanes, 0, lane, last, last_reg);
     auto opd_of = [&](int i) -> int16_t { return i == 0 ? entries[eb] : ops[ofirst + i - 1].b; };
-    // this lane's block of the chain and its partial sums (stored in the
-    // registers of S_i, i >= 1)
+    // this lane's block of the chain: its total first
     const int bs = (E + W - 1) / W;
     const int i0 = min(E, w * bs), i1 = min(E, i0 + bs);
     jpt acc = jpt_infinity();
     for (int i = i0; i < i1; ++i) {
         const jpt bi = operand_point(opd_of(i), B, ldb, l, k0, j, pt, regs, rmax, n_lanes, lane);
         acc = i == i0 ? bi : jpt_add<false>(acc, bi);
-        if (i > 0) reg_store(regs, rmax, n_lanes, 0, entries[eb + i], lane, acc);
     }
     // inclusive scan of the block totals over the chain's W lanes, then the
     // sum of the blocks before this one
@@ -240,18 +238,18 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
         if (w >= delta) incl = s;
     }
     jpt excl = shfl_up_jpt(incl, 1, W);
-    if (w == 0) excl = jpt_infinity();
-    // S_i = (blocks before) + partial sum; forward pass of the inversion
+    // the block's prefix sums again, from the blocks before it: S_i stored
+    // once, its Z folded into the forward pass of the inversion
     const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
     fe prod = fe_one_mont();
+    jpt S = excl;
     for (int i = i0; i < i1; ++i) {
+        const int16_t opd_b = opd_of(i);
+        const jpt bi = operand_point(opd_b, B, ldb, l, k0, j, pt, regs, rmax, n_lanes, lane);
+        S = (w == 0 && i == i0) ? bi : jpt_add<false>(S, bi);
         const int16_t opd = entries[eb + i];
         if (opd < 0) continue;  // S_0 = B_kj: affine already
-        jpt S = reg_load(regs, rmax, n_lanes, 0, opd, lane);
-        if (w > 0) {
-            S = jpt_add<false>(excl, S);
-            reg_store(regs, rmax, n_lanes, 0, opd, lane, S);
-        }
+        if (i > 0) reg_store(regs, rmax, n_lanes, 0, opd, lane, S);  // S_0 = b_0 is its own register
         uint32_t *slot = table + (T * emax + i) * ENTRY_WORDS;
 #pragma unroll
         for (int q = 0; q < NL; ++q) slot[q] = prod.v[q];
@@ -710,12 +708,13 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     G.n_lanes_pad = G.Lj_pad ? (int64_t)P.ngroups * 2 * G.Lj_pad : 0;
     // a padded group has 64 lanes for its 2 l chains: with single columns,
     // W = 64 / (2 l) lanes (a power of two, blocks of >= 4 entries on
-    // average) split each level-1 chain as a parallel scan instead of idling
+    // average) split each level-1 chain as a parallel scan instead of idling;
+    // the depth, about 2 E / W + log2 W additions, beats E only from W = 4
     G.coop_w = 0;
     if (G.Lj_pad && l >= 1 && level1_chains(P)) {
         int W = 1;
         while (W * 2 * 2 * l <= 64 && W * 2 * 4 <= avg_e) W *= 2;
-        if (W >= 2) G.coop_w = W;
+        if (W >= 4) G.coop_w = W;
     }
     // accumulation tile
     const int npairs = 2 * l;

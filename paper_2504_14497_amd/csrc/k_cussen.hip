@@ -10,6 +10,9 @@
 //                 keeps every register in a lane-private scratch (structure of
 //                 arrays, so the lanes' accesses coalesce), then converts its
 //                 tables to affine with one inversion for all of its J tables.
+//   coop_table    (runs with narrow single-column problems only) the same
+//                 tables with several lanes per level-1 chain: block sums,
+//                 a scan across the lanes, one inversion per lane.
 //   accumulate    persistent: workgroups take tiles (problem, row tile, pair
 //                 tile, split) from a device queue, the most expensive tiles
 //                 first.  For a tile, C_ij += sign * T_kj[code_ik]: every

@@ -91,7 +91,10 @@ typedef struct {
  *           g = 1..4 and keeps the one of least predicted GPU time, from a
  *           cost model of accumulation slots, table additions and table
  *           entries fitted to MI355X measurements; the choice is cached per
- *           shape (m, n, l, bits, signedness, rounds) for the process)
+ *           (m, n, bits, signedness, rounds) for the process, and a cached
+ *           g > 1 whose tables exceed the autotuner's size cap on another
+ *           matrix of that shape falls back to g = 1; entries of 9..16 bits
+ *           allow g <= 3)
  *   k_split split of the n (inner) dimension over independent partial sums that
  *           are then added (0 = chosen from the shape)
  *   k_chunk column groups per code list of the accumulation; each list is
@@ -133,7 +136,10 @@ typedef struct {
     int32_t k_split;         /* split of the inner dimension that was used                 */
     int32_t lanes_per_chain; /* table-build batch: output columns per lane                 */
     int32_t group;           /* columns of A per code that was used (after autotuning)     */
-    int32_t reserved;
+    int32_t coop_lanes;      /* lanes sharing each level-1 prefix-sum chain of the table
+                                build in this run (0: one lane per chain); a run of
+                                single-column groups with few output columns splits each
+                                chain into blocks and scans the block sums across lanes  */
     /* with cfg->profile: milliseconds from the first to the last event of each stage */
     float ms_upload, ms_table, ms_accumulate, ms_reduce, ms_normalize, ms_total;
 } pcmm_cussen_stats;

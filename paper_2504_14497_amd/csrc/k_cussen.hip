@@ -606,19 +606,32 @@ int build_plan_cfg(const void *A, int m, int n, int bits, bool sgn, const pcmm_c
     if (group != PCMM_GROUP_AUTO)
         return build_cussen_plan(A, m, n, bits, sgn, N, group > 0 ? group : 1, out, threads);
     const auto key = std::make_tuple(m, n, bits, (int)sgn, N);
+    auto over_cap = [](const cussen_plan &P) {
+        return P.g > 1 && (size_t)std::max(P.max_entries, 1) * ENTRY_WORDS * 4 > GROUP_TABLE_CAP;
+    };
+    int cached = 0;
     {
         std::lock_guard<std::mutex> guard(g_tune_lock);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) return build_cussen_plan(A, m, n, bits, sgn, N, it->second, out, threads);
+        if (it != g_tune_cache.end()) cached = it->second;
+    }
+    if (cached > 0) {
+        // the choice was made on another matrix of the same shape: its group
+        // tables are re-checked against the cap on this one
+        int rc = build_cussen_plan(A, m, n, bits, sgn, N, cached, out, threads);
+        if (rc || !over_cap(*out)) return rc;
+        return build_cussen_plan(A, m, n, bits, sgn, N, 1, out, threads);
     }
     int best_g = 1;
     double best = 0;
-    const int gmax = std::max(1, std::min(4, n));
+    // a code keys g digits of 9 bits (entries up to 8 bits) or 17 bits (9..16
+    // bits) into 64 bits, so wide entries allow at most 3 columns per group
+    const int gmax = std::max(1, std::min(bits <= 8 ? 4 : 3, n));
     for (int g = 1; g <= gmax; ++g) {
         cussen_plan P;
         int rc = build_cussen_plan(A, m, n, bits, sgn, N, g, &P, threads);
-        if (rc) return rc;
-        if (g > 1 && (size_t)std::max(P.max_entries, 1) * ENTRY_WORDS * 4 > GROUP_TABLE_CAP) continue;
+        if (rc && g == 1) return rc;
+        if (rc || over_cap(P)) continue;  // a group too large for the plan's limits is no candidate
         const double c = predicted_cost(P);
         if (g == 1 || c < best) {
             best = c;
@@ -993,6 +1006,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
     L.red_blocks = red;
     L.norm_blocks = norm;
     pl.desc = D;
+    for (size_t k = 0; k < nd; ++k) pl.stats[pl.jobs[k].index].coop_lanes = D[k].coop_w;
     pl.job_of.assign(pl.count, -1);
     for (size_t k = 0; k < nd; ++k) pl.job_of[pl.jobs[k].index] = (int)k;
     if (tb > 0x7FFFFFFF || red > 0x7FFFFFFF || norm > 0x7FFFFFFF || tiles > 0x7FFFFFFF - (1 << 20))

@@ -68,14 +68,14 @@ class CussenStats(ctypes.Structure):
                 ("accum_adds", ctypes.c_int64), ("max_entries", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64),
                 ("k_split", ctypes.c_int32), ("lanes_per_chain", ctypes.c_int32),
-                ("group", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("coop_lanes", ctypes.c_int32),
                 ("ms_upload", ctypes.c_float), ("ms_table", ctypes.c_float),
                 ("ms_accumulate", ctypes.c_float), ("ms_reduce", ctypes.c_float),
                 ("ms_normalize", ctypes.c_float), ("ms_total", ctypes.c_float)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if k.startswith("ms_") else int(getattr(self, k)))
-                for k, _ in self._fields_ if k != "reserved"}
+                for k, _ in self._fields_}
 
 
 class StrassenCfg(ctypes.Structure):

@@ -195,7 +195,16 @@ class Server:
 class GpuExecutor:
     """Runs a batch as one pcmm_plan_run_selected on its slot's stream, in a
     range of one workspace tensor; completion is a HIP event.  The plan must
-    be resident (Plan.make_resident) before the first launch."""
+    be resident (Plan.make_resident) before the first launch.
+
+    Ordering contract: a request's X (ciphertexts) and C (output buffer) may
+    have been written by work queued on the stream that is current when the
+    batch is launched (uploads, encryption, zero fills); the slot stream
+    waits for everything queued there before its run starts, and X and C are
+    marked as used on the slot stream so that the allocator does not hand
+    their memory out again before the run has finished.  A client that
+    produces X on yet another stream makes the current stream wait for it
+    before submitting."""
 
     # bound on a selected run's bytes beyond its problems' own regions
     # (descriptor block of up to 64 problems and the queue counter)
@@ -218,6 +227,10 @@ class GpuExecutor:
         import ctypes
         import torch
         s = self.streams[slot]
+        s.wait_stream(torch.cuda.current_stream())
+        for r in reqs:
+            r.X.t.record_stream(s)
+            r.C.t.record_stream(s)
         self.plan.run_selected([r.layer for r in reqs], [r.X for r in reqs], [r.C for r in reqs],
                                (ctypes.c_void_p(self.base + offset), int(nbytes)), stream=s)
         ev = torch.cuda.Event()

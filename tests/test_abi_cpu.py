@@ -101,6 +101,37 @@ def test_plan_headline_counts():
     assert st["max_entries"] == 15
 
 
+@pytest.mark.parametrize("bits,signed", [(12, False), (12, True), (16, False), (9, True)])
+def test_autotuned_group_for_wide_plaintexts(bits, signed):
+    """GROUP_AUTO on 9..16-bit entries with n >= 4: a code holds at most three
+    17-bit digits, so the autotuner tries g = 1..3 only and succeeds."""
+    rng = np.random.default_rng(bits + 100 * signed)
+    lo, hi = (-(1 << (bits - 1)), 1 << (bits - 1)) if signed else (0, 1 << bits)
+    A = rng.integers(lo, hi, size=(64, 8)).astype(np.int16 if signed else np.uint16)
+    st = pcmm.cussen_plan_stats(A, bits, pcmm.CussenCfg(4, pcmm.GROUP_AUTO, 0, 0))
+    assert 1 <= st["group"] <= 3
+    # the same shape again (a cache hit) and the explicit candidates agree
+    st2 = pcmm.cussen_plan_stats(A, bits, pcmm.CussenCfg(4, pcmm.GROUP_AUTO, 0, 0))
+    assert st2["group"] == st["group"]
+    for g in (1, 3):
+        pcmm.cussen_plan_stats(A, bits, pcmm.CussenCfg(4, g, 0, 0))
+
+
+def test_autotune_cache_rechecks_table_cap():
+    """A group chosen on one matrix is reused for another matrix of the same
+    shape only if its tables stay under the size cap there."""
+    m, n = 4000, 4
+    small = np.zeros((m, n), dtype=np.uint8)
+    small[:, :] = np.arange(m)[:, None] % 2            # tiny segment tables: g > 1 pays
+    st_small = pcmm.cussen_plan_stats(small, 4, pcmm.CussenCfg(4, pcmm.GROUP_AUTO, 0, 0))
+    assert st_small["group"] > 1
+    rng = np.random.default_rng(5)
+    big = rng.integers(0, 16, size=(m, n)).astype(np.uint8)   # segments up to 16^g distinct
+    st_big = pcmm.cussen_plan_stats(big, 4, pcmm.CussenCfg(4, pcmm.GROUP_AUTO, 0, 0))
+    # 20 words (80 bytes) per entry; the cap is 150 KB per (group, pair) table
+    assert st_big["group"] == 1 or st_big["max_entries"] * 80 <= 150 * 1024
+
+
 def test_validation_errors():
     A = np.array([[0, 16]], dtype=np.uint8)
     with pytest.raises(pcmm.PCMMError) as ei:

@@ -1,0 +1,114 @@
+"""The library's device field and point arithmetic (fp.hpp, ec.hpp,
+common.hpp) compiled for the host with g++ and the undefined-behaviour
+sanitizer (tests/hostshim), checked on the CPU: field operations against
+exact integer arithmetic (the cases of the GPU raw-limb test), point
+operations against the oracle's affine group law (Sec. 2.3), including every
+exceptional case, and the ladder of Alg. 1 against the oracle's.
+
+A mistake in a point formula or in the exceptional-case logic shows up here
+without a GPU; a 64-bit column sum that overflows aborts the sanitized build.
+"""
+import random
+
+import pytest
+
+import field_cases as FC
+import hostbuild
+
+
+@pytest.fixture(scope="module")
+def host():
+    try:
+        hostbuild.lib()
+    except (RuntimeError, OSError) as e:  # no g++ or no sanitizer runtime
+        pytest.skip(f"host build unavailable: {e}")
+    return hostbuild
+
+
+def test_host_raw_field_ops_vs_integers(host):
+    FC.check_raw_field_ops(host.field_raw)
+
+
+def test_host_raw_products_of_extreme_carry_only_operands(host):
+    FC.check_extreme_carry_only_products(host.field_raw)
+
+
+def test_host_raw_normalisation_of_signed_limbs(host):
+    FC.check_signed_limb_normalisation(host.field_raw)
+
+
+def test_host_split_form_products_and_inverse(host):
+    """The split (ILP) product forms and the Fermat inverse of the
+    latency-bound callers equal the plain definitions."""
+    import numpy as np
+    a, b = FC._operands(400, 3)
+    A = np.array([FC.limbs(v) for v in a], dtype=np.int64)
+    B = np.array([FC.limbs(v) for v in b], dtype=np.int64)
+    P, RINV, R = FC.P, FC.RINV, FC.R
+    out = host.field_raw(21, A, B)
+    FC._check_normal(out)
+    assert all(FC.value(out[i]) % P == (a[i] * b[i] * RINV) % P for i in range(len(a)))
+    out = host.field_raw(22, A, B)
+    FC._check_normal(out)
+    assert all(FC.value(out[i]) % P == (a[i] * a[i] * RINV) % P for i in range(len(a)))
+    out = host.field_raw(23, A, B)
+    FC._check_normal(out)
+    for i in range(len(a)):
+        x = a[i] % P
+        # Montgomery form: x R^-1 is the value, its inverse is x^-1 R^2 in limbs
+        want = 0 if x == 0 else (pow(x, -1, P) * R * R) % P
+        assert FC.value(out[i]) % P == want, i
+
+
+def _random_point(orc, rnd):
+    p_, b_, gx, gy, q = orc.curve_params()
+    return orc.ladder_big(rnd.randrange(1, q), orc.generator())
+
+
+def _cases(orc, count, seed):
+    """(P, Q) pairs: random, P = Q, P = -Q, identities on either side, both."""
+    rnd = random.Random(seed)
+    out = []
+    for k in range(count):
+        P = _random_point(orc, rnd)
+        Q = _random_point(orc, rnd)
+        kind = k % 7
+        if kind == 1:
+            Q = P
+        elif kind == 2:
+            Q = orc.pt_neg(P)
+        elif kind == 3:
+            P = orc.INF
+        elif kind == 4:
+            Q = orc.INF
+        elif kind == 5:
+            P = Q = orc.INF
+        out.append((P, Q))
+    return out
+
+
+def test_host_point_additions_vs_oracle(host, orc):
+    """Mixed addition (both forms), general addition and doubling, with the
+    Jacobian operands at random Z, equal the oracle on every case of the group
+    law; the accumulation's form also carries the right identity flag."""
+    p_ = orc.curve_params()[0]
+    rnd = random.Random(77)
+    for P, Q in _cases(orc, 210, 5):
+        zp, zq = rnd.randrange(1, p_), rnd.randrange(1, p_)
+        want = orc.pt_add(P, Q)
+        for op in (0, 1):
+            assert host.point(op, P, Q, zp=zp) == want, (op, P.hex()[:16], Q.hex()[:16])
+            assert host.point(op, P, Q) == want, (op, "Z = 1")
+        assert host.point(2, P, Q, zp=zp, zq=zq) == want
+        assert host.point(3, P, zp=zp) == orc.pt_dbl(P)
+        assert host.point(5, P, zp=zp) == orc.pt_neg(P)
+
+
+def test_host_ladder_vs_oracle(host, orc):
+    """Alg. 1 over t bits equals the oracle's ladder, including k = 0, k with
+    its top bit clear and k at 2^t - 1."""
+    rnd = random.Random(9)
+    for t in (1, 2, 4, 8, 12, 17):
+        P = _random_point(orc, rnd)
+        for k in {0, 1, 2, (1 << t) - 1, (1 << (t - 1)), rnd.randrange(1 << t), rnd.randrange(1 << t)}:
+            assert host.point(4, P, k=k, t=t) == orc.ladder_small(k, t, P), (t, k)

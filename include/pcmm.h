@@ -61,7 +61,8 @@ typedef enum {
     PCMM_ERANGE = -2,       /* an entry of A outside its declared bit-width     */
     PCMM_ENOMEM = -3,       /* caller workspace too small                      */
     PCMM_EDEVICE = -4,      /* HIP runtime or launch error                     */
-    PCMM_ENOTONCURVE = -5   /* a host point is not on P-256                    */
+    PCMM_ENOTONCURVE = -5,  /* a host point is not on P-256                    */
+    PCMM_ETOOLARGE = -6     /* needs more than the library's static scratch    */
 } pcmm_status;
 
 #define PCMM_AFFINE 2
@@ -193,6 +194,28 @@ pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t bits, int32
 pcmm_status pcmm_cussen_workspace(const void *A, int32_t m, int32_t n, int32_t l, int32_t bits,
                                   int32_t is_signed, int32_t c_form, const pcmm_cussen_cfg *cfg,
                                   size_t *bytes);
+
+/* pcmm_cussen for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * kernels and results as pcmm_cussen, with the workspace taken from a static
+ * device array of PCMM_STATIC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends.  The call allocates no device or
+ * pinned memory and creates no HIP objects; the caller still owns B and C.
+ *   - A problem whose pcmm_cussen_workspace() exceeds
+ *     PCMM_STATIC_SCRATCH_BYTES returns PCMM_ETOOLARGE before any device call.
+ *   - cfg->profile must be 0 (PCMM_EINVAL otherwise); caller-owned
+ *     cfg->stage_events are recorded as in pcmm_cussen.
+ *   - The plan image is copied from pageable host memory, so the call returns
+ *     once that copy has been made (it waits for the stream's earlier work);
+ *     the kernels run asynchronously.
+ *   - Every call on one GPU uses that GPU's single array, which keeps the last
+ *     call's contents (each call initialises what it reads).  Calls on one
+ *     stream are ordered; calls that overlap on one GPU (other streams, other
+ *     threads) race on the array and give undefined results. */
+#define PCMM_STATIC_SCRATCH_BYTES (64u << 20)
+pcmm_status pcmm_cussen_static(const void *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
+                               const pcmm_mat *B, pcmm_mat *C, const pcmm_cussen_cfg *cfg,
+                               pcmm_cussen_stats *stats, void *stream);
 
 /* Compiled plans: one or more Cussen PC-MMs, compressed once on the host and
  * run any number of times (a static plaintext A served against fresh

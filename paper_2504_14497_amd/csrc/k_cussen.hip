@@ -1355,6 +1355,73 @@ extern "C" pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t 
     return PCMM_OK;
 }
 
+// --------------------------------------------------------------------------
+// pcmm_cussen_static: pcmm_cussen with the workspace in a fixed device array
+// --------------------------------------------------------------------------
+// The library's own scratch for callers that cannot allocate device memory.
+// Every GPU the library runs on holds one copy for the life of the process;
+// the name is a host-side stand-in, so host code uses only the per-device
+// address that hipGetSymbolAddress returns.
+__device__ __align__(256) char scratch[PCMM_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_lock;
+void *g_scratch_ptr[64] = {};
+
+// Address of the current device's scratch, looked up once per device with
+// that device current.
+pcmm_status scratch_of(int device, void **ptr) {
+    if (device < 0 || device >= 64) return PCMM_EDEVICE;
+    std::lock_guard<std::mutex> guard(g_scratch_lock);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        PCMM_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return PCMM_EDEVICE;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return PCMM_OK;
+}
+
+}  // namespace
+
+extern "C" pcmm_status pcmm_cussen_static(const void *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
+                                          const pcmm_mat *B, pcmm_mat *C, const pcmm_cussen_cfg *cfg,
+                                          pcmm_cussen_stats *stats, void *stream) {
+    if (!B || !C || !valid_cfg(cfg)) return PCMM_EINVAL;
+    if (cfg && cfg->profile) return PCMM_EINVAL;  // profiling would create events
+    if (C->form != PCMM_AFFINE && C->form != PCMM_JACOBIAN) return PCMM_EINVAL;
+    hipEvent_t ev[PCMM_STAGE_EVENTS] = {};
+    const bool caller_events = cfg && cfg->stage_events;
+    if (caller_events) {
+        for (int i = 0; i < PCMM_STAGE_EVENTS; ++i) {
+            ev[i] = (hipEvent_t)cfg->stage_events[i];
+            if (!ev[i]) return PCMM_EINVAL;
+        }
+    }
+    pcmm_plan_s pl;
+    pcmm_problem q = single_problem(A, m, n, B->cols, bits, is_signed, C->form, cfg);
+    pcmm_status st = build_plan(&q, 1, pl);
+    if (st != PCMM_OK) return st;
+    if (stats) *stats = pl.stats[0];
+    const bool gpu_work = pl.full.count > 0;
+    // the size check comes before any device call
+    if (gpu_work && pl.full.ws_bytes > (size_t)PCMM_STATIC_SCRATCH_BYTES) return PCMM_ETOOLARGE;
+    st = check_mats(m, n, B->cols, C->form, B, C);
+    if (st != PCMM_OK) return st;
+    st = bind_device(pl);
+    if (st != PCMM_OK) return st;
+    void *ws = nullptr;
+    st = scratch_of(pl.device, &ws);
+    if (st != PCMM_OK) return st;
+    // The image is copied from pageable host memory: the copy is ordered
+    // after the stream's earlier work (which may still read the scratch) and
+    // has consumed the host bytes when the call returns.
+    return enqueue_run(pl.full, pl.image.data(), nullptr, B, C, 1, ws, caller_events ? ev : nullptr,
+                       (hipStream_t)stream, nullptr);
+}
+
 extern "C" pcmm_status pcmm_plan_create(const pcmm_problem *problems, int32_t count, pcmm_plan *out) {
     if (!out) return PCMM_EINVAL;
     *out = nullptr;

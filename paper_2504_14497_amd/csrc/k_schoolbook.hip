@@ -134,6 +134,7 @@ extern "C" const char *pcmm_strerror(pcmm_status s) {
         case PCMM_ENOMEM: return "workspace too small";
         case PCMM_EDEVICE: return "HIP runtime or launch error";
         case PCMM_ENOTONCURVE: return "point is not a finite point of P-256";
+        case PCMM_ETOOLARGE: return "problem needs more than the library's static scratch (PCMM_STATIC_SCRATCH_BYTES)";
         default: return "unknown status";
     }
 }

@@ -22,7 +22,8 @@ JACOBIAN = 3
 STAGE_EVENTS = 6  # PCMM_STAGE_EVENTS
 
 _STATUS = {0: "PCMM_OK", -1: "PCMM_EINVAL", -2: "PCMM_ERANGE", -3: "PCMM_ENOMEM",
-           -4: "PCMM_EDEVICE", -5: "PCMM_ENOTONCURVE"}
+           -4: "PCMM_EDEVICE", -5: "PCMM_ENOTONCURVE", -6: "PCMM_ETOOLARGE"}
+STATIC_SCRATCH_BYTES = 64 << 20  # PCMM_STATIC_SCRATCH_BYTES
 
 
 class PCMMError(RuntimeError):
@@ -118,6 +119,8 @@ _SIG = {
     "pcmm_cussen": ([_VP, _I32, _I32, _I32, _I32, ctypes.POINTER(Mat), ctypes.POINTER(Mat),
                      ctypes.POINTER(CussenCfg), _VP, ctypes.c_size_t, ctypes.POINTER(CussenStats),
                      _VP], _I32),
+    "pcmm_cussen_static": ([_VP, _I32, _I32, _I32, _I32, ctypes.POINTER(Mat), ctypes.POINTER(Mat),
+                            ctypes.POINTER(CussenCfg), ctypes.POINTER(CussenStats), _VP], _I32),
     "pcmm_cussen_workspace": ([_VP, _I32, _I32, _I32, _I32, _I32, _I32, ctypes.POINTER(CussenCfg),
                                ctypes.POINTER(ctypes.c_size_t)], _I32),
     "pcmm_cussen_plan_stats": ([_VP, _I32, _I32, _I32, _I32, ctypes.POINTER(CussenCfg),
@@ -177,6 +180,12 @@ def lib():
     """Load libpcmm.so (no fallback: raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch brings its own HIP runtime (libamdhip64.so, soname
+        # libamdhip64.so.7).  Loaded first, it is the runtime that
+        # libpcmm.so's dependency resolves to; loaded after libpcmm.so, it
+        # would be a second runtime in the process, and whichever initialised
+        # second finds no device.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libpcmm.so not found at {LIB_PATH}; build it with "
                                "`python -m paper_2504_14497_amd.build`")
@@ -527,6 +536,19 @@ def cussen(A, bits: int, B: DevPoints, c_form: int = AFFINE, cfg: CussenCfg = No
           ctypes.byref(cfg) if cfg is not None else None, _tensor_ptr(ws), ws.numel(),
           ctypes.byref(st), stream_ptr(stream))
     C._keep = (ws,)
+    return C, st.as_dict()
+
+
+def cussen_static(A, bits: int, B: DevPoints, c_form: int = AFFINE, cfg: CussenCfg = None, stream=None,
+                  out: DevPoints = None):
+    """Cussen PC-MM through pcmm_cussen_static (workspace in the library's
+    static device array, no allocation by the library); returns (C, stats)."""
+    A, signed = _host_A(A, bits)
+    m, n = A.shape
+    C = out if out is not None else DevPoints.empty(m, B.cols, 2, c_form)
+    st = CussenStats()
+    _call("pcmm_cussen_static", A.ctypes.data_as(_VP), m, n, bits, signed, B.ref(), C.ref(),
+          ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(st), stream_ptr(stream))
     return C, st.as_dict()
 
 

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_and_status_codes():
     assert pcmm.strerror(0) == "success"
-    for code in (-1, -2, -3, -4, -5):
+    for code in (-1, -2, -3, -4, -5, -6):
         assert pcmm.strerror(code) and pcmm.strerror(code) != "unknown status"
 
 

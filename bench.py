@@ -93,7 +93,38 @@ def cpu_baseline(sh, A, target_seconds, threads):
     return {"value": (ncols / sh.l) / dt, "unit": "PC-MM/s", "cores": threads, "kind": "oracle",
             "sample": f"{ncols} of {sh.l} output columns of the same workload (all {sh.m} rows, both "
                       f"points, compression of all {sh.n} columns of A), scaled by {sh.l}/{ncols}; "
-                      f"{dt:.1f} s wall on {threads} threads"}, C, cols
+                      f"{dt:.1f} s wall on {threads} threads",
+            "threads": threads, "nproc": os.cpu_count(), "physical_cores": physical_cores(),
+            "cpu_model": cpu_model(),
+            "one_thread_pcmm_per_s": 1.0 / (t_one * sh.l),
+            "one_thread_sample": f"output column 0 alone on one thread ({t_one:.2f} s), scaled by {sh.l}",
+            "thread_cap": "the oracle runs at most 16 threads, the host CPU share of one GPU"}, C, cols
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def physical_cores():
+    """Distinct (physical id, core id) pairs in /proc/cpuinfo, or None."""
+    try:
+        cores, phys = set(), None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("physical id"):
+                    phys = line.split(":", 1)[1].strip()
+                elif line.startswith("core id"):
+                    cores.add((phys, line.split(":", 1)[1].strip()))
+        return len(cores) or None
+    except OSError:
+        return None
 
 
 def time_region(fn, reps, stream):
@@ -108,6 +139,83 @@ def time_region(fn, reps, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+# issued 32x32 -> 64-bit multiply-adds of one product in the library's field
+# form (nine 29-bit limbs): 81 partial products + 4 per quotient digit of the
+# Montgomery reduction (9 digits)
+ISSUED_MADS_MUL = 81 + 4 * 9
+
+
+def field_mul_leg(blocks=2048):
+    """Field-multiplication throughput (one dependent chain of products per
+    lane, 8 wavefronts per SIMD) and the issue rates of single instructions
+    (8 independent chains per lane), from the library's probe kernels."""
+    from paper_2504_14497_amd import pcmm
+    kinds = {"v_mad_u64_u32": (0, 4000), "v_add3_u32": (1, 4000), "v_xor_b32": (5, 4000),
+             "v_fma_f64": (4, 4000), "fe_mul": (2, 2000), "mixed_add": (3, 200)}
+    rates = {}
+    for name, (kind, iters) in kinds.items():
+        pcmm.diag_probe(kind, iters // 10, blocks)  # warm-up
+        sec, ops = pcmm.diag_probe(kind, iters, blocks)
+        rates[name] = ops / sec
+    peak = PEAK_INT32_MAD
+    mad_rate = rates["v_mad_u64_u32"]
+    fe = rates["fe_mul"]
+    return {"what": "probe kernels, 2048 workgroups x 256 lanes; fe_mul: x = x * y mod p in the library's "
+                    "Montgomery form, one dependent chain per lane; instruction rates: 8 independent chains "
+                    "per lane, lane-dependent operands",
+            "fe_mul_per_s": fe,
+            "algorithmic_mads_per_mul": MADS_MUL, "issued_mads_per_mul": ISSUED_MADS_MUL,
+            "algorithmic_tops": fe * MADS_MUL / 1e12,
+            "frac_of_peak": fe * MADS_MUL / peak,
+            "frac_of_measured_mad_rate": fe * MADS_MUL / mad_rate,
+            "issued_mad_frac_of_measured_mad_rate": fe * ISSUED_MADS_MUL / mad_rate,
+            "mixed_adds_per_s": rates["mixed_add"],
+            "mixed_add_frac_of_peak": rates["mixed_add"] * MADS_MIXED_ADD / peak,
+            "lane_ops_per_s": {k: v for k, v in rates.items() if k not in ("fe_mul", "mixed_add")},
+            "peak_lane_ops_per_s": peak}
+
+
+def config_leg(sh, reps, school_reps):
+    """A paper-shaped workload besides the headline: Cussen with the autotuned
+    column group and with g = 1 against schoolbook, on GPU-encrypted inputs
+    (A on the host, B resident in HBM; each call includes host planning and
+    the affine normalisation of C)."""
+    import torch
+    from paper_2504_14497_amd import pcmm, workloads as W
+    stream = torch.cuda.current_stream()
+    A, msg = W.make_inputs(sh)
+    _, pk = pcmm.keygen(sh.seed)
+    B = pcmm.encrypt(pk, msg, sh.seed)
+    out = {"workload": f"{sh.name}: A {sh.m}x{sh.n} uniform {'signed' if sh.signed else 'unsigned'} {sh.bits}-bit "
+                       f"x B {sh.n}x{sh.l} ciphertexts of uniform {sh.msg_bits}-bit messages (seed {sh.seed})",
+           "unit": "PC-MM/s"}
+    results = {}
+    for key, group in (("cussen_autotuned", pcmm.GROUP_AUTO), ("cussen_g1", 1)):
+        cfg = pcmm.cussen_cfg(4, group)
+        ws = torch.empty(pcmm.cussen_workspace_bytes(A, sh.bits, sh.l, pcmm.AFFINE, cfg), dtype=torch.uint8,
+                         device="cuda")
+        C = pcmm.DevPoints.empty(sh.m, sh.l, 2, pcmm.AFFINE)
+        _, st = pcmm.cussen(A, sh.bits, B, cfg=cfg, workspace=ws, out=C)
+        torch.cuda.synchronize()
+        ms = time_region(lambda: pcmm.cussen(A, sh.bits, B, cfg=cfg, workspace=ws, out=C), reps, stream)
+        results[key] = C
+        out[key] = {"value": 1e3 / ms, "ms_per_step": ms, "group": st["group"], "k_split": st["k_split"],
+                    "accum_adds_per_column": st["accum_adds"], "table_adds_per_column": st["table_adds"],
+                    "workspace_mb": ws.numel() / 1e6}
+        del ws
+    wss = torch.empty(pcmm.lib().pcmm_schoolbook_workspace(sh.m, sh.n, sh.l, pcmm.AFFINE), dtype=torch.uint8,
+                      device="cuda")
+    Cs = pcmm.schoolbook(A, sh.bits, B, workspace=wss)
+    torch.cuda.synchronize()
+    ms_s = time_region(lambda: pcmm.schoolbook(A, sh.bits, B, workspace=wss), school_reps, stream)
+    out["schoolbook"] = {"value": 1e3 / ms_s, "ms_per_step": ms_s}
+    out["speedup_autotuned_vs_schoolbook"] = ms_s / out["cussen_autotuned"]["ms_per_step"]
+    out["speedup_autotuned_vs_g1"] = out["cussen_g1"]["ms_per_step"] / out["cussen_autotuned"]["ms_per_step"]
+    out["same_output"] = bool(torch.equal(results["cussen_autotuned"].t, Cs.t)
+                              and torch.equal(results["cussen_g1"].t, Cs.t))
+    return out
 
 
 def batch_leg(reps):
@@ -424,6 +532,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--no-vector", action="store_true", help="skip the vector x ciphertext-scalar microbench")
     ap.add_argument("--no-paillier", action="store_true", help="skip the Paillier PC-MM leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the signed 128^3 8-bit and 512^3 2-bit workloads")
+    ap.add_argument("--no-field", action="store_true", help="skip the field-multiply and instruction-rate probes")
     ap.add_argument("--paillier-shape", default="64,64,64,4", help="m,n,l,bits of the Paillier PC-MM leg")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--serve-fractions", default="0.25,0.5,0.75,1.0,1.25",
@@ -592,8 +703,12 @@ def main():
         "roofline": roofline,
         "device": dev,
     }
+    if not args.no_field:
+        out["field_mul"] = field_mul_leg()
+    del ws
+    if not args.no_configs:
+        out["configs"] = {x.name: config_leg(x, 5, 1) for x in (W.SIGNED128, W.LARGE_T2)}
     if not args.no_batch:
-        del ws
         out["batch"] = batch_leg(args.batch_reps)
     if not args.no_vector:
         out["vector"] = vector_leg((8, 64, 512), (4, 8, 16), 4096, 20)

@@ -128,12 +128,17 @@ typedef struct {
 typedef struct {
     int64_t level_mults;     /* sum over columns of n_N (ECSMs per ciphertext point)       */
     int64_t level_adds;      /* sum over columns of sum_{w<N} n_w (paper's counting)        */
-    int64_t table_entries;   /* sum over columns (groups) of table entries per output column */
-    int64_t table_adds;      /* point additions executed per output column to build tables */
+    int64_t table_entries;   /* sum over groups of table entries per output column (digit
+                                tables and, for g > 1, digit combinations)               */
+    int64_t table_adds;      /* point additions executed per output column to build tables
+                                (digit-table prefix sums and combinations)               */
     int64_t accum_adds;      /* mixed additions executed per output column (all rows)      */
     int64_t max_entries;     /* largest table (entries) of one column (group)              */
     int64_t workspace_bytes; /* device workspace of this problem's tables, scratch and
                                 partial sums within a plan run (0 without GPU work)      */
+    int64_t combo_adds;      /* of table_adds: combinations of digits (g > 1), each one
+                                affine addition of two table entries                     */
+    int64_t digit_entries;   /* of table_entries: entries of the columns' digit tables    */
     int32_t k_split;         /* split of the inner dimension that was used                 */
     int32_t lanes_per_chain; /* table-build batch: output columns per lane                 */
     int32_t group;           /* columns of A per code that was used (after autotuning)     */

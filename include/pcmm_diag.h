@@ -70,7 +70,8 @@ pcmm_status pcmm_diag_point(int32_t op, const pcmm_mat *P, const pcmm_mat *Q, co
 
 /* Throughput probes.  kind: 0 v_mad_u64_u32 (32x32+64 -> 64-bit multiply-add),
  * 1 v_add3_u32 (32-bit three-input add), 2 field multiplication,
- * 3 mixed point addition, 4 v_fma_f64.  Launches `blocks` x 256 threads that
+ * 3 mixed point addition, 4 v_fma_f64, 5 v_xor_b32 (lane-dependent operands,
+ * so the work stays on the vector unit).  Launches `blocks` x 256 threads that
  * each run `iters` iterations; returns the kernel time (HIP events) and the
  * number of operations of that kind executed. */
 pcmm_status pcmm_diag_probe(int32_t kind, int64_t iters, int32_t blocks, double *seconds,

@@ -4,15 +4,19 @@
 // Every run queues the same kernels whatever the number of problems; each
 // kernel finds the problem of its block (or tile) by a binary search over the
 // per-problem prefix offsets held in the descriptors of the plan image:
-//   table_build   one lane per (problem, column group, J output columns j,
-//                 point): runs the group's straight-line program (level-N
-//                 ladders, prefix sums, digit combinations) on B[k0.., j],
-//                 keeps every register in a lane-private scratch (structure of
-//                 arrays, so the lanes' accesses coalesce), then converts its
+//   table_build   one lane per (problem, unit = column k of A, J output
+//                 columns j, point): runs the column's straight-line program
+//                 (level-N ladders, prefix sums) on B[k, j], keeps every
+//                 register in a lane-private scratch (structure of arrays, so
+//                 the lanes' accesses coalesce), then converts its digit
 //                 tables to affine with one inversion for all of its J tables.
-//   coop_table    (runs with narrow single-column problems only) the same
-//                 tables with several lanes per level-1 chain: block sums,
-//                 a scan across the lanes, one inversion per lane.
+//   coop_table    (runs with narrow problems only) the same digit tables
+//                 with several lanes per level-1 chain: block sums, a scan
+//                 across the lanes, one inversion per lane.
+//   combo_table   (column groups g > 1) one lane per (group, output column j,
+//                 point): the group's digit combinations, level by level, each
+//                 an affine addition of two entries of the table, with one
+//                 batched inversion per level.
 //   accumulate    persistent: workgroups take tiles (problem, row tile, pair
 //                 tile, split) from a device queue, the most expensive tiles
 //                 first.  For a tile, C_ij += sign * T_kj[code_ik]: every
@@ -63,13 +67,16 @@ struct prob_desc {
     int32_t J, Lj, tm, pp;
     int32_t kc, S, gps, io;  // io: index of the problem's matrices in the run
     int32_t tiles_x, tiles_y, norm_per, coop_w;  // coop_w: lanes per level-1 chain (0: one lane per chain)
+    int32_t nunits, levels;  // digit-table units (columns); largest combination level (1: none)
     int64_t n_lanes, tb_block0;
+    int64_t cb_lanes, cb_block0;  // combination lanes (group, pair), 0 without combinations
     int64_t tile0;
     int64_t red_block0, red_threads;
     int64_t norm_block0, norm_threads;
     int64_t ldj;     // ld of the internal Jacobian buffers (partials, C before normalisation)
     int64_t ld_pre;  // ld of the normalisation prefixes
     int64_t o_ops, o_op_begin, o_entry_begin, o_entries;
+    int64_t o_unit_col, o_unit_grp, o_unit_off, o_combo_begin, o_combos;
     int64_t o_lists, o_chunk_off, o_chunk_len;  // nonzero codes per (split, chunk), see pack_codes
     int32_t chunks_per_split, pad2;
     int64_t w_regs, w_table, w_part, w_cjac, w_norm;
@@ -199,7 +206,7 @@ __device__ __forceinline__ jpt shfl_up_jpt(const jpt &P, int delta, int width) {
 // Chain depth ~ 2 E / W + log2 W additions instead of E.
 __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_desc &d, int64_t lane) {
     const int W = d.coop_w, l = d.l;
-    const int grp = (int)(lane / 64);
+    const int u = (int)(lane / 64);
     const int rem = (int)(lane % 64);
     const int chain = rem / W, w = rem % W;
     if (chain >= 2 * l) return;  // whole W-lane segments idle
@@ -214,9 +221,11 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
     const int64_t ldb = a.io[d.io].ldb;
     const int rmax = d.rmax, emax = d.emax;
     const int64_t n_lanes = d.n_lanes;
-    const int k0 = grp;
-    const int ob = op_begin[grp], oe = op_begin[grp + 1];
-    const int eb = entry_begin[grp], E = entry_begin[grp + 1] - eb;
+    const int k0 = plan_at<int32_t>(a, d.o_unit_col)[u];
+    const int grp = plan_at<int32_t>(a, d.o_unit_grp)[u];
+    const int off = plan_at<int32_t>(a, d.o_unit_off)[u];
+    const int ob = op_begin[u], oe = op_begin[u + 1];
+    const int eb = entry_begin[u], E = entry_begin[u + 1] - eb;
     if (E == 0) return;  // uniform over the chain's lanes
     const int ofirst = oe - (E - 1);
     // levels >= 2, on every lane (each keeps its own register column)
@@ -243,7 +252,9 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
     jpt excl = shfl_up_jpt(incl, 1, W);
     // the block's prefix sums again, from the blocks before it: S_i stored
     // once, its Z folded into the forward pass of the inversion
-    const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
+    const int64_t npairs = 2 * (int64_t)l;
+    uint32_t *tab = table + (((int64_t)grp * emax + off) * npairs + 2 * j + pt) * ENTRY_WORDS;
+    const int64_t estride = npairs * ENTRY_WORDS;  // words from one entry to the next
     fe prod = fe_one_mont();
     jpt S = excl;
     for (int i = i0; i < i1; ++i) {
@@ -253,7 +264,7 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
         const int16_t opd = entries[eb + i];
         if (opd < 0) continue;  // S_0 = B_kj: affine already
         if (i > 0) reg_store(regs, rmax, n_lanes, 0, opd, lane, S);  // S_0 = b_0 is its own register
-        uint32_t *slot = table + (T * emax + i) * ENTRY_WORDS;
+        uint32_t *slot = tab + i * estride;
 #pragma unroll
         for (int q = 0; q < NL; ++q) slot[q] = prod.v[q];
         if (!fe_is_zero(S.Z)) prod = fe_mul_ilp(prod, S.Z);
@@ -261,10 +272,10 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
     fe inv = fe_inv(prod);
     for (int i = i1 - 1; i >= i0; --i) {
         const int16_t opd = entries[eb + i];
-        uint32_t *slot = table + (T * emax + i) * ENTRY_WORDS;
+        uint32_t *slot = tab + i * estride;
         apt A;
         if (opd < 0) {
-            A = load_affine(B, ldb, pt, (int64_t)(k0 + (-1 - opd)) * l + j);
+            A = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
         } else {
             const jpt P = reg_load(regs, rmax, n_lanes, 0, opd, lane);
             fe pre;
@@ -318,15 +329,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
     const int64_t ldb = a.io[d.io].ldb;
     const int l = d.l, rmax = d.rmax, emax = d.emax;
     const int64_t n_lanes = d.n_lanes;
+    const int64_t npairs = 2 * (int64_t)l;
+    const int64_t estride = npairs * ENTRY_WORDS;  // words from one entry to the next
 
-    const int lanes_per_group = 2 * d.Lj;
-    const int grp = (int)(lane / lanes_per_group);
-    const int rem = (int)(lane % lanes_per_group);
+    const int lanes_per_unit = 2 * d.Lj;
+    const int u = (int)(lane / lanes_per_unit);
+    const int rem = (int)(lane % lanes_per_unit);
     const int jslot = rem >> 1;
     const int pt = rem & 1;
-    const int k0 = grp * d.g;
-    const int ob = op_begin[grp], oe = op_begin[grp + 1];
-    const int eb = entry_begin[grp], ee = entry_begin[grp + 1];
+    const int k0 = plan_at<int32_t>(a, d.o_unit_col)[u];
+    const int grp = plan_at<int32_t>(a, d.o_unit_grp)[u];
+    const int off = plan_at<int32_t>(a, d.o_unit_off)[u];
+    const int ob = op_begin[u], oe = op_begin[u + 1];
+    const int eb = entry_begin[u], ee = entry_begin[u + 1];
     const int E = ee - eb;
 
     fe prod = fe_one_mont();
@@ -337,7 +352,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
         last_r = r;
         jpt last = jpt_infinity();
         int last_reg = -1;
-        const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
+        uint32_t *tab = table + (((int64_t)grp * emax + off) * npairs + 2 * j + pt) * ENTRY_WORDS;
         // forward pass of the batched inversion, folded into the program: the
         // plan orders a group's entries by their producing ops, so the next
         // register entry is always the next one an op produces, and its Z
@@ -349,7 +364,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
             const plan_op op = ops[o];
             run_op(op, B, ldb, l, k0, j, pt, regs, rmax, n_lanes, r, lane, last, last_reg);
             if (ne < E && op.dst == entries[eb + ne]) {
-                uint32_t *slot = table + (T * emax + ne) * ENTRY_WORDS;
+                uint32_t *slot = tab + ne * estride;
 #pragma unroll
                 for (int w = 0; w < NL; ++w) slot[w] = prod.v[w];
                 if (!fe_is_zero(last.Z)) prod = fe_mul_ilp(prod, last.Z);
@@ -362,13 +377,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
     fe inv = fe_inv(prod);
     for (int r = last_r; r >= 0; --r) {
         const int j = jslot + r * d.Lj;
-        const int64_t T = ((int64_t)grp * l + j) * 2 + pt;
+        uint32_t *tab = table + (((int64_t)grp * emax + off) * npairs + 2 * j + pt) * ENTRY_WORDS;
         for (int e = E - 1; e >= 0; --e) {
             const int16_t opd = entries[eb + e];
-            uint32_t *slot = table + (T * emax + e) * ENTRY_WORDS;
+            uint32_t *slot = tab + e * estride;
             apt A;
             if (opd < 0) {
-                A = load_affine(B, ldb, pt, (int64_t)(k0 + (-1 - opd)) * l + j);
+                A = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
             } else {
                 jpt P = reg_load(regs, rmax, n_lanes, r, opd, lane);
                 fe pre;
@@ -394,15 +409,207 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
 }
 
 // --------------------------------------------------------------------------
+// Combination entries (column groups g > 1)
+// --------------------------------------------------------------------------
+// An affine table entry: x, y (Montgomery, normal form) and its identity flag.
+__device__ __forceinline__ apt read_entry(const uint32_t *slot, bool &inf) {
+    uint4 w4[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) w4[q] = ((const uint4 *)slot)[q];
+    const uint32_t *w = (const uint32_t *)w4;
+    apt A;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        A.x.v[k] = w[k];
+        A.y.v[k] = w[NL + k];
+    }
+    inf = w[ENTRY_INF] != 0;
+    return A;
+}
+
+__device__ __forceinline__ void write_entry(uint32_t *slot, const apt &A, bool inf) {
+    uint32_t w[ENTRY_WORDS];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        w[k] = inf ? 0u : A.x.v[k];
+        w[NL + k] = inf ? 0u : A.y.v[k];
+    }
+    w[ENTRY_INF] = inf ? 1u : 0u;
+    w[ENTRY_INF + 1] = 0u;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) ((uint4 *)slot)[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+// a - b - c + 4p (mod p) for a, b, c normal: one limb pass (value in
+// (0, 6p)), then normalised
+__device__ __forceinline__ fe fe_sub_sub(const fe &a, const fe &b, const fe &c) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = a.v[i] - b.v[i] - c.v[i] + (uint32_t)KP4.v[i];
+    return fe_norm(x);
+}
+
+// x and the identity flag of an entry (what the forward pass needs)
+struct entry_x {
+    uint4 x0, x1;
+    uint32_t x8, inf;
+};
+
+__device__ __forceinline__ entry_x read_entry_x(const uint32_t *slot) {
+    entry_x r;
+    r.x0 = ((const uint4 *)slot)[0];
+    r.x1 = ((const uint4 *)slot)[1];
+    r.x8 = slot[8];
+    r.inf = slot[ENTRY_INF];
+    return r;
+}
+
+__device__ __forceinline__ fe fe_of(const entry_x &r) {
+    return fe{{r.x0.x, r.x0.y, r.x0.z, r.x0.w, r.x1.x, r.x1.y, r.x1.z, r.x1.w, r.x8}};
+}
+
+// a + b for the cases the chord formula does not cover: an identity operand,
+// b = -a (the identity) and b = a (the doubling, with an inversion of its
+// own; a P-256 point has no order 2, so 2a is finite).  Rare: random
+// ciphertexts never meet them, forced inputs in the tests do.
+__device__ __noinline__ void combo_special(const uint32_t *sa, const uint32_t *sb, bool neg_b, uint32_t *dst) {
+    bool a_inf, b_inf;
+    const apt A = read_entry(sa, a_inf);
+    apt Bn = read_entry(sb, b_inf);
+    if (neg_b) Bn.y = fe_neg(Bn.y);
+    apt R = A;
+    bool inf = false;
+    if (a_inf && b_inf) {
+        inf = true;
+    } else if (a_inf) {
+        R = Bn;
+    } else if (b_inf) {
+        R = A;
+    } else if (!fe_eq(A.y, Bn.y)) {  // x equal, y opposite
+        inf = true;
+    } else {
+        const jpt D = jpt_dbl<false>(jpt_from_affine(A));
+        R = jpt_to_affine_with(D, fe_inv(D.Z));
+    }
+    write_entry(dst, R, inf);
+}
+
+// The combinations of one (group, output column j, point), lane = (group,
+// pair) of the problem; the lanes of a wavefront are consecutive pairs, so
+// with the pair-fastest table layout their accesses to one entry are
+// contiguous.  Within a level every combination reads only lower levels, so
+// one inversion (Montgomery's trick) serves the whole level: forward, each
+// destination slot keeps the product of the dx before it; one inversion;
+// backward, each slot receives its affine sum by the chord formula.  Entries
+// the chord formula does not cover (x_a = x_b or an identity operand) are
+// marked in the forward pass and finished in a third pass, which runs only
+// when some lane of the wavefront has one.  Descriptors are loaded two
+// combinations ahead and operands (backward also the slot) one ahead, so an
+// iteration waits only for loads issued during the previous one.
+constexpr uint32_t ENTRY_PENDING = 2;  // flag word of an entry left to the third pass
+
+__device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &d, int64_t lane) {
+    const int npairs = 2 * d.l;
+    const int grp = (int)(lane / npairs);
+    const int p = (int)(lane - (int64_t)grp * npairs);
+    const int32_t *combo_begin = plan_at<int32_t>(a, d.o_combo_begin);
+    const plan_combo *combos = plan_at<plan_combo>(a, d.o_combos);
+    uint32_t *tab = at<uint32_t>(a, d.w_table) + ((int64_t)grp * d.emax * npairs + p) * ENTRY_WORDS;
+    const int64_t estride = (int64_t)npairs * ENTRY_WORDS;
+    const int cb = combo_begin[grp], ce = combo_begin[grp + 1];
+    for (int c0 = cb; c0 < ce;) {
+        const int level = combos[c0].level;
+        int c1 = c0 + 1;
+        while (c1 < ce && combos[c1].level == level) ++c1;
+        // forward: prefix products of dx into the destination slots
+        fe prod = fe_one_mont();
+        bool pending = false;
+        plan_combo d1 = combos[c0];
+        plan_combo d2 = combos[min(c0 + 1, c1 - 1)];
+        entry_x xa = read_entry_x(tab + d1.a * estride), xb = read_entry_x(tab + d1.b * estride);
+        for (int c = c0; c < c1; ++c) {
+            const plan_combo cm = d1;
+            const entry_x ea = xa, eb = xb;
+            d1 = d2;
+            if (c + 1 < c1) {
+                // a run of combinations shares its first operand (uniform
+                // over the wavefront: one group)
+                if (d1.a != cm.a) xa = read_entry_x(tab + d1.a * estride);
+                xb = read_entry_x(tab + d1.b * estride);
+            }
+            if (c + 2 < c1) d2 = combos[c + 2];
+            const fe dx = fe_sub(fe_of(eb), fe_of(ea));
+            const bool chord = (ea.inf | eb.inf) == 0 && !fe_is_zero(dx);
+            uint32_t *slot = tab + cm.dst * estride;
+            ((uint4 *)slot)[0] = make_uint4(prod.v[0], prod.v[1], prod.v[2], prod.v[3]);
+            ((uint4 *)slot)[1] = make_uint4(prod.v[4], prod.v[5], prod.v[6], prod.v[7]);
+            slot[8] = prod.v[8];
+            slot[ENTRY_INF] = chord ? 0u : ENTRY_PENDING;
+            pending = pending || !chord;
+            if (chord) prod = fe_mul_ilp(prod, dx);
+        }
+        fe inv = fe_inv(prod);
+        // backward: the chord formula for every slot not marked
+        d1 = combos[c1 - 1];
+        d2 = combos[max(c1 - 2, c0)];
+        bool dummy;
+        apt na = read_entry(tab + d1.a * estride, dummy), nb = read_entry(tab + d1.b * estride, dummy);
+        entry_x np = read_entry_x(tab + d1.dst * estride);
+        for (int c = c1 - 1; c >= c0; --c) {
+            const plan_combo cm = d1;
+            const apt A = na;
+            apt Bn = nb;
+            const entry_x pr = np;
+            d1 = d2;
+            if (c > c0) {
+                if (d1.a != cm.a) na = read_entry(tab + d1.a * estride, dummy);
+                nb = read_entry(tab + d1.b * estride, dummy);
+                np = read_entry_x(tab + d1.dst * estride);
+            }
+            if (c - 2 >= c0) d2 = combos[c - 2];
+            if (pr.inf == ENTRY_PENDING) continue;
+            if (cm.neg_b) Bn.y = fe_neg(Bn.y);
+            const fe dx = fe_sub(Bn.x, A.x);
+            const fe dinv = fe_mul_ilp(inv, fe_of(pr));
+            inv = fe_mul_ilp(inv, dx);
+            const fe lam = fe_mul_ilp(fe_sub(Bn.y, A.y), dinv);
+            apt R;
+            R.x = fe_sub_sub(fe_sqr_ilp(lam), A.x, Bn.x);
+            R.y = fe_sub(fe_mul_ilp(lam, fe_sub_w(A.x, R.x)), A.y);
+            write_entry(tab + cm.dst * estride, R, false);
+        }
+        // the rest: identity operands, x_a = x_b
+        if (__ballot(pending)) {
+            for (int c = c0; c < c1; ++c) {
+                const plan_combo cm = combos[c];
+                uint32_t *slot = tab + cm.dst * estride;
+                if (pending && slot[ENTRY_INF] == ENTRY_PENDING)
+                    combo_special(tab + cm.a * estride, tab + cm.b * estride, cm.neg_b != 0, slot);
+            }
+        }
+        c0 = c1;
+    }
+}
+
+__global__ void __launch_bounds__(256) combo_table_kernel(run_args a) {
+    const int b = find_problem(a, offsetof(prob_desc, cb_block0), blockIdx.x);
+    const prob_desc &d = descs(a)[b];
+    const int64_t lane = ((int64_t)blockIdx.x - d.cb_block0) * blockDim.x + threadIdx.x;
+    if (lane >= d.cb_lanes) return;
+    combo_build(a, d, lane);
+}
+
+// --------------------------------------------------------------------------
 // Accumulation (persistent)
 // --------------------------------------------------------------------------
 // Affine table entry e of group k for pair p, read from global memory (the
 // lanes of a wavefront share the pair, so they gather from one small table
 // that L1 and L2 serve): five 16-byte loads.
-__device__ __forceinline__ void load_entry(const uint32_t *tp, int64_t gstride, int32_t v, uint4 (&en)[5]) {
+__device__ __forceinline__ void load_entry(const uint32_t *tp, int64_t gstride, int64_t estride, int32_t v,
+                                           uint4 (&en)[5]) {
     const int c = (int16_t)(v & 0xFFFF);
     const int e = (c < 0 ? -c : c) - 1;
-    const uint4 *ep = (const uint4 *)(tp + (int64_t)(v >> 16) * gstride + (int64_t)e * ENTRY_WORDS);
+    const uint4 *ep = (const uint4 *)(tp + (int64_t)(v >> 16) * gstride + (int64_t)e * estride);
 #pragma unroll
     for (int q = 0; q < 5; ++q) en[q] = ep[q];
 }
@@ -429,6 +636,7 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
     const int64_t *chunk_off = plan_at<int64_t>(a, d.o_chunk_off);
     const int32_t *chunk_len = plan_at<int32_t>(a, d.o_chunk_len);
     const int64_t gstride = (int64_t)npairs * emax * ENTRY_WORDS;  // words from one group's tables to the next
+    const int64_t estride = (int64_t)npairs * ENTRY_WORDS;         // from one entry of a table to the next
 
     jpt acc = jpt_infinity();
     bool acc_inf = true;  // whether acc is the identity, kept by the additions
@@ -436,7 +644,7 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
         const int chunk = bz * d.chunks_per_split + (gc - g_begin) / d.kc;
         const int len = chunk_len[chunk];
         const int32_t *lst = lists + chunk_off[chunk] * m + i;
-        const uint32_t *tp = table + ((int64_t)gc * npairs + p) * emax * ENTRY_WORDS;
+        const uint32_t *tp = table + ((int64_t)gc * emax * npairs + p) * ENTRY_WORDS;
         // software pipeline: codes three slots ahead, the entry one slot
         // ahead, so that their memory latency overlaps the point additions
         int32_t v_cur = len > 0 ? lst[0] : 0;
@@ -444,7 +652,7 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
         int32_t v_nx2 = len > 2 ? lst[2 * (int64_t)m] : 0;
         uint4 en[5];
         if ((int16_t)(v_cur & 0xFFFF) != 0) {
-            load_entry(tp, gstride, v_cur, en);
+            load_entry(tp, gstride, estride, v_cur, en);
         } else {
 #pragma unroll
             for (int q = 0; q < 5; ++q) en[q] = make_uint4(0, 0, 0, 0);
@@ -457,7 +665,7 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
             v_cur = v_nxt;
             v_nxt = v_nx2;
             if (it + 3 < len) v_nx2 = lst[(int64_t)(it + 3) * m];
-            if (it + 1 < len && (int16_t)(v_cur & 0xFFFF) != 0) load_entry(tp, gstride, v_cur, en);
+            if (it + 1 < len && (int16_t)(v_cur & 0xFFFF) != 0) load_entry(tp, gstride, estride, v_cur, en);
             const int code = (int16_t)(v & 0xFFFF);
             if (code == 0) continue;  // padding after the row's last nonzero code
             const uint32_t *w = (const uint32_t *)ec;
@@ -651,7 +859,8 @@ struct job {
     int l = 0, c_form = PCMM_AFFINE;
     int J = 1, Lj = 1;
     int64_t n_lanes = 0;
-    int Lj_pad = 0;           // table-build lanes with each group padded to a
+    int64_t cb_lanes = 0;     // combination lanes: (group, pair), if the plan has combinations
+    int Lj_pad = 0;           // table-build lanes with each unit padded to a
     int64_t n_lanes_pad = 0;  // whole wavefront (0: not applicable), chosen per run
     size_t regs_bytes_pad = 0;
     int coop_w = 0;           // padded runs: lanes sharing each level-1 chain (0: none)
@@ -681,14 +890,13 @@ bool pad_run(size_t count, JobOf job_at) {
     return lanes <= PAD_LANES_MAX;
 }
 
-// Whether every group of a single-column plan ends its program with its
-// level-1 reconstruction, the prefix sums S_i = S_{i-1} + b_i (S_0 = b_0,
-// the table's entry 0): then lanes of a padded group can share that chain.
+// Whether every unit (column) ends its program with its level-1
+// reconstruction, the prefix sums S_i = S_{i-1} + b_i (S_0 = b_0, the digit
+// table's entry 0): then lanes of a padded unit can share that chain.
 bool level1_chains(const cussen_plan &P) {
-    if (P.g != 1) return false;
-    for (int grp = 0; grp < P.ngroups; ++grp) {
-        const int eb = P.entry_begin[grp], E = P.entry_begin[grp + 1] - eb;
-        const int ob = P.op_begin[grp], oe = P.op_begin[grp + 1];
+    for (int u = 0; u < P.nunits; ++u) {
+        const int eb = P.entry_begin[u], E = P.entry_begin[u + 1] - eb;
+        const int ob = P.op_begin[u], oe = P.op_begin[u + 1];
         if (E == 0) continue;  // an all-zero column: no table
         if (oe - ob < E - 1) return false;
         for (int i = 1; i < E; ++i) {
@@ -704,28 +912,29 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
     const cussen_plan &P = G.P;
     const int m = P.m, l = G.l;
     const int emax = std::max(P.max_entries, 1);
-    // table build: J chains per lane so that one inversion serves >= ~64 entries,
-    // while keeping >= ~16K lanes
-    double avg_e = P.ngroups ? (double)P.table_entries / P.ngroups : 1.0;
+    // digit tables: J chains per lane so that one inversion serves >= ~64
+    // entries, while keeping >= ~16K lanes
+    double avg_e = P.nunits ? (double)P.digit_entries / P.nunits : 1.0;
     int J = 1;
     while (J < 8 && 2.0 * J * std::max(avg_e, 1.0) <= 64.0) J *= 2;
-    while (J > 1 && (int64_t)P.ngroups * 2 * ((l + J - 1) / J) < 16384) J /= 2;
+    while (J > 1 && (int64_t)P.nunits * 2 * ((l + J - 1) / J) < 16384) J /= 2;
     G.J = J;
     G.Lj = (l + J - 1) / J;
-    // lanes of one group fill whole wavefronts (uniform control flow) when
-    // possible.  With few output columns a group's chains fill less than a
-    // wavefront; packing several groups into one wavefront runs their
-    // different programs divergently, so a run pads each group to a whole
+    // lanes of one unit fill whole wavefronts (uniform control flow) when
+    // possible.  With few output columns a unit's chains fill less than a
+    // wavefront; packing several units into one wavefront runs their
+    // different programs divergently, so a run pads each unit to a whole
     // wavefront when its padded grid stays small (pad_run): the build is then
     // bound by its chains' latency, not by lanes.
     if (2 * G.Lj >= 64) G.Lj = (G.Lj + 31) / 32 * 32;
     else G.Lj_pad = 32;
-    G.n_lanes = (int64_t)P.ngroups * 2 * G.Lj;
-    G.n_lanes_pad = G.Lj_pad ? (int64_t)P.ngroups * 2 * G.Lj_pad : 0;
-    // a padded group has 64 lanes for its 2 l chains: with single columns,
-    // W = 64 / (2 l) lanes (a power of two, blocks of >= 4 entries on
-    // average) split each level-1 chain as a parallel scan instead of idling;
-    // the depth, about 2 E / W + log2 W additions, beats E only from W = 4
+    G.n_lanes = (int64_t)P.nunits * 2 * G.Lj;
+    G.n_lanes_pad = G.Lj_pad ? (int64_t)P.nunits * 2 * G.Lj_pad : 0;
+    G.cb_lanes = P.combos.empty() ? 0 : (int64_t)P.ngroups * 2 * l;
+    // a padded unit has 64 lanes for its 2 l chains: W = 64 / (2 l) lanes (a
+    // power of two, blocks of >= 4 entries on average) split each level-1
+    // chain as a parallel scan instead of idling; the depth, about 2 E / W +
+    // log2 W additions, beats E only from W = 4
     G.coop_w = 0;
     if (G.Lj_pad && l >= 1 && level1_chains(P)) {
         int W = 1;
@@ -858,7 +1067,7 @@ namespace {
 struct run_layout {
     int32_t count = 0;  // descriptors
     size_t copy_bytes = 0, ctr_off = 0, ws_bytes = 256;
-    int64_t tb_blocks = 0, tiles = 0, red_blocks = 0, norm_blocks = 0;
+    int64_t tb_blocks = 0, cb_blocks = 0, tiles = 0, red_blocks = 0, norm_blocks = 0;
     int acc_grid = 0;
     bool coop = false;  // some problem's tables are built by coop_table_kernel
     std::vector<int> fills;  // run indices whose inner dimension is empty (identity outputs)
@@ -913,6 +1122,8 @@ void fill_stats(const job &G, pcmm_cussen_stats *st) {
     st->k_split = G.S;
     st->lanes_per_chain = G.J;
     st->group = P.g;
+    st->combo_adds = P.combo_adds;
+    st->digit_entries = P.digit_entries;
 }
 
 // Lays out descriptors, plan image and workspace regions of the plan's jobs,
@@ -929,6 +1140,16 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         D[k] = prob_desc{};
         D[k].o_ops = (int64_t)img;
         img += align256(G.P.ops.size() * sizeof(plan_op));
+        D[k].o_unit_col = (int64_t)img;
+        img += align256(G.P.unit_col.size() * 4);
+        D[k].o_unit_grp = (int64_t)img;
+        img += align256(G.P.unit_grp.size() * 4);
+        D[k].o_unit_off = (int64_t)img;
+        img += align256(G.P.unit_off.size() * 4);
+        D[k].o_combo_begin = (int64_t)img;
+        img += align256(G.P.combo_begin.size() * 4);
+        D[k].o_combos = (int64_t)img;
+        img += align256(G.P.combos.size() * sizeof(plan_combo));
         D[k].o_op_begin = (int64_t)img;
         img += align256(G.P.op_begin.size() * 4);
         D[k].o_entry_begin = (int64_t)img;
@@ -948,7 +1169,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
     L.copy_bytes = img;
     L.ctr_off = img;
     size_t ws = img + 256;
-    int64_t tb = 0, tiles = 0, red = 0, norm = 0;
+    int64_t tb = 0, cbb = 0, tiles = 0, red = 0, norm = 0;
     const bool pad = pad_run(nd, [&](size_t q) -> const job & { return pl.jobs[q]; });
     for (size_t k = 0; k < nd; ++k) {
         const job &G = pl.jobs[k];
@@ -977,8 +1198,13 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         d.norm_per = G.norm_per;
         d.chunks_per_split = G.chunks_per_split;
         d.n_lanes = pad_k ? G.n_lanes_pad : G.n_lanes;
+        d.nunits = G.P.nunits;
+        d.levels = G.P.max_levels;
         d.tb_block0 = tb;
         tb += (d.n_lanes + 255) / 256;
+        d.cb_lanes = G.cb_lanes;
+        d.cb_block0 = cbb;
+        cbb += (G.cb_lanes + 255) / 256;
         d.tile0 = tiles;
         tiles += (int64_t)G.tiles_x * G.tiles_y * G.S;
         d.red_block0 = red;
@@ -1002,6 +1228,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
     }
     L.ws_bytes = ws + 256;
     L.tb_blocks = tb;
+    L.cb_blocks = cbb;
     L.tiles = tiles;
     L.red_blocks = red;
     L.norm_blocks = norm;
@@ -1009,7 +1236,8 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
     for (size_t k = 0; k < nd; ++k) pl.stats[pl.jobs[k].index].coop_lanes = D[k].coop_w;
     pl.job_of.assign(pl.count, -1);
     for (size_t k = 0; k < nd; ++k) pl.job_of[pl.jobs[k].index] = (int)k;
-    if (tb > 0x7FFFFFFF || red > 0x7FFFFFFF || norm > 0x7FFFFFFF || tiles > 0x7FFFFFFF - (1 << 20))
+    if (tb > 0x7FFFFFFF || cbb > 0x7FFFFFFF || red > 0x7FFFFFFF || norm > 0x7FFFFFFF ||
+        tiles > 0x7FFFFFFF - (1 << 20))
         return PCMM_EINVAL;
     pl.image.assign(img, 0);
     memcpy(pl.image.data(), D.data(), nd * sizeof(prob_desc));
@@ -1019,6 +1247,11 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
             if (bytes) memcpy(pl.image.data() + off, src, bytes);
         };
         put(D[k].o_ops, P.ops.data(), P.ops.size() * sizeof(plan_op));
+        put(D[k].o_unit_col, P.unit_col.data(), P.unit_col.size() * 4);
+        put(D[k].o_unit_grp, P.unit_grp.data(), P.unit_grp.size() * 4);
+        put(D[k].o_unit_off, P.unit_off.data(), P.unit_off.size() * 4);
+        put(D[k].o_combo_begin, P.combo_begin.data(), P.combo_begin.size() * 4);
+        put(D[k].o_combos, P.combos.data(), P.combos.size() * sizeof(plan_combo));
         put(D[k].o_op_begin, P.op_begin.data(), P.op_begin.size() * 4);
         put(D[k].o_entry_begin, P.entry_begin.data(), P.entry_begin.size() * 4);
         put(D[k].o_entries, P.entries.data(), P.entries.size() * 2);
@@ -1177,6 +1410,10 @@ pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *p
         PCMM_LAUNCH_CHECK();
         if (L.coop) {
             hipLaunchKernelGGL(coop_table_kernel, dim3((unsigned)L.tb_blocks), dim3(256), 0, s, ra);
+            PCMM_LAUNCH_CHECK();
+        }
+        if (L.cb_blocks > 0) {
+            hipLaunchKernelGGL(combo_table_kernel, dim3((unsigned)L.cb_blocks), dim3(256), 0, s, ra);
             PCMM_LAUNCH_CHECK();
         }
     }
@@ -1511,7 +1748,7 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
     L.ctr_off = L.copy_bytes;
     size_t ws = L.ctr_off + 256;
     D.resize(nd);
-    int64_t tb = 0, tiles = 0, red = 0, norm = 0;
+    int64_t tb = 0, cbb = 0, tiles = 0, red = 0, norm = 0;
     const bool pad = pad_run(nd, [&](size_t q) -> const job & { return pl.jobs[pl.job_of[which[order[q]]]]; });
     for (size_t q = 0; q < nd; ++q) {
         const int r = order[q];
@@ -1526,6 +1763,8 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         d.io = r;
         d.tb_block0 = tb;
         tb += (d.n_lanes + 255) / 256;
+        d.cb_block0 = cbb;
+        cbb += (d.cb_lanes + 255) / 256;
         d.tile0 = tiles;
         tiles += (int64_t)G.tiles_x * G.tiles_y * G.S;
         d.red_block0 = red;
@@ -1546,6 +1785,7 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
     }
     L.ws_bytes = ws + 256;
     L.tb_blocks = tb;
+    L.cb_blocks = cbb;
     L.tiles = tiles;
     L.red_blocks = red;
     L.norm_blocks = norm;

@@ -143,6 +143,24 @@ __global__ void __launch_bounds__(256) probe_add3_kernel(uint32_t *out, uint32_t
     if (s == 0x12345678u) out[tid] = s;
 }
 
+// 32-bit exclusive-or: 8 chains per lane, each reading another chain's value,
+// with lane-dependent operands (so the compiler can neither fold the loop nor
+// move the work to the scalar unit)
+__global__ void __launch_bounds__(256) probe_xor_kernel(uint32_t *out, uint32_t seed, int64_t iters) {
+    uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = (seed + tid * 0x9E3779B9u) ^ (0x85EBCA6Bu * (i + 1));
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] ^= acc[(i + 1) & 7];
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += acc[i];
+    if (s == 0x12345678u) out[tid] = s;
+}
+
 __global__ void __launch_bounds__(256) probe_fma64_kernel(uint32_t *out, uint32_t seed, int64_t iters) {
     uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     double acc[8], y[8];
@@ -261,7 +279,7 @@ extern "C" pcmm_status pcmm_diag_point(int32_t op, const pcmm_mat *P, const pcmm
 
 extern "C" pcmm_status pcmm_diag_probe(int32_t kind, int64_t iters, int32_t blocks, double *seconds,
                                        double *ops) {
-    if (kind < 0 || kind > 4 || iters <= 0 || blocks <= 0 || !seconds || !ops) return PCMM_EINVAL;
+    if (kind < 0 || kind > 5 || iters <= 0 || blocks <= 0 || !seconds || !ops) return PCMM_EINVAL;
     uint32_t *scratch = nullptr;
     PCMM_HIP_TRY(hipMalloc(&scratch, (size_t)blocks * 256 * sizeof(uint32_t)));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -278,7 +296,8 @@ extern "C" pcmm_status pcmm_diag_probe(int32_t kind, int64_t iters, int32_t bloc
             case 1: hipLaunchKernelGGL(probe_add3_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
             case 2: hipLaunchKernelGGL(probe_femul_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
             case 3: hipLaunchKernelGGL(probe_madd_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
-            default: hipLaunchKernelGGL(probe_fma64_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
+            case 4: hipLaunchKernelGGL(probe_fma64_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
+            default: hipLaunchKernelGGL(probe_xor_kernel, dim3(blocks), dim3(256), 0, 0, scratch, 1u, iters); break;
         }
         keep(hipGetLastError());
         keep(hipEventRecord(e1, 0));
@@ -289,7 +308,7 @@ extern "C" pcmm_status pcmm_diag_probe(int32_t kind, int64_t iters, int32_t bloc
     if (e1) keep(hipEventDestroy(e1));
     keep(hipFree(scratch));
     if (err != hipSuccess) return PCMM_EDEVICE;
-    double per_thread = (kind <= 1 || kind == 4) ? 8.0 * (double)iters : (double)iters;
+    double per_thread = (kind <= 1 || kind >= 4) ? 8.0 * (double)iters : (double)iters;
     *seconds = ms * 1e-3;
     *ops = per_thread * (double)blocks * 256.0;
     return PCMM_OK;

@@ -181,26 +181,30 @@ __global__ void __launch_bounds__(256) paillier_schoolbook_kernel(const paillier
     from_mont(acc, C + ((int64_t)i * l + j) * BN_WORDS, N, n0, w.lds);
 }
 
-// Cussen table build: one wavefront per (group, output column j) runs the
-// group's straight-line program (MUL: an Alg. 4 power of a base; ADD: a
-// product of two operands) into its register file
+// Cussen digit tables: one wavefront per (unit = column k of A, output
+// column j) runs the column's straight-line program (MUL: an Alg. 4 power of
+// the base B_kj; ADD: a product of two operands) into its register file, then
+// copies the column's digit-table entries into its group's table
 __global__ void __launch_bounds__(256) paillier_table_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
                                                    const plan_op *__restrict__ ops,
-                                                   const int32_t *__restrict__ op_begin, int ngroups, int g,
-                                                   int l, int rmax, const uint32_t *__restrict__ Bm,
-                                                   uint32_t *__restrict__ regs) {
+                                                   const int32_t *__restrict__ op_begin,
+                                                   const int32_t *__restrict__ entry_begin,
+                                                   const int16_t *__restrict__ entries,
+                                                   const int32_t *__restrict__ unit_col,
+                                                   const int32_t *__restrict__ unit_grp,
+                                                   const int32_t *__restrict__ unit_off, int nunits, int l,
+                                                   int rmax, int emax, const uint32_t *__restrict__ Bm,
+                                                   uint32_t *__restrict__ regs, uint32_t *__restrict__ table) {
     __shared__ uint32_t lds[WAVES_PER_BLOCK * BN_LIMBS];
     const wave_ctx w = wave_of(lds);
-    if (w.inst >= (int64_t)ngroups * l) return;
-    const int grp = (int)(w.inst / l), j = (int)(w.inst % l);
-    const int k0 = grp * g;
+    if (w.inst >= (int64_t)nunits * l) return;
+    const int u = (int)(w.inst / l), j = (int)(w.inst % l);
+    const int k = unit_col[u];
     const bn N = bn_load(K->N), one = bn_load(K->one);
     uint32_t *R = regs + w.inst * rmax * BN_LIMBS;
-    auto operand = [&](int o) -> bn {
-        return o >= 0 ? bn_load(R + (int64_t)o * BN_LIMBS)
-                      : bn_load(Bm + ((int64_t)(k0 - 1 - o) * l + j) * BN_LIMBS);
-    };
-    for (int o = op_begin[grp]; o < op_begin[grp + 1]; ++o) {
+    const uint32_t *base = Bm + ((int64_t)k * l + j) * BN_LIMBS;
+    auto operand = [&](int o) -> bn { return o >= 0 ? bn_load(R + (int64_t)o * BN_LIMBS) : bn_load(base); };
+    for (int o = op_begin[u]; o < op_begin[u + 1]; ++o) {
         const plan_op op = ops[o];
         bn r;
         if (op.kind == OP_MUL) {
@@ -211,16 +215,38 @@ __global__ void __launch_bounds__(256) paillier_table_kernel(const paillier_cons
         }
         bn_store(R + (int64_t)op.dst * BN_LIMBS, r);
     }
+    uint32_t *T = table + (((int64_t)unit_grp[u] * l + j) * emax + unit_off[u]) * BN_LIMBS;
+    for (int e = 0; e < entry_begin[u + 1] - entry_begin[u]; ++e)
+        bn_store(T + (int64_t)e * BN_LIMBS, operand(entries[entry_begin[u] + e]));
+}
+
+// Cussen digit combinations (column groups g > 1): one wavefront per (group,
+// output column j); each combination is the product of two entries of the
+// group's table (plaintexts are unsigned here, so no entry is inverted),
+// level by level
+__global__ void __launch_bounds__(256) paillier_combo_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
+                                                   const plan_combo *__restrict__ combos,
+                                                   const int32_t *__restrict__ combo_begin, int ngroups, int l,
+                                                   int emax, uint32_t *__restrict__ table) {
+    __shared__ uint32_t lds[WAVES_PER_BLOCK * BN_LIMBS];
+    const wave_ctx w = wave_of(lds);
+    if (w.inst >= (int64_t)ngroups * l) return;
+    const int grp = (int)(w.inst / l);
+    const bn N = bn_load(K->N);
+    uint32_t *T = table + w.inst * emax * BN_LIMBS;
+    for (int c = combo_begin[grp]; c < combo_begin[grp + 1]; ++c) {
+        const plan_combo cm = combos[c];
+        bn_store(T + (int64_t)cm.dst * BN_LIMBS,
+                 bn_mont(bn_load(T + (int64_t)cm.a * BN_LIMBS), bn_load(T + (int64_t)cm.b * BN_LIMBS), N, n0));
+    }
 }
 
 // Cussen accumulation: one wavefront per output (i, j), i fastest; the
 // product over the groups of the table entry each row segment's code names
 __global__ void __launch_bounds__(256) paillier_accumulate_kernel(const paillier_consts *__restrict__ K, uint32_t n0,
-                                                         const int16_t *__restrict__ codes,
-                                                         const int32_t *__restrict__ entry_begin,
-                                                         const int16_t *__restrict__ entries, int m, int ngroups,
-                                                         int g, int l, int rmax, const uint32_t *__restrict__ Bm,
-                                                         const uint32_t *__restrict__ regs, uint32_t *__restrict__ C) {
+                                                         const int16_t *__restrict__ codes, int m, int ngroups,
+                                                         int l, int emax, const uint32_t *__restrict__ table,
+                                                         uint32_t *__restrict__ C) {
     __shared__ uint32_t lds[WAVES_PER_BLOCK * BN_LIMBS];
     const wave_ctx w = wave_of(lds);
     if (w.inst >= (int64_t)m * l) return;
@@ -230,9 +256,7 @@ __global__ void __launch_bounds__(256) paillier_accumulate_kernel(const paillier
     for (int grp = 0; grp < ngroups; ++grp) {
         const int code = codes[(int64_t)grp * m + i];
         if (code == 0) continue;
-        const int o = entries[entry_begin[grp] + code - 1];
-        const uint32_t *src = o >= 0 ? regs + (((int64_t)grp * l + j) * rmax + o) * BN_LIMBS
-                                     : Bm + ((int64_t)(grp * g - 1 - o) * l + j) * BN_LIMBS;
+        const uint32_t *src = table + (((int64_t)grp * l + j) * emax + code - 1) * BN_LIMBS;
         acc = bn_mont(acc, bn_load(src), N, n0);
     }
     from_mont(acc, C + ((int64_t)i * l + j) * BN_WORDS, N, n0, w.lds);
@@ -380,7 +404,8 @@ pcmm_status fill_identity(uint32_t *C, int64_t count, hipStream_t s) {
 }
 
 struct cussen_layout {
-    size_t off_bm, off_regs, off_ops, off_opb, off_entb, off_ent, off_codes, total;
+    size_t off_bm, off_regs, off_table, off_ops, off_opb, off_entb, off_ent, off_ucol, off_ugrp, off_uoff, off_cbeg,
+        off_combos, off_codes, total;
 };
 
 cussen_layout cussen_geom(const cussen_plan &P, int n, int l) {
@@ -389,17 +414,23 @@ cussen_layout cussen_geom(const cussen_plan &P, int n, int l) {
     L.off_bm = o;
     o = align256(o + (size_t)n * l * BN_BYTES);
     L.off_regs = o;
-    o = align256(o + (size_t)P.ngroups * l * std::max(P.max_regs, 1) * BN_BYTES);
-    L.off_ops = o;
-    o = align256(o + P.ops.size() * sizeof(plan_op));
-    L.off_opb = o;
-    o = align256(o + P.op_begin.size() * 4);
-    L.off_entb = o;
-    o = align256(o + P.entry_begin.size() * 4);
-    L.off_ent = o;
-    o = align256(o + P.entries.size() * 2);
-    L.off_codes = o;
-    o = align256(o + P.codes.size() * 2);
+    o = align256(o + (size_t)P.nunits * l * std::max(P.max_regs, 1) * BN_BYTES);
+    L.off_table = o;
+    o = align256(o + (size_t)P.ngroups * l * std::max(P.max_entries, 1) * BN_BYTES);
+    auto arr = [&](size_t &off, size_t bytes) {
+        off = o;
+        o = align256(o + bytes);
+    };
+    arr(L.off_ops, P.ops.size() * sizeof(plan_op));
+    arr(L.off_opb, P.op_begin.size() * 4);
+    arr(L.off_entb, P.entry_begin.size() * 4);
+    arr(L.off_ent, P.entries.size() * 2);
+    arr(L.off_ucol, P.unit_col.size() * 4);
+    arr(L.off_ugrp, P.unit_grp.size() * 4);
+    arr(L.off_uoff, P.unit_off.size() * 4);
+    arr(L.off_cbeg, P.combo_begin.size() * 4);
+    arr(L.off_combos, P.combos.size() * sizeof(plan_combo));
+    arr(L.off_codes, P.codes.size() * 2);
     L.total = o;
     return L;
 }
@@ -551,6 +582,8 @@ pcmm_status pcmm_paillier_cussen(pcmm_paillier ctx, const void *A, int32_t m, in
         stats->level_adds = P.level_adds;
         stats->table_entries = P.table_entries;
         stats->table_adds = P.table_adds;
+        stats->combo_adds = P.combo_adds;
+        stats->digit_entries = P.digit_entries;
         stats->accum_adds = P.accum_adds;
         stats->max_entries = P.max_entries;
         stats->workspace_bytes = (int64_t)L.total;
@@ -570,25 +603,36 @@ pcmm_status pcmm_paillier_cussen(pcmm_paillier ctx, const void *A, int32_t m, in
     put(L.off_opb, P.op_begin.data(), P.op_begin.size() * 4);
     put(L.off_entb, P.entry_begin.data(), P.entry_begin.size() * 4);
     put(L.off_ent, P.entries.data(), P.entries.size() * 2);
+    put(L.off_ucol, P.unit_col.data(), P.unit_col.size() * 4);
+    put(L.off_ugrp, P.unit_grp.data(), P.unit_grp.size() * 4);
+    put(L.off_uoff, P.unit_off.data(), P.unit_off.size() * 4);
+    put(L.off_cbeg, P.combo_begin.data(), P.combo_begin.size() * 4);
+    put(L.off_combos, P.combos.data(), P.combos.size() * sizeof(plan_combo));
     put(L.off_codes, P.codes.data(), P.codes.size() * 2);
     pcmm_status st = upload(ws + L.off_ops, blob.data(), blob.size(), s);
     if (st) return st;
     uint32_t *Bm = (uint32_t *)(ws + L.off_bm);
     uint32_t *regs = (uint32_t *)(ws + L.off_regs);
+    uint32_t *table = (uint32_t *)(ws + L.off_table);
     const int rmax = std::max(P.max_regs, 1);
+    const int emax = std::max(P.max_entries, 1);
     hipLaunchKernelGGL(paillier_to_mont_kernel, dim3(blocks_for((int64_t)n * l)), dim3(256), 0, s, ctx->d_consts, ctx->n0, B,
                        Bm, (int64_t)n * l);
     PCMM_LAUNCH_CHECK();
-    if (!P.ops.empty()) {
-        hipLaunchKernelGGL(paillier_table_kernel, dim3(blocks_for((int64_t)P.ngroups * l)), dim3(256), 0, s, ctx->d_consts,
-                           ctx->n0, (const plan_op *)(ws + L.off_ops), (const int32_t *)(ws + L.off_opb),
-                           P.ngroups, P.g, l, rmax, (const uint32_t *)Bm, regs);
+    hipLaunchKernelGGL(paillier_table_kernel, dim3(blocks_for((int64_t)P.nunits * l)), dim3(256), 0, s, ctx->d_consts,
+                       ctx->n0, (const plan_op *)(ws + L.off_ops), (const int32_t *)(ws + L.off_opb),
+                       (const int32_t *)(ws + L.off_entb), (const int16_t *)(ws + L.off_ent),
+                       (const int32_t *)(ws + L.off_ucol), (const int32_t *)(ws + L.off_ugrp),
+                       (const int32_t *)(ws + L.off_uoff), P.nunits, l, rmax, emax, (const uint32_t *)Bm, regs, table);
+    PCMM_LAUNCH_CHECK();
+    if (!P.combos.empty()) {
+        hipLaunchKernelGGL(paillier_combo_kernel, dim3(blocks_for((int64_t)P.ngroups * l)), dim3(256), 0, s,
+                           ctx->d_consts, ctx->n0, (const plan_combo *)(ws + L.off_combos),
+                           (const int32_t *)(ws + L.off_cbeg), P.ngroups, l, emax, table);
         PCMM_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(paillier_accumulate_kernel, dim3(blocks_for((int64_t)m * l)), dim3(256), 0, s, ctx->d_consts, ctx->n0,
-                       (const int16_t *)(ws + L.off_codes), (const int32_t *)(ws + L.off_entb),
-                       (const int16_t *)(ws + L.off_ent), m, P.ngroups, P.g, l, rmax, (const uint32_t *)Bm,
-                       (const uint32_t *)regs, C);
+                       (const int16_t *)(ws + L.off_codes), m, P.ngroups, l, emax, (const uint32_t *)table, C);
     PCMM_LAUNCH_CHECK();
     return PCMM_OK;
 }

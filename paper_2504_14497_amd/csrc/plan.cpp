@@ -130,12 +130,21 @@ column_result compress_column(const std::vector<int> &vals, int N, int t, std::v
 
 namespace {
 
-// One column group's share of the plan: its program, its table entries and
+// One column of a group: its digit-table program and entries.
+struct unit_plan {
+    std::vector<plan_op> ops;
+    std::vector<int16_t> entries;  // level-1 operands, ascending values
+    std::vector<int> pos_of_rank;  // rank of a value among them -> position in `entries`
+    int nreg = 0;
+};
+
+// One column group's share of the plan: its units, its combinations and
 // (written in place) its row codes.
 struct group_plan {
-    std::vector<plan_op> ops;
-    std::vector<int16_t> entries;
-    int nreg = 0;
+    std::vector<unit_plan> units;
+    std::vector<plan_combo> combos;
+    int entries = 0;  // entries of the group's table
+    int levels = 1;
     int64_t level_mults = 0, level_adds = 0, mul_bits = 0, accum_adds = 0;
     int err = 0;  // 0, -1 (too many registers or entries), -2 (entry outside the bit-width)
 };
@@ -147,16 +156,18 @@ struct group_scratch {
     std::vector<int32_t> col[4];
 };
 
-// The table build folds each entry's Z into its batched inversion as soon as
-// the op producing the entry ends, so a group's entries must be in the order
-// of their producing ops (entries that are base points, which need no
-// inversion, may sit anywhere).  Reorders the entries stably by that op and
-// renumbers the group's row codes to match.
-void order_entries(group_plan &gp, int16_t *codes, int m) {
-    const size_t E = gp.entries.size();
-    std::vector<int> made_by(std::max(gp.nreg, 1), -1);
-    for (size_t o = 0; o < gp.ops.size(); ++o) made_by[gp.ops[o].dst] = (int)o;
-    auto key = [&](size_t e) { return gp.entries[e] < 0 ? -1 : made_by[gp.entries[e]]; };
+// The digit-table build folds each entry's Z into its batched inversion as
+// soon as the op producing the entry ends, so a unit's entries must be in
+// the order of their producing ops (entries that are the base point, which
+// need no inversion, may sit anywhere).  Reorders the entries stably by that
+// op and records where each rank went.
+void order_entries(unit_plan &u) {
+    const size_t E = u.entries.size();
+    u.pos_of_rank.resize(E);
+    for (size_t e = 0; e < E; ++e) u.pos_of_rank[e] = (int)e;
+    std::vector<int> made_by(std::max(u.nreg, 1), -1);
+    for (size_t o = 0; o < u.ops.size(); ++o) made_by[u.ops[o].dst] = (int)o;
+    auto key = [&](size_t e) { return u.entries[e] < 0 ? -1 : made_by[u.entries[e]]; };
     // already in order (always for single columns): the producing ops of the
     // register entries increase
     bool sorted = true;
@@ -171,16 +182,11 @@ void order_entries(group_plan &gp, int16_t *codes, int m) {
     for (size_t e = 0; e < E; ++e) order[e] = (int)e;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
     std::vector<int16_t> entries(E);
-    std::vector<int> renum(E);
     for (size_t k = 0; k < E; ++k) {
-        entries[k] = gp.entries[order[k]];
-        renum[order[k]] = (int)k;
+        entries[k] = u.entries[order[k]];
+        u.pos_of_rank[order[k]] = (int)k;
     }
-    gp.entries = std::move(entries);
-    for (int i = 0; i < m; ++i) {
-        const int c = codes[i];
-        if (c != 0) codes[i] = (int16_t)(c < 0 ? -(renum[-c - 1] + 1) : renum[c - 1] + 1);
-    }
+    u.entries = std::move(entries);
 }
 
 void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, int g, int key_bits, int grp,
@@ -201,34 +207,48 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
             sc.col[t][i] = v;
         }
     }
-    int nreg = 0;
-    // per-digit tables
-    std::vector<std::vector<int16_t>> digit_operand(gg);
+    // digit tables: Alg. 2 on each column's magnitudes
+    gp.units.assign(gg, unit_plan{});
+    std::vector<std::vector<int>> rank(gg);
+    std::vector<int> off(gg, 0);
     sc.vals.resize(m);
+    int entries = 0;
     for (int t = 0; t < gg; ++t) {
+        unit_plan &u = gp.units[t];
         const int32_t *col = sc.col[t].data();
         for (int i = 0; i < m; ++i) sc.vals[i] = std::abs((int)col[i]);
-        column_result cr = compress_column(sc.vals, N, t, gp.ops, &nreg, &gp.mul_bits);
+        column_result cr = compress_column(sc.vals, N, 0, u.ops, &u.nreg, &gp.mul_bits);
         gp.level_mults += cr.nN;
         gp.level_adds += cr.adds_counted;
-        if (gg == 1) {
-            // one column: the table is the level-1 reconstruction itself,
-            // entry e = the e-th smallest distinct |a|; code = sign (e + 1)
-            for (int i = 0; i < m; ++i) {
-                if (cr.row_rank[i] < 0) continue;
-                codes[i] = (int16_t)(col[i] < 0 ? -(cr.row_rank[i] + 1) : cr.row_rank[i] + 1);
-                ++gp.accum_adds;
-            }
-            gp.entries = std::move(cr.level1);
-            gp.nreg = nreg;
-            if (nreg > 32000) gp.err = -1;
-            else order_entries(gp, codes, m);
+        u.entries = std::move(cr.level1);
+        if (u.nreg > 32000) {
+            gp.err = -1;
             return;
         }
-        digit_operand[t] = std::move(cr.row_operand);
+        order_entries(u);
+        rank[t] = std::move(cr.row_rank);
+        off[t] = entries;
+        entries += (int)u.entries.size();
     }
-    // distinct row segments up to sign (first nonzero digit made positive);
-    // a segment is keyed by its digits, key_bits each
+    auto digit_entry = [&](int t, int i) { return off[t] + gp.units[t].pos_of_rank[rank[t][i]]; };
+    if (gg == 1) {
+        // one column: the table is the level-1 reconstruction itself; code =
+        // sign (entry + 1)
+        const int32_t *col = sc.col[0].data();
+        for (int i = 0; i < m; ++i) {
+            if (rank[0][i] < 0) continue;
+            const int e = digit_entry(0, i);
+            codes[i] = (int16_t)(col[i] < 0 ? -(e + 1) : e + 1);
+            ++gp.accum_adds;
+        }
+        gp.entries = entries;
+        return;
+    }
+    // Row segments up to sign (first nonzero digit made positive).  A
+    // segment's entry is built digit by digit: the entry of its prefix
+    // (s_0 .. s_{t-1}) plus s_t times digit t's entry, one combination per
+    // distinct prefix with at least two nonzero digits (memoised on the
+    // prefix, keyed by its digits, key_bits each, and its length).
     const bool direct = gg <= 2 && key_bits == 9;
     if (direct && sc.stamp.empty()) {
         sc.stamp.assign((size_t)1 << 18, -1);
@@ -243,53 +263,63 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
             if (first < 0 && seg[t] != 0) first = t;
         }
         if (first < 0) continue;  // code 0: all-zero segment
-        int sigma = seg[first] < 0 ? -1 : 1;
+        const int sigma = seg[first] < 0 ? -1 : 1;
+        int cur = -1, nz = 0;
         uint64_t key = 0;
         for (int t = 0; t < gg; ++t) {
             seg[t] *= sigma;
             key |= (uint64_t)(seg[t] + (1 << (key_bits - 1))) << (key_bits * t);
-        }
-        int e = -1;
-        if (direct) {
-            if (sc.stamp[key] == grp) e = sc.slot[key];
-        } else {
-            auto it = entry_of.find(key);
-            if (it != entry_of.end()) e = it->second;
-        }
-        if (e < 0) {
-            // entry = sum_t seg_t B_t from the digit tables
-            int16_t acc = INT16_MIN;
-            for (int t = 0; t < gg; ++t) {
-                if (seg[t] == 0) continue;
-                int16_t d = digit_operand[t][i];
-                if (acc == INT16_MIN) {
-                    acc = d;  // first nonzero digit is positive
+            if (seg[t] == 0) continue;
+            const int d = digit_entry(t, i);
+            ++nz;
+            if (cur < 0) {  // the first nonzero digit (positive)
+                cur = d;
+                continue;
+            }
+            // the prefix up to t: its digits and its length
+            const uint64_t pkey = key | ((uint64_t)t << 62);
+            int e = -1;
+            if (direct) {
+                if (sc.stamp[key] == grp) e = sc.slot[key];
+            } else {
+                auto it = entry_of.find(pkey);
+                if (it != entry_of.end()) e = it->second;
+            }
+            if (e < 0) {
+                e = entries++;
+                plan_combo c{};
+                c.dst = (int16_t)e;
+                c.a = (int16_t)cur;
+                c.b = (int16_t)d;
+                c.neg_b = seg[t] < 0 ? 1 : 0;
+                c.level = (uint8_t)nz;
+                gp.combos.push_back(c);
+                gp.levels = std::max(gp.levels, nz);
+                if (direct) {
+                    sc.stamp[key] = grp;
+                    sc.slot[key] = e;
                 } else {
-                    plan_op op{};
-                    op.kind = OP_ADD;
-                    op.dst = (int16_t)nreg++;
-                    op.a = acc;
-                    op.b = d;
-                    op.neg_b = seg[t] < 0 ? 1 : 0;
-                    gp.ops.push_back(op);
-                    acc = op.dst;
+                    entry_of.emplace(pkey, e);
                 }
             }
-            e = (int)gp.entries.size();
-            gp.entries.push_back(acc);
-            if (direct) {
-                sc.stamp[key] = grp;
-                sc.slot[key] = e;
-            } else {
-                entry_of.emplace(key, e);
-            }
+            cur = e;
         }
-        codes[i] = (int16_t)(sigma * (e + 1));
+        codes[i] = (int16_t)(sigma * (cur + 1));
         ++gp.accum_adds;
     }
-    gp.nreg = nreg;
-    if (nreg > 32000 || gp.entries.size() > 32000) gp.err = -1;
-    else order_entries(gp, codes, m);
+    gp.entries = entries;
+    if (entries > 32000) {
+        gp.err = -1;
+        return;
+    }
+    // one level after another (a combination's first operand has the level
+    // below its own, its second is a digit entry); within a level by first
+    // operand, so the GPU keeps it in registers over a run of combinations
+    std::sort(gp.combos.begin(), gp.combos.end(), [](const plan_combo &x, const plan_combo &y) {
+        if (x.level != y.level) return x.level < y.level;
+        if (x.a != y.a) return x.a < y.a;
+        return x.b < y.b;
+    });
 }
 
 }  // namespace
@@ -300,9 +330,9 @@ int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int
     if ((int64_t)m * n > 0 && !A) return -1;
     if (m > 32767) return -1;
     // row segments of g digits are keyed with 9 bits per digit up to 8-bit
-    // entries and 17 bits beyond (so at most 3 digits fit the 64-bit key)
+    // entries and 17 bits beyond (so at most 3 digits fit beside the length)
     const int key_bits = bits <= 8 ? 9 : 17;
-    if (g * key_bits > 64) return -1;
+    if (g * key_bits > 62) return -1;
     cussen_plan P;
     P.m = m;
     P.n = n;
@@ -331,99 +361,145 @@ int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int
         if (gp.err == -2) return -2;
     for (const group_plan &gp : parts)
         if (gp.err) return gp.err;
-    size_t nops = 0, nent = 0;
+    size_t nops = 0, nent = 0, ncombo = 0;
     for (const group_plan &gp : parts) {
-        nops += gp.ops.size();
-        nent += gp.entries.size();
+        for (const unit_plan &u : gp.units) {
+            nops += u.ops.size();
+            nent += u.entries.size();
+        }
+        ncombo += gp.combos.size();
     }
     P.ops.reserve(nops);
     P.entries.reserve(nent);
-    P.op_begin.reserve(P.ngroups + 1);
-    P.entry_begin.reserve(P.ngroups + 1);
+    P.combos.reserve(ncombo);
     P.op_begin.push_back(0);
     P.entry_begin.push_back(0);
-    for (group_plan &gp : parts) {
-        P.ops.insert(P.ops.end(), gp.ops.begin(), gp.ops.end());
-        P.entries.insert(P.entries.end(), gp.entries.begin(), gp.entries.end());
-        P.op_begin.push_back((int32_t)P.ops.size());
-        P.entry_begin.push_back((int32_t)P.entries.size());
-        P.nregs.push_back(gp.nreg);
-        P.max_regs = std::max(P.max_regs, gp.nreg);
-        P.max_entries = std::max(P.max_entries, (int)gp.entries.size());
-        P.table_entries += (int64_t)gp.entries.size();
+    P.combo_begin.push_back(0);
+    for (int grp = 0; grp < P.ngroups; ++grp) {
+        group_plan &gp = parts[grp];
+        int off = 0;
+        for (size_t t = 0; t < gp.units.size(); ++t) {
+            unit_plan &u = gp.units[t];
+            P.unit_col.push_back(grp * g + (int)t);
+            P.unit_grp.push_back(grp);
+            P.unit_off.push_back(off);
+            off += (int)u.entries.size();
+            P.ops.insert(P.ops.end(), u.ops.begin(), u.ops.end());
+            P.entries.insert(P.entries.end(), u.entries.begin(), u.entries.end());
+            P.op_begin.push_back((int32_t)P.ops.size());
+            P.entry_begin.push_back((int32_t)P.entries.size());
+            P.nregs.push_back(u.nreg);
+            P.max_regs = std::max(P.max_regs, u.nreg);
+            P.digit_entries += (int64_t)u.entries.size();
+        }
+        P.combos.insert(P.combos.end(), gp.combos.begin(), gp.combos.end());
+        P.combo_begin.push_back((int32_t)P.combos.size());
+        P.group_entries.push_back(gp.entries);
+        P.max_entries = std::max(P.max_entries, gp.entries);
+        P.max_levels = std::max(P.max_levels, gp.levels);
+        P.table_entries += gp.entries;
         P.level_mults += gp.level_mults;
         P.level_adds += gp.level_adds;
         P.table_mul_bits += gp.mul_bits;
         P.accum_adds += gp.accum_adds;
     }
+    P.nunits = (int)P.unit_col.size();
     for (const plan_op &op : P.ops)
         if (op.kind == OP_ADD) ++P.table_adds;
+    P.combo_adds = (int64_t)P.combos.size();
+    P.table_adds += P.combo_adds;
     *out = std::move(P);
     return 0;
 }
 
-// Verifies a plan by running every group's program on integer coefficient
-// vectors over the group's base points (B_t -> the t-th unit vector).  0 when
-// the plan is sound, else the first failure: 1 register entries out of the
-// order of their producing ops, 2 a code outside its group's table, 3 an
-// entry that is not the row segment its code stands for, 4 a malformed
-// program (operand undefined or out of range, a register written twice).
+// Verifies a plan by running every unit's program and every group's
+// combinations on integer coefficient vectors over the group's base points
+// (B_t -> the t-th unit vector).  0 when the plan is sound, else the first
+// failure: 1 digit entries out of the order of their producing ops, 2 a code
+// outside its group's table, 3 an entry that is not the row segment its code
+// stands for, 4 a malformed program (an operand undefined or out of range, a
+// register or entry written twice, a unit outside its group, a combination
+// reading a level not below its own).
 int check_cussen_plan(const cussen_plan &P, const void *A, int bits, bool is_signed) {
     const int m = P.m, n = P.n, g = P.g;
-    if ((int)P.op_begin.size() != P.ngroups + 1 || (int)P.entry_begin.size() != P.ngroups + 1 ||
-        (int)P.nregs.size() != P.ngroups || P.codes.size() != (size_t)P.ngroups * m)
+    if ((int)P.op_begin.size() != P.nunits + 1 || (int)P.entry_begin.size() != P.nunits + 1 ||
+        (int)P.nregs.size() != P.nunits || (int)P.unit_col.size() != P.nunits ||
+        (int)P.unit_grp.size() != P.nunits || (int)P.unit_off.size() != P.nunits ||
+        (int)P.combo_begin.size() != P.ngroups + 1 || (int)P.group_entries.size() != P.ngroups ||
+        P.codes.size() != (size_t)P.ngroups * m)
         return 4;
     using vec = std::array<int64_t, 4>;
+    int u = 0;
     for (int grp = 0; grp < P.ngroups; ++grp) {
         const int k0 = grp * g;
         const int gg = std::min(g, n - k0);
-        const int nreg = P.nregs[grp];
-        std::vector<vec> reg(std::max(nreg, 1));
-        std::vector<int> made_by(std::max(nreg, 1), -1);
-        bool bad = false;
-        auto value = [&](int16_t opd) -> vec {
-            vec v{0, 0, 0, 0};
-            if (opd < 0) {
-                const int t = -1 - opd;
-                if (t >= gg) bad = true;
-                else v[t] = 1;
-            } else if (opd >= nreg || made_by[opd] < 0) {
-                bad = true;
-            } else {
-                v = reg[opd];
+        const int E = P.group_entries[grp];
+        if (E < 0 || E > P.max_entries) return 4;
+        std::vector<vec> ent(E, vec{0, 0, 0, 0});
+        std::vector<int> level(E, 0);  // 0: not yet defined
+        // the group's units: digit t of the group is column k0 + t
+        for (int t = 0; t < gg; ++t, ++u) {
+            if (u >= P.nunits || P.unit_grp[u] != grp || P.unit_col[u] != k0 + t) return 4;
+            const int nreg = P.nregs[u];
+            std::vector<vec> reg(std::max(nreg, 1));
+            std::vector<int> made_by(std::max(nreg, 1), -1);
+            bool bad = false;
+            auto value = [&](int16_t opd) -> vec {
+                vec v{0, 0, 0, 0};
+                if (opd < 0) {
+                    if (opd != -1) bad = true;
+                    else v[t] = 1;
+                } else if (opd >= nreg || made_by[opd] < 0) {
+                    bad = true;
+                } else {
+                    v = reg[opd];
+                }
+                return v;
+            };
+            for (int o = P.op_begin[u]; o < P.op_begin[u + 1]; ++o) {
+                const plan_op &op = P.ops[o];
+                if (op.dst < 0 || op.dst >= nreg || made_by[op.dst] >= 0) return 4;
+                vec r{0, 0, 0, 0};
+                if (op.kind == OP_MUL) {
+                    if (op.a >= 0 || op.s < 1) return 4;
+                    const vec b = value(op.a);
+                    for (int q = 0; q < 4; ++q) r[q] = (int64_t)op.s * b[q];
+                } else if (op.kind == OP_ADD) {
+                    const vec x = value(op.a), y = value(op.b);
+                    for (int q = 0; q < 4; ++q) r[q] = x[q] + (op.neg_b ? -y[q] : y[q]);
+                } else {
+                    return 4;
+                }
+                if (bad) return 4;
+                reg[op.dst] = r;
+                made_by[op.dst] = o;
             }
-            return v;
-        };
-        for (int o = P.op_begin[grp]; o < P.op_begin[grp + 1]; ++o) {
-            const plan_op &op = P.ops[o];
-            if (op.dst < 0 || op.dst >= nreg || made_by[op.dst] >= 0) return 4;
-            vec r{0, 0, 0, 0};
-            if (op.kind == OP_MUL) {
-                if (op.a >= 0 || op.s < 1) return 4;
-                const vec b = value(op.a);
-                for (int t = 0; t < 4; ++t) r[t] = (int64_t)op.s * b[t];
-            } else if (op.kind == OP_ADD) {
-                const vec x = value(op.a), y = value(op.b);
-                for (int t = 0; t < 4; ++t) r[t] = x[t] + (op.neg_b ? -y[t] : y[t]);
-            } else {
-                return 4;
+            const int eb = P.entry_begin[u], ne = P.entry_begin[u + 1] - eb;
+            const int off = P.unit_off[u];
+            if (off < 0 || off + ne > E) return 4;
+            int last = -1;
+            for (int e = 0; e < ne; ++e) {
+                const int16_t opd = P.entries[eb + e];
+                if (level[off + e]) return 4;
+                ent[off + e] = value(opd);
+                level[off + e] = 1;
+                if (bad) return 4;
+                if (opd >= 0) {
+                    if (made_by[opd] <= last) return 1;
+                    last = made_by[opd];
+                }
             }
-            if (bad) return 4;
-            reg[op.dst] = r;
-            made_by[op.dst] = o;
         }
-        const int eb = P.entry_begin[grp], E = P.entry_begin[grp + 1] - eb;
-        std::vector<vec> ent(E);
-        int last = -1;
-        for (int e = 0; e < E; ++e) {
-            const int16_t opd = P.entries[eb + e];
-            ent[e] = value(opd);
-            if (bad) return 4;
-            if (opd >= 0) {
-                if (made_by[opd] <= last) return 1;
-                last = made_by[opd];
-            }
+        for (int c = P.combo_begin[grp]; c < P.combo_begin[grp + 1]; ++c) {
+            const plan_combo &cb = P.combos[c];
+            if (cb.dst < 0 || cb.dst >= E || cb.a < 0 || cb.a >= E || cb.b < 0 || cb.b >= E) return 4;
+            if (level[cb.dst] || !level[cb.a] || level[cb.b] != 1 || level[cb.a] >= cb.level) return 4;
+            if (c > P.combo_begin[grp] && P.combos[c - 1].level > cb.level) return 4;
+            for (int q = 0; q < 4; ++q) ent[cb.dst][q] = ent[cb.a][q] + (cb.neg_b ? -ent[cb.b][q] : ent[cb.b][q]);
+            level[cb.dst] = cb.level;
         }
+        for (int e = 0; e < E; ++e)
+            if (!level[e]) return 4;
         for (int i = 0; i < m; ++i) {
             vec seg{0, 0, 0, 0};
             bool zero = true;
@@ -436,11 +512,11 @@ int check_cussen_plan(const cussen_plan &P, const void *A, int bits, bool is_sig
             if (c == 0) continue;
             const int e = (c < 0 ? -c : c) - 1;
             if (e >= E) return 2;
-            for (int t = 0; t < 4; ++t)
-                if ((c < 0 ? -ent[e][t] : ent[e][t]) != seg[t]) return 3;
+            for (int q = 0; q < 4; ++q)
+                if ((c < 0 ? -ent[e][q] : ent[e][q]) != seg[q]) return 3;
         }
     }
-    return 0;
+    return u == P.nunits ? 0 : 4;
 }
 
 }  // namespace pcmm

@@ -1,15 +1,20 @@
 // plan.hpp -- host-side compression plan for Cussen PC-MM (internal).
 //
-// For each column group of A (g consecutive columns; g = 1 is Alg. 3 as
-// printed) the plan holds
-//   * a straight-line program that builds, for one output column j and one
-//     ciphertext point, the table of point multiples needed by the group:
-//       MUL  dst = s * B_t                      (Alg. 2 level-N multiply, Alg. 1)
-//       ADD  dst = src_a + (-1)^neg * src_b     (Alg. 2 prefix sums; for g > 1 also
-//                                               the combination of the g digits)
-//     where an operand is a register (the result of an earlier op) or one of
-//     the group's base points B_t = B[k0 + t, j] (affine input);
-//   * the table entries, each an operand of that program;
+// A column group is g consecutive columns of A (g = 1 is Alg. 3 as printed).
+// Its table, for one output column j and one ciphertext point, holds every
+// point the group's rows need: first each column's digit table (Alg. 2
+// reconstruction of that column), then the combinations of digits that the
+// group's row segments use.  The plan holds
+//   * per column ("unit") a straight-line program that builds the column's
+//     digit table from its base point B_k = B[k, j]:
+//       MUL  dst = s * B_k                      (Alg. 2 level-N multiply, Alg. 1)
+//       ADD  dst = src_a + (-1)^neg * src_b     (Alg. 2 prefix sums)
+//     where an operand is a register (the result of an earlier op of the
+//     unit) or the base point itself, and the unit's level-1 entries (the
+//     digit table, ascending values) as operands of that program;
+//   * per group (g > 1) the combinations, each one addition of two entries
+//     of the group's table, dst = a + (-1)^neg * b, ordered by level (the
+//     number of nonzero digits), so one level depends only on lower ones;
 //   * one code per row: 0 for an all-zero row segment, else +-(entry + 1).
 // The un-sort / re-insert steps of the reconstruction are resolved at plan
 // time into operand references, so the GPU executes only point operations.
@@ -22,33 +27,50 @@ namespace pcmm {
 
 enum : uint8_t { OP_MUL = 1, OP_ADD = 2 };
 
-// operand: >= 0 register id; < 0 base point t = -1 - operand
+// operand: >= 0 register id; < 0 the unit's base point
 struct plan_op {
     uint8_t kind;
     uint8_t neg_b;  // ADD: subtract operand b
     int16_t dst;
-    int16_t a;      // ADD: first operand; MUL: base index operand (< 0)
+    int16_t a;      // ADD: first operand; MUL: base point operand (< 0)
     int16_t b;      // ADD: second operand
     int32_t s;      // MUL: small non-negative scalar
 };
 
+// One combination entry of a group's table: dst = a + (-1)^neg_b b, all
+// three entry indices of the group's table; level = nonzero digits of dst.
+struct plan_combo {
+    int16_t dst, a, b;
+    uint8_t neg_b;
+    uint8_t level;
+};
+
 struct cussen_plan {
-    int m = 0, n = 0, g = 1, N = 4, ngroups = 0;
-    int max_entries = 0;   // E: largest table of a group (layout stride)
-    int max_regs = 0;      // largest register count of a group
-    std::vector<int32_t> op_begin;      // ngroups + 1
+    int m = 0, n = 0, g = 1, N = 4, ngroups = 0, nunits = 0;
+    int max_entries = 0;      // E: largest table of a group (layout stride)
+    int max_regs = 0;         // largest register count of a unit
+    int max_levels = 1;       // largest combination level of a group (1: none)
+    std::vector<int32_t> unit_col;      // nunits: column of A (row of B) of the unit
+    std::vector<int32_t> unit_grp;      // nunits: its group
+    std::vector<int32_t> unit_off;      // nunits: offset of its digit table in the group's table
+    std::vector<int32_t> op_begin;      // nunits + 1
     std::vector<plan_op> ops;
-    std::vector<int32_t> nregs;         // per group
-    std::vector<int32_t> entry_begin;   // ngroups + 1
-    std::vector<int16_t> entries;       // operand of every table entry
+    std::vector<int32_t> nregs;         // per unit
+    std::vector<int32_t> entry_begin;   // nunits + 1
+    std::vector<int16_t> entries;       // operand of every digit-table entry
+    std::vector<int32_t> combo_begin;   // ngroups + 1
+    std::vector<plan_combo> combos;
+    std::vector<int32_t> group_entries; // ngroups: entries of each group's table
     std::vector<int16_t> codes;         // ngroups x m (group-major)
     // operation counts
     int64_t level_mults = 0;   // sum over columns of n_N
     int64_t level_adds = 0;    // sum over columns of sum_{w<N} n_w (paper's counting)
-    int64_t table_adds = 0;    // ADD ops per (output column, point)
+    int64_t table_adds = 0;    // point additions per (output column, point): ADD ops + combinations
+    int64_t combo_adds = 0;    // of which combinations
     int64_t table_mul_bits = 0;  // sum of ladder lengths of MUL ops
     int64_t accum_adds = 0;    // nonzero codes (mixed additions per output column and point)
-    int64_t table_entries = 0;
+    int64_t table_entries = 0; // entries of all groups' tables
+    int64_t digit_entries = 0; // of which digit-table entries
 };
 
 // Plaintext element x of A: int8 / uint8 for bits <= 8, int16 / uint16 for

@@ -68,6 +68,7 @@ class CussenStats(ctypes.Structure):
                 ("table_entries", ctypes.c_int64), ("table_adds", ctypes.c_int64),
                 ("accum_adds", ctypes.c_int64), ("max_entries", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64),
+                ("combo_adds", ctypes.c_int64), ("digit_entries", ctypes.c_int64),
                 ("k_split", ctypes.c_int32), ("lanes_per_chain", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("coop_lanes", ctypes.c_int32),
                 ("ms_upload", ctypes.c_float), ("ms_table", ctypes.c_float),

@@ -228,9 +228,12 @@ def test_out_of_range_is_rejected(dev, orc):
     assert ei.value.code == -2
 
 
-def _full_size(dev, orc, sh, cfg=None, n_samples=24, check_schoolbook=True):
+def _full_size(dev, orc, sh, cfg=None, n_samples=24, check_schoolbook=True, whole_columns=(0, -1)):
     """The benchmark's path: GPU keygen + encrypt from the seed, Cussen with the
-    default (autotuned-free) configuration, canonical affine output."""
+    default (autotuned-free) configuration, canonical affine output.  Sampled
+    outputs are compared with the oracle's closed form and the columns
+    `whole_columns` (negative: from the end) with the oracle's own Alg. 3 on
+    ciphertexts it encrypted from the same seed."""
     import torch
     A, msg = W.make_inputs(sh)
     log("full size", sh.name, "keygen+encrypt")
@@ -246,6 +249,13 @@ def _full_size(dev, orc, sh, cfg=None, n_samples=24, check_schoolbook=True):
     want = orc.pcmm_closed_form(A, sh.l, osk, msg, sh.seed, ii, jj)
     got = C[ii, jj]
     assert (got == want).all()
+    cols = sorted({j % sh.l for j in whole_columns})
+    if cols:
+        log("full size", sh.name, "oracle Alg. 3 on whole columns", cols)
+        _, opk = orc.keygen(sh.seed)
+        Bo = orc.encrypt_columns(opk, msg, cols, sh.seed)
+        Co = orc.pcmm_cussen(A, Bo, cols=cols)
+        assert (C[:, cols] == Co[:, cols]).all()
     # decryption of the sampled outputs gives (A.B) G
     AB = A.astype(np.int64) @ msg.astype(np.int64)
     p_, b_, gx, gy, q = orc.curve_params()
@@ -267,7 +277,7 @@ def test_full_size_large_t4(dev, orc):
 
 def test_full_size_large_t2(dev, orc):
     _full_size(dev, orc, W.LARGE_T2, check_schoolbook=False)
-    _full_size(dev, orc, W.LARGE_T2, cfg=dev_cfg(3), n_samples=8, check_schoolbook=False)
+    _full_size(dev, orc, W.LARGE_T2, cfg=dev_cfg(3), n_samples=8, check_schoolbook=False, whole_columns=(5,))
 
 
 def dev_cfg(group):
@@ -277,7 +287,7 @@ def dev_cfg(group):
 
 def test_full_size_signed128(dev, orc):
     _full_size(dev, orc, W.SIGNED128)
-    _full_size(dev, orc, W.SIGNED128, cfg=dev_cfg(2), n_samples=8, check_schoolbook=False)
+    _full_size(dev, orc, W.SIGNED128, cfg=dev_cfg(2), n_samples=8, check_schoolbook=False, whole_columns=(5,))
 
 
 def test_full_size_serve_layer(dev, orc):
@@ -292,7 +302,7 @@ def test_long_inner_dimension_in_one_split(dev, orc):
     closed form on every output."""
     from paper_2504_14497_amd import pcmm
     sh = W.PCMMShape(m=3, n=40000, l=2, bits=2, signed=False, msg_bits=4, seed=57, name="long_n")
-    _full_size(dev, orc, sh, cfg=pcmm.CussenCfg(4, 1, 1, 0), n_samples=6)
+    _full_size(dev, orc, sh, cfg=pcmm.CussenCfg(4, 1, 1, 0), n_samples=6, whole_columns=())
 
 
 @pytest.mark.parametrize("m,l,bits,signed,coop", [(300, 1, 8, False, True), (257, 2, 12, True, True),
@@ -307,7 +317,7 @@ def test_narrow_tables_built_cooperatively(dev, orc, m, l, bits, signed, coop):
     on every output."""
     from paper_2504_14497_amd import pcmm
     sh = W.PCMMShape(m=m, n=3, l=l, bits=bits, signed=signed, msg_bits=8, seed=61 + m, name="narrow")
-    st = _full_size(dev, orc, sh, cfg=pcmm.CussenCfg(4, 1, 0, 0), n_samples=m * l)
+    st = _full_size(dev, orc, sh, cfg=pcmm.CussenCfg(4, 1, 0, 0), n_samples=m * l, whole_columns=())
     if coop:
         assert 4 <= st["coop_lanes"] <= 64 // (2 * l), st
     else:

@@ -76,7 +76,7 @@ struct prob_desc {
     int64_t ldj;     // ld of the internal Jacobian buffers (partials, C before normalisation)
     int64_t ld_pre;  // ld of the normalisation prefixes
     int64_t o_ops, o_op_begin, o_entry_begin, o_entries;
-    int64_t o_unit_col, o_unit_grp, o_unit_off, o_combo_begin, o_combos;
+    int64_t o_unit_col, o_unit_grp, o_unit_off, o_cblock_begin, o_cblocks, o_cruns;
     int64_t o_lists, o_chunk_off, o_chunk_len;  // nonzero codes per (split, chunk), see pack_codes
     int32_t chunks_per_split, pad2;
     int64_t w_regs, w_table, w_part, w_cjac, w_norm;
@@ -498,96 +498,143 @@ __device__ __noinline__ void combo_special(const uint32_t *sa, const uint32_t *s
 // pair) of the problem; the lanes of a wavefront are consecutive pairs, so
 // with the pair-fastest table layout their accesses to one entry are
 // contiguous.  Within a level every combination reads only lower levels, so
-// one inversion (Montgomery's trick) serves the whole level: forward, each
-// destination slot keeps the product of the dx before it; one inversion;
-// backward, each slot receives its affine sum by the chord formula.  Entries
-// the chord formula does not cover (x_a = x_b or an identity operand) are
-// marked in the forward pass and finished in a third pass, which runs only
-// when some lane of the wavefront has one.  Descriptors are loaded two
-// combinations ahead and operands (backward also the slot) one ahead, so an
-// iteration waits only for loads issued during the previous one.
+// one inversion (Montgomery's trick) serves the whole level.  The level's
+// combinations come in blocks of up to COMBO_BLOCK first operands a[r],
+// held in registers, and runs of one second operand b each (loaded once per
+// run):
+//   forward   the product of the dx = x_b - x_a[r] of all chord additions,
+//             one prefix (the product before the run) stored per run, in
+//             the slot of its first combination;
+//   inverse   one inversion per level;
+//   backward  per run (in reverse) the prefixes inside the run again from
+//             the run's dx, then each combination's 1/dx and its affine sum
+//             by the chord formula.
+// Combinations the chord formula does not cover (an identity operand, x_a =
+// x_b) are marked in the forward pass and finished in a third pass, which
+// runs only when some lane of the wavefront has one.
 constexpr uint32_t ENTRY_PENDING = 2;  // flag word of an entry left to the third pass
+constexpr int CB = COMBO_BLOCK;
 
 __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &d, int64_t lane) {
     const int npairs = 2 * d.l;
     const int grp = (int)(lane / npairs);
     const int p = (int)(lane - (int64_t)grp * npairs);
-    const int32_t *combo_begin = plan_at<int32_t>(a, d.o_combo_begin);
-    const plan_combo *combos = plan_at<plan_combo>(a, d.o_combos);
+    const int32_t *cblock_begin = plan_at<int32_t>(a, d.o_cblock_begin);
+    const plan_cblock *blocks = plan_at<plan_cblock>(a, d.o_cblocks);
+    const plan_crun *runs = plan_at<plan_crun>(a, d.o_cruns);
     uint32_t *tab = at<uint32_t>(a, d.w_table) + ((int64_t)grp * d.emax * npairs + p) * ENTRY_WORDS;
     const int64_t estride = (int64_t)npairs * ENTRY_WORDS;
-    const int cb = combo_begin[grp], ce = combo_begin[grp + 1];
-    for (int c0 = cb; c0 < ce;) {
-        const int level = combos[c0].level;
-        int c1 = c0 + 1;
-        while (c1 < ce && combos[c1].level == level) ++c1;
-        // forward: prefix products of dx into the destination slots
+    const int bb = cblock_begin[grp], be = cblock_begin[grp + 1];
+    for (int b0 = bb; b0 < be;) {
+        const int level = blocks[b0].level;
+        int b1 = b0 + 1;
+        while (b1 < be && blocks[b1].level == level) ++b1;
+        // ---- forward
         fe prod = fe_one_mont();
         bool pending = false;
-        plan_combo d1 = combos[c0];
-        plan_combo d2 = combos[min(c0 + 1, c1 - 1)];
-        entry_x xa = read_entry_x(tab + d1.a * estride), xb = read_entry_x(tab + d1.b * estride);
-        for (int c = c0; c < c1; ++c) {
-            const plan_combo cm = d1;
-            const entry_x ea = xa, eb = xb;
-            d1 = d2;
-            if (c + 1 < c1) {
-                // a run of combinations shares its first operand (uniform
-                // over the wavefront: one group)
-                if (d1.a != cm.a) xa = read_entry_x(tab + d1.a * estride);
-                xb = read_entry_x(tab + d1.b * estride);
+        for (int bi = b0; bi < b1; ++bi) {
+            const plan_cblock blk = blocks[bi];
+            entry_x xa[CB];
+#pragma unroll
+            for (int r = 0; r < CB; ++r)
+                if (r < blk.na) xa[r] = read_entry_x(tab + blk.a[r] * estride);
+            plan_crun nr = runs[blk.run_begin];
+            entry_x nxb = read_entry_x(tab + nr.b * estride);
+            for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
+                const plan_crun run = nr;
+                const entry_x xb = nxb;
+                if (ri + 1 < blk.run_end) {
+                    nr = runs[ri + 1];
+                    nxb = read_entry_x(tab + nr.b * estride);
+                }
+                int first = 0;
+                while (run.dst[first] < 0) ++first;
+                uint32_t *pslot = tab + run.dst[first] * estride;
+                ((uint4 *)pslot)[0] = make_uint4(prod.v[0], prod.v[1], prod.v[2], prod.v[3]);
+                ((uint4 *)pslot)[1] = make_uint4(prod.v[4], prod.v[5], prod.v[6], prod.v[7]);
+                pslot[8] = prod.v[8];
+#pragma unroll
+                for (int r = 0; r < CB; ++r) {
+                    if (run.dst[r] < 0) continue;
+                    const fe dx = fe_sub(fe_of(xb), fe_of(xa[r]));
+                    const bool chord = (xa[r].inf | xb.inf) == 0 && !fe_is_zero(dx);
+                    if (chord) {
+                        prod = fe_mul_ilp(prod, dx);
+                    } else {
+                        tab[run.dst[r] * estride + ENTRY_INF] = ENTRY_PENDING;
+                        pending = true;
+                    }
+                }
             }
-            if (c + 2 < c1) d2 = combos[c + 2];
-            const fe dx = fe_sub(fe_of(eb), fe_of(ea));
-            const bool chord = (ea.inf | eb.inf) == 0 && !fe_is_zero(dx);
-            uint32_t *slot = tab + cm.dst * estride;
-            ((uint4 *)slot)[0] = make_uint4(prod.v[0], prod.v[1], prod.v[2], prod.v[3]);
-            ((uint4 *)slot)[1] = make_uint4(prod.v[4], prod.v[5], prod.v[6], prod.v[7]);
-            slot[8] = prod.v[8];
-            slot[ENTRY_INF] = chord ? 0u : ENTRY_PENDING;
-            pending = pending || !chord;
-            if (chord) prod = fe_mul_ilp(prod, dx);
         }
         fe inv = fe_inv(prod);
-        // backward: the chord formula for every slot not marked
-        d1 = combos[c1 - 1];
-        d2 = combos[max(c1 - 2, c0)];
-        bool dummy;
-        apt na = read_entry(tab + d1.a * estride, dummy), nb = read_entry(tab + d1.b * estride, dummy);
-        entry_x np = read_entry_x(tab + d1.dst * estride);
-        for (int c = c1 - 1; c >= c0; --c) {
-            const plan_combo cm = d1;
-            const apt A = na;
-            apt Bn = nb;
-            const entry_x pr = np;
-            d1 = d2;
-            if (c > c0) {
-                if (d1.a != cm.a) na = read_entry(tab + d1.a * estride, dummy);
-                nb = read_entry(tab + d1.b * estride, dummy);
-                np = read_entry_x(tab + d1.dst * estride);
+        // ---- backward
+        for (int bi = b1 - 1; bi >= b0; --bi) {
+            const plan_cblock blk = blocks[bi];
+            apt A[CB];
+            bool ainf[CB];
+#pragma unroll
+            for (int r = 0; r < CB; ++r)
+                if (r < blk.na) A[r] = read_entry(tab + blk.a[r] * estride, ainf[r]);
+            plan_crun nr = runs[blk.run_end - 1];
+            bool nbinf;
+            apt nb = read_entry(tab + nr.b * estride, nbinf);
+            for (int ri = blk.run_end - 1; ri >= blk.run_begin; --ri) {
+                const plan_crun run = nr;
+                const apt Bv = nb;
+                const bool binf = nbinf;
+                if (ri > blk.run_begin) {
+                    nr = runs[ri - 1];
+                    nb = read_entry(tab + nr.b * estride, nbinf);
+                }
+                int first = 0;
+                while (run.dst[first] < 0) ++first;
+                const uint32_t *pslot = tab + run.dst[first] * estride;
+                const uint4 p0 = ((const uint4 *)pslot)[0], p1 = ((const uint4 *)pslot)[1];
+                // the prefix before each combination of the run (dx is
+                // formed again below: registers are tight)
+                fe q[CB];
+                bool chord[CB];
+                fe cur = {{p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, pslot[8]}};
+#pragma unroll
+                for (int r = 0; r < CB; ++r) {
+                    chord[r] = false;
+                    if (run.dst[r] < 0) continue;
+                    const fe dx = fe_sub(Bv.x, A[r].x);
+                    chord[r] = !ainf[r] && !binf && !fe_is_zero(dx);
+                    q[r] = cur;
+                    if (chord[r] && r + 1 < CB) cur = fe_mul_ilp(cur, dx);
+                }
+#pragma unroll
+                for (int r = CB - 1; r >= 0; --r) {
+                    if (!chord[r]) continue;
+                    const fe dinv = fe_mul_ilp(inv, q[r]);
+                    inv = fe_mul_ilp(inv, fe_sub(Bv.x, A[r].x));
+                    const fe by = ((run.neg >> r) & 1) ? fe_neg(Bv.y) : Bv.y;
+                    const fe lam = fe_mul_ilp(fe_sub(by, A[r].y), dinv);
+                    apt R;
+                    R.x = fe_sub_sub(fe_sqr_ilp(lam), A[r].x, Bv.x);
+                    R.y = fe_sub(fe_mul_ilp(lam, fe_sub_w(A[r].x, R.x)), A[r].y);
+                    write_entry(tab + run.dst[r] * estride, R, false);
+                }
             }
-            if (c - 2 >= c0) d2 = combos[c - 2];
-            if (pr.inf == ENTRY_PENDING) continue;
-            if (cm.neg_b) Bn.y = fe_neg(Bn.y);
-            const fe dx = fe_sub(Bn.x, A.x);
-            const fe dinv = fe_mul_ilp(inv, fe_of(pr));
-            inv = fe_mul_ilp(inv, dx);
-            const fe lam = fe_mul_ilp(fe_sub(Bn.y, A.y), dinv);
-            apt R;
-            R.x = fe_sub_sub(fe_sqr_ilp(lam), A.x, Bn.x);
-            R.y = fe_sub(fe_mul_ilp(lam, fe_sub_w(A.x, R.x)), A.y);
-            write_entry(tab + cm.dst * estride, R, false);
         }
-        // the rest: identity operands, x_a = x_b
+        // ---- the rest: identity operands, x_a = x_b
         if (__ballot(pending)) {
-            for (int c = c0; c < c1; ++c) {
-                const plan_combo cm = combos[c];
-                uint32_t *slot = tab + cm.dst * estride;
-                if (pending && slot[ENTRY_INF] == ENTRY_PENDING)
-                    combo_special(tab + cm.a * estride, tab + cm.b * estride, cm.neg_b != 0, slot);
+            for (int bi = b0; bi < b1; ++bi) {
+                const plan_cblock blk = blocks[bi];
+                for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
+                    const plan_crun run = runs[ri];
+                    for (int r = 0; r < CB; ++r) {
+                        if (run.dst[r] < 0) continue;
+                        uint32_t *slot = tab + run.dst[r] * estride;
+                        if (pending && slot[ENTRY_INF] == ENTRY_PENDING)
+                            combo_special(tab + blk.a[r] * estride, tab + run.b * estride, (run.neg >> r) & 1, slot);
+                    }
+                }
             }
         }
-        c0 = c1;
+        b0 = b1;
     }
 }
 
@@ -1146,10 +1193,12 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         img += align256(G.P.unit_grp.size() * 4);
         D[k].o_unit_off = (int64_t)img;
         img += align256(G.P.unit_off.size() * 4);
-        D[k].o_combo_begin = (int64_t)img;
-        img += align256(G.P.combo_begin.size() * 4);
-        D[k].o_combos = (int64_t)img;
-        img += align256(G.P.combos.size() * sizeof(plan_combo));
+        D[k].o_cblock_begin = (int64_t)img;
+        img += align256(G.P.cblock_begin.size() * 4);
+        D[k].o_cblocks = (int64_t)img;
+        img += align256(G.P.cblocks.size() * sizeof(plan_cblock));
+        D[k].o_cruns = (int64_t)img;
+        img += align256(G.P.cruns.size() * sizeof(plan_crun));
         D[k].o_op_begin = (int64_t)img;
         img += align256(G.P.op_begin.size() * 4);
         D[k].o_entry_begin = (int64_t)img;
@@ -1250,8 +1299,9 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         put(D[k].o_unit_col, P.unit_col.data(), P.unit_col.size() * 4);
         put(D[k].o_unit_grp, P.unit_grp.data(), P.unit_grp.size() * 4);
         put(D[k].o_unit_off, P.unit_off.data(), P.unit_off.size() * 4);
-        put(D[k].o_combo_begin, P.combo_begin.data(), P.combo_begin.size() * 4);
-        put(D[k].o_combos, P.combos.data(), P.combos.size() * sizeof(plan_combo));
+        put(D[k].o_cblock_begin, P.cblock_begin.data(), P.cblock_begin.size() * 4);
+        put(D[k].o_cblocks, P.cblocks.data(), P.cblocks.size() * sizeof(plan_cblock));
+        put(D[k].o_cruns, P.cruns.data(), P.cruns.size() * sizeof(plan_crun));
         put(D[k].o_op_begin, P.op_begin.data(), P.op_begin.size() * 4);
         put(D[k].o_entry_begin, P.entry_begin.data(), P.entry_begin.size() * 4);
         put(D[k].o_entries, P.entries.data(), P.entries.size() * 2);

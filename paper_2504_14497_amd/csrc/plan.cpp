@@ -143,6 +143,8 @@ struct unit_plan {
 struct group_plan {
     std::vector<unit_plan> units;
     std::vector<plan_combo> combos;
+    std::vector<plan_cblock> cblocks;  // run indices local to the group
+    std::vector<plan_crun> cruns;
     int entries = 0;  // entries of the group's table
     int levels = 1;
     int64_t level_mults = 0, level_adds = 0, mul_bits = 0, accum_adds = 0;
@@ -188,6 +190,8 @@ void order_entries(unit_plan &u) {
     }
     u.entries = std::move(entries);
 }
+
+void block_combos(group_plan &gp);
 
 void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, int g, int key_bits, int grp,
                  int16_t *codes, group_plan &gp, group_scratch &sc) {
@@ -320,6 +324,51 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
         if (x.a != y.a) return x.a < y.a;
         return x.b < y.b;
     });
+    block_combos(gp);
+}
+
+// Blocks of up to COMBO_BLOCK consecutive first operands per level, each
+// with its runs by second operand (ascending).
+void block_combos(group_plan &gp) {
+    const auto &C = gp.combos;
+    size_t c = 0;
+    while (c < C.size()) {
+        plan_cblock blk{};
+        blk.level = C[c].level;
+        blk.run_begin = (int32_t)gp.cruns.size();
+        size_t e = c;  // combinations of the block: [c, e)
+        while (e < C.size() && C[e].level == blk.level) {
+            if (e == c || C[e].a != C[e - 1].a) {
+                if (blk.na == COMBO_BLOCK) break;
+                blk.a[blk.na++] = C[e].a;
+            }
+            ++e;
+        }
+        // runs by second operand; a + b and a - b (signed plaintexts) both
+        // occur, so a run ends where its slot for a combination's a is taken
+        std::vector<size_t> idx;
+        for (size_t k = c; k < e; ++k) idx.push_back(k);
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+            return C[x].b != C[y].b ? C[x].b < C[y].b : C[x].neg_b < C[y].neg_b;
+        });
+        for (size_t k = 0; k < idx.size();) {
+            plan_crun run{};
+            run.b = C[idx[k]].b;
+            for (int r = 0; r < COMBO_BLOCK; ++r) run.dst[r] = -1;
+            for (; k < idx.size() && C[idx[k]].b == run.b; ++k) {
+                const plan_combo &cm = C[idx[k]];
+                int r = 0;
+                while (blk.a[r] != cm.a) ++r;
+                if (run.dst[r] >= 0) break;
+                run.dst[r] = cm.dst;
+                if (cm.neg_b) run.neg |= (uint8_t)(1u << r);
+            }
+            gp.cruns.push_back(run);
+        }
+        blk.run_end = (int32_t)gp.cruns.size();
+        gp.cblocks.push_back(blk);
+        c = e;
+    }
 }
 
 }  // namespace
@@ -375,6 +424,7 @@ int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int
     P.op_begin.push_back(0);
     P.entry_begin.push_back(0);
     P.combo_begin.push_back(0);
+    P.cblock_begin.push_back(0);
     for (int grp = 0; grp < P.ngroups; ++grp) {
         group_plan &gp = parts[grp];
         int off = 0;
@@ -394,6 +444,14 @@ int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int
         }
         P.combos.insert(P.combos.end(), gp.combos.begin(), gp.combos.end());
         P.combo_begin.push_back((int32_t)P.combos.size());
+        const int32_t run0 = (int32_t)P.cruns.size();
+        for (plan_cblock blk : gp.cblocks) {
+            blk.run_begin += run0;
+            blk.run_end += run0;
+            P.cblocks.push_back(blk);
+        }
+        P.cruns.insert(P.cruns.end(), gp.cruns.begin(), gp.cruns.end());
+        P.cblock_begin.push_back((int32_t)P.cblocks.size());
         P.group_entries.push_back(gp.entries);
         P.max_entries = std::max(P.max_entries, gp.entries);
         P.max_levels = std::max(P.max_levels, gp.levels);
@@ -425,7 +483,8 @@ int check_cussen_plan(const cussen_plan &P, const void *A, int bits, bool is_sig
     if ((int)P.op_begin.size() != P.nunits + 1 || (int)P.entry_begin.size() != P.nunits + 1 ||
         (int)P.nregs.size() != P.nunits || (int)P.unit_col.size() != P.nunits ||
         (int)P.unit_grp.size() != P.nunits || (int)P.unit_off.size() != P.nunits ||
-        (int)P.combo_begin.size() != P.ngroups + 1 || (int)P.group_entries.size() != P.ngroups ||
+        (int)P.combo_begin.size() != P.ngroups + 1 || (int)P.cblock_begin.size() != P.ngroups + 1 ||
+        (int)P.group_entries.size() != P.ngroups ||
         P.codes.size() != (size_t)P.ngroups * m)
         return 4;
     using vec = std::array<int64_t, 4>;
@@ -500,6 +559,33 @@ int check_cussen_plan(const cussen_plan &P, const void *A, int bits, bool is_sig
         }
         for (int e = 0; e < E; ++e)
             if (!level[e]) return 4;
+        // the blocked form holds exactly the group's combinations
+        {
+            std::vector<int> seen(E, 0);
+            size_t count = 0;
+            int last_level = 0;
+            for (int bi = P.cblock_begin[grp]; bi < P.cblock_begin[grp + 1]; ++bi) {
+                const plan_cblock &blk = P.cblocks[bi];
+                if (blk.na < 1 || blk.na > COMBO_BLOCK || blk.level < last_level) return 4;
+                last_level = blk.level;
+                for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
+                    const plan_crun &run = P.cruns[ri];
+                    for (int r = 0; r < COMBO_BLOCK; ++r) {
+                        if (run.dst[r] < 0) continue;
+                        if (r >= blk.na || run.dst[r] >= E || seen[run.dst[r]]++) return 4;
+                        bool found = false;
+                        for (int c = P.combo_begin[grp]; c < P.combo_begin[grp + 1] && !found; ++c) {
+                            const plan_combo &cb = P.combos[c];
+                            found = cb.dst == run.dst[r] && cb.a == blk.a[r] && cb.b == run.b &&
+                                    cb.neg_b == ((run.neg >> r) & 1) && cb.level == blk.level;
+                        }
+                        if (!found) return 4;
+                        ++count;
+                    }
+                }
+            }
+            if (count != (size_t)(P.combo_begin[grp + 1] - P.combo_begin[grp])) return 4;
+        }
         for (int i = 0; i < m; ++i) {
             vec seg{0, 0, 0, 0};
             bool zero = true;

@@ -45,6 +45,25 @@ struct plan_combo {
     uint8_t level;
 };
 
+// The same combinations blocked for register reuse: a block holds up to
+// COMBO_BLOCK first operands of one level (consecutive in the sorted list)
+// and runs; a run is one second operand b and the combinations a[r] +- b
+// that the block's rows need (dst[r] < 0: none).
+constexpr int COMBO_BLOCK = 2;
+
+struct plan_cblock {
+    int16_t a[COMBO_BLOCK];
+    int32_t run_begin, run_end;
+    uint8_t level, na, pad[2];
+};
+
+struct plan_crun {
+    int16_t b;
+    int16_t dst[COMBO_BLOCK];
+    uint8_t neg;  // bit r: subtract b for a[r]
+    uint8_t pad;
+};
+
 struct cussen_plan {
     int m = 0, n = 0, g = 1, N = 4, ngroups = 0, nunits = 0;
     int max_entries = 0;      // E: largest table of a group (layout stride)
@@ -60,6 +79,9 @@ struct cussen_plan {
     std::vector<int16_t> entries;       // operand of every digit-table entry
     std::vector<int32_t> combo_begin;   // ngroups + 1
     std::vector<plan_combo> combos;
+    std::vector<int32_t> cblock_begin;  // ngroups + 1
+    std::vector<plan_cblock> cblocks;   // runs indexed into cruns (whole plan)
+    std::vector<plan_crun> cruns;
     std::vector<int32_t> group_entries; // ngroups: entries of each group's table
     std::vector<int16_t> codes;         // ngroups x m (group-major)
     // operation counts

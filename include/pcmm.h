@@ -90,14 +90,17 @@ typedef struct {
  *           one code and builds the table of their ciphertext combinations;
  *           1..4, or PCMM_GROUP_AUTO: the autotuner builds the plans for
  *           g = 1..4 and keeps the one of least predicted GPU time, from a
- *           cost model of accumulation slots, table additions and table
- *           entries fitted to MI355X measurements; the choice is cached per
- *           (m, n, bits, signedness, rounds) for the process, and a cached
- *           g > 1 whose tables exceed the autotuner's size cap on another
- *           matrix of that shape falls back to g = 1; entries of 9..16 bits
- *           allow g <= 3)
+ *           cost model of the persistent accumulation (row chains and tile
+ *           rounds), the digit combinations (throughput, or a lane's chain
+ *           when lanes are few) and the split-k reduction, fitted to MI355X
+ *           kernel times; the choice of g and k_split is cached per
+ *           (m, n, l, bits, signedness, rounds, requested k_split) for the
+ *           process, and a cached g > 1 whose tables exceed the autotuner's
+ *           size cap on another matrix of that shape falls back to g = 1;
+ *           entries of 9..16 bits allow g <= 3)
  *   k_split split of the n (inner) dimension over independent partial sums that
- *           are then added (0 = chosen from the shape)
+ *           are then added (a power of two <= 64; 0 = the split of least
+ *           predicted time under the same cost model)
  *   k_chunk column groups per code list of the accumulation; each list is
  *           padded to its longest row (0 = one list per split of n)
  *   profile nonzero: record HIP events around every launch of the call on
@@ -341,7 +344,9 @@ pcmm_status pcmm_decrypt(const uint8_t sk_be[32], const pcmm_mat *C, int64_t bou
                          size_t table_bytes, int32_t log2_baby, int64_t *out, void *workspace,
                          size_t ws_bytes, void *stream);
 
-/* Host-only: the compression plan's operation counts for A (no GPU work). */
+/* Host-only: the compression plan's operation counts for A (no GPU work).
+ * With cfg->group = PCMM_GROUP_AUTO the autotuner assumes a square problem
+ * (l = m output columns) for its choice. */
 pcmm_status pcmm_cussen_plan_stats(const void *A, int32_t m, int32_t n, int32_t bits,
                                    int32_t is_signed, const pcmm_cussen_cfg *cfg,
                                    pcmm_cussen_stats *stats);

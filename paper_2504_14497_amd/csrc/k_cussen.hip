@@ -836,48 +836,130 @@ bool valid_cfg(const pcmm_cussen_cfg *cfg) {
 
 int cfg_rounds(const pcmm_cussen_cfg *cfg) { return cfg && cfg->rounds > 0 ? cfg->rounds : 4; }
 
-// Predicted GPU time (ps per output column and point) of a plan on MI355X:
-// accumulation slots (rows x column groups, a wavefront pays for a slot even
-// where some of its rows have a zero code), table additions and table
-// entries (affine conversion), with costs fitted to measurements of the
-// accumulation and table-build kernels at 512 x 512 x 512, t = 2 and 4,
-// g = 1..4 (least squares over the eight runs, each within 7%).
-double predicted_cost(const cussen_plan &P) {
-    return 67.7 * (double)P.m * P.ngroups + 112.2 * (double)P.table_adds + 182.8 * (double)P.table_entries;
+// Accumulation tile: rows per tile, the fewest padded rows, the larger tile
+// on ties (the wavefronts of a workgroup then gather from the same pairs'
+// tables); pp (j, point) pairs per tile of 256 lanes.
+struct acc_tiling {
+    int tm, pp, tiles_x, tiles_y;
+};
+
+acc_tiling acc_tiles(int m, int l) {
+    acc_tiling t;
+    t.tm = 256;
+    for (int tm : {128, 64, 32})
+        if ((int64_t)(m + tm - 1) / tm * tm < (int64_t)(m + t.tm - 1) / t.tm * t.tm) t.tm = tm;
+    t.pp = 256 / t.tm;
+    t.tiles_x = (m + t.tm - 1) / t.tm;
+    t.tiles_y = (2 * l + t.pp - 1) / t.pp;
+    return t;
 }
 
+// The autotuner's cost model: predicted GPU milliseconds of the parts of a
+// run that depend on the column group g and the split S of the inner
+// dimension (the digit tables are the same for every g and S), fitted to
+// kernel times measured on MI355X at 17 shapes (512^3 and 128^3 at 1..8
+// bits, the serving layer 256 x 1024 x 8 with S = 1..64, a sample of the
+// uneven batch; g = 1..4); it picks the measured best g for 16 of them and
+// the 17th within 4 %.
+//   accumulation  persistent: a tile's time is its rows' chain of mixed
+//                 additions (nonzero codes per row and split) times tau;
+//                 tiles run W = 512 at a time (2 per CU), and a tile alone
+//                 still takes beta of its time under full load
+//   combinations  throughput (all combinations) or, with few lanes, one
+//                 lane's chain: an inversion per level and its share of the
+//                 group's combinations; 2048 wavefronts resident
+//   reduction     (S > 1) per output, min(S, 8) lanes adding S / min(S, 8)
+//                 partials each, then a shuffle tree
+double predicted_ms(const cussen_plan &P, int l, int S) {
+    constexpr double TAU = 8.35e-3, BETA = 0.618, ACC0 = 0.043;
+    constexpr double COMBO = 1.361e-7, COMBO_LANE = 8.79e-3, COMBO_LEVEL = 5.77e-2, COMBO0 = 0.0382;
+    constexpr double RED0 = 0.0322, RED = 0.0936e-6;
+    constexpr double W = 512, WAVES = 2048;
+    const int m = std::max(P.m, 1);
+    const acc_tiling t = acc_tiles(m, l);
+    const double tiles = (double)t.tiles_x * t.tiles_y * S;
+    const double pairs = 2.0 * l;
+    double ms = ACC0 + TAU * ((double)P.accum_adds / m / S) * std::max(tiles / W, BETA);
+    if (!P.combos.empty()) {
+        const double rounds = std::max(1.0, std::ceil((double)P.ngroups * pairs / 64 / WAVES));
+        const double lane = COMBO_LEVEL * (std::min(P.g, P.n) - 1) + COMBO_LANE * (double)P.combo_adds / P.ngroups;
+        ms += COMBO0 + std::max(COMBO * (double)P.combo_adds * pairs, lane * rounds);
+    }
+    if (S > 1) {
+        const double s8 = std::min(S, 8);
+        ms += RED0 + RED * P.m * pairs * s8 * ((double)S / s8 + std::log2(s8));
+    }
+    return ms;
+}
+
+// Splits of the inner dimension the tuner considers: powers of two up to 64,
+// each split holding at least two column groups.
+int max_split(const cussen_plan &P) {
+    int S = 1;
+    while (S < 64 && P.ngroups / (S * 2) >= 2) S *= 2;
+    return S;
+}
+
+// (m, n, l, bits, signed, N, requested group, requested split) -> (g, S)
+using tune_key = std::tuple<int, int, int, int, int, int, int, int>;
 std::mutex g_tune_lock;
-std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;  // (m, n, bits, signed, N) -> g
+std::map<tune_key, std::pair<int, int>> g_tune_cache;
 
 // host threads for planning: the CPU share of one GPU
 int host_threads() { return std::max(1, std::min(16, (int)std::thread::hardware_concurrency())); }
 
-// Builds the plan for cfg's group, or for the autotuned one, on up to
-// `threads` host threads.
-int build_plan_cfg(const void *A, int m, int n, int bits, bool sgn, const pcmm_cussen_cfg *cfg,
-                   cussen_plan *out, int threads) {
+// Builds the plan for cfg's group, or for the autotuned one, and picks the
+// split of the inner dimension (cfg's, else the model's best), on up to
+// `threads` host threads.  l: output columns the plan runs with.
+int build_plan_cfg(const void *A, int m, int n, int l, int bits, bool sgn, const pcmm_cussen_cfg *cfg,
+                   cussen_plan *out, int *split, int threads) {
     const int N = cfg_rounds(cfg);
     const int group = cfg ? cfg->group : 0;
-    if (group != PCMM_GROUP_AUTO)
-        return build_cussen_plan(A, m, n, bits, sgn, N, group > 0 ? group : 1, out, threads);
-    const auto key = std::make_tuple(m, n, bits, (int)sgn, N);
+    const int req_split = cfg && cfg->k_split > 0 ? cfg->k_split : 0;
     auto over_cap = [](const cussen_plan &P) {
         return P.g > 1 && (size_t)std::max(P.max_entries, 1) * ENTRY_WORDS * 4 > GROUP_TABLE_CAP;
     };
-    int cached = 0;
+    // the best split of one plan under the model
+    auto best_split = [&](const cussen_plan &P, double *cost) {
+        int bs = req_split ? req_split : 1;
+        double bc = predicted_ms(P, l, bs);
+        if (!req_split)
+            for (int S = 2; S <= max_split(P); S *= 2) {
+                const double c = predicted_ms(P, l, S);
+                if (c < bc) {
+                    bc = c;
+                    bs = S;
+                }
+            }
+        if (cost) *cost = bc;
+        return bs;
+    };
+    if (group != PCMM_GROUP_AUTO) {
+        int rc = build_cussen_plan(A, m, n, bits, sgn, N, group > 0 ? group : 1, out, threads);
+        if (!rc) *split = best_split(*out, nullptr);
+        return rc;
+    }
+    const tune_key key{m, n, l, bits, (int)sgn, N, group, req_split};
+    std::pair<int, int> cached{0, 0};
     {
         std::lock_guard<std::mutex> guard(g_tune_lock);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) cached = it->second;
     }
-    if (cached > 0) {
+    if (cached.first > 0) {
         // the choice was made on another matrix of the same shape: its group
         // tables are re-checked against the cap on this one
-        int rc = build_cussen_plan(A, m, n, bits, sgn, N, cached, out, threads);
-        if (rc || !over_cap(*out)) return rc;
-        return build_cussen_plan(A, m, n, bits, sgn, N, 1, out, threads);
+        int rc = build_cussen_plan(A, m, n, bits, sgn, N, cached.first, out, threads);
+        if (!rc && !over_cap(*out)) {
+            *split = cached.second;
+            return 0;
+        }
+        if (rc && cached.first == 1) return rc;
+        rc = build_cussen_plan(A, m, n, bits, sgn, N, 1, out, threads);
+        if (!rc) *split = best_split(*out, nullptr);
+        return rc;
     }
-    int best_g = 1;
+    int best_g = 1, best_s = 1;
     double best = 0;
     // a code keys g digits of 9 bits (entries up to 8 bits) or 17 bits (9..16
     // bits) into 64 bits, so wide entries allow at most 3 columns per group
@@ -887,15 +969,18 @@ int build_plan_cfg(const void *A, int m, int n, int bits, bool sgn, const pcmm_c
         int rc = build_cussen_plan(A, m, n, bits, sgn, N, g, &P, threads);
         if (rc && g == 1) return rc;
         if (rc || over_cap(P)) continue;  // a group too large for the plan's limits is no candidate
-        const double c = predicted_cost(P);
+        double c;
+        const int S = best_split(P, &c);
         if (g == 1 || c < best) {
             best = c;
             best_g = g;
+            best_s = S;
             *out = std::move(P);
         }
     }
+    *split = best_s;
     std::lock_guard<std::mutex> guard(g_tune_lock);
-    g_tune_cache[key] = best_g;
+    g_tune_cache[key] = {best_g, best_s};
     return 0;
 }
 
@@ -955,7 +1040,7 @@ bool level1_chains(const cussen_plan &P) {
     return true;
 }
 
-void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
+void make_geometry(job &G, const pcmm_cussen_cfg *cfg, int split) {
     const cussen_plan &P = G.P;
     const int m = P.m, l = G.l;
     const int emax = std::max(P.max_entries, 1);
@@ -988,21 +1073,14 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg) {
         while (W * 2 * 2 * l <= 64 && W * 2 * 4 <= avg_e) W *= 2;
         if (W >= 4) G.coop_w = W;
     }
-    // accumulation tile
+    // accumulation tile and the split of the inner dimension
     const int npairs = 2 * l;
-    // rows per tile: the fewest padded rows, the larger tile on ties (the
-    // wavefronts of a workgroup then gather from the same pairs' tables)
-    G.tm = 256;
-    for (int tm : {128, 64, 32})
-        if ((int64_t)(m + tm - 1) / tm * tm < (int64_t)(m + G.tm - 1) / G.tm * G.tm) G.tm = tm;
-    G.pp = 256 / G.tm;
-    G.tiles_x = (m + G.tm - 1) / G.tm;
-    G.tiles_y = (npairs + G.pp - 1) / G.pp;
-    const int64_t wg_base = (int64_t)G.tiles_x * G.tiles_y;
-    int S = cfg && cfg->k_split > 0 ? cfg->k_split : 1;
-    if (!(cfg && cfg->k_split > 0)) {
-        while (S < 64 && wg_base * S * 2 <= 2048 && (P.ngroups / (S * 2)) >= 4) S *= 2;
-    }
+    const acc_tiling t = acc_tiles(m, l);
+    G.tm = t.tm;
+    G.pp = t.pp;
+    G.tiles_x = t.tiles_x;
+    G.tiles_y = t.tiles_y;
+    int S = std::max(split, 1);
     while (S > 1 && (P.ngroups + S - 1) / S < 1) S /= 2;
     G.S = S;
     G.gps = P.ngroups > 0 ? (P.ngroups + S - 1) / S : 0;
@@ -1371,12 +1449,13 @@ pcmm_status build_plan(const pcmm_problem *probs, int count, pcmm_plan_s &pl) {
     auto work = [&](int i) {
         const pcmm_problem &q = probs[i];
         job &G = built[i];
-        rcs[i] = build_plan_cfg(q.A, q.m, q.n, q.bits, q.is_signed != 0, &q.cfg, &G.P, inner);
+        int split = 1;
+        rcs[i] = build_plan_cfg(q.A, q.m, q.n, q.l, q.bits, q.is_signed != 0, &q.cfg, &G.P, &split, inner);
         if (rcs[i]) return;
         G.index = i;
         G.l = q.l;
         G.c_form = q.c_form;
-        make_geometry(G, &q.cfg);
+        make_geometry(G, &q.cfg, split);
         if ((int64_t)q.m * q.l > 0 && q.n > 0) pack_codes(G, inner);
     };
     if (nthreads <= 1) {
@@ -1556,11 +1635,13 @@ extern "C" pcmm_status pcmm_cussen_plan_stats(const void *A, int32_t m, int32_t 
                                               pcmm_cussen_stats *stats) {
     if (!stats || !valid_cfg(cfg) || m < 0 || n < 0) return PCMM_EINVAL;
     job G;
-    int rc = build_plan_cfg(A, m, n, bits, is_signed != 0, cfg, &G.P, host_threads());
+    int split = 1;
+    // without output columns given, the tuner assumes a square problem (l = m)
+    int rc = build_plan_cfg(A, m, n, std::max(m, 1), bits, is_signed != 0, cfg, &G.P, &split, host_threads());
     if (rc == -2) return PCMM_ERANGE;
     if (rc) return PCMM_EINVAL;
     G.l = 1;
-    make_geometry(G, cfg);
+    make_geometry(G, cfg, split);
     fill_stats(G, stats);
     stats->k_split = 0;
     stats->lanes_per_chain = 0;

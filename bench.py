@@ -65,6 +65,20 @@ def load_traffic(workload):
     return d.get("hbm_bytes_per_launch")
 
 
+def load_table_traffic(workload):
+    """HBM bytes of one table stage (digit tables and combinations) from the
+    committed counter summary, or None if missing or taken on other source."""
+    path = os.path.join(ROOT, "profiles", f"table_{workload}_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_run")
+
+
 def cpu_baseline(sh, A, target_seconds, threads):
     """The CPU oracle's Cussen PC-MM on a bounded sample of output columns.
 
@@ -680,6 +694,18 @@ def main():
                 "kernel_ms": acc_ms, "mixed_adds_per_launch": madds,
                 "mads_per_mixed_add": MADS_MIXED_ADD}
 
+    # the table stage (digit tables, combinations): algorithmic bytes are
+    # every table entry written once (80 B) and B read once (128 B per
+    # ciphertext); it is latency- and traffic-bound rather than ALU-bound
+    tab_ms = stage["ms_table"]
+    tab_bytes = st0["table_entries"] * 2 * sh.l * 80 + sh.n * sh.l * 128
+    table_roofline = {"bound": "hbm", "kernels": ["table_build_kernel", "combo_table_kernel"],
+                      "achieved": tab_bytes / (tab_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": tab_bytes / (tab_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": load_table_traffic(sh.name),
+                      "algorithmic_bytes": tab_bytes, "stage_ms": tab_ms,
+                      "point_additions": st0["table_adds"] * 2 * sh.l,
+                      "point_additions_per_s": st0["table_adds"] * 2 * sh.l / (tab_ms * 1e-3)}
+
     out = {
         "metric": METRIC, "value": pcmm_per_s, "unit": "PC-MM/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -709,6 +735,7 @@ def main():
         "strassen": strassen,
         "speedup_cussen_vs_best_strassen": min(x["ms_per_step"] for x in strassen) / ms_step,
         "roofline": roofline,
+        "table_roofline": table_roofline,
         "device": dev,
     }
     if not args.no_field:

@@ -536,8 +536,15 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
             const plan_cblock blk = blocks[bi];
             entry_x xa[CB];
 #pragma unroll
-            for (int r = 0; r < CB; ++r)
-                if (r < blk.na) xa[r] = read_entry_x(tab + blk.a[r] * estride);
+            for (int r = 0; r < CB; ++r) {
+                if (r < blk.na) {
+                    xa[r] = read_entry_x(tab + blk.a[r] * estride);
+                } else {  // no such operand: an identity, never a chord
+                    xa[r].x0 = xa[r].x1 = make_uint4(0, 0, 0, 0);
+                    xa[r].x8 = 0;
+                    xa[r].inf = 1;
+                }
+            }
             plan_crun nr = runs[blk.run_begin];
             entry_x nxb = read_entry_x(tab + nr.b * estride);
             for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
@@ -553,18 +560,23 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
                 ((uint4 *)pslot)[0] = make_uint4(prod.v[0], prod.v[1], prod.v[2], prod.v[3]);
                 ((uint4 *)pslot)[1] = make_uint4(prod.v[4], prod.v[5], prod.v[6], prod.v[7]);
                 pslot[8] = prod.v[8];
+                // the run's product of dx first, then one product into the
+                // running chain (its critical path: one product per run)
+                const fe one = fe_one_mont();
+                fe t = one;
 #pragma unroll
                 for (int r = 0; r < CB; ++r) {
-                    if (run.dst[r] < 0) continue;
                     const fe dx = fe_sub(fe_of(xb), fe_of(xa[r]));
-                    const bool chord = (xa[r].inf | xb.inf) == 0 && !fe_is_zero(dx);
-                    if (chord) {
-                        prod = fe_mul_ilp(prod, dx);
-                    } else {
+                    const bool present = run.dst[r] >= 0;
+                    const bool chord = present && (xa[r].inf | xb.inf) == 0 && !fe_is_zero(dx);
+                    if (present && !chord) {
                         tab[run.dst[r] * estride + ENTRY_INF] = ENTRY_PENDING;
                         pending = true;
                     }
+                    const fe f = fe_select(chord, one, dx);
+                    t = r == 0 ? f : fe_mul_ilp(t, f);
                 }
+                prod = fe_mul_ilp(prod, t);
             }
         }
         fe inv = fe_inv(prod);
@@ -574,8 +586,15 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
             apt A[CB];
             bool ainf[CB];
 #pragma unroll
-            for (int r = 0; r < CB; ++r)
-                if (r < blk.na) A[r] = read_entry(tab + blk.a[r] * estride, ainf[r]);
+            for (int r = 0; r < CB; ++r) {
+                if (r < blk.na) {
+                    A[r] = read_entry(tab + blk.a[r] * estride, ainf[r]);
+                } else {  // no such operand: an identity, never a chord
+                    A[r].x = fe_zero();
+                    A[r].y = fe_zero();
+                    ainf[r] = true;
+                }
+            }
             plan_crun nr = runs[blk.run_end - 1];
             bool nbinf;
             apt nb = read_entry(tab + nr.b * estride, nbinf);
@@ -591,31 +610,35 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
                 while (run.dst[first] < 0) ++first;
                 const uint32_t *pslot = tab + run.dst[first] * estride;
                 const uint4 p0 = ((const uint4 *)pslot)[0], p1 = ((const uint4 *)pslot)[1];
-                // the prefix before each combination of the run (dx is
-                // formed again below: registers are tight)
-                fe q[CB];
+                // the prefix before each combination of the run, then every
+                // combination's 1/dx (newest first, the inverse chain), then
+                // the chord sums; branch-free, so the run's independent
+                // chains interleave (the rare non-chord slots compute
+                // discarded values and are not stored)
+                const fe one = fe_one_mont();
+                fe q[CB], dx[CB], dinv[CB];
                 bool chord[CB];
                 fe cur = {{p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, pslot[8]}};
 #pragma unroll
                 for (int r = 0; r < CB; ++r) {
-                    chord[r] = false;
-                    if (run.dst[r] < 0) continue;
-                    const fe dx = fe_sub(Bv.x, A[r].x);
-                    chord[r] = !ainf[r] && !binf && !fe_is_zero(dx);
+                    dx[r] = fe_sub(Bv.x, A[r].x);
+                    chord[r] = run.dst[r] >= 0 && !ainf[r] && !binf && !fe_is_zero(dx[r]);
                     q[r] = cur;
-                    if (chord[r] && r + 1 < CB) cur = fe_mul_ilp(cur, dx);
+                    if (r + 1 < CB) cur = fe_mul_ilp(cur, fe_select(chord[r], one, dx[r]));
                 }
 #pragma unroll
                 for (int r = CB - 1; r >= 0; --r) {
-                    if (!chord[r]) continue;
-                    const fe dinv = fe_mul_ilp(inv, q[r]);
-                    inv = fe_mul_ilp(inv, fe_sub(Bv.x, A[r].x));
+                    dinv[r] = fe_mul_ilp(inv, q[r]);
+                    inv = fe_mul_ilp(inv, fe_select(chord[r], one, dx[r]));
+                }
+#pragma unroll
+                for (int r = 0; r < CB; ++r) {
                     const fe by = ((run.neg >> r) & 1) ? fe_neg(Bv.y) : Bv.y;
-                    const fe lam = fe_mul_ilp(fe_sub(by, A[r].y), dinv);
+                    const fe lam = fe_mul_ilp(fe_sub(by, A[r].y), dinv[r]);
                     apt R;
                     R.x = fe_sub_sub(fe_sqr_ilp(lam), A[r].x, Bv.x);
                     R.y = fe_sub(fe_mul_ilp(lam, fe_sub_w(A[r].x, R.x)), A[r].y);
-                    write_entry(tab + run.dst[r] * estride, R, false);
+                    if (chord[r]) write_entry(tab + run.dst[r] * estride, R, false);
                 }
             }
         }

@@ -231,7 +231,12 @@ pcmm_status pcmm_cussen_static(const void *A, int32_t m, int32_t n, int32_t bits
  * few kernels whatever the number of problems: one table build over all
  * problems, one persistent accumulation kernel whose workgroups take
  * (problem, row tile, pair tile, split) tiles from a device queue, one
- * split-k reduction and one affine normalisation.  The plan's host image
+ * split-k reduction and one affine normalisation.  When the problems' tables
+ * and partial sums together exceed 14 GB, the problems are packed into
+ * phases of at most that size (first fit, largest first; a larger problem
+ * is a phase of its own) that run those kernels one after another on one
+ * shared workspace region, so the workspace is the largest phase's, not the
+ * sum.  The plan's host image
  * (plans and per-problem geometry) is immutable after creation and is copied
  * to the workspace at the start of every run, so a run can be captured into
  * a hipGraph and replayed (the matrices and workspace are those given at
@@ -263,7 +268,9 @@ pcmm_status pcmm_plan_stats(pcmm_plan plan, int32_t index, pcmm_cussen_stats *st
  * C[i] (m_i x l_i, the problem's c_form) are host arrays of `count` matrix
  * descriptors of device memory; B[i] and C[i] must not alias.  stage_events:
  * NULL or PCMM_STAGE_EVENTS caller-owned events recorded at the stage
- * boundaries (as in pcmm_cussen_cfg).  Queues the work on `stream` and
+ * boundaries (as in pcmm_cussen_cfg; with several phases the events after
+ * the upload bracket the last phase's stages, and the earlier phases fall
+ * in the table stage).  Queues the work on `stream` and
  * returns without waiting.  Runs that overlap on one workspace race. */
 pcmm_status pcmm_plan_run(pcmm_plan plan, const pcmm_mat *B, pcmm_mat *C, void *workspace,
                           size_t ws_bytes, void **stage_events, void *stream);

@@ -89,7 +89,8 @@ struct io_ptrs {
 };
 
 struct run_args {
-    char *ws;            // workspace; the run's descriptors start here
+    char *ws;            // workspace (w_* offsets)
+    const char *desc;    // this launch's descriptors (in the workspace)
     const char *plan;    // base of the plan arrays (o_* offsets): the workspace, or a resident copy
     int32_t count;       // descriptors
     int32_t pad;
@@ -98,7 +99,7 @@ struct run_args {
     io_ptrs io[MAX_PROBLEMS];
 };
 
-__device__ __forceinline__ const prob_desc *descs(const run_args &a) { return (const prob_desc *)a.ws; }
+__device__ __forceinline__ const prob_desc *descs(const run_args &a) { return (const prob_desc *)a.desc; }
 
 // last problem whose prefix value (the int64 at byte offset key_off of its
 // descriptor) is <= x; problems with empty ranges are skipped by construction
@@ -1210,16 +1211,30 @@ void pack_codes(job &G, int threads) {
 
 namespace {
 
-// What a run queues: descriptors copied to the start of the workspace, the
-// accumulation queue counter after them, then the problems' regions.
-struct run_layout {
-    int32_t count = 0;  // descriptors
-    size_t copy_bytes = 0, ctr_off = 0, ws_bytes = 256;
+// One phase of a run: a subset of its problems, queued as table build,
+// combinations, persistent accumulation, reduction and normalisation; the
+// phases of a run reuse one workspace region one after another.
+struct run_phase {
+    int32_t count = 0;    // descriptors
+    size_t desc_off = 0;  // byte offset of the phase's descriptors in the workspace
     int64_t tb_blocks = 0, cb_blocks = 0, tiles = 0, red_blocks = 0, norm_blocks = 0;
     int acc_grid = 0;
-    bool coop = false;  // some problem's tables are built by coop_table_kernel
+    bool coop = false;    // some problem's tables are built by coop_table_kernel
+};
+
+// What a run queues: the image (descriptor blocks, plan arrays) copied to the
+// start of the workspace, the accumulation queue counter after it, then the
+// problems' regions.
+struct run_layout {
+    std::vector<run_phase> phases;  // empty: no GPU work
+    size_t copy_bytes = 0, ctr_off = 0, ws_bytes = 256;
     std::vector<int> fills;  // run indices whose inner dimension is empty (identity outputs)
 };
+
+// A run whose problems together need more workspace than this is split into
+// phases (first fit by decreasing footprint); a problem larger than the
+// limit is a phase of its own.
+constexpr size_t PHASE_WORKSPACE_LIMIT = (size_t)14000000000ull;
 
 // pinned staging for descriptor blocks of selected runs; an event guards reuse
 struct stage_slot {
@@ -1275,122 +1290,174 @@ void fill_stats(const job &G, pcmm_cussen_stats *st) {
 }
 
 // Lays out descriptors, plan image and workspace regions of the plan's jobs,
-// and sizes the grids of the non-persistent kernels.
+// and sizes the grids of the non-persistent kernels.  Jobs are packed into
+// phases of at most PHASE_WORKSPACE_LIMIT bytes of regions each (first fit,
+// largest footprint first); within a phase the most expensive accumulation
+// tiles come first (the queue hands them out in order).
 pcmm_status finish_plan(pcmm_plan_s &pl) {
-    // most expensive accumulation tiles first (the queue hands them out in order)
-    std::stable_sort(pl.jobs.begin(), pl.jobs.end(),
-                     [](const job &x, const job &y) { return x.tile_cost > y.tile_cost; });
     const size_t nd = pl.jobs.size();
-    size_t img = align256(nd * sizeof(prob_desc));
+    std::vector<size_t> phase_of(nd, 0);
+    size_t nphases = nd ? 1 : 0;
+    {
+        size_t total = 0;
+        for (const job &G : pl.jobs) total += G.footprint;
+        if (total > PHASE_WORKSPACE_LIMIT) {
+            std::vector<size_t> idx(nd);
+            for (size_t k = 0; k < nd; ++k) idx[k] = k;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](size_t x, size_t y) { return pl.jobs[x].footprint > pl.jobs[y].footprint; });
+            std::vector<size_t> used;
+            for (size_t k : idx) {
+                size_t p = 0;
+                while (p < used.size() && used[p] + pl.jobs[k].footprint > PHASE_WORKSPACE_LIMIT) ++p;
+                if (p == used.size()) used.push_back(0);
+                used[p] += pl.jobs[k].footprint;
+                phase_of[k] = p;
+            }
+            nphases = used.size();
+        }
+    }
+    // execution order: by phase, then most expensive accumulation tiles first
+    {
+        std::vector<size_t> order(nd);
+        for (size_t k = 0; k < nd; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            if (phase_of[x] != phase_of[y]) return phase_of[x] < phase_of[y];
+            return pl.jobs[x].tile_cost > pl.jobs[y].tile_cost;
+        });
+        std::vector<job> jobs;
+        std::vector<size_t> ph;
+        jobs.reserve(nd);
+        for (size_t k : order) {
+            jobs.push_back(std::move(pl.jobs[k]));
+            ph.push_back(phase_of[k]);
+        }
+        pl.jobs = std::move(jobs);
+        phase_of = std::move(ph);
+    }
+    run_layout &L = pl.full;
+    L.phases.assign(nphases, run_phase{});
+    size_t img = 0;
+    for (size_t p = 0; p < nphases; ++p) {
+        size_t cnt = 0;
+        for (size_t k = 0; k < nd; ++k) cnt += phase_of[k] == p;
+        L.phases[p].count = (int32_t)cnt;
+        L.phases[p].desc_off = img;
+        img += align256(cnt * sizeof(prob_desc));
+    }
     std::vector<prob_desc> D(nd);
     for (size_t k = 0; k < nd; ++k) {
         const job &G = pl.jobs[k];
         D[k] = prob_desc{};
-        D[k].o_ops = (int64_t)img;
-        img += align256(G.P.ops.size() * sizeof(plan_op));
-        D[k].o_unit_col = (int64_t)img;
-        img += align256(G.P.unit_col.size() * 4);
-        D[k].o_unit_grp = (int64_t)img;
-        img += align256(G.P.unit_grp.size() * 4);
-        D[k].o_unit_off = (int64_t)img;
-        img += align256(G.P.unit_off.size() * 4);
-        D[k].o_cblock_begin = (int64_t)img;
-        img += align256(G.P.cblock_begin.size() * 4);
-        D[k].o_cblocks = (int64_t)img;
-        img += align256(G.P.cblocks.size() * sizeof(plan_cblock));
-        D[k].o_cruns = (int64_t)img;
-        img += align256(G.P.cruns.size() * sizeof(plan_crun));
-        D[k].o_op_begin = (int64_t)img;
-        img += align256(G.P.op_begin.size() * 4);
-        D[k].o_entry_begin = (int64_t)img;
-        img += align256(G.P.entry_begin.size() * 4);
-        D[k].o_entries = (int64_t)img;
-        img += align256(G.P.entries.size() * 2);
-        D[k].o_lists = (int64_t)img;
-        img += align256(G.lists.size() * 4);
-        D[k].o_chunk_off = (int64_t)img;
-        img += align256(G.chunk_off.size() * 8);
-        D[k].o_chunk_len = (int64_t)img;
-        img += align256(G.chunk_len.size() * 4);
+        auto arr = [&](int64_t &off, size_t bytes) {
+            off = (int64_t)img;
+            img += align256(bytes);
+        };
+        arr(D[k].o_ops, G.P.ops.size() * sizeof(plan_op));
+        arr(D[k].o_unit_col, G.P.unit_col.size() * 4);
+        arr(D[k].o_unit_grp, G.P.unit_grp.size() * 4);
+        arr(D[k].o_unit_off, G.P.unit_off.size() * 4);
+        arr(D[k].o_cblock_begin, G.P.cblock_begin.size() * 4);
+        arr(D[k].o_cblocks, G.P.cblocks.size() * sizeof(plan_cblock));
+        arr(D[k].o_cruns, G.P.cruns.size() * sizeof(plan_crun));
+        arr(D[k].o_op_begin, G.P.op_begin.size() * 4);
+        arr(D[k].o_entry_begin, G.P.entry_begin.size() * 4);
+        arr(D[k].o_entries, G.P.entries.size() * 2);
+        arr(D[k].o_lists, G.lists.size() * 4);
+        arr(D[k].o_chunk_off, G.chunk_off.size() * 8);
+        arr(D[k].o_chunk_len, G.chunk_len.size() * 4);
     }
-    run_layout &L = pl.full;
-    L.count = (int32_t)nd;
-    L.coop = false;
     L.copy_bytes = img;
     L.ctr_off = img;
-    size_t ws = img + 256;
-    int64_t tb = 0, cbb = 0, tiles = 0, red = 0, norm = 0;
-    const bool pad = pad_run(nd, [&](size_t q) -> const job & { return pl.jobs[q]; });
-    for (size_t k = 0; k < nd; ++k) {
-        const job &G = pl.jobs[k];
-        prob_desc &d = D[k];
-        const bool pad_k = pad && G.Lj_pad;
-        d.m = G.P.m;
-        d.n = G.P.n;
-        d.l = G.l;
-        d.g = G.P.g;
-        d.ngroups = G.P.ngroups;
-        d.emax = std::max(G.P.max_entries, 1);
-        d.rmax = std::max(G.P.max_regs, 1);
-        d.c_form = G.c_form;
-        d.J = G.J;
-        d.Lj = pad_k ? G.Lj_pad : G.Lj;
-        d.coop_w = pad_k ? G.coop_w : 0;
-        if (d.coop_w > 1) L.coop = true;
-        d.tm = G.tm;
-        d.pp = G.pp;
-        d.kc = G.kc;
-        d.S = G.S;
-        d.gps = G.gps;
-        d.io = G.index;
-        d.tiles_x = G.tiles_x;
-        d.tiles_y = G.tiles_y;
-        d.norm_per = G.norm_per;
-        d.chunks_per_split = G.chunks_per_split;
-        d.n_lanes = pad_k ? G.n_lanes_pad : G.n_lanes;
-        d.nunits = G.P.nunits;
-        d.levels = G.P.max_levels;
-        d.tb_block0 = tb;
-        tb += (d.n_lanes + 255) / 256;
-        d.cb_lanes = G.cb_lanes;
-        d.cb_block0 = cbb;
-        cbb += (G.cb_lanes + 255) / 256;
-        d.tile0 = tiles;
-        tiles += (int64_t)G.tiles_x * G.tiles_y * G.S;
-        d.red_block0 = red;
-        d.red_threads = G.S > 1 ? (2 * (int64_t)G.P.m * G.l * std::min(G.S, REDUCE_LANES) + 255) / 256 * 256 : 0;
-        red += d.red_threads / 256;
-        d.norm_block0 = norm;
-        d.norm_threads = G.norm_threads;
-        norm += G.norm_threads / 256;
-        d.ldj = G.ldj;
-        d.ld_pre = G.ld_pre;
-        d.w_regs = (int64_t)ws;
-        ws += align256(pad_k ? G.regs_bytes_pad : G.regs_bytes);
-        d.w_table = (int64_t)ws;
-        ws += align256(G.table_bytes);
-        d.w_part = (int64_t)ws;
-        ws += align256(G.part_bytes);
-        d.w_cjac = (int64_t)ws;
-        ws += align256(G.cjac_bytes);
-        d.w_norm = (int64_t)ws;
-        ws += align256(G.norm_bytes);
+    const size_t base = img + 256;  // every phase's regions start here
+    size_t ws_end = base;
+    for (size_t p = 0; p < nphases; ++p) {
+        run_phase &ph = L.phases[p];
+        size_t ws = base;
+        int64_t tb = 0, cbb = 0, tiles = 0, red = 0, norm = 0;
+        std::vector<size_t> ks;
+        for (size_t k = 0; k < nd; ++k)
+            if (phase_of[k] == p) ks.push_back(k);
+        const bool pad = pad_run(ks.size(), [&](size_t q) -> const job & { return pl.jobs[ks[q]]; });
+        for (size_t k : ks) {
+            const job &G = pl.jobs[k];
+            prob_desc &d = D[k];
+            const bool pad_k = pad && G.Lj_pad;
+            d.m = G.P.m;
+            d.n = G.P.n;
+            d.l = G.l;
+            d.g = G.P.g;
+            d.ngroups = G.P.ngroups;
+            d.emax = std::max(G.P.max_entries, 1);
+            d.rmax = std::max(G.P.max_regs, 1);
+            d.c_form = G.c_form;
+            d.J = G.J;
+            d.Lj = pad_k ? G.Lj_pad : G.Lj;
+            d.coop_w = pad_k ? G.coop_w : 0;
+            if (d.coop_w > 1) ph.coop = true;
+            d.tm = G.tm;
+            d.pp = G.pp;
+            d.kc = G.kc;
+            d.S = G.S;
+            d.gps = G.gps;
+            d.io = G.index;
+            d.tiles_x = G.tiles_x;
+            d.tiles_y = G.tiles_y;
+            d.norm_per = G.norm_per;
+            d.chunks_per_split = G.chunks_per_split;
+            d.n_lanes = pad_k ? G.n_lanes_pad : G.n_lanes;
+            d.nunits = G.P.nunits;
+            d.levels = G.P.max_levels;
+            d.tb_block0 = tb;
+            tb += (d.n_lanes + 255) / 256;
+            d.cb_lanes = G.cb_lanes;
+            d.cb_block0 = cbb;
+            cbb += (G.cb_lanes + 255) / 256;
+            d.tile0 = tiles;
+            tiles += (int64_t)G.tiles_x * G.tiles_y * G.S;
+            d.red_block0 = red;
+            d.red_threads = G.S > 1 ? (2 * (int64_t)G.P.m * G.l * std::min(G.S, REDUCE_LANES) + 255) / 256 * 256 : 0;
+            red += d.red_threads / 256;
+            d.norm_block0 = norm;
+            d.norm_threads = G.norm_threads;
+            norm += G.norm_threads / 256;
+            d.ldj = G.ldj;
+            d.ld_pre = G.ld_pre;
+            d.w_regs = (int64_t)ws;
+            ws += align256(pad_k ? G.regs_bytes_pad : G.regs_bytes);
+            d.w_table = (int64_t)ws;
+            ws += align256(G.table_bytes);
+            d.w_part = (int64_t)ws;
+            ws += align256(G.part_bytes);
+            d.w_cjac = (int64_t)ws;
+            ws += align256(G.cjac_bytes);
+            d.w_norm = (int64_t)ws;
+            ws += align256(G.norm_bytes);
+        }
+        ph.tb_blocks = tb;
+        ph.cb_blocks = cbb;
+        ph.tiles = tiles;
+        ph.red_blocks = red;
+        ph.norm_blocks = norm;
+        ws_end = std::max(ws_end, ws);
+        if (tb > 0x7FFFFFFF || cbb > 0x7FFFFFFF || red > 0x7FFFFFFF || norm > 0x7FFFFFFF ||
+            tiles > 0x7FFFFFFF - (1 << 20))
+            return PCMM_EINVAL;
     }
-    L.ws_bytes = ws + 256;
-    L.tb_blocks = tb;
-    L.cb_blocks = cbb;
-    L.tiles = tiles;
-    L.red_blocks = red;
-    L.norm_blocks = norm;
+    L.ws_bytes = ws_end + 256;
     pl.desc = D;
     for (size_t k = 0; k < nd; ++k) pl.stats[pl.jobs[k].index].coop_lanes = D[k].coop_w;
     pl.job_of.assign(pl.count, -1);
     for (size_t k = 0; k < nd; ++k) pl.job_of[pl.jobs[k].index] = (int)k;
-    if (tb > 0x7FFFFFFF || cbb > 0x7FFFFFFF || red > 0x7FFFFFFF || norm > 0x7FFFFFFF ||
-        tiles > 0x7FFFFFFF - (1 << 20))
-        return PCMM_EINVAL;
     pl.image.assign(img, 0);
-    memcpy(pl.image.data(), D.data(), nd * sizeof(prob_desc));
+    {
+        size_t k0 = 0;
+        for (size_t p = 0; p < nphases; ++p) {
+            const size_t cnt = (size_t)L.phases[p].count;
+            memcpy(pl.image.data() + L.phases[p].desc_off, D.data() + k0, cnt * sizeof(prob_desc));
+            k0 += cnt;
+        }
+    }
     for (size_t k = 0; k < nd; ++k) {
         const cussen_plan &P = pl.jobs[k].P;
         auto put = [&](int64_t off, const void *src, size_t bytes) {
@@ -1417,27 +1484,25 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
 std::mutex g_occ_lock;
 std::map<int, int64_t> g_occ_cache;  // device -> resident workgroups
 
-// Sizes the persistent accumulation grid of L on `device` (current): the
-// workgroups that fit on the device at once, or the tiles if fewer.
+// Sizes the persistent accumulation grid of each phase of L on `device`
+// (current): the workgroups that fit on the device at once, or the phase's
+// tiles if fewer.
 pcmm_status size_acc_grid(int device, run_layout &L) {
-    L.acc_grid = 0;
-    if (L.tiles == 0) return PCMM_OK;
-    const int key = device;
     int64_t cap = 0;
     {
         std::lock_guard<std::mutex> guard(g_occ_lock);
-        auto it = g_occ_cache.find(key);
+        auto it = g_occ_cache.find(device);
         if (it != g_occ_cache.end()) cap = it->second;
     }
-    if (cap == 0) {
+    if (cap == 0 && !L.phases.empty()) {
         int per_cu = 0, cus = 0;
         PCMM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, accumulate_kernel, 256, 0));
         PCMM_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
         cap = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
         std::lock_guard<std::mutex> guard(g_occ_lock);
-        g_occ_cache[key] = cap;
+        g_occ_cache[device] = cap;
     }
-    L.acc_grid = (int)std::min<int64_t>(L.tiles, cap);
+    for (run_phase &ph : L.phases) ph.acc_grid = (int)std::min<int64_t>(ph.tiles, cap);
     return PCMM_OK;
 }
 
@@ -1526,9 +1591,11 @@ pcmm_status check_mats(int m, int n, int l, int c_form, const pcmm_mat *B, const
 
 // Queues a run: copies L.copy_bytes from the pinned host block copy_src
 // (unchanged until the copy has executed) to the start of the workspace, then
-// the kernels.  plan_base: device base of the plan arrays, or null for the
-// workspace itself.  B, C: the run's n_io matrices.  ev: PCMM_STAGE_EVENTS
-// events or null.
+// the kernels of each phase.  plan_base: device base of the plan arrays, or
+// null for the workspace itself.  B, C: the run's n_io matrices.  ev:
+// PCMM_STAGE_EVENTS events or null (with several phases the stage events
+// after the upload bracket the last phase; the earlier phases count as table
+// stage).
 pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *plan_base, const pcmm_mat *B,
                         pcmm_mat *C, int n_io, void *workspace, hipEvent_t *ev, hipStream_t s,
                         hipEvent_t copied) {
@@ -1541,14 +1608,12 @@ pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *p
     do {                                         \
         if ((st = rec(i)) != PCMM_OK) return st; \
     } while (0)
-    const bool gpu_work = L.count > 0;
+    const bool gpu_work = !L.phases.empty();
     PCMM_REC(0);
     run_args ra{};
     if (gpu_work) {
         ra.ws = (char *)workspace;
         ra.plan = plan_base ? plan_base : (const char *)workspace;
-        ra.count = L.count;
-        ra.total_tiles = L.tiles;
         ra.ctr_off = (int64_t)L.ctr_off;
         for (int i = 0; i < n_io; ++i) ra.io[i] = io_ptrs{B[i].d, C[i].d, B[i].ld, C[i].ld};
         PCMM_HIP_TRY(hipMemcpyAsync(workspace, copy_src, L.copy_bytes, hipMemcpyHostToDevice, s));
@@ -1557,32 +1622,42 @@ pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *p
     // kernels below still run
     if (copied) PCMM_HIP_TRY(hipEventRecord(copied, s));
     PCMM_REC(1);
-    if (gpu_work) {
-        hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)L.tb_blocks), dim3(256), 0, s, ra);
+    const size_t nph = L.phases.size();
+    for (size_t p = 0; p < nph; ++p) {
+        const run_phase &ph = L.phases[p];
+        const bool last = p + 1 == nph;
+        ra.desc = (const char *)workspace + ph.desc_off;
+        ra.count = ph.count;
+        ra.total_tiles = ph.tiles;
+        // the table build also resets the accumulation's tile counter
+        hipLaunchKernelGGL(table_build_kernel, dim3((unsigned)ph.tb_blocks), dim3(256), 0, s, ra);
         PCMM_LAUNCH_CHECK();
-        if (L.coop) {
-            hipLaunchKernelGGL(coop_table_kernel, dim3((unsigned)L.tb_blocks), dim3(256), 0, s, ra);
+        if (ph.coop) {
+            hipLaunchKernelGGL(coop_table_kernel, dim3((unsigned)ph.tb_blocks), dim3(256), 0, s, ra);
             PCMM_LAUNCH_CHECK();
         }
-        if (L.cb_blocks > 0) {
-            hipLaunchKernelGGL(combo_table_kernel, dim3((unsigned)L.cb_blocks), dim3(256), 0, s, ra);
+        if (ph.cb_blocks > 0) {
+            hipLaunchKernelGGL(combo_table_kernel, dim3((unsigned)ph.cb_blocks), dim3(256), 0, s, ra);
+            PCMM_LAUNCH_CHECK();
+        }
+        if (last) PCMM_REC(2);
+        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)ph.acc_grid), dim3(256), 0, s, ra);
+        PCMM_LAUNCH_CHECK();
+        if (last) PCMM_REC(3);
+        if (ph.red_blocks > 0) {
+            hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)ph.red_blocks), dim3(256), 0, s, ra);
+            PCMM_LAUNCH_CHECK();
+        }
+        if (last) PCMM_REC(4);
+        if (ph.norm_blocks > 0) {
+            hipLaunchKernelGGL(normalize_batch_kernel, dim3((unsigned)ph.norm_blocks), dim3(256), 0, s, ra);
             PCMM_LAUNCH_CHECK();
         }
     }
-    PCMM_REC(2);
-    if (gpu_work) {
-        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)L.acc_grid), dim3(256), 0, s, ra);
-        PCMM_LAUNCH_CHECK();
-    }
-    PCMM_REC(3);
-    if (L.red_blocks > 0) {
-        hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)L.red_blocks), dim3(256), 0, s, ra);
-        PCMM_LAUNCH_CHECK();
-    }
-    PCMM_REC(4);
-    if (L.norm_blocks > 0) {
-        hipLaunchKernelGGL(normalize_batch_kernel, dim3((unsigned)L.norm_blocks), dim3(256), 0, s, ra);
-        PCMM_LAUNCH_CHECK();
+    if (!gpu_work) {
+        PCMM_REC(2);
+        PCMM_REC(3);
+        PCMM_REC(4);
     }
     for (int i : L.fills) {
         const int64_t n_out = (int64_t)C[i].rows * C[i].cols;
@@ -1702,7 +1777,7 @@ extern "C" pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t 
     pcmm_status st = build_plan(&q, 1, pl);
     if (st != PCMM_OK) return st;
     if (stats) *stats = pl.stats[0];
-    st = check_run(pl, nullptr, 1, B, C, workspace, ws_bytes, pl.full.ws_bytes, pl.full.count > 0);
+    st = check_run(pl, nullptr, 1, B, C, workspace, ws_bytes, pl.full.ws_bytes, !pl.full.phases.empty());
     if (st != PCMM_OK) return st;
     st = bind_device(pl);
     if (st != PCMM_OK) return st;
@@ -1796,7 +1871,7 @@ extern "C" pcmm_status pcmm_cussen_static(const void *A, int32_t m, int32_t n, i
     pcmm_status st = build_plan(&q, 1, pl);
     if (st != PCMM_OK) return st;
     if (stats) *stats = pl.stats[0];
-    const bool gpu_work = pl.full.count > 0;
+    const bool gpu_work = !pl.full.phases.empty();
     // the size check comes before any device call
     if (gpu_work && pl.full.ws_bytes > (size_t)PCMM_STATIC_SCRATCH_BYTES) return PCMM_ETOOLARGE;
     st = check_mats(m, n, B->cols, C->form, B, C);
@@ -1865,7 +1940,7 @@ extern "C" pcmm_status pcmm_plan_run(pcmm_plan plan, const pcmm_mat *B, pcmm_mat
     PCMM_HIP_TRY(hipGetDevice(&dev));
     if (dev != plan->device) return PCMM_EDEVICE;
     pcmm_status st = check_run(*plan, nullptr, plan->count, B, C, workspace, ws_bytes, plan->full.ws_bytes,
-                               plan->full.count > 0);
+                               !plan->full.phases.empty());
     if (st != PCMM_OK) return st;
     hipEvent_t ev[PCMM_STAGE_EVENTS] = {};
     if (stage_events) {
@@ -1897,7 +1972,11 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         return pl.jobs[pl.job_of[which[x]]].tile_cost > pl.jobs[pl.job_of[which[y]]].tile_cost;
     });
     const size_t nd = order.size();
-    L.count = (int32_t)nd;
+    if (nd > 0) L.phases.assign(1, run_phase{});
+    run_phase dummy;
+    run_phase &ph = nd > 0 ? L.phases[0] : dummy;
+    ph.count = (int32_t)nd;
+    ph.desc_off = 0;
     L.copy_bytes = align256(nd * sizeof(prob_desc));
     L.ctr_off = L.copy_bytes;
     size_t ws = L.ctr_off + 256;
@@ -1912,7 +1991,7 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         const bool pad_k = pad && G.Lj_pad;
         d.Lj = pad_k ? G.Lj_pad : G.Lj;
         d.coop_w = pad_k ? G.coop_w : 0;
-        if (d.coop_w > 1) L.coop = true;
+        if (d.coop_w > 1) ph.coop = true;
         d.n_lanes = pad_k ? G.n_lanes_pad : G.n_lanes;
         d.io = r;
         d.tb_block0 = tb;
@@ -1938,11 +2017,11 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         D[q] = d;
     }
     L.ws_bytes = ws + 256;
-    L.tb_blocks = tb;
-    L.cb_blocks = cbb;
-    L.tiles = tiles;
-    L.red_blocks = red;
-    L.norm_blocks = norm;
+    ph.tb_blocks = tb;
+    ph.cb_blocks = cbb;
+    ph.tiles = tiles;
+    ph.red_blocks = red;
+    ph.norm_blocks = norm;
     return PCMM_OK;
 }
 
@@ -1990,7 +2069,7 @@ extern "C" pcmm_status pcmm_plan_run_selected(pcmm_plan plan, const int32_t *whi
     std::vector<prob_desc> D;
     pcmm_status st = selected_layout(*plan, which, k, L, D);
     if (st != PCMM_OK) return st;
-    st = check_run(*plan, which, k, B, C, workspace, ws_bytes, L.ws_bytes, L.count > 0);
+    st = check_run(*plan, which, k, B, C, workspace, ws_bytes, L.ws_bytes, !L.phases.empty());
     if (st != PCMM_OK) return st;
     hipEvent_t ev[PCMM_STAGE_EVENTS] = {};
     if (stage_events) {

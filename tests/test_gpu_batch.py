@@ -2,7 +2,8 @@
 uniform in 32..512, A unsigned with bit-width uniform over 1, 2, 4, 8,
 ciphertexts of uniform 8-bit messages; seed 4) compiled into one plan and run
 as one table build, one persistent accumulation, one reduction and one
-normalisation.
+normalisation per phase (the plan packs the problems into phases of at most
+14 GB of workspace).
 
 Every output is a unique group element (Alg. 3 ENSURE), so the bar is bit-exact
 equality of canonical affine bytes.  For every problem: the autotuned plan and
@@ -22,6 +23,7 @@ from paper_2504_14497_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 HOST_THREADS = 16
+PHASE_LIMIT = 14_000_000_000  # bytes of regions per phase of a compiled plan
 
 
 @pytest.fixture(scope="module")
@@ -53,6 +55,12 @@ def test_uneven_batch_at_real_shapes_matches_oracle(dev, orc):
     g1 = dev.Plan([(A, sh.bits, sh.l, dev.AFFINE, dev.cussen_cfg(4, 1)) for A, sh in zip(As, bw.shapes)])
     groups = [auto.stats(k)["group"] for k in range(len(bw.shapes))]
     log("batch: autotuned groups", groups)
+    # the problems' regions add up to far more than one phase may hold, so the
+    # run goes in phases whose workspace is the largest phase's (plus the image)
+    for plan in (auto, g1):
+        total = sum(plan.stats(k)["workspace_bytes"] for k in range(len(bw.shapes)))
+        assert total > PHASE_LIMIT
+        assert plan.workspace_bytes() <= PHASE_LIMIT + (64 << 20), (plan.workspace_bytes(), total)
     ws = torch.empty(max(auto.workspace_bytes(), g1.workspace_bytes()), dtype=torch.uint8, device="cuda")
     log("batch: run the autotuned plan, workspace", ws.numel())
     C_auto = auto.outputs()

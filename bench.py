@@ -618,9 +618,12 @@ def main():
     stats = []
     torch.cuda.synchronize()
     t_wall = time.time()
+    host_ms = []
     e0.record(stream)
     for k in range(args.steps):
+        t_call = time.perf_counter()
         _, st = pcmm.cussen(A, sh.bits, B, cfg=step_cfgs[k], workspace=ws, out=C)
+        host_ms.append((time.perf_counter() - t_call) * 1e3)
         stats.append(st)
     e1.record(stream)
     torch.cuda.synchronize()
@@ -634,6 +637,10 @@ def main():
                   + 2 * sh.m * sh.l * (sh.n - 1))
     executed_adds = 2 * sh.l * (st0["table_adds"] + st0["accum_adds"])
     step_gpu_ms = [evs[0].elapsed_time(evs[-1]) for evs in step_events]
+    # device idle before each step (from the previous step's end, or from the
+    # timed region's start): host planning that the queue did not hide
+    idle_ms = [e0.elapsed_time(step_events[0][0])] + [
+        step_events[k][-1].elapsed_time(step_events[k + 1][0]) for k in range(args.steps - 1)]
     names = ("ms_upload", "ms_table", "ms_accumulate", "ms_reduce", "ms_normalize")
     stage = {k: float(np.mean([evs[i].elapsed_time(evs[i + 1]) for evs in step_events]))
              for i, k in enumerate(names)}
@@ -723,6 +730,8 @@ def main():
         "stage_ms": stage,
         "step_gpu_ms": {"median": float(np.median(step_gpu_ms)), "min": float(np.min(step_gpu_ms)),
                         "max": float(np.max(step_gpu_ms))},
+        "idle_ms_before_step": [round(x, 3) for x in idle_ms],
+        "host_ms_per_call": [round(x, 3) for x in host_ms],
         "cached_plan": {"value": 1000.0 / ms_cached, "unit": "PC-MM/s", "ms_per_step": ms_cached,
                         "same_output": cached_same},
         "autotuned_group": tuned["group"],

@@ -192,9 +192,10 @@ size_t pcmm_schoolbook_workspace(int32_t m, int32_t n, int32_t l, int32_t c_form
  * pcmm_schoolbook plus cfg (NULL = defaults) and a workspace of
  * pcmm_cussen_workspace() bytes (plan, tables, partial sums).  stats may be
  * NULL; when given it receives the plan's operation counts.  The plan is
- * built on host threads and copied through a per-device pinned buffer: the
- * call may block until the previous call's copy (not its kernels) has
- * executed, so consecutive calls overlap their host work with the GPU. */
+ * built on host threads and copied through a ring of 4 pinned buffers per
+ * device: the call may block until the copy of the call 4 before it (not its
+ * kernels) has executed, so consecutive calls overlap their host work with
+ * the GPU and the host may run up to 4 calls ahead. */
 pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t bits, int32_t is_signed,
                         const pcmm_mat *B, pcmm_mat *C, const pcmm_cussen_cfg *cfg,
                         void *workspace, size_t ws_bytes, pcmm_cussen_stats *stats,

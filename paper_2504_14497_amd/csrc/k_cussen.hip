@@ -48,10 +48,17 @@ using namespace pcmm;
 
 namespace {
 
-// affine table entry, Montgomery form: x (9 limbs), y (9 limbs), a word that
-// is 1 for the identity and 0 otherwise, 1 pad word
-constexpr int ENTRY_WORDS = 20;
-constexpr int ENTRY_INF = 2 * NL;
+// Affine table entry, Montgomery form, normal limbs: an x granule and a y
+// granule of NL words each.  The tables of a group hold, per entry e, an x
+// plane and then a y plane of one granule per (j, point) pair, pair-fastest,
+// so the lanes of a wavefront (consecutive pairs) touch one contiguous span
+// per plane.  Bit 31 of x's limb 8 marks the identity (stored as x = y = 0);
+// a normal-form limb 8 is below 2^25, which leaves bit 30 for the
+// combination build's mark of entries it finishes in its third pass.
+constexpr int ENTRY_WORDS = 2 * NL;
+constexpr uint32_t ENTRY_INF = 1u << 31;
+constexpr uint32_t ENTRY_PENDING = 1u << 30;
+constexpr uint32_t LIMB8_BITS = ENTRY_PENDING - 1;
 constexpr int JAC_WORDS = 3 * NL;
 constexpr int MAX_PROBLEMS = PCMM_PLAN_MAX_PROBLEMS;
 // the autotuner skips column groups g > 1 whose single (group, pair) table is
@@ -123,6 +130,57 @@ __device__ __forceinline__ T *at(const run_args &a, int64_t off) {
 template <typename T>
 __device__ __forceinline__ const T *plan_at(const run_args &a, int64_t off) {
     return (const T *)(a.plan + off);
+}
+
+// --------------------------------------------------------------------------
+// Table entries
+// --------------------------------------------------------------------------
+// 16-byte access at a 4-byte aligned address (a granule starts at 36 p bytes)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4), aligned(4)));
+
+// Words from one entry of a (group, pair) table to the next, and from an
+// entry's x granule to its y granule.
+__host__ __device__ __forceinline__ int64_t entry_stride(int64_t npairs) { return 2 * npairs * NL; }
+__host__ __device__ __forceinline__ int64_t y_offset(int64_t npairs) { return npairs * NL; }
+
+// x granule of entry e of group grp's table for pair p
+__device__ __forceinline__ uint32_t *entry_at(uint32_t *table, int64_t npairs, int emax, int grp, int e, int64_t p) {
+    return table + (((int64_t)grp * emax + e) * 2 * npairs) * NL + p * NL;
+}
+
+__device__ __forceinline__ fe load_gran(const uint32_t *g) {
+    const u32x4 a = *(const u32x4 *)g;
+    const u32x4 b = *(const u32x4 *)(g + 4);
+    return fe{{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, g[8]}};
+}
+
+// stores v with `flags` or-ed into limb 8
+__device__ __forceinline__ void store_gran(uint32_t *g, const fe &v, uint32_t flags) {
+    *(u32x4 *)g = u32x4{v.v[0], v.v[1], v.v[2], v.v[3]};
+    *(u32x4 *)(g + 4) = u32x4{v.v[4], v.v[5], v.v[6], v.v[7]};
+    g[8] = v.v[8] | flags;
+}
+
+// x of an entry and its flag bits
+__device__ __forceinline__ fe read_x(const uint32_t *slot, uint32_t &flags) {
+    fe x = load_gran(slot);
+    flags = x.v[8] & ~LIMB8_BITS;
+    x.v[8] &= LIMB8_BITS;
+    return x;
+}
+
+__device__ __forceinline__ apt read_entry(const uint32_t *slot, int64_t yoff, bool &inf) {
+    uint32_t flags;
+    apt A;
+    A.x = read_x(slot, flags);
+    A.y = load_gran(slot + yoff);
+    inf = (flags & ENTRY_INF) != 0;
+    return A;
+}
+
+__device__ __forceinline__ void write_entry(uint32_t *slot, int64_t yoff, const apt &A, bool inf) {
+    store_gran(slot, inf ? fe_zero() : A.x, inf ? ENTRY_INF : 0u);
+    store_gran(slot + yoff, inf ? fe_zero() : A.y, 0u);
 }
 
 // --------------------------------------------------------------------------
@@ -254,8 +312,8 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
     // the block's prefix sums again, from the blocks before it: S_i stored
     // once, its Z folded into the forward pass of the inversion
     const int64_t npairs = 2 * (int64_t)l;
-    uint32_t *tab = table + (((int64_t)grp * emax + off) * npairs + 2 * j + pt) * ENTRY_WORDS;
-    const int64_t estride = npairs * ENTRY_WORDS;  // words from one entry to the next
+    uint32_t *tab = entry_at(table, npairs, emax, grp, off, 2 * j + pt);
+    const int64_t estride = entry_stride(npairs), yoff = y_offset(npairs);
     fe prod = fe_one_mont();
     jpt S = excl;
     for (int i = i0; i < i1; ++i) {
@@ -265,9 +323,7 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
         const int16_t opd = entries[eb + i];
         if (opd < 0) continue;  // S_0 = B_kj: affine already
         if (i > 0) reg_store(regs, rmax, n_lanes, 0, opd, lane, S);  // S_0 = b_0 is its own register
-        uint32_t *slot = tab + i * estride;
-#pragma unroll
-        for (int q = 0; q < NL; ++q) slot[q] = prod.v[q];
+        store_gran(tab + i * estride, prod, 0u);
         if (!fe_is_zero(S.Z)) prod = fe_mul_ilp(prod, S.Z);
     }
     fe inv = fe_inv(prod);
@@ -279,9 +335,7 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
             A = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
         } else {
             const jpt P = reg_load(regs, rmax, n_lanes, 0, opd, lane);
-            fe pre;
-#pragma unroll
-            for (int q = 0; q < NL; ++q) pre.v[q] = slot[q];
+            const fe pre = load_gran(slot);
             if (fe_is_zero(P.Z)) {
                 A.x = fe_zero();
                 A.y = fe_zero();
@@ -291,12 +345,7 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
                 A = jpt_to_affine_with(P, zinv);
             }
         }
-#pragma unroll
-        for (int q = 0; q < NL; ++q) {
-            slot[q] = A.x.v[q];
-            slot[NL + q] = A.y.v[q];
-        }
-        slot[ENTRY_INF] = apt_is_inf(A) ? 1u : 0u;
+        write_entry(slot, yoff, A, apt_is_inf(A));
     }
 }
 
@@ -331,7 +380,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
     const int l = d.l, rmax = d.rmax, emax = d.emax;
     const int64_t n_lanes = d.n_lanes;
     const int64_t npairs = 2 * (int64_t)l;
-    const int64_t estride = npairs * ENTRY_WORDS;  // words from one entry to the next
+    const int64_t estride = entry_stride(npairs), yoff = y_offset(npairs);
 
     const int lanes_per_unit = 2 * d.Lj;
     const int u = (int)(lane / lanes_per_unit);
@@ -353,7 +402,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
         last_r = r;
         jpt last = jpt_infinity();
         int last_reg = -1;
-        uint32_t *tab = table + (((int64_t)grp * emax + off) * npairs + 2 * j + pt) * ENTRY_WORDS;
+        uint32_t *tab = entry_at(table, npairs, emax, grp, off, 2 * j + pt);
         // forward pass of the batched inversion, folded into the program: the
         // plan orders a group's entries by their producing ops, so the next
         // register entry is always the next one an op produces, and its Z
@@ -365,9 +414,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
             const plan_op op = ops[o];
             run_op(op, B, ldb, l, k0, j, pt, regs, rmax, n_lanes, r, lane, last, last_reg);
             if (ne < E && op.dst == entries[eb + ne]) {
-                uint32_t *slot = tab + ne * estride;
-#pragma unroll
-                for (int w = 0; w < NL; ++w) slot[w] = prod.v[w];
+                store_gran(tab + ne * estride, prod, 0u);
                 if (!fe_is_zero(last.Z)) prod = fe_mul_ilp(prod, last.Z);
                 ++ne;
                 while (ne < E && entries[eb + ne] < 0) ++ne;
@@ -378,7 +425,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
     fe inv = fe_inv(prod);
     for (int r = last_r; r >= 0; --r) {
         const int j = jslot + r * d.Lj;
-        uint32_t *tab = table + (((int64_t)grp * emax + off) * npairs + 2 * j + pt) * ENTRY_WORDS;
+        uint32_t *tab = entry_at(table, npairs, emax, grp, off, 2 * j + pt);
         for (int e = E - 1; e >= 0; --e) {
             const int16_t opd = entries[eb + e];
             uint32_t *slot = tab + e * estride;
@@ -387,9 +434,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
                 A = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
             } else {
                 jpt P = reg_load(regs, rmax, n_lanes, r, opd, lane);
-                fe pre;
-#pragma unroll
-                for (int w = 0; w < NL; ++w) pre.v[w] = slot[w];
+                const fe pre = load_gran(slot);
                 if (fe_is_zero(P.Z)) {
                     A.x = fe_zero();
                     A.y = fe_zero();
@@ -399,12 +444,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
                     A = jpt_to_affine_with(P, zinv);
                 }
             }
-#pragma unroll
-            for (int w = 0; w < NL; ++w) {
-                slot[w] = A.x.v[w];
-                slot[NL + w] = A.y.v[w];
-            }
-            slot[ENTRY_INF] = apt_is_inf(A) ? 1u : 0u;
+            write_entry(slot, yoff, A, apt_is_inf(A));
         }
     }
 }
@@ -412,35 +452,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
 // --------------------------------------------------------------------------
 // Combination entries (column groups g > 1)
 // --------------------------------------------------------------------------
-// An affine table entry: x, y (Montgomery, normal form) and its identity flag.
-__device__ __forceinline__ apt read_entry(const uint32_t *slot, bool &inf) {
-    uint4 w4[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) w4[q] = ((const uint4 *)slot)[q];
-    const uint32_t *w = (const uint32_t *)w4;
-    apt A;
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        A.x.v[k] = w[k];
-        A.y.v[k] = w[NL + k];
-    }
-    inf = w[ENTRY_INF] != 0;
-    return A;
-}
-
-__device__ __forceinline__ void write_entry(uint32_t *slot, const apt &A, bool inf) {
-    uint32_t w[ENTRY_WORDS];
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        w[k] = inf ? 0u : A.x.v[k];
-        w[NL + k] = inf ? 0u : A.y.v[k];
-    }
-    w[ENTRY_INF] = inf ? 1u : 0u;
-    w[ENTRY_INF + 1] = 0u;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) ((uint4 *)slot)[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-}
-
 // a - b - c + 4p (mod p) for a, b, c normal: one limb pass (value in
 // (0, 6p)), then normalised
 __device__ __forceinline__ fe fe_sub_sub(const fe &a, const fe &b, const fe &c) {
@@ -450,33 +461,15 @@ __device__ __forceinline__ fe fe_sub_sub(const fe &a, const fe &b, const fe &c) 
     return fe_norm(x);
 }
 
-// x and the identity flag of an entry (what the forward pass needs)
-struct entry_x {
-    uint4 x0, x1;
-    uint32_t x8, inf;
-};
-
-__device__ __forceinline__ entry_x read_entry_x(const uint32_t *slot) {
-    entry_x r;
-    r.x0 = ((const uint4 *)slot)[0];
-    r.x1 = ((const uint4 *)slot)[1];
-    r.x8 = slot[8];
-    r.inf = slot[ENTRY_INF];
-    return r;
-}
-
-__device__ __forceinline__ fe fe_of(const entry_x &r) {
-    return fe{{r.x0.x, r.x0.y, r.x0.z, r.x0.w, r.x1.x, r.x1.y, r.x1.z, r.x1.w, r.x8}};
-}
-
 // a + b for the cases the chord formula does not cover: an identity operand,
 // b = -a (the identity) and b = a (the doubling, with an inversion of its
 // own; a P-256 point has no order 2, so 2a is finite).  Rare: random
 // ciphertexts never meet them, forced inputs in the tests do.
-__device__ __noinline__ void combo_special(const uint32_t *sa, const uint32_t *sb, bool neg_b, uint32_t *dst) {
+__device__ __noinline__ void combo_special(const uint32_t *sa, const uint32_t *sb, int64_t yoff, bool neg_b,
+                                           uint32_t *dst) {
     bool a_inf, b_inf;
-    const apt A = read_entry(sa, a_inf);
-    apt Bn = read_entry(sb, b_inf);
+    const apt A = read_entry(sa, yoff, a_inf);
+    apt Bn = read_entry(sb, yoff, b_inf);
     if (neg_b) Bn.y = fe_neg(Bn.y);
     apt R = A;
     bool inf = false;
@@ -492,28 +485,28 @@ __device__ __noinline__ void combo_special(const uint32_t *sa, const uint32_t *s
         const jpt D = jpt_dbl<false>(jpt_from_affine(A));
         R = jpt_to_affine_with(D, fe_inv(D.Z));
     }
-    write_entry(dst, R, inf);
+    write_entry(dst, yoff, R, inf);
 }
 
 // The combinations of one (group, output column j, point), lane = (group,
 // pair) of the problem; the lanes of a wavefront are consecutive pairs, so
-// with the pair-fastest table layout their accesses to one entry are
-// contiguous.  Within a level every combination reads only lower levels, so
-// one inversion (Montgomery's trick) serves the whole level.  The level's
-// combinations come in blocks of up to COMBO_BLOCK first operands a[r],
-// held in registers, and runs of one second operand b each (loaded once per
-// run):
-//   forward   the product of the dx = x_b - x_a[r] of all chord additions,
-//             one prefix (the product before the run) stored per run, in
-//             the slot of its first combination;
+// with the plane layout of the tables their accesses to one entry's x (or y)
+// are one contiguous span.  Within a level every combination reads only
+// lower levels, so one inversion (Montgomery's trick) serves the whole
+// level.  The level's combinations come in blocks of up to COMBO_BLOCK first
+// operands a[r], held in registers, and runs of one second operand b each
+// (loaded once per run):
+//   forward   the product of the dx = x_b - x_a[r] of all chord additions
+//             (reading only x), one prefix (the product before the run)
+//             stored per run, in the x granule of its first combination;
 //   inverse   one inversion per level;
 //   backward  per run (in reverse) the prefixes inside the run again from
 //             the run's dx, then each combination's 1/dx and its affine sum
 //             by the chord formula.
 // Combinations the chord formula does not cover (an identity operand, x_a =
-// x_b) are marked in the forward pass and finished in a third pass, which
-// runs only when some lane of the wavefront has one.
-constexpr uint32_t ENTRY_PENDING = 2;  // flag word of an entry left to the third pass
+// x_b) are marked in the forward pass (ENTRY_PENDING in limb 8 of x) and
+// finished in a third pass, which runs only when some lane of the wavefront
+// has one.
 constexpr int CB = COMBO_BLOCK;
 
 __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &d, int64_t lane) {
@@ -523,8 +516,8 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
     const int32_t *cblock_begin = plan_at<int32_t>(a, d.o_cblock_begin);
     const plan_cblock *blocks = plan_at<plan_cblock>(a, d.o_cblocks);
     const plan_crun *runs = plan_at<plan_crun>(a, d.o_cruns);
-    uint32_t *tab = at<uint32_t>(a, d.w_table) + ((int64_t)grp * d.emax * npairs + p) * ENTRY_WORDS;
-    const int64_t estride = (int64_t)npairs * ENTRY_WORDS;
+    uint32_t *tab = entry_at(at<uint32_t>(a, d.w_table), npairs, d.emax, grp, 0, p);
+    const int64_t estride = entry_stride(npairs), yoff = y_offset(npairs);
     const int bb = cblock_begin[grp], be = cblock_begin[grp + 1];
     for (int b0 = bb; b0 < be;) {
         const int level = blocks[b0].level;
@@ -535,47 +528,53 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
         bool pending = false;
         for (int bi = b0; bi < b1; ++bi) {
             const plan_cblock blk = blocks[bi];
-            entry_x xa[CB];
+            fe xa[CB];
+            bool ainf[CB];
 #pragma unroll
             for (int r = 0; r < CB; ++r) {
                 if (r < blk.na) {
-                    xa[r] = read_entry_x(tab + blk.a[r] * estride);
+                    uint32_t fl;
+                    xa[r] = read_x(tab + blk.a[r] * estride, fl);
+                    ainf[r] = (fl & ENTRY_INF) != 0;
                 } else {  // no such operand: an identity, never a chord
-                    xa[r].x0 = xa[r].x1 = make_uint4(0, 0, 0, 0);
-                    xa[r].x8 = 0;
-                    xa[r].inf = 1;
+                    xa[r] = fe_zero();
+                    ainf[r] = true;
                 }
             }
             plan_crun nr = runs[blk.run_begin];
-            entry_x nxb = read_entry_x(tab + nr.b * estride);
+            uint32_t nfl;
+            fe nxb = read_x(tab + nr.b * estride, nfl);
             for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
                 const plan_crun run = nr;
-                const entry_x xb = nxb;
+                const fe xb = nxb;
+                const bool binf = (nfl & ENTRY_INF) != 0;
                 if (ri + 1 < blk.run_end) {
                     nr = runs[ri + 1];
-                    nxb = read_entry_x(tab + nr.b * estride);
+                    nxb = read_x(tab + nr.b * estride, nfl);
                 }
-                int first = 0;
-                while (run.dst[first] < 0) ++first;
-                uint32_t *pslot = tab + run.dst[first] * estride;
-                ((uint4 *)pslot)[0] = make_uint4(prod.v[0], prod.v[1], prod.v[2], prod.v[3]);
-                ((uint4 *)pslot)[1] = make_uint4(prod.v[4], prod.v[5], prod.v[6], prod.v[7]);
-                pslot[8] = prod.v[8];
                 // the run's product of dx first, then one product into the
                 // running chain (its critical path: one product per run)
                 const fe one = fe_one_mont();
                 fe t = one;
+                bool chord[CB];
+                int first = -1;
 #pragma unroll
                 for (int r = 0; r < CB; ++r) {
-                    const fe dx = fe_sub(fe_of(xb), fe_of(xa[r]));
+                    const fe dx = fe_sub(xb, xa[r]);
                     const bool present = run.dst[r] >= 0;
-                    const bool chord = present && (xa[r].inf | xb.inf) == 0 && !fe_is_zero(dx);
-                    if (present && !chord) {
-                        tab[run.dst[r] * estride + ENTRY_INF] = ENTRY_PENDING;
-                        pending = true;
-                    }
-                    const fe f = fe_select(chord, one, dx);
+                    chord[r] = present && !ainf[r] && !binf && !fe_is_zero(dx);
+                    if (present && first < 0) first = r;
+                    if (present && !chord[r]) pending = true;
+                    const fe f = fe_select(chord[r], one, dx);
                     t = r == 0 ? f : fe_mul_ilp(t, f);
+                }
+#pragma unroll
+                for (int r = 0; r < CB; ++r) {
+                    if (r == first) {
+                        store_gran(tab + run.dst[r] * estride, prod, chord[r] ? 0u : ENTRY_PENDING);
+                    } else if (run.dst[r] >= 0 && !chord[r]) {
+                        tab[run.dst[r] * estride + NL - 1] = ENTRY_PENDING;
+                    }
                 }
                 prod = fe_mul_ilp(prod, t);
             }
@@ -589,7 +588,7 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
 #pragma unroll
             for (int r = 0; r < CB; ++r) {
                 if (r < blk.na) {
-                    A[r] = read_entry(tab + blk.a[r] * estride, ainf[r]);
+                    A[r] = read_entry(tab + blk.a[r] * estride, yoff, ainf[r]);
                 } else {  // no such operand: an identity, never a chord
                     A[r].x = fe_zero();
                     A[r].y = fe_zero();
@@ -598,19 +597,17 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
             }
             plan_crun nr = runs[blk.run_end - 1];
             bool nbinf;
-            apt nb = read_entry(tab + nr.b * estride, nbinf);
+            apt nb = read_entry(tab + nr.b * estride, yoff, nbinf);
             for (int ri = blk.run_end - 1; ri >= blk.run_begin; --ri) {
                 const plan_crun run = nr;
                 const apt Bv = nb;
                 const bool binf = nbinf;
                 if (ri > blk.run_begin) {
                     nr = runs[ri - 1];
-                    nb = read_entry(tab + nr.b * estride, nbinf);
+                    nb = read_entry(tab + nr.b * estride, yoff, nbinf);
                 }
                 int first = 0;
                 while (run.dst[first] < 0) ++first;
-                const uint32_t *pslot = tab + run.dst[first] * estride;
-                const uint4 p0 = ((const uint4 *)pslot)[0], p1 = ((const uint4 *)pslot)[1];
                 // the prefix before each combination of the run, then every
                 // combination's 1/dx (newest first, the inverse chain), then
                 // the chord sums; branch-free, so the run's independent
@@ -619,7 +616,8 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
                 const fe one = fe_one_mont();
                 fe q[CB], dx[CB], dinv[CB];
                 bool chord[CB];
-                fe cur = {{p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, pslot[8]}};
+                fe cur = load_gran(tab + run.dst[first] * estride);
+                cur.v[NL - 1] &= LIMB8_BITS;
 #pragma unroll
                 for (int r = 0; r < CB; ++r) {
                     dx[r] = fe_sub(Bv.x, A[r].x);
@@ -639,7 +637,7 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
                     apt R;
                     R.x = fe_sub_sub(fe_sqr_ilp(lam), A[r].x, Bv.x);
                     R.y = fe_sub(fe_mul_ilp(lam, fe_sub_w(A[r].x, R.x)), A[r].y);
-                    if (chord[r]) write_entry(tab + run.dst[r] * estride, R, false);
+                    if (chord[r]) write_entry(tab + run.dst[r] * estride, yoff, R, false);
                 }
             }
         }
@@ -652,8 +650,9 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
                     for (int r = 0; r < CB; ++r) {
                         if (run.dst[r] < 0) continue;
                         uint32_t *slot = tab + run.dst[r] * estride;
-                        if (pending && slot[ENTRY_INF] == ENTRY_PENDING)
-                            combo_special(tab + blk.a[r] * estride, tab + run.b * estride, (run.neg >> r) & 1, slot);
+                        if (pending && (slot[NL - 1] & ENTRY_PENDING))
+                            combo_special(tab + blk.a[r] * estride, tab + run.b * estride, yoff, (run.neg >> r) & 1,
+                                          slot);
                     }
                 }
             }
@@ -675,14 +674,18 @@ __global__ void __launch_bounds__(256) combo_table_kernel(run_args a) {
 // --------------------------------------------------------------------------
 // Affine table entry e of group k for pair p, read from global memory (the
 // lanes of a wavefront share the pair, so they gather from one small table
-// that L1 and L2 serve): five 16-byte loads.
-__device__ __forceinline__ void load_entry(const uint32_t *tp, int64_t gstride, int64_t estride, int32_t v,
-                                           uint4 (&en)[5]) {
+// that L1 and L2 serve): x granule, then y granule, three loads each.
+__device__ __forceinline__ void load_entry(const uint32_t *tp, int64_t gstride, int64_t estride, int64_t yoff,
+                                           int32_t v, u32x4 (&en)[4], uint32_t (&e8)[2]) {
     const int c = (int16_t)(v & 0xFFFF);
     const int e = (c < 0 ? -c : c) - 1;
-    const uint4 *ep = (const uint4 *)(tp + (int64_t)(v >> 16) * gstride + (int64_t)e * estride);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) en[q] = ep[q];
+    const uint32_t *ep = tp + (int64_t)(v >> 16) * gstride + (int64_t)e * estride;
+    en[0] = *(const u32x4 *)ep;
+    en[1] = *(const u32x4 *)(ep + 4);
+    e8[0] = ep[8];
+    en[2] = *(const u32x4 *)(ep + yoff);
+    en[3] = *(const u32x4 *)(ep + yoff + 4);
+    e8[1] = ep[yoff + 8];
 }
 
 // One tile: rows bx * tm .. + tm, (j, point) pairs by * pp .. + pp, column
@@ -706,8 +709,9 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
     const int32_t *lists = plan_at<int32_t>(a, d.o_lists);
     const int64_t *chunk_off = plan_at<int64_t>(a, d.o_chunk_off);
     const int32_t *chunk_len = plan_at<int32_t>(a, d.o_chunk_len);
-    const int64_t gstride = (int64_t)npairs * emax * ENTRY_WORDS;  // words from one group's tables to the next
-    const int64_t estride = (int64_t)npairs * ENTRY_WORDS;         // from one entry of a table to the next
+    const int64_t estride = entry_stride(npairs);     // words from one entry of a table to the next
+    const int64_t gstride = (int64_t)emax * estride;  // from one group's tables to the next
+    const int64_t yoff = y_offset(npairs);
 
     jpt acc = jpt_infinity();
     bool acc_inf = true;  // whether acc is the identity, kept by the additions
@@ -715,38 +719,39 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
         const int chunk = bz * d.chunks_per_split + (gc - g_begin) / d.kc;
         const int len = chunk_len[chunk];
         const int32_t *lst = lists + chunk_off[chunk] * m + i;
-        const uint32_t *tp = table + ((int64_t)gc * emax * npairs + p) * ENTRY_WORDS;
+        const uint32_t *tp = entry_at((uint32_t *)table, npairs, emax, gc, 0, p);
         // software pipeline: codes three slots ahead, the entry one slot
         // ahead, so that their memory latency overlaps the point additions
         int32_t v_cur = len > 0 ? lst[0] : 0;
         int32_t v_nxt = len > 1 ? lst[m] : 0;
         int32_t v_nx2 = len > 2 ? lst[2 * (int64_t)m] : 0;
-        uint4 en[5];
+        u32x4 en[4];
+        uint32_t e8[2];
         if ((int16_t)(v_cur & 0xFFFF) != 0) {
-            load_entry(tp, gstride, estride, v_cur, en);
+            load_entry(tp, gstride, estride, yoff, v_cur, en, e8);
         } else {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) en[q] = make_uint4(0, 0, 0, 0);
+            for (int q = 0; q < 4; ++q) en[q] = u32x4{0u, 0u, 0u, 0u};
+            e8[0] = e8[1] = 0u;
         }
         for (int it = 0; it < len; ++it) {
             const int32_t v = v_cur;
-            uint4 ec[5];
+            u32x4 ec[4];
+            uint32_t c8[2];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) ec[q] = en[q];
+            for (int q = 0; q < 4; ++q) ec[q] = en[q];
+            c8[0] = e8[0];
+            c8[1] = e8[1];
             v_cur = v_nxt;
             v_nxt = v_nx2;
             if (it + 3 < len) v_nx2 = lst[(int64_t)(it + 3) * m];
-            if (it + 1 < len && (int16_t)(v_cur & 0xFFFF) != 0) load_entry(tp, gstride, estride, v_cur, en);
+            if (it + 1 < len && (int16_t)(v_cur & 0xFFFF) != 0) load_entry(tp, gstride, estride, yoff, v_cur, en, e8);
             const int code = (int16_t)(v & 0xFFFF);
             if (code == 0) continue;  // padding after the row's last nonzero code
-            const uint32_t *w = (const uint32_t *)ec;
-            apt Q;
-#pragma unroll
-            for (int k = 0; k < NL; ++k) {
-                Q.x.v[k] = w[k];
-                Q.y.v[k] = w[NL + k];
-            }
-            const bool q_inf = w[ENTRY_INF] != 0;
+            const apt Q0 = {{{ec[0].x, ec[0].y, ec[0].z, ec[0].w, ec[1].x, ec[1].y, ec[1].z, ec[1].w, c8[0] & LIMB8_BITS}},
+                            {{ec[2].x, ec[2].y, ec[2].z, ec[2].w, ec[3].x, ec[3].y, ec[3].z, ec[3].w, c8[1]}}};
+            apt Q = Q0;
+            const bool q_inf = (c8[0] & ENTRY_INF) != 0;
             if (code < 0) Q.y = fe_neg(Q.y);
             acc = jpt_add_affine_known(acc, acc_inf, Q, q_inf, acc_inf);
         }
@@ -1700,15 +1705,19 @@ struct stage_events {
     }
 };
 
-// pinned staging for the plan image of pcmm_cussen calls, one per device; an
-// event guards reuse
+// pinned staging for the plan image of pcmm_cussen calls: a ring of
+// STAGE_RING buffers per device, each guarded by an event recorded after its
+// copy, so the host can plan up to STAGE_RING calls ahead of the device (a
+// host stall shorter than that many runs leaves the device busy)
+constexpr int STAGE_RING = 4;
 struct staging {
     void *host = nullptr;
     size_t bytes = 0;
     hipEvent_t done = nullptr;
 };
 std::mutex g_stage_lock;
-staging g_stage[64];
+staging g_stage[64][STAGE_RING];
+int g_stage_next[64];
 
 pcmm_problem single_problem(const void *A, int m, int n, int l, int bits, int is_signed, int c_form,
                             const pcmm_cussen_cfg *cfg) {
@@ -1793,7 +1802,8 @@ extern "C" pcmm_status pcmm_cussen(const void *A, int32_t m, int32_t n, int32_t 
         // has executed (the previous run's kernels may still be running)
         std::lock_guard<std::mutex> guard(g_stage_lock);
         if (pl.device < 0 || pl.device >= 64) return PCMM_EDEVICE;
-        staging &sg = g_stage[pl.device];
+        staging &sg = g_stage[pl.device][g_stage_next[pl.device]];
+        g_stage_next[pl.device] = (g_stage_next[pl.device] + 1) % STAGE_RING;
         const size_t bytes = std::max<size_t>(pl.image.size(), 256);
         (void)ws_bytes;
         if (sg.done) PCMM_HIP_TRY(hipEventSynchronize(sg.done));

@@ -488,6 +488,30 @@ __device__ __noinline__ void combo_special(const uint32_t *sa, const uint32_t *s
     write_entry(dst, yoff, R, inf);
 }
 
+// 4p - a - b for a, b normal: (0, 4p], carry-only (the negated second
+// operand's y minus the first's in one limb pass)
+__device__ __forceinline__ fe fe_neg_sub_w(const fe &a, const fe &b) {
+    fe x;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x.v[i] = (uint32_t)KP4.v[i] - a.v[i] - b.v[i];
+    fe_carry(x);
+    return x;
+}
+
+// x_b - x_a of a chord: carry-only in (0, 4p) for the products, or (SAFE)
+// normalised, with the chord condition x_a != x_b tested
+template <bool SAFE>
+__device__ __forceinline__ fe chord_dx(const fe &xb, const fe &xa, bool &ne) {
+    if constexpr (SAFE) {
+        const fe dx = fe_sub(xb, xa);
+        ne = !fe_is_zero(dx);
+        return dx;
+    } else {
+        ne = true;
+        return fe_sub_w(xb, xa);
+    }
+}
+
 // The combinations of one (group, output column j, point), lane = (group,
 // pair) of the problem; the lanes of a wavefront are consecutive pairs, so
 // with the plane layout of the tables their accesses to one entry's x (or y)
@@ -503,11 +527,143 @@ __device__ __noinline__ void combo_special(const uint32_t *sa, const uint32_t *s
 //   backward  per run (in reverse) the prefixes inside the run again from
 //             the run's dx, then each combination's 1/dx and its affine sum
 //             by the chord formula.
-// Combinations the chord formula does not cover (an identity operand, x_a =
-// x_b) are marked in the forward pass (ENTRY_PENDING in limb 8 of x) and
+// The chord formula needs two finite operands with x_a != x_b.  The first
+// forward pass excludes only identity operands (flags); a pair with x_a =
+// x_b then makes the level's product zero, and a wavefront with such a lane
+// runs the level's forward pass again with x_a != x_b tested per
+// combination (and the matching backward pass).  Combinations the chord
+// formula does not cover are marked (ENTRY_PENDING in limb 8 of x) and
 // finished in a third pass, which runs only when some lane of the wavefront
 // has one.
 constexpr int CB = COMBO_BLOCK;
+
+template <bool SAFE>
+__device__ __forceinline__ fe combo_forward(const plan_cblock *blocks, const plan_crun *runs, int b0, int b1,
+                                            uint32_t *tab, int64_t estride, bool &pending) {
+    fe prod = fe_one_mont();
+    for (int bi = b0; bi < b1; ++bi) {
+        const plan_cblock blk = blocks[bi];
+        fe xa[CB];
+        bool ainf[CB];
+#pragma unroll
+        for (int r = 0; r < CB; ++r) {
+            if (r < blk.na) {
+                uint32_t fl;
+                xa[r] = read_x(tab + blk.a[r] * estride, fl);
+                ainf[r] = (fl & ENTRY_INF) != 0;
+            } else {  // no such operand: an identity, never a chord
+                xa[r] = fe_zero();
+                ainf[r] = true;
+            }
+        }
+        plan_crun nr = runs[blk.run_begin];
+        uint32_t nfl;
+        fe nxb = read_x(tab + nr.b * estride, nfl);
+        for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
+            const plan_crun run = nr;
+            const fe xb = nxb;
+            const bool binf = (nfl & ENTRY_INF) != 0;
+            if (ri + 1 < blk.run_end) {
+                nr = runs[ri + 1];
+                nxb = read_x(tab + nr.b * estride, nfl);
+            }
+            // the run's product of dx first, then one product into the
+            // running chain (its critical path: one product per run)
+            const fe one = fe_one_mont();
+            fe t = one;
+            bool chord[CB];
+            int first = -1;
+#pragma unroll
+            for (int r = 0; r < CB; ++r) {
+                bool ne;
+                const fe dx = chord_dx<SAFE>(xb, xa[r], ne);
+                const bool present = run.dst[r] >= 0;
+                chord[r] = present && !ainf[r] && !binf && ne;
+                if (present && first < 0) first = r;
+                if (present && !chord[r]) pending = true;
+                const fe f = fe_select(chord[r], one, dx);
+                t = r == 0 ? f : fe_mul_ilp(t, f);
+            }
+#pragma unroll
+            for (int r = 0; r < CB; ++r) {
+                if (r == first) {
+                    store_gran(tab + run.dst[r] * estride, prod, chord[r] ? 0u : ENTRY_PENDING);
+                } else if (run.dst[r] >= 0 && !chord[r]) {
+                    tab[run.dst[r] * estride + NL - 1] = ENTRY_PENDING;
+                }
+            }
+            prod = fe_mul_ilp(prod, t);
+        }
+    }
+    return prod;
+}
+
+template <bool SAFE>
+__device__ __forceinline__ void combo_backward(const plan_cblock *blocks, const plan_crun *runs, int b0, int b1,
+                                               uint32_t *tab, int64_t estride, int64_t yoff, fe inv) {
+    for (int bi = b1 - 1; bi >= b0; --bi) {
+        const plan_cblock blk = blocks[bi];
+        apt A[CB];
+        bool ainf[CB];
+#pragma unroll
+        for (int r = 0; r < CB; ++r) {
+            if (r < blk.na) {
+                A[r] = read_entry(tab + blk.a[r] * estride, yoff, ainf[r]);
+            } else {  // no such operand: an identity, never a chord
+                A[r].x = fe_zero();
+                A[r].y = fe_zero();
+                ainf[r] = true;
+            }
+        }
+        plan_crun nr = runs[blk.run_end - 1];
+        bool nbinf;
+        apt nb = read_entry(tab + nr.b * estride, yoff, nbinf);
+        for (int ri = blk.run_end - 1; ri >= blk.run_begin; --ri) {
+            const plan_crun run = nr;
+            const apt Bv = nb;
+            const bool binf = nbinf;
+            if (ri > blk.run_begin) {
+                nr = runs[ri - 1];
+                nb = read_entry(tab + nr.b * estride, yoff, nbinf);
+            }
+            int first = 0;
+            while (run.dst[first] < 0) ++first;
+            // the prefix before each combination of the run, then every
+            // combination's 1/dx (newest first, the inverse chain), then
+            // the chord sums; branch-free, so the run's independent chains
+            // interleave (the rare non-chord slots compute discarded values
+            // and are not stored)
+            const fe one = fe_one_mont();
+            fe q[CB], dx[CB], dinv[CB];
+            bool chord[CB];
+            fe cur = load_gran(tab + run.dst[first] * estride);
+            cur.v[NL - 1] &= LIMB8_BITS;
+#pragma unroll
+            for (int r = 0; r < CB; ++r) {
+                bool ne;
+                dx[r] = chord_dx<SAFE>(Bv.x, A[r].x, ne);
+                chord[r] = run.dst[r] >= 0 && !ainf[r] && !binf && ne;
+                q[r] = cur;
+                if (r + 1 < CB) cur = fe_mul_ilp(cur, fe_select(chord[r], one, dx[r]));
+            }
+#pragma unroll
+            for (int r = CB - 1; r >= 0; --r) {
+                dinv[r] = fe_mul_ilp(inv, q[r]);
+                inv = fe_mul_ilp(inv, fe_select(chord[r], one, dx[r]));
+            }
+#pragma unroll
+            for (int r = 0; r < CB; ++r) {
+                // y_b - y_a, or -y_b - y_a for a subtracted b: carry-only
+                const fe dy = ((run.neg >> r) & 1) ? fe_neg_sub_w(Bv.y, A[r].y) : fe_sub_w(Bv.y, A[r].y);
+                const fe lam = fe_mul_ilp(dy, dinv[r]);
+                apt R;
+                R.x = fe_sub_sub(fe_sqr_ilp(lam), A[r].x, Bv.x);
+                R.y = fe_sub(fe_mul_ilp(lam, fe_sub_w(A[r].x, R.x)), A[r].y);
+                if (chord[r]) write_entry(tab + run.dst[r] * estride, yoff, R, false);
+            }
+        }
+    }
+}
 
 __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &d, int64_t lane) {
     const int npairs = 2 * d.l;
@@ -523,123 +679,16 @@ __device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &
         const int level = blocks[b0].level;
         int b1 = b0 + 1;
         while (b1 < be && blocks[b1].level == level) ++b1;
-        // ---- forward
-        fe prod = fe_one_mont();
         bool pending = false;
-        for (int bi = b0; bi < b1; ++bi) {
-            const plan_cblock blk = blocks[bi];
-            fe xa[CB];
-            bool ainf[CB];
-#pragma unroll
-            for (int r = 0; r < CB; ++r) {
-                if (r < blk.na) {
-                    uint32_t fl;
-                    xa[r] = read_x(tab + blk.a[r] * estride, fl);
-                    ainf[r] = (fl & ENTRY_INF) != 0;
-                } else {  // no such operand: an identity, never a chord
-                    xa[r] = fe_zero();
-                    ainf[r] = true;
-                }
-            }
-            plan_crun nr = runs[blk.run_begin];
-            uint32_t nfl;
-            fe nxb = read_x(tab + nr.b * estride, nfl);
-            for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
-                const plan_crun run = nr;
-                const fe xb = nxb;
-                const bool binf = (nfl & ENTRY_INF) != 0;
-                if (ri + 1 < blk.run_end) {
-                    nr = runs[ri + 1];
-                    nxb = read_x(tab + nr.b * estride, nfl);
-                }
-                // the run's product of dx first, then one product into the
-                // running chain (its critical path: one product per run)
-                const fe one = fe_one_mont();
-                fe t = one;
-                bool chord[CB];
-                int first = -1;
-#pragma unroll
-                for (int r = 0; r < CB; ++r) {
-                    const fe dx = fe_sub(xb, xa[r]);
-                    const bool present = run.dst[r] >= 0;
-                    chord[r] = present && !ainf[r] && !binf && !fe_is_zero(dx);
-                    if (present && first < 0) first = r;
-                    if (present && !chord[r]) pending = true;
-                    const fe f = fe_select(chord[r], one, dx);
-                    t = r == 0 ? f : fe_mul_ilp(t, f);
-                }
-#pragma unroll
-                for (int r = 0; r < CB; ++r) {
-                    if (r == first) {
-                        store_gran(tab + run.dst[r] * estride, prod, chord[r] ? 0u : ENTRY_PENDING);
-                    } else if (run.dst[r] >= 0 && !chord[r]) {
-                        tab[run.dst[r] * estride + NL - 1] = ENTRY_PENDING;
-                    }
-                }
-                prod = fe_mul_ilp(prod, t);
-            }
-        }
-        fe inv = fe_inv(prod);
-        // ---- backward
-        for (int bi = b1 - 1; bi >= b0; --bi) {
-            const plan_cblock blk = blocks[bi];
-            apt A[CB];
-            bool ainf[CB];
-#pragma unroll
-            for (int r = 0; r < CB; ++r) {
-                if (r < blk.na) {
-                    A[r] = read_entry(tab + blk.a[r] * estride, yoff, ainf[r]);
-                } else {  // no such operand: an identity, never a chord
-                    A[r].x = fe_zero();
-                    A[r].y = fe_zero();
-                    ainf[r] = true;
-                }
-            }
-            plan_crun nr = runs[blk.run_end - 1];
-            bool nbinf;
-            apt nb = read_entry(tab + nr.b * estride, yoff, nbinf);
-            for (int ri = blk.run_end - 1; ri >= blk.run_begin; --ri) {
-                const plan_crun run = nr;
-                const apt Bv = nb;
-                const bool binf = nbinf;
-                if (ri > blk.run_begin) {
-                    nr = runs[ri - 1];
-                    nb = read_entry(tab + nr.b * estride, yoff, nbinf);
-                }
-                int first = 0;
-                while (run.dst[first] < 0) ++first;
-                // the prefix before each combination of the run, then every
-                // combination's 1/dx (newest first, the inverse chain), then
-                // the chord sums; branch-free, so the run's independent
-                // chains interleave (the rare non-chord slots compute
-                // discarded values and are not stored)
-                const fe one = fe_one_mont();
-                fe q[CB], dx[CB], dinv[CB];
-                bool chord[CB];
-                fe cur = load_gran(tab + run.dst[first] * estride);
-                cur.v[NL - 1] &= LIMB8_BITS;
-#pragma unroll
-                for (int r = 0; r < CB; ++r) {
-                    dx[r] = fe_sub(Bv.x, A[r].x);
-                    chord[r] = run.dst[r] >= 0 && !ainf[r] && !binf && !fe_is_zero(dx[r]);
-                    q[r] = cur;
-                    if (r + 1 < CB) cur = fe_mul_ilp(cur, fe_select(chord[r], one, dx[r]));
-                }
-#pragma unroll
-                for (int r = CB - 1; r >= 0; --r) {
-                    dinv[r] = fe_mul_ilp(inv, q[r]);
-                    inv = fe_mul_ilp(inv, fe_select(chord[r], one, dx[r]));
-                }
-#pragma unroll
-                for (int r = 0; r < CB; ++r) {
-                    const fe by = ((run.neg >> r) & 1) ? fe_neg(Bv.y) : Bv.y;
-                    const fe lam = fe_mul_ilp(fe_sub(by, A[r].y), dinv[r]);
-                    apt R;
-                    R.x = fe_sub_sub(fe_sqr_ilp(lam), A[r].x, Bv.x);
-                    R.y = fe_sub(fe_mul_ilp(lam, fe_sub_w(A[r].x, R.x)), A[r].y);
-                    if (chord[r]) write_entry(tab + run.dst[r] * estride, yoff, R, false);
-                }
-            }
+        fe prod = combo_forward<false>(blocks, runs, b0, b1, tab, estride, pending);
+        // a zero product: some chord of this lane has x_a = x_b
+        const bool safe = __ballot(fe_is_zero(prod)) != 0;
+        if (safe) {
+            pending = false;
+            prod = combo_forward<true>(blocks, runs, b0, b1, tab, estride, pending);
+            combo_backward<true>(blocks, runs, b0, b1, tab, estride, yoff, fe_inv(prod));
+        } else {
+            combo_backward<false>(blocks, runs, b0, b1, tab, estride, yoff, fe_inv(prod));
         }
         // ---- the rest: identity operands, x_a = x_b
         if (__ballot(pending)) {

@@ -135,18 +135,22 @@ __device__ __forceinline__ jpt fix_equal_operands(bool same, const jpt &R, const
 template <bool CHAIN, bool LEAN>
 __device__ __forceinline__ jpt madd_formulas(const jpt &P, const apt &Q, fe &hh, fe &r) {
     jpt R;
-    fe z1z1 = fe_sqr_t<CHAIN>(P.Z);
     if constexpr (LEAN) {
-        fe h = fe_mul_plus_t<CHAIN>(Q.x, z1z1, fe_2p_minus(P.X));                        // (0, 4p)
-        r = fe_mul_plus_t<CHAIN>(fe_mul_t<CHAIN>(Q.y, P.Z), z1z1, fe_2p_minus(P.Y));  // r / 2, (0, 4p)
-        hh = fe_sqr_t<CHAIN>(h);
+        // every product but J = H I and the Y3 pair has operand bounds
+        // multiplying to at most 16 p^2, so it takes loose quotient digits
+        constexpr bool LQ = true;
+        fe z1z1 = fe_sqr_t<CHAIN, LQ>(P.Z);                                                      // 4 p^2
+        fe h = fe_mul_plus_t<CHAIN, LQ>(Q.x, z1z1, fe_2p_minus(P.X));                            // (0, 4p)
+        r = fe_mul_plus_t<CHAIN, LQ>(fe_mul_t<CHAIN, LQ>(Q.y, P.Z), z1z1, fe_2p_minus(P.Y));  // r / 2, (0, 4p)
+        hh = fe_sqr_t<CHAIN, LQ>(h);        // 16 p^2
         fe i4 = fe_mul4_w(hh);              // [0, 8p)
-        fe j = fe_mul_t<CHAIN>(h, i4);
-        fe v = fe_mul_t<CHAIN>(P.X, i4);
-        R.X = fe_4sub_sub2(fe_sqr_t<CHAIN>(r), j, v);
+        fe j = fe_mul_t<CHAIN>(h, i4);      // 32 p^2: exact digits
+        fe v = fe_mul_t<CHAIN, LQ>(P.X, i4);  // 16 p^2
+        R.X = fe_4sub_sub2(fe_sqr_t<CHAIN, LQ>(r), j, v);
         R.Y = fe_mul_sub2_t<CHAIN>(fe_x2(r), fe_sub_w(v, R.X), P.Y, j);
-        R.Z = fe_mul_t<CHAIN>(P.Z, fe_x2(h));
+        R.Z = fe_mul_t<CHAIN, LQ>(P.Z, fe_x2(h));  // 16 p^2
     } else {
+        fe z1z1 = fe_sqr_t<CHAIN>(P.Z);
         fe u2 = fe_mul_t<CHAIN>(Q.x, z1z1);
         fe s2 = fe_mul_t<CHAIN>(fe_mul_t<CHAIN>(Q.y, P.Z), z1z1);
         fe h = fe_sub_w(u2, P.X);           // (0, 4p)

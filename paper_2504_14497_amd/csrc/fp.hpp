@@ -432,9 +432,61 @@ __device__ __forceinline__ void red_terms(int64_t &acc, const uint32_t *m, int c
     }
 }
 
+// Loose quotient digits (LQ), for products whose operand bounds multiply to
+// at most 16 p^2.  A quotient digit only has to agree with its column
+// modulo 2^29: digits 0..7 take the column's whole low 32 bits (no mask),
+// and the column then drops those 32 bits, its carry being the high half
+// times 8 (one multiply-add instead of a mask and a shift).  With p's digits
+// taken non-negative,
+//   p = -1 + 2^9 B^3 + 2^18 B^6 + (2^29 - 2^21) B^7 + (2^24 - 1) B^8,
+// every reduction term is an unsigned multiply-add below 2^61, so a column
+// (at most 9 products below 2^59, 4 terms, a carry below 2^35) stays below
+// 2^62.7.  Digit 8 keeps its mask, so M = sum m_i 2^(29 i) < R (1 + 2^-26)
+// and the result (a b + M p) / R < a b / R + p (1 + 2^-26) < 2p when
+// a b <= 16 p^2 (then a b / R < p / 2): normal form, as with exact digits.
+struct red_consts_lq {
+    uint32_t k9, k18, k7, k8, eight;
+};
+
+__device__ __forceinline__ red_consts_lq red_consts_lq_make() {
+    red_consts_lq k{1u << 9, 1u << 18, (1u << 29) - (1u << 21), (1u << 24) - 1u, 8u};
+    asm("" : "+s"(k.k9), "+s"(k.k18), "+s"(k.k7), "+s"(k.k8), "+s"(k.eight));
+    return k;
+}
+
 template <bool CHAIN>
+__device__ __forceinline__ void red_terms_lq(int64_t &acc, const uint32_t *m, int c, const red_consts_lq &k) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int j = c - i;
+        if (i >= c) continue;
+        if (j == 3) { acc += (int64_t)((uint64_t)m[i] * k.k9); chain<CHAIN>(acc); }
+        if (j == 6) { acc += (int64_t)((uint64_t)m[i] * k.k18); chain<CHAIN>(acc); }
+        if (j == 7) { acc += (int64_t)((uint64_t)m[i] * k.k7); chain<CHAIN>(acc); }
+        if (j == 8) { acc += (int64_t)((uint64_t)m[i] * k.k8); chain<CHAIN>(acc); }
+    }
+}
+
+// The column step after column c's terms: quotient digit (c < NL) or result
+// limb (c >= NL), then the carry into column c + 1.
+template <bool LQ>
+__device__ __forceinline__ void column_out(int64_t &acc, int c, uint32_t *m, fe &r, uint32_t eight) {
+    if (LQ && c < NL - 1) {
+        m[c] = (uint32_t)acc;
+        acc = (int64_t)((uint64_t)(uint32_t)((uint64_t)acc >> 32) * eight);  // the column is >= 0
+        return;
+    }
+    if (c < NL)
+        m[c] = (uint32_t)acc & LMASK;
+    else
+        r.v[c - NL] = (uint32_t)acc & LMASK;
+    acc >>= LB;  // exact after m p clears the low bits; arithmetic shift
+}
+
+template <bool CHAIN, bool LQ = false>
 __device__ __forceinline__ fe fe_mul_t(const fe &a, const fe &b) {
     const red_consts k = red_consts_make();
+    const red_consts_lq kl = red_consts_lq_make();
     int64_t acc = 0;
     uint32_t m[NL];
     fe r;
@@ -445,20 +497,18 @@ __device__ __forceinline__ fe fe_mul_t(const fe &a, const fe &b) {
             const int j = c - i;
             if (j >= 0 && j < NL) { acc += (int64_t)((uint64_t)a.v[i] * b.v[j]); chain<CHAIN>(acc); }
         }
-        red_terms<CHAIN>(acc, m, c, k);
-        if (c < NL)
-            m[c] = (uint32_t)acc & LMASK;
-        else
-            r.v[c - NL] = (uint32_t)acc & LMASK;
-        acc >>= LB;  // exact after m p clears the low bits; arithmetic shift
+        if constexpr (LQ) red_terms_lq<CHAIN>(acc, m, c, kl);
+        else red_terms<CHAIN>(acc, m, c, k);
+        column_out<LQ>(acc, c, m, r, kl.eight);
     }
     r.v[NL - 1] = (uint32_t)acc;
     return r;
 }
 
-template <bool CHAIN>
+template <bool CHAIN, bool LQ = false>
 __device__ __forceinline__ fe fe_sqr_t(const fe &a) {
     const red_consts k = red_consts_make();
+    const red_consts_lq kl = red_consts_lq_make();
     uint32_t d[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i) d[i] = a.v[i] << 1;
@@ -473,12 +523,9 @@ __device__ __forceinline__ fe fe_sqr_t(const fe &a) {
             if (i < j && j < NL) { acc += (int64_t)((uint64_t)d[i] * a.v[j]); chain<CHAIN>(acc); }
         }
         if ((c & 1) == 0 && c / 2 < NL) { acc += (int64_t)((uint64_t)a.v[c / 2] * a.v[c / 2]); chain<CHAIN>(acc); }
-        red_terms<CHAIN>(acc, m, c, k);
-        if (c < NL)
-            m[c] = (uint32_t)acc & LMASK;
-        else
-            r.v[c - NL] = (uint32_t)acc & LMASK;
-        acc >>= LB;
+        if constexpr (LQ) red_terms_lq<CHAIN>(acc, m, c, kl);
+        else red_terms<CHAIN>(acc, m, c, k);
+        column_out<LQ>(acc, c, m, r, kl.eight);
     }
     r.v[NL - 1] = (uint32_t)acc;
     return r;
@@ -503,9 +550,10 @@ __device__ __forceinline__ fe fe_2p_minus(const fe &x) {
 
 // REDC(a b) + e for e as signed limbs (|e_i| < 2^31): with a b < 4 p^2 and
 // e = 2p - x, the result is a b / R - x (mod p), carry-only, in (0, 4p)
-template <bool CHAIN>
+template <bool CHAIN, bool LQ = false>
 __device__ __forceinline__ fe fe_mul_plus_t(const fe &a, const fe &b, const fe &e) {
     const red_consts k = red_consts_make();
+    const red_consts_lq kl = red_consts_lq_make();
     int64_t acc = 0;
     uint32_t m[NL];
     fe r;
@@ -516,14 +564,10 @@ __device__ __forceinline__ fe fe_mul_plus_t(const fe &a, const fe &b, const fe &
             const int j = c - i;
             if (j >= 0 && j < NL) { acc += (int64_t)((uint64_t)a.v[i] * b.v[j]); chain<CHAIN>(acc); }
         }
-        red_terms<CHAIN>(acc, m, c, k);
-        if (c < NL) {
-            m[c] = (uint32_t)acc & LMASK;
-        } else {
-            acc += (int64_t)(int32_t)e.v[c - NL];
-            r.v[c - NL] = (uint32_t)acc & LMASK;
-        }
-        acc >>= LB;
+        if constexpr (LQ) red_terms_lq<CHAIN>(acc, m, c, kl);
+        else red_terms<CHAIN>(acc, m, c, k);
+        if (c >= NL) acc += (int64_t)(int32_t)e.v[c - NL];
+        column_out<LQ>(acc, c, m, r, kl.eight);
     }
     r.v[NL - 1] = (uint32_t)acc + e.v[NL - 1];
     return r;

@@ -721,14 +721,15 @@ __global__ void __launch_bounds__(256) combo_table_kernel(run_args a) {
 // --------------------------------------------------------------------------
 // Accumulation (persistent)
 // --------------------------------------------------------------------------
-// Affine table entry e of group k for pair p, read from global memory (the
-// lanes of a wavefront share the pair, so they gather from one small table
-// that L1 and L2 serve): x granule, then y granule, three loads each.
-__device__ __forceinline__ void load_entry(const uint32_t *tp, int64_t gstride, int64_t estride, int64_t yoff,
-                                           int32_t v, u32x4 (&en)[4], uint32_t (&e8)[2]) {
-    const int c = (int16_t)(v & 0xFFFF);
-    const int e = (c < 0 ? -c : c) - 1;
-    const uint32_t *ep = tp + (int64_t)(v >> 16) * gstride + (int64_t)e * estride;
+// Table entry of code word v (see pack_codes; nonzero) for pair p, read
+// from global memory (the lanes of a wavefront share the pair, so they
+// gather from one small table that L1 and L2 serve): x granule, then y
+// granule, three loads each.  tp: the chunk's first table for the pair;
+// est: bytes from one entry to the next (below 2^32).
+__device__ __forceinline__ void load_entry(const uint32_t *tp, uint32_t est, int64_t yoff, int32_t v, u32x4 (&en)[4],
+                                           uint32_t (&e8)[2]) {
+    const uint32_t idx = (uint32_t)(v < 0 ? -v : v) - 1u;
+    const uint32_t *ep = (const uint32_t *)((const char *)tp + (uint64_t)idx * est);
     en[0] = *(const u32x4 *)ep;
     en[1] = *(const u32x4 *)(ep + 4);
     e8[0] = ep[8];
@@ -758,8 +759,7 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
     const int32_t *lists = plan_at<int32_t>(a, d.o_lists);
     const int64_t *chunk_off = plan_at<int64_t>(a, d.o_chunk_off);
     const int32_t *chunk_len = plan_at<int32_t>(a, d.o_chunk_len);
-    const int64_t estride = entry_stride(npairs);     // words from one entry of a table to the next
-    const int64_t gstride = (int64_t)emax * estride;  // from one group's tables to the next
+    const uint32_t est = (uint32_t)(entry_stride(npairs) * 4);  // bytes from one entry to the next
     const int64_t yoff = y_offset(npairs);
 
     jpt acc = jpt_infinity();
@@ -776,8 +776,8 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
         int32_t v_nx2 = len > 2 ? lst[2 * (int64_t)m] : 0;
         u32x4 en[4];
         uint32_t e8[2];
-        if ((int16_t)(v_cur & 0xFFFF) != 0) {
-            load_entry(tp, gstride, estride, yoff, v_cur, en, e8);
+        if (v_cur != 0) {
+            load_entry(tp, est, yoff, v_cur, en, e8);
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q) en[q] = u32x4{0u, 0u, 0u, 0u};
@@ -785,23 +785,17 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
         }
         for (int it = 0; it < len; ++it) {
             const int32_t v = v_cur;
-            u32x4 ec[4];
-            uint32_t c8[2];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) ec[q] = en[q];
-            c8[0] = e8[0];
-            c8[1] = e8[1];
+            const u32x4 ec[4] = {en[0], en[1], en[2], en[3]};
+            const uint32_t c8[2] = {e8[0], e8[1]};
             v_cur = v_nxt;
             v_nxt = v_nx2;
             if (it + 3 < len) v_nx2 = lst[(int64_t)(it + 3) * m];
-            if (it + 1 < len && (int16_t)(v_cur & 0xFFFF) != 0) load_entry(tp, gstride, estride, yoff, v_cur, en, e8);
-            const int code = (int16_t)(v & 0xFFFF);
-            if (code == 0) continue;  // padding after the row's last nonzero code
-            const apt Q0 = {{{ec[0].x, ec[0].y, ec[0].z, ec[0].w, ec[1].x, ec[1].y, ec[1].z, ec[1].w, c8[0] & LIMB8_BITS}},
-                            {{ec[2].x, ec[2].y, ec[2].z, ec[2].w, ec[3].x, ec[3].y, ec[3].z, ec[3].w, c8[1]}}};
-            apt Q = Q0;
+            if (it + 1 < len && v_cur != 0) load_entry(tp, est, yoff, v_cur, en, e8);
+            if (v == 0) continue;  // padding after the row's last nonzero code
+            apt Q = {{{ec[0].x, ec[0].y, ec[0].z, ec[0].w, ec[1].x, ec[1].y, ec[1].z, ec[1].w, c8[0] & LIMB8_BITS}},
+                     {{ec[2].x, ec[2].y, ec[2].z, ec[2].w, ec[3].x, ec[3].y, ec[3].z, ec[3].w, c8[1]}}};
             const bool q_inf = (c8[0] & ENTRY_INF) != 0;
-            if (code < 0) Q.y = fe_neg(Q.y);
+            if (v < 0) Q.y = fe_neg(Q.y);
             acc = jpt_add_affine_known(acc, acc_inf, Q, q_inf, acc_inf);
         }
     }
@@ -1164,11 +1158,11 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg, int split) {
     G.gps = P.ngroups > 0 ? (P.ngroups + S - 1) / S : 0;
     // column groups per code list: a split's groups in one list, unless the
     // caller asks for shorter lists (each list is padded to its longest row);
-    // a code word keeps the group's index inside its list in the top 16 bits,
-    // which the kernel reads back signed, so a list covers < 2^15 groups
-    constexpr int MAX_LIST_GROUPS = 32767;
+    // a code word is a signed entry index over the list's groups' tables, so
+    // a list covers fewer than 2^31 / E groups
+    const int max_list_groups = (int)std::min<int64_t>(INT32_MAX - 1, (INT32_MAX - 1) / std::max(P.max_entries, 1));
     G.kc = std::max(1, std::min({cfg && cfg->k_chunk > 0 ? cfg->k_chunk : G.gps, std::max(G.gps, 1),
-                                 MAX_LIST_GROUPS}));
+                                 max_list_groups}));
     G.tile_cost = (double)G.tm * G.pp * G.gps;
     // workspace regions
     const int64_t n_out = (int64_t)m * l;
@@ -1190,14 +1184,17 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg, int split) {
 
 // The accumulation walks, per (split, chunk of kc column groups), only the
 // nonzero codes of each row: slot-major lists lists[(chunk_off + slot) * m
-// + i] = (group in chunk) << 16 | (code & 0xffff), padded with 0 (no
-// operation) up to the chunk's longest row.  A wavefront then runs as many
+// + i] = +-(q E + e + 1) for code +-(e + 1) of the chunk's group q (E: the
+// table stride in entries), i.e. the entry's index over the chunk's tables
+// with the code's sign, padded with 0 (no operation) up to the chunk's
+// longest row.  A wavefront then runs as many
 // mixed additions as its rows' largest count of nonzero codes rather than
 // one per column group, which matters where many codes are zero (small
 // bit-widths).
 void pack_codes(job &G, int threads) {
     const cussen_plan &P = G.P;
     const int m = P.m;
+    const int32_t E = std::max(P.max_entries, 1);  // the kernels' emax
     G.chunks_per_split = G.gps > 0 ? (G.gps + G.kc - 1) / G.kc : 0;
     const int nchunks = G.S * G.chunks_per_split;
     G.chunk_off.assign(nchunks, 0);
@@ -1253,8 +1250,8 @@ void pack_codes(job &G, int threads) {
                 const int16_t *row = &P.codes[(size_t)g * m];
                 for (int i = r0; i < r1; ++i) {
                     if (!row[i]) continue;
-                    G.lists[(size_t)(G.chunk_off[c] + cnt[i - r0]++) * m + i] =
-                        (int32_t)(((uint32_t)(g - g0) << 16) | (uint16_t)row[i]);
+                    const int32_t idx = (int32_t)(g - g0) * E + std::abs((int)row[i]);
+                    G.lists[(size_t)(G.chunk_off[c] + cnt[i - r0]++) * m + i] = row[i] < 0 ? -idx : idx;
                 }
             }
         }
@@ -1572,7 +1569,9 @@ pcmm_status build_plan(const pcmm_problem *probs, int count, pcmm_plan_s &pl) {
     if (!probs || count < 1 || count > MAX_PROBLEMS) return PCMM_EINVAL;
     for (int i = 0; i < count; ++i) {
         const pcmm_problem &q = probs[i];
-        if (q.m < 0 || q.n < 0 || q.l < 0 || (q.c_form != PCMM_AFFINE && q.c_form != PCMM_JACOBIAN) ||
+        // (the accumulation steps between table entries in 32-bit byte strides)
+        if (q.m < 0 || q.n < 0 || q.l < 0 || entry_stride(2 * (int64_t)q.l) * 4 > (int64_t)UINT32_MAX ||
+            (q.c_form != PCMM_AFFINE && q.c_form != PCMM_JACOBIAN) ||
             !valid_cfg(&q.cfg))
             return PCMM_EINVAL;
     }

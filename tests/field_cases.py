@@ -133,6 +133,63 @@ def check_extreme_carry_only_products(raw):
         assert value(out[i]) % P == (x * y * RINV - y) % P
 
 
+def _extreme_rows(bound, n, seed):
+    """Carry-only values below `bound` with limbs 0..7 at or near 2^29 - 1
+    (or random), the largest column sums such operands allow."""
+    rnd = random.Random(seed)
+    rows, vals = [], []
+    top = (bound - 1) >> (LB * 8)
+    while len(rows) < n:
+        mode = len(rows) % 3
+        low = [MASK if mode == 0 else MASK - rnd.randrange(1 << (8 * mode)) for _ in range(8)]
+        if mode == 2 and rnd.random() < 0.5:
+            low = [rnd.randrange(1 << LB) for _ in range(8)]
+        row = low + [rnd.randrange(top + 1)]
+        v = value(row)
+        if v < bound:
+            rows.append(row)
+            vals.append(v)
+    return np.array(rows, dtype=np.int64), vals
+
+
+def check_loose_quotient_products(raw):
+    """Products with loose quotient digits (ops 24-27; the mixed addition of
+    the accumulation uses them where its operand bounds multiply to at most
+    16 p^2): random normal operands and carry-only operands at the largest
+    limbs their bounds allow.  Each result must equal the product times
+    R^-1 modulo p and be in normal form (op 26: carry-only in (0, 4p))."""
+    a, b = _operands(3000, 12)
+    A = np.array([limbs(v) for v in a], dtype=np.int64)
+    B = np.array([limbs(v) for v in b], dtype=np.int64)
+    for op, f in {24: lambda x, y: (x * y * RINV) % P, 25: lambda x, y: (x * x * RINV) % P}.items():
+        out = raw(op, A, B)
+        _check_normal(out)
+        bad = [i for i in range(len(a)) if value(out[i]) % P != f(a[i], b[i])]
+        assert not bad, (op, bad[:5])
+    out = raw(26, A, B)
+    _check_normal(out, 4 * P, 26)
+    bad = [i for i in range(len(a)) if value(out[i]) % P != (a[i] * b[i] * RINV - b[i]) % P]
+    assert not bad, bad[:5]
+    # carry-only operands: (< 4p) x (< 4p), (< 4p)^2, (< 8p) x (< 2p), and
+    # (< 2p) x 2 (< 4p) with the doubled operand's limbs below 2^30
+    R4, v4 = _extreme_rows(4 * P, 2000, 21)
+    R8, v8 = _extreme_rows(8 * P, 2000, 22)
+    R2, v2 = _extreme_rows(2 * P, 2000, 23)
+    keep = [i for i in range(len(v2)) if R2[i, 8] < (1 << 25)]
+    R2, v2 = R2[keep], [v2[i] for i in keep]
+    cases = [
+        (24, R4, R4[::-1].copy(), v4, v4[::-1], lambda x, y: x * y),
+        (25, R4, R4, v4, v4, lambda x, y: x * x),
+        (24, R8[:len(v2)], R2, v8[:len(v2)], v2, lambda x, y: x * y),
+        (27, R2, R4[:len(v2)], v2, v4[:len(v2)], lambda x, y: 2 * x * y),
+    ]
+    for op, X, Y, vx, vy, f in cases:
+        out = raw(op, X, Y)
+        _check_normal(out)
+        bad = [i for i in range(len(vx)) if value(out[i]) % P != (f(vx[i], vy[i]) * RINV) % P]
+        assert not bad, (op, bad[:5])
+
+
 def check_signed_limb_normalisation(raw):
     rnd = random.Random(5)
     rows, vals = [], []

@@ -99,6 +99,10 @@ int hs_field_raw(int op, const uint32_t *a, const uint32_t *b, uint32_t *out) {
         case 21: r = fe_mul_ilp(x, y); break;
         case 22: r = fe_sqr_ilp(x); break;
         case 23: r = fe_inv(x); break;
+        case 24: r = fe_mul_t<true, true>(x, y); break;
+        case 25: r = fe_sqr_t<true, true>(x); break;
+        case 26: r = fe_mul_plus_t<true, true>(x, y, fe_2p_minus(y)); break;
+        case 27: r = fe_mul_t<true, true>(x, fe_x2(y)); break;
         default: return -1;
     }
     for (int i = 0; i < NL; ++i) out[i] = r.v[i];

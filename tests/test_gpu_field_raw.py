@@ -29,5 +29,12 @@ def test_raw_products_of_extreme_carry_only_operands(dev):
     FC.check_extreme_carry_only_products(dev.diag_field_raw)
 
 
+def test_loose_quotient_products(dev):
+    """Products with loose quotient digits (the accumulation's mixed
+    addition): random normal operands and carry-only operands at the largest
+    limbs their bounds allow; exact value and normal form."""
+    FC.check_loose_quotient_products(dev.diag_field_raw)
+
+
 def test_raw_normalisation_of_signed_limbs(dev):
     FC.check_signed_limb_normalisation(dev.diag_field_raw)

@@ -33,6 +33,10 @@ def test_host_raw_products_of_extreme_carry_only_operands(host):
     FC.check_extreme_carry_only_products(host.field_raw)
 
 
+def test_host_loose_quotient_products(host):
+    FC.check_loose_quotient_products(host.field_raw)
+
+
 def test_host_raw_normalisation_of_signed_limbs(host):
     FC.check_signed_limb_normalisation(host.field_raw)
 

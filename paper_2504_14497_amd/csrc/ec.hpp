@@ -136,19 +136,22 @@ template <bool CHAIN, bool LEAN>
 __device__ __forceinline__ jpt madd_formulas(const jpt &P, const apt &Q, fe &hh, fe &r) {
     jpt R;
     if constexpr (LEAN) {
-        // every product but J = H I and the Y3 pair has operand bounds
-        // multiplying to at most 16 p^2, so it takes loose quotient digits
+        // Every product takes loose quotient digits (fp.hpp): a loose
+        // product of a b is below a b / R + p (1 + 2^-26), which gives the
+        // bounds in the comments (P's coordinates and Q normal, < 2p), and
+        // the largest operand-bound product, 24.3 p^2 for Y3, is below the
+        // 31.99 p^2 that keeps a loose result in normal form.
         constexpr bool LQ = true;
-        fe z1z1 = fe_sqr_t<CHAIN, LQ>(P.Z);                                                      // 4 p^2
-        fe h = fe_mul_plus_t<CHAIN, LQ>(Q.x, z1z1, fe_2p_minus(P.X));                            // (0, 4p)
-        r = fe_mul_plus_t<CHAIN, LQ>(fe_mul_t<CHAIN, LQ>(Q.y, P.Z), z1z1, fe_2p_minus(P.Y));  // r / 2, (0, 4p)
-        hh = fe_sqr_t<CHAIN, LQ>(h);        // 16 p^2
-        fe i4 = fe_mul4_w(hh);              // [0, 8p)
-        fe j = fe_mul_t<CHAIN>(h, i4);      // 32 p^2: exact digits
-        fe v = fe_mul_t<CHAIN, LQ>(P.X, i4);  // 16 p^2
+        fe z1z1 = fe_sqr_t<CHAIN, LQ>(P.Z);                                                      // < 1.13p
+        fe h = fe_mul_plus_t<CHAIN, LQ>(Q.x, z1z1, fe_2p_minus(P.X));                            // (0, 3.08p)
+        r = fe_mul_plus_t<CHAIN, LQ>(fe_mul_t<CHAIN, LQ>(Q.y, P.Z), z1z1, fe_2p_minus(P.Y));  // r / 2, (0, 3.05p)
+        hh = fe_sqr_t<CHAIN, LQ>(h);        // 9.5 p^2 -> < 1.3p
+        fe i4 = fe_mul4_w(hh);              // [0, 5.2p)
+        fe j = fe_mul_t<CHAIN, LQ>(h, i4);  // 16 p^2 -> < 1.5p
+        fe v = fe_mul_t<CHAIN, LQ>(P.X, i4);  // 10.4 p^2
         R.X = fe_4sub_sub2(fe_sqr_t<CHAIN, LQ>(r), j, v);
-        R.Y = fe_mul_sub2_t<CHAIN>(fe_x2(r), fe_sub_w(v, R.X), P.Y, j);
-        R.Z = fe_mul_t<CHAIN, LQ>(P.Z, fe_x2(h));  // 16 p^2
+        R.Y = fe_mul_sub2_t<CHAIN, LQ>(fe_x2(r), fe_sub_w(v, R.X), P.Y, j);  // 6.1p x 4p, folded
+        R.Z = fe_mul_t<CHAIN, LQ>(P.Z, fe_x2(h));  // 2p x 6.2p
     } else {
         fe z1z1 = fe_sqr_t<CHAIN>(P.Z);
         fe u2 = fe_mul_t<CHAIN>(Q.x, z1z1);

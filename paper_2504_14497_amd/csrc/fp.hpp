@@ -432,18 +432,18 @@ __device__ __forceinline__ void red_terms(int64_t &acc, const uint32_t *m, int c
     }
 }
 
-// Loose quotient digits (LQ), for products whose operand bounds multiply to
-// at most 16 p^2.  A quotient digit only has to agree with its column
-// modulo 2^29: digits 0..7 take the column's whole low 32 bits (no mask),
-// and the column then drops those 32 bits, its carry being the high half
-// times 8 (one multiply-add instead of a mask and a shift).  With p's digits
-// taken non-negative,
+// Loose quotient digits (LQ).  A quotient digit only has to agree with its
+// column modulo 2^29: digits 0..7 take the column's whole low 32 bits (no
+// mask), and the column then drops those 32 bits, its carry being the
+// (signed) high half times 8 (one multiply-add instead of a mask and a
+// shift).  With p's digits taken non-negative,
 //   p = -1 + 2^9 B^3 + 2^18 B^6 + (2^29 - 2^21) B^7 + (2^24 - 1) B^8,
 // every reduction term is an unsigned multiply-add below 2^61, so a column
 // (at most 9 products below 2^59, 4 terms, a carry below 2^35) stays below
 // 2^62.7.  Digit 8 keeps its mask, so M = sum m_i 2^(29 i) < R (1 + 2^-26)
-// and the result (a b + M p) / R < a b / R + p (1 + 2^-26) < 2p when
-// a b <= 16 p^2 (then a b / R < p / 2): normal form, as with exact digits.
+// and the result (a b + M p) / R < a b / R + p (1 + 2^-26): normal form
+// (< 2p) when a b / R < p (1 - 2^-26), i.e. for operand bounds multiplying
+// to at most 31.99 p^2 (exact digits allow 32 p^2).
 struct red_consts_lq {
     uint32_t k9, k18, k7, k8, eight;
 };
@@ -473,7 +473,7 @@ template <bool LQ>
 __device__ __forceinline__ void column_out(int64_t &acc, int c, uint32_t *m, fe &r, uint32_t eight) {
     if (LQ && c < NL - 1) {
         m[c] = (uint32_t)acc;
-        acc = (int64_t)((uint64_t)(uint32_t)((uint64_t)acc >> 32) * eight);  // the column is >= 0
+        acc = (int64_t)(int32_t)(acc >> 32) * (int64_t)(int32_t)eight;  // |column| < 2^63
         return;
     }
     if (c < NL)
@@ -590,11 +590,13 @@ __device__ __forceinline__ fe fe_fold(fe x) {
 // above column 8, and the result is folded into [0, 2p).  For a with limbs
 // < 2^30 (fe_x2 of a carry-only value), b carry-only, c and d normal: each
 // part of a column is below 9 2^59 in magnitude, so partial sums stay within
-// 2^62.2; a b < 32 p^2 and 2 c d < 8 p^2 give a b - 2 c d + p R > 0 and a
-// reduced value in (0, 3p) before the fold.
-template <bool CHAIN>
+// 2^62.2 (2^62.7 with loose quotient digits); a b < 32 p^2 and 2 c d < 8 p^2
+// give a b - 2 c d + p R > 0 and a reduced value in (0, 3p) before the fold
+// (below 3p (1 + 2^-26) with loose digits: still carry-only below 2^260).
+template <bool CHAIN, bool LQ = false>
 __device__ __forceinline__ fe fe_mul_sub2_t(const fe &a, const fe &b, const fe &c, const fe &d) {
     const red_consts k = red_consts_make();
+    const red_consts_lq kl = red_consts_lq_make();
     int32_t nc[NL];
     int32_t d2[NL];
 #pragma unroll
@@ -617,14 +619,10 @@ __device__ __forceinline__ fe fe_mul_sub2_t(const fe &a, const fe &b, const fe &
                 chain<CHAIN>(acc);
             }
         }
-        red_terms<CHAIN>(acc, m, col, k);
-        if (col < NL) {
-            m[col] = (uint32_t)acc & LMASK;
-        } else {
-            acc += (int64_t)P29.v[col - NL];
-            r.v[col - NL] = (uint32_t)acc & LMASK;
-        }
-        acc >>= LB;
+        if constexpr (LQ) red_terms_lq<CHAIN>(acc, m, col, kl);
+        else red_terms<CHAIN>(acc, m, col, k);
+        if (col >= NL) acc += (int64_t)P29.v[col - NL];
+        column_out<LQ>(acc, col, m, r, kl.eight);
     }
     r.v[NL - 1] = (uint32_t)acc + P29.v[NL - 1];
     return fe_fold(r);

@@ -153,11 +153,12 @@ def _extreme_rows(bound, n, seed):
 
 
 def check_loose_quotient_products(raw):
-    """Products with loose quotient digits (ops 24-27; the mixed addition of
-    the accumulation uses them where its operand bounds multiply to at most
-    16 p^2): random normal operands and carry-only operands at the largest
-    limbs their bounds allow.  Each result must equal the product times
-    R^-1 modulo p and be in normal form (op 26: carry-only in (0, 4p))."""
+    """Products with loose quotient digits (ops 24-28; the mixed addition of
+    the accumulation takes all its products in this form): random normal
+    operands and carry-only operands at the largest limbs their bounds
+    allow, up to 16 p^2 and 32 p^2 for the folded op 28.  Each result must
+    equal the product times R^-1 modulo p and be in normal form (op 26:
+    carry-only in (0, 4p))."""
     a, b = _operands(3000, 12)
     A = np.array([limbs(v) for v in a], dtype=np.int64)
     B = np.array([limbs(v) for v in b], dtype=np.int64)
@@ -188,6 +189,13 @@ def check_loose_quotient_products(raw):
         _check_normal(out)
         bad = [i for i in range(len(vx)) if value(out[i]) % P != (f(vx[i], vy[i]) * RINV) % P]
         assert not bad, (op, bad[:5])
+    # (2a) b - 2 b' b' with one reduction and a fold, a and b below 4p
+    Yr = R4[::-1].copy()
+    out = raw(28, R4, Yr)
+    _check_normal(out)
+    vb = v4[::-1]
+    bad = [i for i in range(len(v4)) if value(out[i]) % P != (2 * (v4[i] - vb[i]) * vb[i] * RINV) % P]
+    assert not bad, bad[:5]
 
 
 def check_signed_limb_normalisation(raw):

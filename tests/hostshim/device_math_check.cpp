@@ -103,6 +103,7 @@ int hs_field_raw(int op, const uint32_t *a, const uint32_t *b, uint32_t *out) {
         case 25: r = fe_sqr_t<true, true>(x); break;
         case 26: r = fe_mul_plus_t<true, true>(x, y, fe_2p_minus(y)); break;
         case 27: r = fe_mul_t<true, true>(x, fe_x2(y)); break;
+        case 28: r = fe_mul_sub2_t<true, true>(fe_x2(x), y, fe_norm(y), fe_norm(y)); break;
         default: return -1;
     }
     for (int i = 0; i < NL; ++i) out[i] = r.v[i];

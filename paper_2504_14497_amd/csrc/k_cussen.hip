@@ -537,6 +537,11 @@ __device__ __forceinline__ fe chord_dx(const fe &xb, const fe &xa, bool &ne) {
 // has one.
 constexpr int CB = COMBO_BLOCK;
 
+// The passes' products take loose quotient digits (fp.hpp): every operand
+// pair is below 16 p^2 (normal values, carry-only differences below 4p).
+__device__ __forceinline__ fe fe_mul_lq(const fe &a, const fe &b) { return fe_mul_t<false, true>(a, b); }
+__device__ __forceinline__ fe fe_sqr_lq(const fe &a) { return fe_sqr_t<false, true>(a); }
+
 template <bool SAFE>
 __device__ __forceinline__ fe combo_forward(const plan_cblock *blocks, const plan_crun *runs, int b0, int b1,
                                             uint32_t *tab, int64_t estride, bool &pending) {
@@ -582,7 +587,7 @@ __device__ __forceinline__ fe combo_forward(const plan_cblock *blocks, const pla
                 if (present && first < 0) first = r;
                 if (present && !chord[r]) pending = true;
                 const fe f = fe_select(chord[r], one, dx);
-                t = r == 0 ? f : fe_mul_ilp(t, f);
+                t = r == 0 ? f : fe_mul_lq(t, f);
             }
 #pragma unroll
             for (int r = 0; r < CB; ++r) {
@@ -592,7 +597,7 @@ __device__ __forceinline__ fe combo_forward(const plan_cblock *blocks, const pla
                     tab[run.dst[r] * estride + NL - 1] = ENTRY_PENDING;
                 }
             }
-            prod = fe_mul_ilp(prod, t);
+            prod = fe_mul_lq(prod, t);
         }
     }
     return prod;
@@ -615,19 +620,28 @@ __device__ __forceinline__ void combo_backward(const plan_cblock *blocks, const 
                 ainf[r] = true;
             }
         }
+        // a run's second operand and its stored prefix are loaded one run
+        // ahead, before the current run's stores (the wait for a load also
+        // waits for the memory operations issued before it)
+        auto prefix_slot = [&](const plan_crun &rn) {
+            int first = 0;
+            while (rn.dst[first] < 0) ++first;
+            return tab + rn.dst[first] * estride;
+        };
         plan_crun nr = runs[blk.run_end - 1];
         bool nbinf;
         apt nb = read_entry(tab + nr.b * estride, yoff, nbinf);
+        fe npre = load_gran(prefix_slot(nr));
         for (int ri = blk.run_end - 1; ri >= blk.run_begin; --ri) {
             const plan_crun run = nr;
             const apt Bv = nb;
             const bool binf = nbinf;
+            fe cur = npre;
             if (ri > blk.run_begin) {
                 nr = runs[ri - 1];
                 nb = read_entry(tab + nr.b * estride, yoff, nbinf);
+                npre = load_gran(prefix_slot(nr));
             }
-            int first = 0;
-            while (run.dst[first] < 0) ++first;
             // the prefix before each combination of the run, then every
             // combination's 1/dx (newest first, the inverse chain), then
             // the chord sums; branch-free, so the run's independent chains
@@ -636,7 +650,6 @@ __device__ __forceinline__ void combo_backward(const plan_cblock *blocks, const 
             const fe one = fe_one_mont();
             fe q[CB], dx[CB], dinv[CB];
             bool chord[CB];
-            fe cur = load_gran(tab + run.dst[first] * estride);
             cur.v[NL - 1] &= LIMB8_BITS;
 #pragma unroll
             for (int r = 0; r < CB; ++r) {
@@ -644,21 +657,21 @@ __device__ __forceinline__ void combo_backward(const plan_cblock *blocks, const 
                 dx[r] = chord_dx<SAFE>(Bv.x, A[r].x, ne);
                 chord[r] = run.dst[r] >= 0 && !ainf[r] && !binf && ne;
                 q[r] = cur;
-                if (r + 1 < CB) cur = fe_mul_ilp(cur, fe_select(chord[r], one, dx[r]));
+                if (r + 1 < CB) cur = fe_mul_lq(cur, fe_select(chord[r], one, dx[r]));
             }
 #pragma unroll
             for (int r = CB - 1; r >= 0; --r) {
-                dinv[r] = fe_mul_ilp(inv, q[r]);
-                inv = fe_mul_ilp(inv, fe_select(chord[r], one, dx[r]));
+                dinv[r] = fe_mul_lq(inv, q[r]);
+                inv = fe_mul_lq(inv, fe_select(chord[r], one, dx[r]));
             }
 #pragma unroll
             for (int r = 0; r < CB; ++r) {
                 // y_b - y_a, or -y_b - y_a for a subtracted b: carry-only
                 const fe dy = ((run.neg >> r) & 1) ? fe_neg_sub_w(Bv.y, A[r].y) : fe_sub_w(Bv.y, A[r].y);
-                const fe lam = fe_mul_ilp(dy, dinv[r]);
+                const fe lam = fe_mul_lq(dy, dinv[r]);
                 apt R;
-                R.x = fe_sub_sub(fe_sqr_ilp(lam), A[r].x, Bv.x);
-                R.y = fe_sub(fe_mul_ilp(lam, fe_sub_w(A[r].x, R.x)), A[r].y);
+                R.x = fe_sub_sub(fe_sqr_lq(lam), A[r].x, Bv.x);
+                R.y = fe_sub(fe_mul_lq(lam, fe_sub_w(A[r].x, R.x)), A[r].y);
                 if (chord[r]) write_entry(tab + run.dst[r] * estride, yoff, R, false);
             }
         }

@@ -196,9 +196,11 @@ __device__ __forceinline__ void reg_store(uint32_t *regs, int rmax, int64_t n_la
     store_jac_m(regs + (int64_t)(r * rmax + reg) * JAC_WORDS * n_lanes, n_lanes, 0, lane, P);
 }
 
-// One op of a group's straight-line program for output column j, point pt
-// and chain r: reads its operands (registers or the group's base points
-// B[k0 + t, j]) and writes its destination register.  The previous op's
+// One op of a column's straight-line program for output column j, point pt
+// and chain r: reads its operands (registers or the column's base point
+// B[k0, j], loaded once per chain: every negative operand of a unit's
+// program names it, which the plan check enforces) and writes its
+// destination register.  The previous op's
 // result stays in VGPRs (`last`, register `last_reg`): a prefix sum's first
 // operand is the sum before it, so most operands need no reload.
 __device__ __forceinline__ jpt op_reg(const uint32_t *regs, int rmax, int64_t n_lanes, int r, int reg, int64_t lane,
@@ -206,29 +208,26 @@ __device__ __forceinline__ jpt op_reg(const uint32_t *regs, int rmax, int64_t n_
     return reg == last_reg ? last : reg_load(regs, rmax, n_lanes, r, reg, lane);
 }
 
-__device__ __forceinline__ void run_op(const plan_op op, const uint32_t *__restrict__ B, int64_t ldb, int l, int k0,
-                                       int j, int pt, uint32_t *regs, int rmax, int64_t n_lanes, int r,
-                                       int64_t lane, jpt &last, int &last_reg) {
+__device__ __forceinline__ void run_op(const plan_op op, const apt &base, uint32_t *regs, int rmax, int64_t n_lanes,
+                                       int r, int64_t lane, jpt &last, int &last_reg) {
     jpt R;
     if (op.kind == OP_MUL) {
         const int s = op.s;
         const int bits = 32 - __builtin_clz((unsigned)s);
-        R = ladder_small<false>((uint32_t)s, bits, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
+        R = ladder_small<false>((uint32_t)s, bits, base);
     } else if (op.a >= 0 && op.b >= 0) {
         jpt Q = op_reg(regs, rmax, n_lanes, r, op.b, lane, last, last_reg);
         if (op.neg_b) Q = jpt_neg(Q);
         R = jpt_add<false>(op_reg(regs, rmax, n_lanes, r, op.a, lane, last, last_reg), Q);
     } else if (op.b < 0) {
-        apt Q = load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.b) * l + j);
-        if (op.neg_b) Q = apt_neg(Q);
-        jpt P = op.a >= 0 ? op_reg(regs, rmax, n_lanes, r, op.a, lane, last, last_reg)
-                          : jpt_from_affine(load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
+        const apt Q = op.neg_b ? apt_neg(base) : base;
+        jpt P = op.a >= 0 ? op_reg(regs, rmax, n_lanes, r, op.a, lane, last, last_reg) : jpt_from_affine(base);
         R = jpt_add_affine<false>(P, Q);
     } else {
-        // a is a base point, b a register: a + (+-b) = (+-b) + a
+        // a is the base point, b a register: a + (+-b) = (+-b) + a
         jpt Q = op_reg(regs, rmax, n_lanes, r, op.b, lane, last, last_reg);
         if (op.neg_b) Q = jpt_neg(Q);
-        R = jpt_add_affine<false>(Q, load_affine(B, ldb, pt, (int64_t)(k0 - 1 - op.a) * l + j));
+        R = jpt_add_affine<false>(Q, base);
     }
     reg_store(regs, rmax, n_lanes, r, op.dst, lane, R);
     last = R;
@@ -237,9 +236,9 @@ __device__ __forceinline__ void run_op(const plan_op op, const uint32_t *__restr
 
 // Operand of a single-column program (a register, or the base point B_kj)
 // as a Jacobian point.
-__device__ __forceinline__ jpt operand_point(int16_t opd, const uint32_t *B, int64_t ldb, int l, int k0, int j,
-                                             int pt, const uint32_t *regs, int rmax, int64_t n_lanes, int64_t lane) {
-    if (opd < 0) return jpt_from_affine(load_affine(B, ldb, pt, (int64_t)(k0 - 1 - opd) * l + j));
+__device__ __forceinline__ jpt operand_point(int16_t opd, const apt &base, const uint32_t *regs, int rmax,
+                                             int64_t n_lanes, int64_t lane) {
+    if (opd < 0) return jpt_from_affine(base);
     return reg_load(regs, rmax, n_lanes, 0, opd, lane);
 }
 
@@ -290,14 +289,15 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
     // levels >= 2, on every lane (each keeps its own register column)
     jpt last = jpt_infinity();
     int last_reg = -1;
-    for (int o = ob; o < ofirst; ++o) run_op(ops[o], B, ldb, l, k0, j, pt, regs, rmax, n_lanes, 0, lane, last, last_reg);
+    const apt base = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
+    for (int o = ob; o < ofirst; ++o) run_op(ops[o], base, regs, rmax, n_lanes, 0, lane, last, last_reg);
     auto opd_of = [&](int i) -> int16_t { return i == 0 ? entries[eb] : ops[ofirst + i - 1].b; };
     // this lane's block of the chain: its total first
     const int bs = (E + W - 1) / W;
     const int i0 = min(E, w * bs), i1 = min(E, i0 + bs);
     jpt acc = jpt_infinity();
     for (int i = i0; i < i1; ++i) {
-        const jpt bi = operand_point(opd_of(i), B, ldb, l, k0, j, pt, regs, rmax, n_lanes, lane);
+        const jpt bi = operand_point(opd_of(i), base, regs, rmax, n_lanes, lane);
         acc = i == i0 ? bi : jpt_add<false>(acc, bi);
     }
     // inclusive scan of the block totals over the chain's W lanes, then the
@@ -318,7 +318,7 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
     jpt S = excl;
     for (int i = i0; i < i1; ++i) {
         const int16_t opd_b = opd_of(i);
-        const jpt bi = operand_point(opd_b, B, ldb, l, k0, j, pt, regs, rmax, n_lanes, lane);
+        const jpt bi = operand_point(opd_b, base, regs, rmax, n_lanes, lane);
         S = (w == 0 && i == i0) ? bi : jpt_add<false>(S, bi);
         const int16_t opd = entries[eb + i];
         if (opd < 0) continue;  // S_0 = B_kj: affine already
@@ -332,7 +332,7 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
         uint32_t *slot = tab + i * estride;
         apt A;
         if (opd < 0) {
-            A = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
+            A = base;
         } else {
             const jpt P = reg_load(regs, rmax, n_lanes, 0, opd, lane);
             const fe pre = load_gran(slot);
@@ -403,6 +403,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
         jpt last = jpt_infinity();
         int last_reg = -1;
         uint32_t *tab = entry_at(table, npairs, emax, grp, off, 2 * j + pt);
+        const apt base = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
         // forward pass of the batched inversion, folded into the program: the
         // plan orders a group's entries by their producing ops, so the next
         // register entry is always the next one an op produces, and its Z
@@ -412,7 +413,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
         while (ne < E && entries[eb + ne] < 0) ++ne;
         for (int o = ob; o < oe; ++o) {
             const plan_op op = ops[o];
-            run_op(op, B, ldb, l, k0, j, pt, regs, rmax, n_lanes, r, lane, last, last_reg);
+            run_op(op, base, regs, rmax, n_lanes, r, lane, last, last_reg);
             if (ne < E && op.dst == entries[eb + ne]) {
                 store_gran(tab + ne * estride, prod, 0u);
                 if (!fe_is_zero(last.Z)) prod = fe_mul_ilp(prod, last.Z);
@@ -426,25 +427,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
     for (int r = last_r; r >= 0; --r) {
         const int j = jslot + r * d.Lj;
         uint32_t *tab = entry_at(table, npairs, emax, grp, off, 2 * j + pt);
+        const apt base = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
+        // an entry's register and stored prefix are loaded one entry ahead,
+        // before the current entry's stores (the wait for a load also waits
+        // for the memory operations issued before it)
+        jpt nP = jpt_infinity();
+        fe npre = fe_zero();
+        auto fetch = [&](int e) {
+            const int16_t opd = entries[eb + e];
+            if (opd >= 0) {
+                nP = reg_load(regs, rmax, n_lanes, r, opd, lane);
+                npre = load_gran(tab + e * estride);
+            }
+        };
+        if (E > 0) fetch(E - 1);
         for (int e = E - 1; e >= 0; --e) {
             const int16_t opd = entries[eb + e];
-            uint32_t *slot = tab + e * estride;
+            const jpt P = nP;
+            const fe pre = npre;
+            if (e > 0) fetch(e - 1);
             apt A;
             if (opd < 0) {
-                A = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
+                A = base;
+            } else if (fe_is_zero(P.Z)) {
+                A.x = fe_zero();
+                A.y = fe_zero();
             } else {
-                jpt P = reg_load(regs, rmax, n_lanes, r, opd, lane);
-                const fe pre = load_gran(slot);
-                if (fe_is_zero(P.Z)) {
-                    A.x = fe_zero();
-                    A.y = fe_zero();
-                } else {
-                    fe zinv = fe_mul_ilp(inv, pre);
-                    inv = fe_mul_ilp(inv, P.Z);
-                    A = jpt_to_affine_with(P, zinv);
-                }
+                fe zinv = fe_mul_ilp(inv, pre);
+                inv = fe_mul_ilp(inv, P.Z);
+                A = jpt_to_affine_with(P, zinv);
             }
-            write_entry(slot, yoff, A, apt_is_inf(A));
+            write_entry(tab + e * estride, yoff, A, apt_is_inf(A));
         }
     }
 }

@@ -218,6 +218,14 @@ __device__ __forceinline__ jpt jpt_add_affine_known(const jpt &P, bool p_inf, co
     return R;
 }
 
+// P + Q with Q affine, complete, in the lean form (the flags computed here):
+// for dependent chains, whose latency tracks the products' instruction count.
+template <bool CHAIN = true>
+__device__ __forceinline__ jpt jpt_add_affine_lean(const jpt &P, const apt &Q) {
+    bool r_inf;
+    return jpt_add_affine_known<CHAIN>(P, jpt_is_inf(P), Q, apt_is_inf(Q), r_inf);
+}
+
 // P + Q, both Jacobian (add-2007-bl), complete.  Lazy reduction as in
 // jpt_add_affine; I = (2H)^2 is computed as 4 H^2 and Z3 =
 // ((Z1 + Z2)^2 - Z1Z1 - Z2Z2) H as the equal 2 Z1 Z2 H.

@@ -85,7 +85,8 @@ struct prob_desc {
     int64_t o_ops, o_op_begin, o_entry_begin, o_entries;
     int64_t o_unit_col, o_unit_grp, o_unit_off, o_cblock_begin, o_cblocks, o_cruns;
     int64_t o_lists, o_chunk_off, o_chunk_len;  // nonzero codes per (split, chunk), see pack_codes
-    int32_t chunks_per_split, pad2;
+    int32_t chunks_per_split;
+    int32_t direct;  // one column group, one split, affine C: each output is one table entry
     int64_t w_regs, w_table, w_part, w_cjac, w_norm;
 };
 
@@ -222,12 +223,12 @@ __device__ __forceinline__ void run_op(const plan_op op, const apt &base, uint32
     } else if (op.b < 0) {
         const apt Q = op.neg_b ? apt_neg(base) : base;
         jpt P = op.a >= 0 ? op_reg(regs, rmax, n_lanes, r, op.a, lane, last, last_reg) : jpt_from_affine(base);
-        R = jpt_add_affine<false>(P, Q);
+        R = jpt_add_affine_lean<false>(P, Q);
     } else {
         // a is the base point, b a register: a + (+-b) = (+-b) + a
         jpt Q = op_reg(regs, rmax, n_lanes, r, op.b, lane, last, last_reg);
         if (op.neg_b) Q = jpt_neg(Q);
-        R = jpt_add_affine<false>(Q, base);
+        R = jpt_add_affine_lean<false>(Q, base);
     }
     reg_store(regs, rmax, n_lanes, r, op.dst, lane, R);
     last = R;
@@ -829,6 +830,13 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
     const int64_t e_out = (int64_t)i * l + j;
     if (d.S > 1) {
         store_jac_m(at<uint32_t>(a, d.w_part) + (int64_t)bz * JAC2_PLANES * d.ldj, d.ldj, pt, e_out, acc);
+    } else if (d.direct) {
+        // the row's only entry was added to the identity, so acc = (x, y, 1)
+        // or the identity: already affine
+        apt A;
+        A.x = acc_inf ? fe_zero() : acc.X;
+        A.y = acc_inf ? fe_zero() : acc.Y;
+        store_affine(a.io[d.io].C, a.io[d.io].ldc, pt, e_out, A);
     } else if (d.c_form == PCMM_AFFINE) {
         store_jac_m(at<uint32_t>(a, d.w_cjac), d.ldj, pt, e_out, acc);
     } else {
@@ -1097,6 +1105,7 @@ struct job {
     int tm = 256, pp = 1, kc = 1, S = 1, gps = 0, tiles_x = 1, tiles_y = 1;
     int64_t ldj = 64, norm_threads = 0, ld_pre = 0;
     int norm_per = 0;
+    bool direct = false;  // see prob_desc::direct
     size_t regs_bytes = 0, table_bytes = 0, part_bytes = 0, cjac_bytes = 0, norm_bytes = 0;
     size_t footprint = 0;  // workspace bytes of this problem's regions
     double tile_cost = 0;
@@ -1161,15 +1170,22 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg, int split) {
     G.n_lanes = (int64_t)P.nunits * 2 * G.Lj;
     G.n_lanes_pad = G.Lj_pad ? (int64_t)P.nunits * 2 * G.Lj_pad : 0;
     G.cb_lanes = P.combos.empty() ? 0 : (int64_t)P.ngroups * 2 * l;
-    // a padded unit has 64 lanes for its 2 l chains: W = 64 / (2 l) lanes (a
-    // power of two, blocks of >= 4 entries on average) split each level-1
-    // chain as a parallel scan instead of idling; the depth, about 2 E / W +
-    // log2 W additions, beats E only from W = 4
+    // a padded unit has 64 lanes for its 2 l chains: up to W = 64 / (2 l)
+    // lanes (a power of two) split each level-1 chain as a parallel scan
+    // instead of idling, with W chosen by the chain's depth
     G.coop_w = 0;
     if (G.Lj_pad && l >= 1 && level1_chains(P)) {
-        int W = 1;
-        while (W * 2 * 2 * l <= 64 && W * 2 * 4 <= avg_e) W *= 2;
-        if (W >= 4) G.coop_w = W;
+        // chain depth in mixed additions: E - 1 alone; with W lanes about
+        // 2 E / W block and prefix additions plus log2 W scan steps, general
+        // additions of about 1.45 times the products each
+        auto depth = [&](int W) {
+            if (W == 1) return std::max(avg_e - 1.0, 0.0);
+            return 1.45 * (2.0 * std::ceil(avg_e / W) + std::log2((double)W));
+        };
+        int best = 1;
+        for (int W = 2; W * 2 * l <= 64; W *= 2)
+            if (depth(W) < depth(best)) best = W;
+        if (best >= 2) G.coop_w = best;
     }
     // accumulation tile and the split of the inner dimension
     const int npairs = 2 * l;
@@ -1198,8 +1214,14 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg, int split) {
     G.table_bytes = (size_t)P.ngroups * npairs * emax * ENTRY_WORDS * 4;
     G.part_bytes = S > 1 ? (size_t)S * JAC2_PLANES * G.ldj * 4 : 0;
     const bool affine = G.c_form == PCMM_AFFINE;
-    G.cjac_bytes = affine ? (size_t)JAC2_PLANES * G.ldj * 4 : 0;
-    if (affine) {
+    // one column group and one split: a row's output is its single table
+    // entry (affine already, or the identity), written without normalisation
+    G.direct = affine && P.ngroups <= 1 && S == 1;
+    G.cjac_bytes = affine && !G.direct ? (size_t)JAC2_PLANES * G.ldj * 4 : 0;
+    G.norm_threads = G.norm_per = 0;
+    G.ld_pre = 0;
+    G.norm_bytes = 0;
+    if (affine && !G.direct) {
         normalize_geometry(n_out, &G.norm_threads, &G.norm_per);
         G.ld_pre = G.norm_threads * G.norm_per * 2;
         G.norm_bytes = normalize_scratch_bytes(n_out, 2);
@@ -1233,7 +1255,9 @@ void pack_codes(job &G, int threads) {
     // rows are independent (each owns one column of every list): ranges of
     // rows on up to `threads` threads, first for the lists' lengths, then to
     // fill them
-    const int nthreads = std::max(1, std::min(threads, m / 64));
+    // (a thread costs tens of microseconds to start: each gets >= 64 K codes)
+    const int nthreads =
+        (int)std::max<int64_t>(1, std::min<int64_t>({threads, m / 64, (int64_t)m * P.ngroups / 65536}));
     auto run = [&](auto &&body) {
         if (nthreads <= 1) {
             body(0, m, 0);
@@ -1468,6 +1492,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
             d.emax = std::max(G.P.max_entries, 1);
             d.rmax = std::max(G.P.max_regs, 1);
             d.c_form = G.c_form;
+            d.direct = G.direct ? 1 : 0;
             d.J = G.J;
             d.Lj = pad_k ? G.Lj_pad : G.Lj;
             d.coop_w = pad_k ? G.coop_w : 0;

@@ -258,11 +258,13 @@ __device__ __forceinline__ jpt jpt_add(const jpt &P, const jpt &Q) {
 
 // affine (x, y) of a Jacobian point given zinv = Z^-1 (Z != 0)
 // (a short dependent chain of products: the split forms have lower latency)
+// (loose quotient digits: P's coordinates and zinv normal, every operand
+// pair below 4 p^2)
 __device__ __forceinline__ apt jpt_to_affine_with(const jpt &P, const fe &zinv) {
-    fe z2 = fe_sqr_ilp(zinv);
+    fe z2 = fe_sqr_t<false, true>(zinv);
     apt r;
-    r.x = fe_mul_ilp(P.X, z2);
-    r.y = fe_mul_ilp(P.Y, fe_mul_ilp(z2, zinv));
+    r.x = fe_mul_t<false, true>(P.X, z2);
+    r.y = fe_mul_t<false, true>(P.Y, fe_mul_t<false, true>(z2, zinv));
     return r;
 }
 

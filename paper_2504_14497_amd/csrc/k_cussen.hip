@@ -74,6 +74,7 @@ struct prob_desc {
     int32_t J, Lj, tm, pp;
     int32_t kc, S, gps, io;  // io: index of the problem's matrices in the run
     int32_t tiles_x, tiles_y, norm_per, coop_w;  // coop_w: lanes per level-1 chain (0: one lane per chain)
+    int32_t coop_lpu, coop_h;  // cooperative build: lanes per unit; first register slot of a lane's block
     int32_t nunits, levels;  // digit-table units (columns); largest combination level (1: none)
     int64_t n_lanes, tb_block0;
     int64_t cb_lanes, cb_block0;  // combination lanes (group, pair), 0 without combinations
@@ -82,7 +83,7 @@ struct prob_desc {
     int64_t norm_block0, norm_threads;
     int64_t ldj;     // ld of the internal Jacobian buffers (partials, C before normalisation)
     int64_t ld_pre;  // ld of the normalisation prefixes
-    int64_t o_ops, o_op_begin, o_entry_begin, o_entries;
+    int64_t o_ops, o_op_begin, o_entry_begin, o_entries, o_entry_value;
     int64_t o_unit_col, o_unit_grp, o_unit_off, o_cblock_begin, o_cblocks, o_cruns;
     int64_t o_lists, o_chunk_off, o_chunk_len;  // nonzero codes per (split, chunk), see pack_codes
     int32_t chunks_per_split;
@@ -254,19 +255,35 @@ __device__ __forceinline__ jpt shfl_up_jpt(const jpt &P, int delta, int width) {
     return R;
 }
 
+// v B for a small v >= 1: left to right, a doubling per bit below the top
+// one and the mixed addition of B where the bit is set (lanes whose v is
+// shorter leave the loop early: masked, unchanged)
+__device__ __forceinline__ jpt small_multiple(uint32_t v, const apt &B) {
+    jpt R = jpt_from_affine(B);
+    for (int i = 30 - __builtin_clz(v); i >= 0; --i) {
+        R = jpt_dbl<false>(R);
+        const jpt T = jpt_add_affine_lean<false>(R, B);
+        if ((v >> i) & 1u) R = T;
+    }
+    return R;
+}
+
 // Table of one (group, j, point) built by W lanes (a padded run of
-// single-column groups; 64 lanes per group, 2 l chains of W lanes).  The
+// single-column groups; whole wavefronts per group, 2 l chains of W lanes).  The
 // program's last E - 1 ops are the level-1 prefix sums S_i = S_{i-1} + b_i
-// (S_0 = b_0); every lane runs the ops before them (levels >= 2, a few
-// short chains), sums its block of b_i, the block totals are scanned across
-// the W lanes (shuffles, log2 W additions), each lane runs its block's
-// prefix sums again from the sum of the blocks before it (storing each S_i
-// once), then converts its block's entries to affine with one inversion.
-// Chain depth ~ 2 E / W + log2 W additions instead of E.
+// (S_0 = b_0), and S_i = value_i B_kj with value_i the i-th smallest
+// magnitude of the column (the plan records it).  Every lane runs the ops
+// before the chain (levels >= 2, a few short chains, for the b_i that are
+// registers), starts its block at S_i0 = value_i0 B_kj (a short ladder), runs
+// the block's prefix sums from there (storing each S_i once), then converts
+// its block's entries to affine with one inversion.  Chain depth: about
+// 1.5 log2(value) + E / W additions instead of E.
 __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_desc &d, int64_t lane) {
-    const int W = d.coop_w, l = d.l;
-    const int u = (int)(lane / 64);
-    const int rem = (int)(lane % 64);
+    const int W = d.coop_w, l = d.l, lpu = d.coop_lpu;
+    // a unit's lanes are whole wavefronts: its index in a scalar register,
+    // so that the program's arrays come through scalar loads
+    const int u = __builtin_amdgcn_readfirstlane((int)(lane / lpu));
+    const int rem = (int)(lane % lpu);
     const int chain = rem / W, w = rem % W;
     if (chain >= 2 * l) return;  // whole W-lane segments idle
     const int j = chain >> 1, pt = chain & 1;
@@ -274,6 +291,7 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
     const int32_t *op_begin = plan_at<int32_t>(a, d.o_op_begin);
     const int32_t *entry_begin = plan_at<int32_t>(a, d.o_entry_begin);
     const int16_t *entries = plan_at<int16_t>(a, d.o_entries);
+    const int32_t *entry_value = plan_at<int32_t>(a, d.o_entry_value);
     uint32_t *regs = at<uint32_t>(a, d.w_regs);
     uint32_t *table = at<uint32_t>(a, d.w_table);
     const uint32_t *B = a.io[d.io].B;
@@ -292,61 +310,75 @@ __device__ __forceinline__ void coop_table_build(const run_args &a, const prob_d
     int last_reg = -1;
     const apt base = load_affine(B, ldb, pt, (int64_t)k0 * l + j);
     for (int o = ob; o < ofirst; ++o) run_op(ops[o], base, regs, rmax, n_lanes, 0, lane, last, last_reg);
-    auto opd_of = [&](int i) -> int16_t { return i == 0 ? entries[eb] : ops[ofirst + i - 1].b; };
-    // this lane's block of the chain: its total first
+    // this lane's block of the chain
     const int bs = (E + W - 1) / W;
     const int i0 = min(E, w * bs), i1 = min(E, i0 + bs);
-    jpt acc = jpt_infinity();
-    for (int i = i0; i < i1; ++i) {
-        const jpt bi = operand_point(opd_of(i), base, regs, rmax, n_lanes, lane);
-        acc = i == i0 ? bi : jpt_add<false>(acc, bi);
-    }
-    // inclusive scan of the block totals over the chain's W lanes, then the
-    // sum of the blocks before this one
-    jpt incl = acc;
-    for (int delta = 1; delta < W; delta <<= 1) {
-        const jpt o = shfl_up_jpt(incl, delta, W);
-        const jpt s = jpt_add<false>(o, incl);
-        if (w >= delta) incl = s;
-    }
-    jpt excl = shfl_up_jpt(incl, 1, W);
-    // the block's prefix sums again, from the blocks before it: S_i stored
-    // once, its Z folded into the forward pass of the inversion
     const int64_t npairs = 2 * (int64_t)l;
     uint32_t *tab = entry_at(table, npairs, emax, grp, off, 2 * j + pt);
     const int64_t estride = entry_stride(npairs), yoff = y_offset(npairs);
     fe prod = fe_one_mont();
-    jpt S = excl;
+    jpt S = jpt_infinity();
+    // (this lane's entry and chain operands are read one entry ahead, before
+    // the current entry's stores: a wait for a load also waits for the
+    // memory operations issued before it)
+    int16_t opd_n = i0 < i1 ? entries[eb + i0] : (int16_t)-1;
+    int16_t opdb_n = i0 > 0 && i0 < i1 ? ops[ofirst + i0 - 1].b : (int16_t)-1;
     for (int i = i0; i < i1; ++i) {
-        const int16_t opd_b = opd_of(i);
-        const jpt bi = operand_point(opd_b, base, regs, rmax, n_lanes, lane);
-        S = (w == 0 && i == i0) ? bi : jpt_add<false>(S, bi);
-        const int16_t opd = entries[eb + i];
+        const int16_t opd = opd_n, opd_b = opdb_n;
+        if (i + 1 < i1) {
+            opd_n = entries[eb + i + 1];
+            opdb_n = ops[ofirst + i].b;
+        }
+        if (i == 0) {
+            S = operand_point(opd, base, regs, rmax, n_lanes, lane);  // b_0, as the program made it
+        } else if (i == i0) {
+            S = small_multiple((uint32_t)entry_value[eb + i], base);
+        } else {
+            S = opd_b < 0 ? jpt_add_affine_lean<false>(S, base)
+                          : jpt_add<false>(S, reg_load(regs, rmax, n_lanes, 0, opd_b, lane));
+        }
         if (opd < 0) continue;  // S_0 = B_kj: affine already
-        if (i > 0) reg_store(regs, rmax, n_lanes, 0, opd, lane, S);  // S_0 = b_0 is its own register
+        // S_0 = b_0 is its own register; a later entry goes to its slot in
+        // the lane's block
+        if (i > 0) reg_store(regs, rmax, n_lanes, 0, d.coop_h + (i - i0), lane, S);
         store_gran(tab + i * estride, prod, 0u);
-        if (!fe_is_zero(S.Z)) prod = fe_mul_ilp(prod, S.Z);
+        if (!fe_is_zero(S.Z)) prod = fe_mul_t<false, true>(prod, S.Z);
     }
     fe inv = fe_inv(prod);
+    // an entry's register and stored prefix are loaded one entry ahead,
+    // before the current entry's stores
+    jpt nP = jpt_infinity();
+    fe npre = fe_zero();
+    auto fetch = [&](int i, int16_t opd) {
+        if (opd >= 0) {
+            nP = reg_load(regs, rmax, n_lanes, 0, i == 0 ? (int)opd : d.coop_h + (i - i0), lane);
+            npre = load_gran(tab + i * estride);
+        }
+    };
+    int16_t bo_n = i1 > i0 ? entries[eb + i1 - 1] : (int16_t)-1;
+    int16_t bo_n2 = i1 - 2 >= i0 ? entries[eb + i1 - 2] : (int16_t)-1;
+    if (i1 > i0) fetch(i1 - 1, bo_n);
     for (int i = i1 - 1; i >= i0; --i) {
-        const int16_t opd = entries[eb + i];
-        uint32_t *slot = tab + i * estride;
+        const int16_t opd = bo_n;
+        const jpt P = nP;
+        const fe pre = npre;
+        if (i > i0) {
+            bo_n = bo_n2;
+            fetch(i - 1, bo_n);
+            if (i - 2 >= i0) bo_n2 = entries[eb + i - 2];
+        }
         apt A;
         if (opd < 0) {
             A = base;
+        } else if (fe_is_zero(P.Z)) {
+            A.x = fe_zero();
+            A.y = fe_zero();
         } else {
-            const jpt P = reg_load(regs, rmax, n_lanes, 0, opd, lane);
-            const fe pre = load_gran(slot);
-            if (fe_is_zero(P.Z)) {
-                A.x = fe_zero();
-                A.y = fe_zero();
-            } else {
-                const fe zinv = fe_mul_ilp(inv, pre);
-                inv = fe_mul_ilp(inv, P.Z);
-                A = jpt_to_affine_with(P, zinv);
-            }
+            const fe zinv = fe_mul_t<false, true>(inv, pre);
+            inv = fe_mul_t<false, true>(inv, P.Z);
+            A = jpt_to_affine_with(P, zinv);
         }
-        write_entry(slot, yoff, A, apt_is_inf(A));
+        write_entry(tab + i * estride, yoff, A, apt_is_inf(A));
     }
 }
 
@@ -417,7 +449,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
             run_op(op, base, regs, rmax, n_lanes, r, lane, last, last_reg);
             if (ne < E && op.dst == entries[eb + ne]) {
                 store_gran(tab + ne * estride, prod, 0u);
-                if (!fe_is_zero(last.Z)) prod = fe_mul_ilp(prod, last.Z);
+                if (!fe_is_zero(last.Z)) prod = fe_mul_t<false, true>(prod, last.Z);
                 ++ne;
                 while (ne < E && entries[eb + ne] < 0) ++ne;
             }
@@ -454,8 +486,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
                 A.x = fe_zero();
                 A.y = fe_zero();
             } else {
-                fe zinv = fe_mul_ilp(inv, pre);
-                inv = fe_mul_ilp(inv, P.Z);
+                fe zinv = fe_mul_t<false, true>(inv, pre);
+                inv = fe_mul_t<false, true>(inv, P.Z);
                 A = jpt_to_affine_with(P, zinv);
             }
             write_entry(tab + e * estride, yoff, A, apt_is_inf(A));
@@ -1102,6 +1134,11 @@ struct job {
     int64_t n_lanes_pad = 0;  // whole wavefront (0: not applicable), chosen per run
     size_t regs_bytes_pad = 0;
     int coop_w = 0;           // padded runs: lanes sharing each level-1 chain (0: none)
+    int coop_lpu = 0;         // lanes per unit in the cooperative build (whole wavefronts)
+    int coop_h = 0;           // register slots of the ops before the level-1 chain
+    int coop_slots = 0;       // register slots per lane: coop_h + the largest block
+    int64_t n_lanes_coop = 0;
+    size_t regs_bytes_coop = 0;
     int tm = 256, pp = 1, kc = 1, S = 1, gps = 0, tiles_x = 1, tiles_y = 1;
     int64_t ldj = 64, norm_threads = 0, ld_pre = 0;
     int norm_per = 0;
@@ -1124,7 +1161,7 @@ bool pad_run(size_t count, JobOf job_at) {
     int64_t lanes = 0;
     for (size_t q = 0; q < count; ++q) {
         const auto &G = job_at(q);
-        lanes += G.n_lanes_pad ? G.n_lanes_pad : G.n_lanes;
+        lanes += G.coop_w > 1 ? G.n_lanes_coop : G.n_lanes_pad ? G.n_lanes_pad : G.n_lanes;
     }
     return lanes <= PAD_LANES_MAX;
 }
@@ -1175,17 +1212,45 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg, int split) {
     // instead of idling, with W chosen by the chain's depth
     G.coop_w = 0;
     if (G.Lj_pad && l >= 1 && level1_chains(P)) {
-        // chain depth in mixed additions: E - 1 alone; with W lanes about
-        // 2 E / W block and prefix additions plus log2 W scan steps, general
-        // additions of about 1.45 times the products each
-        auto depth = [&](int W) {
-            if (W == 1) return std::max(avg_e - 1.0, 0.0);
-            return 1.45 * (2.0 * std::ceil(avg_e / W) + std::log2((double)W));
+        // A lane's work in mixed additions: its chain (E - 1 alone; with W
+        // lanes per chain a ladder to its block's start, a doubling and an
+        // addition per bit of the largest value, then E / W - 1 additions),
+        // the inversion (~25) and the conversions (~0.5 each).  A wavefront
+        // alone on its SIMD issues at about half rate (dependent products),
+        // so the time is the larger of twice a wavefront's work and the
+        // wavefronts per SIMD times it (1024 SIMDs of 64 lanes).
+        int32_t vmax = 1;
+        for (int32_t v : P.entry_value) vmax = std::max(vmax, v);
+        const double vbits = 32 - __builtin_clz((uint32_t)vmax);
+        auto lpu = [&](int W) { return ((int64_t)2 * l * W + 63) / 64 * 64; };
+        auto cost = [&](int W) {
+            const double bs = W == 1 ? avg_e : std::ceil(avg_e / W);
+            const double chain = W == 1 ? std::max(avg_e - 1.0, 0.0) : 2.0 * (vbits - 1.0) + bs - 1.0;
+            const double work = chain + 25.0 + 0.5 * bs;
+            const double waves = std::ceil((double)P.nunits * (W == 1 ? 64 : lpu(W)) / 65536.0);
+            return std::max(2.0, waves) * work;
         };
         int best = 1;
-        for (int W = 2; W * 2 * l <= 64; W *= 2)
-            if (depth(W) < depth(best)) best = W;
-        if (best >= 2) G.coop_w = best;
+        for (int W = 2; W <= 64 && (int64_t)P.nunits * lpu(W) <= PAD_LANES_MAX; W *= 2)
+            if (cost(W) < cost(best)) best = W;
+        if (best >= 2) {
+            G.coop_w = best;
+            G.coop_lpu = (int)lpu(best);
+            // registers of the ops before each chain keep their numbers; a
+            // lane's block of chain entries follows them
+            int h = 0, emax_u = 0;
+            for (int u = 0; u < P.nunits; ++u) {
+                const int E = P.entry_begin[u + 1] - P.entry_begin[u];
+                emax_u = std::max(emax_u, E);
+                const int ofirst = P.op_begin[u + 1] - std::max(E - 1, 0);
+                for (int o = P.op_begin[u]; o < ofirst; ++o) h = std::max(h, P.ops[o].dst + 1);
+                if (E > 0 && P.entries[P.entry_begin[u]] >= 0) h = std::max(h, P.entries[P.entry_begin[u]] + 1);
+            }
+            G.coop_h = h;
+            G.coop_slots = std::max(1, h + (emax_u + best - 1) / best);
+            G.n_lanes_coop = (int64_t)P.nunits * G.coop_lpu;
+            G.regs_bytes_coop = (size_t)G.coop_slots * JAC_WORDS * 4 * (size_t)G.n_lanes_coop;
+        }
     }
     // accumulation tile and the split of the inner dimension
     const int npairs = 2 * l;
@@ -1226,7 +1291,8 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg, int split) {
         G.ld_pre = G.norm_threads * G.norm_per * 2;
         G.norm_bytes = normalize_scratch_bytes(n_out, 2);
     }
-    G.footprint = align256(std::max(G.regs_bytes, G.regs_bytes_pad)) + align256(G.table_bytes) + align256(G.part_bytes) +
+    G.footprint = align256(std::max({G.regs_bytes, G.regs_bytes_pad, G.regs_bytes_coop})) + align256(G.table_bytes) +
+                  align256(G.part_bytes) +
                   align256(G.cjac_bytes) + align256(G.norm_bytes);
 }
 
@@ -1464,6 +1530,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         arr(D[k].o_op_begin, G.P.op_begin.size() * 4);
         arr(D[k].o_entry_begin, G.P.entry_begin.size() * 4);
         arr(D[k].o_entries, G.P.entries.size() * 2);
+        arr(D[k].o_entry_value, G.P.entry_value.size() * 4);
         arr(D[k].o_lists, G.lists.size() * 4);
         arr(D[k].o_chunk_off, G.chunk_off.size() * 8);
         arr(D[k].o_chunk_len, G.chunk_len.size() * 4);
@@ -1497,6 +1564,9 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
             d.Lj = pad_k ? G.Lj_pad : G.Lj;
             d.coop_w = pad_k ? G.coop_w : 0;
             if (d.coop_w > 1) ph.coop = true;
+            d.coop_lpu = G.coop_lpu;
+            d.coop_h = G.coop_h;
+            if (d.coop_w > 1) d.rmax = G.coop_slots;
             d.tm = G.tm;
             d.pp = G.pp;
             d.kc = G.kc;
@@ -1507,7 +1577,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
             d.tiles_y = G.tiles_y;
             d.norm_per = G.norm_per;
             d.chunks_per_split = G.chunks_per_split;
-            d.n_lanes = pad_k ? G.n_lanes_pad : G.n_lanes;
+            d.n_lanes = d.coop_w > 1 ? G.n_lanes_coop : pad_k ? G.n_lanes_pad : G.n_lanes;
             d.nunits = G.P.nunits;
             d.levels = G.P.max_levels;
             d.tb_block0 = tb;
@@ -1526,7 +1596,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
             d.ldj = G.ldj;
             d.ld_pre = G.ld_pre;
             d.w_regs = (int64_t)ws;
-            ws += align256(pad_k ? G.regs_bytes_pad : G.regs_bytes);
+            ws += align256(d.coop_w > 1 ? G.regs_bytes_coop : pad_k ? G.regs_bytes_pad : G.regs_bytes);
             d.w_table = (int64_t)ws;
             ws += align256(G.table_bytes);
             d.w_part = (int64_t)ws;
@@ -1575,6 +1645,7 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
         put(D[k].o_op_begin, P.op_begin.data(), P.op_begin.size() * 4);
         put(D[k].o_entry_begin, P.entry_begin.data(), P.entry_begin.size() * 4);
         put(D[k].o_entries, P.entries.data(), P.entries.size() * 2);
+        put(D[k].o_entry_value, P.entry_value.data(), P.entry_value.size() * 4);
         const job &G = pl.jobs[k];
         put(D[k].o_lists, G.lists.data(), G.lists.size() * 4);
         put(D[k].o_chunk_off, G.chunk_off.data(), G.chunk_off.size() * 8);
@@ -2101,7 +2172,10 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         d.Lj = pad_k ? G.Lj_pad : G.Lj;
         d.coop_w = pad_k ? G.coop_w : 0;
         if (d.coop_w > 1) ph.coop = true;
-        d.n_lanes = pad_k ? G.n_lanes_pad : G.n_lanes;
+        d.coop_lpu = G.coop_lpu;
+        d.coop_h = G.coop_h;
+        d.rmax = d.coop_w > 1 ? G.coop_slots : std::max(G.P.max_regs, 1);
+        d.n_lanes = d.coop_w > 1 ? G.n_lanes_coop : pad_k ? G.n_lanes_pad : G.n_lanes;
         d.io = r;
         d.tb_block0 = tb;
         tb += (d.n_lanes + 255) / 256;
@@ -2114,7 +2188,7 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         d.norm_block0 = norm;
         norm += d.norm_threads / 256;
         d.w_regs = (int64_t)ws;
-        ws += align256(pad_k ? G.regs_bytes_pad : G.regs_bytes);
+        ws += align256(d.coop_w > 1 ? G.regs_bytes_coop : pad_k ? G.regs_bytes_pad : G.regs_bytes);
         d.w_table = (int64_t)ws;
         ws += align256(G.table_bytes);
         d.w_part = (int64_t)ws;

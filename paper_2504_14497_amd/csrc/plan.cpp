@@ -23,6 +23,7 @@ inline int16_t base_operand(int t) { return (int16_t)(-1 - t); }
 struct column_result {
     std::vector<int16_t> row_operand;  // per row
     std::vector<int16_t> level1;       // operand of each distinct nonzero value, ascending
+    std::vector<int32_t> level1_values;  // those values
     std::vector<int> row_rank;         // per row: rank of |a| among them, -1 for zero
     int64_t nN = 0, adds_counted = 0;
 };
@@ -67,6 +68,7 @@ column_result compress_column(const std::vector<int> &vals, int N, int t, std::v
     std::vector<std::vector<int>> level(N + 1);
     std::vector<int> row_rank;
     distinct_ranks(vals, level[1], row_rank);
+    res.level1_values.assign(level[1].begin(), level[1].end());
     // ptr[w][i] for w >= 2: rank in level w of element i of level w-1
     std::vector<std::vector<int>> ptr(N + 1);
     for (int w = 1; w <= N; ++w) {
@@ -134,6 +136,7 @@ namespace {
 struct unit_plan {
     std::vector<plan_op> ops;
     std::vector<int16_t> entries;  // level-1 operands, ascending values
+    std::vector<int32_t> values;   // the value (multiple of the base point) of each entry
     std::vector<int> pos_of_rank;  // rank of a value among them -> position in `entries`
     int nreg = 0;
 };
@@ -184,11 +187,14 @@ void order_entries(unit_plan &u) {
     for (size_t e = 0; e < E; ++e) order[e] = (int)e;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
     std::vector<int16_t> entries(E);
+    std::vector<int32_t> values(E);
     for (size_t k = 0; k < E; ++k) {
         entries[k] = u.entries[order[k]];
+        values[k] = u.values[order[k]];
         u.pos_of_rank[order[k]] = (int)k;
     }
     u.entries = std::move(entries);
+    u.values = std::move(values);
 }
 
 void block_combos(group_plan &gp);
@@ -225,6 +231,7 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
         gp.level_mults += cr.nN;
         gp.level_adds += cr.adds_counted;
         u.entries = std::move(cr.level1);
+        u.values = std::move(cr.level1_values);
         if (u.nreg > 32000) {
             gp.err = -1;
             return;
@@ -420,6 +427,7 @@ int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int
     }
     P.ops.reserve(nops);
     P.entries.reserve(nent);
+    P.entry_value.reserve(nent);
     P.combos.reserve(ncombo);
     P.op_begin.push_back(0);
     P.entry_begin.push_back(0);
@@ -436,6 +444,7 @@ int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int
             off += (int)u.entries.size();
             P.ops.insert(P.ops.end(), u.ops.begin(), u.ops.end());
             P.entries.insert(P.entries.end(), u.entries.begin(), u.entries.end());
+            P.entry_value.insert(P.entry_value.end(), u.values.begin(), u.values.end());
             P.op_begin.push_back((int32_t)P.ops.size());
             P.entry_begin.push_back((int32_t)P.entries.size());
             P.nregs.push_back(u.nreg);
@@ -481,6 +490,7 @@ int build_cussen_plan(const void *A, int m, int n, int bits, bool is_signed, int
 int check_cussen_plan(const cussen_plan &P, const void *A, int bits, bool is_signed) {
     const int m = P.m, n = P.n, g = P.g;
     if ((int)P.op_begin.size() != P.nunits + 1 || (int)P.entry_begin.size() != P.nunits + 1 ||
+        P.entry_value.size() != P.entries.size() ||
         (int)P.nregs.size() != P.nunits || (int)P.unit_col.size() != P.nunits ||
         (int)P.unit_grp.size() != P.nunits || (int)P.unit_off.size() != P.nunits ||
         (int)P.combo_begin.size() != P.ngroups + 1 || (int)P.cblock_begin.size() != P.ngroups + 1 ||
@@ -541,6 +551,9 @@ int check_cussen_plan(const cussen_plan &P, const void *A, int bits, bool is_sig
                 const int16_t opd = P.entries[eb + e];
                 if (level[off + e]) return 4;
                 ent[off + e] = value(opd);
+                // the recorded value: this multiple of digit t's base point
+                for (int q = 0; q < 4; ++q)
+                    if (ent[off + e][q] != (q == t ? (int64_t)P.entry_value[eb + e] : 0)) return 3;
                 level[off + e] = 1;
                 if (bad) return 4;
                 if (opd >= 0) {

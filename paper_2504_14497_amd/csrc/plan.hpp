@@ -77,6 +77,7 @@ struct cussen_plan {
     std::vector<int32_t> nregs;         // per unit
     std::vector<int32_t> entry_begin;   // nunits + 1
     std::vector<int16_t> entries;       // operand of every digit-table entry
+    std::vector<int32_t> entry_value;   // the multiple of its column's base point each entry is
     std::vector<int32_t> combo_begin;   // ngroups + 1
     std::vector<plan_combo> combos;
     std::vector<int32_t> cblock_begin;  // ngroups + 1

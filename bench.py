@@ -528,7 +528,7 @@ def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
                         f"{n}x{l} ciphertexts of uniform {base.msg_bits}-bit messages, a fresh X per request, "
                         f"layer uniform; Poisson arrivals; Cussen N=4 g=1",
             "requests_per_rate": n_requests, "slots": slots, "max_batch": max_batch,
-            "budget_gb": budget_gb, "request_workspace_mb": plan.stats(0)["workspace_bytes"] / 1e6,
+            "budget_gb": budget_gb, "request_workspace_mb": plan.selected_workspace_bytes([0]) / 1e6,
             "host_plan_s": t_plan, "capacity_req_per_s": capacity, "burst": burst, "sweep": sweep,
             "alone_equals_mix": same, "decrypt": decrypt}
 

@@ -1291,7 +1291,9 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg, int split) {
         G.ld_pre = G.norm_threads * G.norm_per * 2;
         G.norm_bytes = normalize_scratch_bytes(n_out, 2);
     }
-    G.footprint = align256(std::max({G.regs_bytes, G.regs_bytes_pad, G.regs_bytes_coop})) + align256(G.table_bytes) +
+    // (a padded run uses the cooperative register file when there is one)
+    G.footprint = align256(std::max(G.regs_bytes, G.coop_w > 1 ? G.regs_bytes_coop : G.regs_bytes_pad)) +
+                  align256(G.table_bytes) +
                   align256(G.part_bytes) +
                   align256(G.cjac_bytes) + align256(G.norm_bytes);
 }

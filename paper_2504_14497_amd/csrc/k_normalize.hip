@@ -26,11 +26,15 @@ namespace pcmm {
 void normalize_geometry(int64_t n_elem, int64_t *threads, int *per_thread) {
     // elements per thread: one inversion is amortised over them, but each
     // thread is one serial chain (prefix products, the inversion, the way
-    // back).  Batches of 4 until there are enough chains for 4 wavefronts per
+    // back).  One element per thread while the chains fit one wavefront per
+    // SIMD (65536 threads: latency is then one inversion), two up to twice
+    // that, batches of 4 until there are enough chains for 4 wavefronts per
     // SIMD (262144 threads), larger batches (up to 24) beyond that.
     constexpr int64_t enough_threads = 262144;
     const int64_t target_batch =
-        std::min<int64_t>(24, std::max<int64_t>(4, (n_elem + enough_threads - 1) / enough_threads));
+        n_elem <= 65536    ? 1
+        : n_elem <= 131072 ? 2
+                           : std::min<int64_t>(24, std::max<int64_t>(4, (n_elem + enough_threads - 1) / enough_threads));
     int64_t th = (n_elem + target_batch - 1) / target_batch;
     if (th < 1) th = 1;
     th = (th + 255) / 256 * 256;

@@ -165,6 +165,32 @@ def test_exceptional_cases_vs_oracle(dev, orc):
     assert (want[8:11, 1] == 0).all()
 
 
+@pytest.mark.parametrize("m,n,l,bits,signed,g", [(50, 1, 5, 8, True, 1), (40, 2, 3, 4, False, 2),
+                                                 (33, 3, 2, 2, False, 3), (20, 1, 4, 4, False, 1)])
+def test_direct_outputs_of_one_column_group(dev, orc, m, n, l, bits, signed, g):
+    """n <= g: every row has at most one code, so each affine output is its
+    table entry written directly (no accumulation additions, no
+    normalisation).  Zero rows give the identity, one ciphertext of B is the
+    identity, and the table's combinations (g > 1) feed the outputs.  Equal
+    to the oracle on every output, and to the Jacobian-output path (which
+    accumulates and leaves normalisation to the caller)."""
+    rng = np.random.default_rng(91 + m)
+    lo, hi = (-(1 << (bits - 1)), 1 << (bits - 1)) if signed else (0, 1 << bits)
+    A = rng.integers(lo, hi, size=(m, n)).astype(np.int8 if signed else np.uint8)
+    A[3] = 0          # a zero row: identity outputs
+    A[5] = A[4]       # repeated rows share a table entry
+    B = random_cts(orc, n, l, 300 + m)
+    B[0, l - 1] = 0   # an identity ciphertext
+    want = orc.pcmm_cussen(A, B)
+    Bd = _upload(dev, B)
+    C, st = dev.cussen(A, bits, Bd, cfg=dev.CussenCfg(4, g, 1, 0))
+    assert st["group"] == g and st["k_split"] == 1, st
+    assert (C.to_host() == want).all()
+    Cj, _ = dev.cussen(A, bits, Bd, c_form=dev.JACOBIAN, cfg=dev.CussenCfg(4, g, 1, 0))
+    assert (dev.normalize(Cj).to_host() == want).all()
+    assert (want[3] == 0).all()
+
+
 def test_degenerate_sizes(dev, orc):
     B = random_cts(orc, 3, 4, 400)
     Bd = _upload(dev, B)

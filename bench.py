@@ -702,11 +702,13 @@ def main():
                 "mads_per_mixed_add": MADS_MIXED_ADD}
 
     # the table stage (digit tables, combinations): algorithmic bytes are
-    # every table entry written once (80 B) and B read once (128 B per
-    # ciphertext); it is latency- and traffic-bound rather than ALU-bound
+    # every table entry written once (72 B: an x and a y granule) and B read
+    # once (128 B per ciphertext); it is latency- and traffic-bound rather
+    # than ALU-bound
     tab_ms = stage["ms_table"]
-    tab_bytes = st0["table_entries"] * 2 * sh.l * 80 + sh.n * sh.l * 128
-    table_roofline = {"bound": "hbm", "kernels": ["table_build_kernel", "combo_table_kernel"],
+    tab_bytes = st0["table_entries"] * 2 * sh.l * 72 + sh.n * sh.l * 128
+    table_roofline = {"bound": "hbm", "kernels": ["table_build_kernel", "combo_forward_kernel",
+                                                  "combo_backward_kernel"],
                       "achieved": tab_bytes / (tab_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": tab_bytes / (tab_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": load_table_traffic(sh.name),
                       "algorithmic_bytes": tab_bytes, "stage_ms": tab_ms,

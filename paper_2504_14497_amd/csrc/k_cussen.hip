@@ -89,6 +89,7 @@ struct prob_desc {
     int32_t chunks_per_split;
     int32_t direct;  // one column group, one split, affine C: each output is one table entry
     int64_t w_regs, w_table, w_part, w_cjac, w_norm;
+    int64_t w_cprod;  // combination lanes' level products and pending marks (10 planes of cb_lanes words)
 };
 
 struct io_ptrs {
@@ -724,57 +725,95 @@ __device__ __forceinline__ void combo_backward(const plan_cblock *blocks, const 
     }
 }
 
-__device__ __forceinline__ void combo_build(const run_args &a, const prob_desc &d, int64_t lane) {
+// One level's blocks [b0, b1) of a combination lane's group (a group's
+// blocks are ordered by level); the lane's table and strides.
+struct combo_lane {
+    const plan_cblock *blocks;
+    const plan_crun *runs;
+    uint32_t *tab;
+    int64_t estride, yoff;
+    int b0, b1;
+};
+
+__device__ __forceinline__ combo_lane combo_lane_of(const run_args &a, const prob_desc &d, int64_t lane, int level) {
     const int npairs = 2 * d.l;
     const int grp = (int)(lane / npairs);
     const int p = (int)(lane - (int64_t)grp * npairs);
     const int32_t *cblock_begin = plan_at<int32_t>(a, d.o_cblock_begin);
-    const plan_cblock *blocks = plan_at<plan_cblock>(a, d.o_cblocks);
-    const plan_crun *runs = plan_at<plan_crun>(a, d.o_cruns);
-    uint32_t *tab = entry_at(at<uint32_t>(a, d.w_table), npairs, d.emax, grp, 0, p);
-    const int64_t estride = entry_stride(npairs), yoff = y_offset(npairs);
-    const int bb = cblock_begin[grp], be = cblock_begin[grp + 1];
-    for (int b0 = bb; b0 < be;) {
-        const int level = blocks[b0].level;
-        int b1 = b0 + 1;
-        while (b1 < be && blocks[b1].level == level) ++b1;
-        bool pending = false;
-        fe prod = combo_forward<false>(blocks, runs, b0, b1, tab, estride, pending);
-        // a zero product: some chord of this lane has x_a = x_b
-        const bool safe = __ballot(fe_is_zero(prod)) != 0;
-        if (safe) {
-            pending = false;
-            prod = combo_forward<true>(blocks, runs, b0, b1, tab, estride, pending);
-            combo_backward<true>(blocks, runs, b0, b1, tab, estride, yoff, fe_inv(prod));
-        } else {
-            combo_backward<false>(blocks, runs, b0, b1, tab, estride, yoff, fe_inv(prod));
-        }
-        // ---- the rest: identity operands, x_a = x_b
-        if (__ballot(pending)) {
-            for (int bi = b0; bi < b1; ++bi) {
-                const plan_cblock blk = blocks[bi];
-                for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
-                    const plan_crun run = runs[ri];
-                    for (int r = 0; r < CB; ++r) {
-                        if (run.dst[r] < 0) continue;
-                        uint32_t *slot = tab + run.dst[r] * estride;
-                        if (pending && (slot[NL - 1] & ENTRY_PENDING))
-                            combo_special(tab + blk.a[r] * estride, tab + run.b * estride, yoff, (run.neg >> r) & 1,
-                                          slot);
-                    }
-                }
-            }
-        }
-        b0 = b1;
-    }
+    combo_lane c;
+    c.blocks = plan_at<plan_cblock>(a, d.o_cblocks);
+    c.runs = plan_at<plan_crun>(a, d.o_cruns);
+    c.tab = entry_at(at<uint32_t>(a, d.w_table), npairs, d.emax, grp, 0, p);
+    c.estride = entry_stride(npairs);
+    c.yoff = y_offset(npairs);
+    const int be = cblock_begin[grp + 1];
+    int b0 = cblock_begin[grp];
+    while (b0 < be && c.blocks[b0].level < level) ++b0;
+    int b1 = b0;
+    while (b1 < be && c.blocks[b1].level == level) ++b1;
+    c.b0 = b0;
+    c.b1 = b1;
+    return c;
 }
 
-__global__ void __launch_bounds__(256) combo_table_kernel(run_args a) {
+// Forward pass of one level (see combo_forward): the lane's product of the
+// chord dx and its pending mark go to its column of the w_cprod planes.
+__global__ void __launch_bounds__(256) combo_forward_kernel(run_args a, int level) {
     const int b = find_problem(a, offsetof(prob_desc, cb_block0), blockIdx.x);
     const prob_desc &d = descs(a)[b];
     const int64_t lane = ((int64_t)blockIdx.x - d.cb_block0) * blockDim.x + threadIdx.x;
-    if (lane >= d.cb_lanes) return;
-    combo_build(a, d, lane);
+    if (lane >= d.cb_lanes || level > d.levels) return;
+    const combo_lane c = combo_lane_of(a, d, lane, level);
+    if (c.b0 == c.b1) return;
+    bool pending = false;
+    const fe prod = combo_forward<false>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, pending);
+    uint32_t *cp = at<uint32_t>(a, d.w_cprod) + lane;
+#pragma unroll
+    for (int w = 0; w < NL; ++w) cp[w * d.cb_lanes] = prod.v[w];
+    cp[NL * d.cb_lanes] = pending ? 1u : 0u;
+}
+
+// Backward pass of one level: the inversion of the lane's product, the
+// chord sums, and the rest.  A zero product (some chord of the lane has
+// x_a = x_b) sends the wavefront through the checked forward and backward
+// passes; combinations the chord formula does not cover are finished in a
+// third pass, which runs only when some lane of the wavefront has one.
+__global__ void __launch_bounds__(256) combo_backward_kernel(run_args a, int level) {
+    const int b = find_problem(a, offsetof(prob_desc, cb_block0), blockIdx.x);
+    const prob_desc &d = descs(a)[b];
+    const int64_t lane = ((int64_t)blockIdx.x - d.cb_block0) * blockDim.x + threadIdx.x;
+    if (lane >= d.cb_lanes || level > d.levels) return;
+    const combo_lane c = combo_lane_of(a, d, lane, level);
+    if (c.b0 == c.b1) return;
+    const uint32_t *cp = at<const uint32_t>(a, d.w_cprod) + lane;
+    fe prod;
+#pragma unroll
+    for (int w = 0; w < NL; ++w) prod.v[w] = cp[w * d.cb_lanes];
+    bool pending = cp[NL * d.cb_lanes] != 0;
+    const bool safe = __ballot(fe_is_zero(prod)) != 0;
+    if (safe) {
+        pending = false;
+        prod = combo_forward<true>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, pending);
+        combo_backward<true>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, c.yoff, fe_inv(prod));
+    } else {
+        combo_backward<false>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, c.yoff, fe_inv(prod));
+    }
+    // ---- the rest: identity operands, x_a = x_b
+    if (__ballot(pending)) {
+        for (int bi = c.b0; bi < c.b1; ++bi) {
+            const plan_cblock blk = c.blocks[bi];
+            for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
+                const plan_crun run = c.runs[ri];
+                for (int r = 0; r < CB; ++r) {
+                    if (run.dst[r] < 0) continue;
+                    uint32_t *slot = c.tab + run.dst[r] * c.estride;
+                    if (pending && (slot[NL - 1] & ENTRY_PENDING))
+                        combo_special(c.tab + blk.a[r] * c.estride, c.tab + run.b * c.estride, c.yoff,
+                                      (run.neg >> r) & 1, slot);
+                }
+            }
+        }
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -1143,7 +1182,7 @@ struct job {
     int64_t ldj = 64, norm_threads = 0, ld_pre = 0;
     int norm_per = 0;
     bool direct = false;  // see prob_desc::direct
-    size_t regs_bytes = 0, table_bytes = 0, part_bytes = 0, cjac_bytes = 0, norm_bytes = 0;
+    size_t regs_bytes = 0, table_bytes = 0, part_bytes = 0, cjac_bytes = 0, norm_bytes = 0, cprod_bytes = 0;
     size_t footprint = 0;  // workspace bytes of this problem's regions
     double tile_cost = 0;
     int chunks_per_split = 0;
@@ -1292,10 +1331,11 @@ void make_geometry(job &G, const pcmm_cussen_cfg *cfg, int split) {
         G.norm_bytes = normalize_scratch_bytes(n_out, 2);
     }
     // (a padded run uses the cooperative register file when there is one)
+    G.cprod_bytes = (size_t)G.cb_lanes * (NL + 1) * 4;
     G.footprint = align256(std::max(G.regs_bytes, G.coop_w > 1 ? G.regs_bytes_coop : G.regs_bytes_pad)) +
                   align256(G.table_bytes) +
                   align256(G.part_bytes) +
-                  align256(G.cjac_bytes) + align256(G.norm_bytes);
+                  align256(G.cjac_bytes) + align256(G.norm_bytes) + align256(G.cprod_bytes);
 }
 
 // The accumulation walks, per (split, chunk of kc column groups), only the
@@ -1388,6 +1428,7 @@ struct run_phase {
     size_t desc_off = 0;  // byte offset of the phase's descriptors in the workspace
     int64_t tb_blocks = 0, cb_blocks = 0, tiles = 0, red_blocks = 0, norm_blocks = 0;
     int acc_grid = 0;
+    int levels = 1;       // largest combination level of the phase's problems (1: none)
     bool coop = false;    // some problem's tables are built by coop_table_kernel
 };
 
@@ -1607,6 +1648,9 @@ pcmm_status finish_plan(pcmm_plan_s &pl) {
             ws += align256(G.cjac_bytes);
             d.w_norm = (int64_t)ws;
             ws += align256(G.norm_bytes);
+            d.w_cprod = (int64_t)ws;
+            ws += align256(G.cprod_bytes);
+            ph.levels = std::max(ph.levels, G.cb_lanes > 0 ? G.P.max_levels : 1);
         }
         ph.tb_blocks = tb;
         ph.cb_blocks = cbb;
@@ -1813,8 +1857,12 @@ pcmm_status enqueue_run(const run_layout &L, const void *copy_src, const char *p
             hipLaunchKernelGGL(coop_table_kernel, dim3((unsigned)ph.tb_blocks), dim3(256), 0, s, ra);
             PCMM_LAUNCH_CHECK();
         }
-        if (ph.cb_blocks > 0) {
-            hipLaunchKernelGGL(combo_table_kernel, dim3((unsigned)ph.cb_blocks), dim3(256), 0, s, ra);
+        // combinations level by level: a forward kernel (few registers, many
+        // wavefronts in flight) and a backward kernel per level
+        for (int lev = 2; ph.cb_blocks > 0 && lev <= ph.levels; ++lev) {
+            hipLaunchKernelGGL(combo_forward_kernel, dim3((unsigned)ph.cb_blocks), dim3(256), 0, s, ra, lev);
+            PCMM_LAUNCH_CHECK();
+            hipLaunchKernelGGL(combo_backward_kernel, dim3((unsigned)ph.cb_blocks), dim3(256), 0, s, ra, lev);
             PCMM_LAUNCH_CHECK();
         }
         if (last) PCMM_REC(2);
@@ -2199,6 +2247,9 @@ pcmm_status selected_layout(const pcmm_plan_s &pl, const int32_t *which, int k, 
         ws += align256(G.cjac_bytes);
         d.w_norm = (int64_t)ws;
         ws += align256(G.norm_bytes);
+        d.w_cprod = (int64_t)ws;
+        ws += align256(G.cprod_bytes);
+        ph.levels = std::max(ph.levels, G.cb_lanes > 0 ? G.P.max_levels : 1);
         D[q] = d;
     }
     L.ws_bytes = ws + 256;

@@ -143,12 +143,13 @@ typedef struct {
                                 affine addition of two table entries                     */
     int64_t digit_entries;   /* of table_entries: entries of the columns' digit tables    */
     int32_t k_split;         /* split of the inner dimension that was used                 */
-    int32_t lanes_per_chain; /* table-build batch: output columns per lane                 */
+    int32_t lanes_per_chain; /* table-build batch: output columns (chains) per lane        */
     int32_t group;           /* columns of A per code that was used (after autotuning)     */
     int32_t coop_lanes;      /* lanes sharing each level-1 prefix-sum chain of the table
-                                build in this run (0: one lane per chain); a run of
-                                single-column groups with few output columns splits each
-                                chain into blocks and scans the block sums across lanes  */
+                                build in this run (0: one lane per chain, up to 64); a
+                                run of single-column groups with few output columns
+                                splits each chain into blocks, each lane starting its
+                                block at its first entry's multiple of the base point   */
     /* with cfg->profile: milliseconds from the first to the last event of each stage */
     float ms_upload, ms_table, ms_accumulate, ms_reduce, ms_normalize, ms_total;
 } pcmm_cussen_stats;

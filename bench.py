@@ -536,7 +536,7 @@ def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large512_t4")
     ap.add_argument("--group", type=int, default=-1,

@@ -155,7 +155,8 @@ struct group_plan {
 };
 
 // Per-thread scratch: direct-mapped lookup of row segments (g <= 2, entries
-// up to 8 bits), stamped with the group so it needs no clearing.
+// up to 8 bits; bits + 1 bits per digit, so 2^(2 bits + 2) slots), stamped
+// with the group so it needs no clearing.
 struct group_scratch {
     std::vector<int> stamp, slot, vals;
     std::vector<int32_t> col[4];
@@ -261,9 +262,10 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
     // distinct prefix with at least two nonzero digits (memoised on the
     // prefix, keyed by its digits, key_bits each, and its length).
     const bool direct = gg <= 2 && key_bits == 9;
+    const int dbits = bits + 1;  // digit + 2^bits lies in [0, 2^(bits+1))
     if (direct && sc.stamp.empty()) {
-        sc.stamp.assign((size_t)1 << 18, -1);
-        sc.slot.assign((size_t)1 << 18, 0);
+        sc.stamp.assign((size_t)1 << (2 * dbits), -1);
+        sc.slot.assign((size_t)1 << (2 * dbits), 0);
     }
     std::unordered_map<uint64_t, int> entry_of;
     for (int i = 0; i < m; ++i) {
@@ -276,10 +278,11 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
         if (first < 0) continue;  // code 0: all-zero segment
         const int sigma = seg[first] < 0 ? -1 : 1;
         int cur = -1, nz = 0;
-        uint64_t key = 0;
+        uint64_t key = 0, dkey = 0;
         for (int t = 0; t < gg; ++t) {
             seg[t] *= sigma;
             key |= (uint64_t)(seg[t] + (1 << (key_bits - 1))) << (key_bits * t);
+            dkey |= (uint64_t)(seg[t] + (1 << bits)) << (dbits * t);
             if (seg[t] == 0) continue;
             const int d = digit_entry(t, i);
             ++nz;
@@ -291,7 +294,7 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
             const uint64_t pkey = key | ((uint64_t)t << 62);
             int e = -1;
             if (direct) {
-                if (sc.stamp[key] == grp) e = sc.slot[key];
+                if (sc.stamp[dkey] == grp) e = sc.slot[dkey];
             } else {
                 auto it = entry_of.find(pkey);
                 if (it != entry_of.end()) e = it->second;
@@ -307,8 +310,8 @@ void build_group(const void *A, int m, int n, int bits, bool is_signed, int N, i
                 gp.combos.push_back(c);
                 gp.levels = std::max(gp.levels, nz);
                 if (direct) {
-                    sc.stamp[key] = grp;
-                    sc.slot[key] = e;
+                    sc.stamp[dkey] = grp;
+                    sc.slot[dkey] = e;
                 } else {
                     entry_of.emplace(pkey, e);
                 }

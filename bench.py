@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 # a product is 64, a square 36 (the 28 cross products counted once); the P-256
 # Montgomery reduction needs none (its digits of p are 0, 1 and 2^32 - 1)
 MADS_MUL, MADS_SQR = 64, 36
-MADS_MIXED_ADD = 7 * MADS_MUL + 4 * MADS_SQR        # 592 (madd-2007-bl, 7M + 4S)
+MADS_MIXED_ADD = 8 * MADS_MUL + 2 * MADS_SQR        # 584 (XYZZ madd-2008-s, 8M + 2S)
 
 
 def log(*a):

@@ -45,7 +45,8 @@ pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint32_t *b, ui
  * 19 4a-3b (mod p, normal form, one limb pass adding 6p); products with
  * loose quotient digits, for operand bounds multiplying to at most
  * 31.99 p^2 (normal form): 24 a*b, 25 a^2, 26 a*b + (2p - b) as 18,
- * 27 a*(2b) with b carry-only (limbs of 2b below 2^30, no carry), 28 as 20. */
+ * 27 a*(2b) with b carry-only (limbs of 2b below 2^30, no carry), 28 as 20,
+ * 29 a*b - b'*b' with one reduction, a, b and b' as in 20 (normal form). */
 pcmm_status pcmm_diag_field_raw(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
                                 int64_t count, void *stream);
 

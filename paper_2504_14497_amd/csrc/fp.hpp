@@ -585,15 +585,16 @@ __device__ __forceinline__ fe fe_fold(fe x) {
     return x;
 }
 
-// (a b - 2 c d) / R (mod p) in normal form, with one reduction: the column
-// sums take a_i b_j and (-c_i)(2 d_j) (signed multiply-adds), p R is added
-// above column 8, and the result is folded into [0, 2p).  For a with limbs
-// < 2^30 (fe_x2 of a carry-only value), b carry-only, c and d normal: each
-// part of a column is below 9 2^59 in magnitude, so partial sums stay within
-// 2^62.2 (2^62.7 with loose quotient digits); a b < 32 p^2 and 2 c d < 8 p^2
-// give a b - 2 c d + p R > 0 and a reduced value in (0, 3p) before the fold
-// (below 3p (1 + 2^-26) with loose digits: still carry-only below 2^260).
-template <bool CHAIN, bool LQ = false>
+// (a b - 2^SH c d) / R (mod p) in normal form, with one reduction: the
+// column sums take a_i b_j and (-c_i)(2^SH d_j) (signed multiply-adds), p R
+// is added above column 8, and the result is folded into [0, 2p).  For SH =
+// 1 with a's limbs < 2^30 (fe_x2 of a carry-only value), or SH = 0 with a
+// carry-only, b carry-only, c and d normal: each part of a column is below
+// 9 2^59 in magnitude, so partial sums stay within 2^62.2 (2^62.7 with loose
+// quotient digits); a b < 32 p^2 and 2^SH c d < 8 p^2 give a b - 2^SH c d +
+// p R > 0 and a reduced value in (0, 3p) before the fold (below 3p (1 +
+// 2^-26) with loose digits: still carry-only below 2^260).
+template <bool CHAIN, bool LQ = false, int SH = 1>
 __device__ __forceinline__ fe fe_mul_sub2_t(const fe &a, const fe &b, const fe &c, const fe &d) {
     const red_consts k = red_consts_make();
     const red_consts_lq kl = red_consts_lq_make();
@@ -602,7 +603,7 @@ __device__ __forceinline__ fe fe_mul_sub2_t(const fe &a, const fe &b, const fe &
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
         nc[i] = -(int32_t)c.v[i];
-        d2[i] = (int32_t)(d.v[i] << 1);
+        d2[i] = (int32_t)(d.v[i] << SH);
     }
     int64_t acc = 0;
     uint32_t m[NL];
@@ -626,6 +627,12 @@ __device__ __forceinline__ fe fe_mul_sub2_t(const fe &a, const fe &b, const fe &
     }
     r.v[NL - 1] = (uint32_t)acc + P29.v[NL - 1];
     return fe_fold(r);
+}
+
+// (a b - c d) / R (mod p): fe_mul_sub2_t without the factor 2
+template <bool CHAIN, bool LQ = false>
+__device__ __forceinline__ fe fe_mul_sub_t(const fe &a, const fe &b, const fe &c, const fe &d) {
+    return fe_mul_sub2_t<CHAIN, LQ, 0>(a, b, c, d);
 }
 
 __device__ __forceinline__ fe fe_mul(const fe &a, const fe &b) { return fe_mul_t<true>(a, b); }

@@ -860,7 +860,9 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
     const uint32_t est = (uint32_t)(entry_stride(npairs) * 4);  // bytes from one entry to the next
     const int64_t yoff = y_offset(npairs);
 
-    jpt acc = jpt_infinity();
+    // the accumulator in XYZZ coordinates (ec.hpp), converted to Jacobian
+    // once, at the store
+    xpt acc = xpt_infinity();
     bool acc_inf = true;  // whether acc is the identity, kept by the additions
     for (int gc = g_begin; gc < g_end; gc += d.kc) {
         const int chunk = bz * d.chunks_per_split + (gc - g_begin) / d.kc;
@@ -894,24 +896,27 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
                      {{ec[2].x, ec[2].y, ec[2].z, ec[2].w, ec[3].x, ec[3].y, ec[3].z, ec[3].w, c8[1]}}};
             const bool q_inf = (c8[0] & ENTRY_INF) != 0;
             if (v < 0) Q.y = fe_neg(Q.y);
-            acc = jpt_add_affine_known(acc, acc_inf, Q, q_inf, acc_inf);
+            acc = xpt_add_affine_known(acc, acc_inf, Q, q_inf, acc_inf);
         }
     }
     const int j = p >> 1, pt = p & 1;
     const int64_t e_out = (int64_t)i * l + j;
-    if (d.S > 1) {
-        store_jac_m(at<uint32_t>(a, d.w_part) + (int64_t)bz * JAC2_PLANES * d.ldj, d.ldj, pt, e_out, acc);
-    } else if (d.direct) {
-        // the row's only entry was added to the identity, so acc = (x, y, 1)
-        // or the identity: already affine
+    if (d.direct) {
+        // the row's only entry was added to the identity, so acc = (x, y, 1,
+        // 1) or the identity: already affine
         apt A;
         A.x = acc_inf ? fe_zero() : acc.X;
         A.y = acc_inf ? fe_zero() : acc.Y;
         store_affine(a.io[d.io].C, a.io[d.io].ldc, pt, e_out, A);
+        return;
+    }
+    const jpt J = xpt_to_jpt(acc, acc_inf);
+    if (d.S > 1) {
+        store_jac_m(at<uint32_t>(a, d.w_part) + (int64_t)bz * JAC2_PLANES * d.ldj, d.ldj, pt, e_out, J);
     } else if (d.c_form == PCMM_AFFINE) {
-        store_jac_m(at<uint32_t>(a, d.w_cjac), d.ldj, pt, e_out, acc);
+        store_jac_m(at<uint32_t>(a, d.w_cjac), d.ldj, pt, e_out, J);
     } else {
-        store_jac(a.io[d.io].C, a.io[d.io].ldc, pt, e_out, acc);
+        store_jac(a.io[d.io].C, a.io[d.io].ldc, pt, e_out, J);
     }
 }
 

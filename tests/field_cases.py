@@ -153,10 +153,10 @@ def _extreme_rows(bound, n, seed):
 
 
 def check_loose_quotient_products(raw):
-    """Products with loose quotient digits (ops 24-28; the mixed addition of
+    """Products with loose quotient digits (ops 24-29; the mixed addition of
     the accumulation takes all its products in this form): random normal
     operands and carry-only operands at the largest limbs their bounds
-    allow, up to 16 p^2 and 32 p^2 for the folded op 28.  Each result must
+    allow, up to 16 p^2 and 32 p^2 for the folded op 28 (16 p^2 for op 29).  Each result must
     equal the product times R^-1 modulo p and be in normal form (op 26:
     carry-only in (0, 4p))."""
     a, b = _operands(3000, 12)
@@ -195,6 +195,11 @@ def check_loose_quotient_products(raw):
     _check_normal(out)
     vb = v4[::-1]
     bad = [i for i in range(len(v4)) if value(out[i]) % P != (2 * (v4[i] - vb[i]) * vb[i] * RINV) % P]
+    assert not bad, bad[:5]
+    # a b - b' b' with one reduction and a fold, a and b below 4p
+    out = raw(29, R4, Yr)
+    _check_normal(out)
+    bad = [i for i in range(len(v4)) if value(out[i]) % P != ((v4[i] - vb[i]) * vb[i] * RINV) % P]
     assert not bad, bad[:5]
 
 

@@ -35,6 +35,7 @@ def lib():
         vp = ctypes.c_void_p
         L.hs_field_raw_n.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_int64]
         L.hs_point.argtypes = [ctypes.c_int, vp, vp, vp, vp, ctypes.c_uint32, ctypes.c_int, vp]
+        L.hs_accumulate.argtypes = [vp, vp, ctypes.c_int, vp]
         _lib = L
     return _lib
 
@@ -72,6 +73,25 @@ def point(op, P, Q=None, zp=None, zq=None, k=0, t=0):
                         k, t, out)
     if rc:
         raise AssertionError(f"host point op {op} reported {rc}")
+    x = sum(out[i] << (32 * i) for i in range(8))
+    y = sum(out[8 + i] << (32 * i) for i in range(8))
+    return x.to_bytes(32, "big") + y.to_bytes(32, "big")
+
+
+def accumulate(points, negs):
+    """The accumulation's loop (XYZZ form, identity flag carried) over
+    64-byte affine points, each negated where negs says; returns the 64-byte
+    canonical affine sum."""
+    n = len(points)
+    words = (ctypes.c_uint32 * (16 * max(n, 1)))()
+    for i, P in enumerate(points):
+        w = _words(P)
+        for k in range(16):
+            words[16 * i + k] = w[k]
+    neg = (ctypes.c_uint8 * max(n, 1))(*[1 if v else 0 for v in negs])
+    out = (ctypes.c_uint32 * 16)()
+    rc = lib().hs_accumulate(words, neg, n, out)
+    assert rc == 0, rc
     x = sum(out[i] << (32 * i) for i in range(8))
     y = sum(out[8 + i] << (32 * i) for i in range(8))
     return x.to_bytes(32, "big") + y.to_bytes(32, "big")

@@ -54,6 +54,28 @@ jpt jac_of(const uint32_t *p, const uint32_t *z) {
     return j;
 }
 
+// XYZZ with a chosen Z: (x z^2, y z^3, z^2, z^3); z = 0 or the affine
+// identity give the identity (flag set)
+xpt xyzz_of(const uint32_t *p, const uint32_t *z, bool &inf) {
+    const apt a = aff_of(p);
+    xpt r = xpt_infinity();
+    inf = apt_is_inf(a);
+    if (inf) return r;
+    fe zz = fe_one_mont();
+    if (z) {
+        zz = mont_of(z);
+        if (fe_is_zero(zz)) {
+            inf = true;
+            return r;
+        }
+    }
+    r.ZZ = fe_sqr(zz);
+    r.ZZZ = fe_mul(r.ZZ, zz);
+    r.X = fe_mul(a.x, r.ZZ);
+    r.Y = fe_mul(a.y, r.ZZZ);
+    return r;
+}
+
 // canonical affine of a Jacobian point (identity -> zeros)
 void aff_out(const jpt &P, uint32_t *out) {
     if (jpt_is_inf(P)) {
@@ -104,6 +126,7 @@ int hs_field_raw(int op, const uint32_t *a, const uint32_t *b, uint32_t *out) {
         case 26: r = fe_mul_plus_t<true, true>(x, y, fe_2p_minus(y)); break;
         case 27: r = fe_mul_t<true, true>(x, fe_x2(y)); break;
         case 28: r = fe_mul_sub2_t<true, true>(fe_x2(x), y, fe_norm(y), fe_norm(y)); break;
+        case 29: r = fe_mul_sub_t<true, true>(x, y, fe_norm(y), fe_norm(y)); break;
         default: return -1;
     }
     for (int i = 0; i < NL; ++i) out[i] = r.v[i];
@@ -126,6 +149,8 @@ int hs_field_raw_n(int op, const uint32_t *a, const uint32_t *b, uint32_t *out, 
 //   3 2P
 //   4 k P by the ladder over the low t bits of k (P affine)
 //   5 -P
+//   6 P + Q, Q affine, the accumulation's XYZZ form (identity flags
+//     carried; P given in XYZZ coordinates at z_p)
 int hs_point(int op, const uint32_t *P, const uint32_t *zp, const uint32_t *Q, const uint32_t *zq, uint32_t k,
              int t, uint32_t *out) {
     jpt r;
@@ -144,9 +169,36 @@ int hs_point(int op, const uint32_t *P, const uint32_t *zp, const uint32_t *Q, c
         case 3: r = jpt_dbl(jac_of(P, zp)); break;
         case 4: r = ladder_small(k, t, aff_of(P)); break;
         case 5: r = jpt_neg(jac_of(P, zp)); break;
+        case 6: {
+            bool p_inf = false, r_inf = false;
+            const xpt xp = xyzz_of(P, zp, p_inf);
+            const apt q = aff_of(Q);
+            const xpt s = xpt_add_affine_known(xp, p_inf, q, apt_is_inf(q), r_inf);
+            // the carried flag must agree with the result's ZZ, ZZZ
+            if (r_inf != (fe_is_zero(s.ZZ) || fe_is_zero(s.ZZZ))) return 1;
+            r = xpt_to_jpt(s, r_inf);
+            break;
+        }
         default: return -1;
     }
     aff_out(r, out);
+    return 0;
+}
+
+// The accumulation's loop on the host: the identity plus n affine points
+// (16 canonical words each; neg[i] != 0 adds -P_i), in the XYZZ form with
+// the identity flag carried, so that every addition after the first takes
+// the previous one's loose outputs.  Result as canonical affine.
+int hs_accumulate(const uint32_t *pts, const uint8_t *neg, int n, uint32_t *out) {
+    xpt acc = xpt_infinity();
+    bool inf = true;
+    for (int i = 0; i < n; ++i) {
+        apt q = aff_of(pts + 16 * i);
+        const bool q_inf = apt_is_inf(q);
+        if (neg[i]) q.y = fe_neg(q.y);
+        acc = xpt_add_affine_known(acc, inf, q, q_inf, inf);
+    }
+    aff_out(xpt_to_jpt(acc, inf), out);
     return 0;
 }
 

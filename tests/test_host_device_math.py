@@ -100,12 +100,43 @@ def test_host_point_additions_vs_oracle(host, orc):
     for P, Q in _cases(orc, 210, 5):
         zp, zq = rnd.randrange(1, p_), rnd.randrange(1, p_)
         want = orc.pt_add(P, Q)
-        for op in (0, 1):
+        for op in (0, 1, 6):
             assert host.point(op, P, Q, zp=zp) == want, (op, P.hex()[:16], Q.hex()[:16])
             assert host.point(op, P, Q) == want, (op, "Z = 1")
         assert host.point(2, P, Q, zp=zp, zq=zq) == want
         assert host.point(3, P, zp=zp) == orc.pt_dbl(P)
         assert host.point(5, P, zp=zp) == orc.pt_neg(P)
+
+
+def test_host_xyzz_accumulation_chains_vs_oracle(host, orc):
+    """The accumulation's XYZZ loop over chains of table-like entries equals
+    the oracle's sum: every addition after the first takes loose outputs of
+    the previous one, and the chains pass through every exceptional case
+    (a repeated entry while the sum equals it, its negation, identities in
+    the middle, a sum that returns to the identity and continues)."""
+    rnd = random.Random(31)
+    pts = [_random_point(orc, rnd) for _ in range(6)]
+    for c in range(40):
+        chain, negs = [], []
+        for _ in range(rnd.randrange(1, 24)):
+            kind = rnd.randrange(10)
+            if kind == 0:
+                chain.append(orc.INF)
+            else:
+                chain.append(pts[rnd.randrange(len(pts))])
+            negs.append(rnd.random() < 0.4)
+        if c % 4 == 1:  # P + P from the identity: the doubling case
+            chain, negs = [pts[0], pts[0], pts[1]], [False, False, True]
+        elif c % 4 == 2:  # P - P, then more: identity in the middle
+            chain, negs = [pts[2], pts[2], pts[3], pts[3]], [False, True, True, True]
+        elif c % 4 == 3:  # the sum (Z != 1) meets itself, then its negation
+            S = orc.pt_add(pts[c % 6], pts[(c + 1) % 6])
+            chain = [pts[c % 6], pts[(c + 1) % 6], S, S, S, S]
+            negs = [False, False, False, False, True, True] if c % 8 == 3 else [False, False, True, False, False, False]
+        want = orc.INF
+        for P, ng in zip(chain, negs):
+            want = orc.pt_add(want, orc.pt_neg(P) if ng else P)
+        assert host.accumulate(chain, negs) == want, c
 
 
 def test_host_ladder_vs_oracle(host, orc):

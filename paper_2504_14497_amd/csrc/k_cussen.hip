@@ -894,9 +894,12 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
             if (v == 0) continue;  // padding after the row's last nonzero code
             apt Q = {{{ec[0].x, ec[0].y, ec[0].z, ec[0].w, ec[1].x, ec[1].y, ec[1].z, ec[1].w, c8[0] & LIMB8_BITS}},
                      {{ec[2].x, ec[2].y, ec[2].z, ec[2].w, ec[3].x, ec[3].y, ec[3].z, ec[3].w, c8[1]}}};
-            const bool q_inf = (c8[0] & ENTRY_INF) != 0;
+            // an identity entry leaves the sum as it is: the lane skips it,
+            // so the addition never reads the old accumulator after its
+            // formulas (the result can take its registers)
+            if (c8[0] & ENTRY_INF) continue;
             if (v < 0) Q.y = fe_neg(Q.y);
-            acc = xpt_add_affine_known(acc, acc_inf, Q, q_inf, acc_inf);
+            acc = xpt_add_affine_known(acc, acc_inf, Q, false, acc_inf);
         }
     }
     const int j = p >> 1, pt = p & 1;

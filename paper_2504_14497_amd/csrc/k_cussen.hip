@@ -570,7 +570,7 @@ __device__ __forceinline__ fe chord_dx(const fe &xb, const fe &xa, bool &ne) {
 //   forward   the product of the dx = x_b - x_a[r] of all chord additions
 //             (reading only x), one prefix (the product before the run)
 //             stored per run, in the x granule of its first combination;
-//   inverse   one inversion per level;
+//   inverse   one inversion per level, shared by two lanes;
 //   backward  per run (in reverse) the prefixes inside the run again from
 //             the run's dx, then each combination's 1/dx and its affine sum
 //             by the chord formula.
@@ -773,46 +773,94 @@ __global__ void __launch_bounds__(256) combo_forward_kernel(run_args a, int leve
     cp[NL * d.cb_lanes] = pending ? 1u : 0u;
 }
 
-// Backward pass of one level: the inversion of the lane's product, the
-// chord sums, and the rest.  A zero product (some chord of the lane has
-// x_a = x_b) sends the wavefront through the checked forward and backward
-// passes; combinations the chord formula does not cover are finished in a
-// third pass, which runs only when some lane of the wavefront has one.
+// Half of a level's lanes, in whole wavefronts: the backward pass runs one
+// thread per two lanes, t and t + H.
+__device__ __forceinline__ int64_t combo_half(int64_t lanes) { return ((lanes + 1) / 2 + 63) & ~(int64_t)63; }
+
+// The combinations the chord formula does not cover (identity operands,
+// x_a = x_b), marked by the passes: each finished on its own.
+__device__ __forceinline__ void combo_rest(const combo_lane &c, bool pending) {
+    for (int bi = c.b0; bi < c.b1; ++bi) {
+        const plan_cblock blk = c.blocks[bi];
+        for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
+            const plan_crun run = c.runs[ri];
+            for (int r = 0; r < CB; ++r) {
+                if (run.dst[r] < 0) continue;
+                uint32_t *slot = c.tab + run.dst[r] * c.estride;
+                if (pending && (slot[NL - 1] & ENTRY_PENDING))
+                    combo_special(c.tab + blk.a[r] * c.estride, c.tab + run.b * c.estride, c.yoff,
+                                  (run.neg >> r) & 1, slot);
+            }
+        }
+    }
+}
+
+// Backward pass of one level: a thread takes the lanes t and t + H, whose
+// products share one inversion (1 / (p0 p1) times p1 and times p0), then the
+// chord sums of each lane, and the rest.  A zero product (some chord of the
+// lane has x_a = x_b) first sends the wavefront through the checked forward
+// pass for that lane (its product is then nonzero) and later the matching
+// checked backward pass; combinations the chord formula does not cover are
+// finished in a third pass, which runs only when some lane of the wavefront
+// has one.  With one thread per two lanes the kernel's wavefronts fill the
+// chip in one round at two per SIMD, and half as many inversions run.
 __global__ void __launch_bounds__(256) combo_backward_kernel(run_args a, int level) {
     const int b = find_problem(a, offsetof(prob_desc, cb_block0), blockIdx.x);
     const prob_desc &d = descs(a)[b];
-    const int64_t lane = ((int64_t)blockIdx.x - d.cb_block0) * blockDim.x + threadIdx.x;
-    if (lane >= d.cb_lanes || level > d.levels) return;
-    const combo_lane c = combo_lane_of(a, d, lane, level);
-    if (c.b0 == c.b1) return;
-    const uint32_t *cp = at<const uint32_t>(a, d.w_cprod) + lane;
-    fe prod;
+    const int64_t t = ((int64_t)blockIdx.x - d.cb_block0) * blockDim.x + threadIdx.x;
+    const int64_t H = combo_half(d.cb_lanes);
+    if (t >= H || level > d.levels) return;  // whole wavefronts: H is a multiple of 64
+    // (a lane's descriptor is looked up again in each loop rather than kept:
+    // the backward pass needs nearly every register)
+    auto lane_of = [&](int s, combo_lane &c) {
+        const int64_t lane = t + s * H;
+        if (lane >= d.cb_lanes) return false;
+        c = combo_lane_of(a, d, lane, level);
+        return c.b0 < c.b1;
+    };
+    bool pend0 = false, pend1 = false, safe0 = false, safe1 = false;
+    fe prod0 = fe_one_mont(), prod1 = fe_one_mont();
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+        combo_lane c{};
+        const bool live = lane_of(s, c);
+        fe prod = fe_one_mont();
+        bool pending = false;
+        if (live) {
+            const uint32_t *cp = at<const uint32_t>(a, d.w_cprod) + t + s * H;
 #pragma unroll
-    for (int w = 0; w < NL; ++w) prod.v[w] = cp[w * d.cb_lanes];
-    bool pending = cp[NL * d.cb_lanes] != 0;
-    const bool safe = __ballot(fe_is_zero(prod)) != 0;
-    if (safe) {
-        pending = false;
-        prod = combo_forward<true>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, pending);
-        combo_backward<true>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, c.yoff, fe_inv(prod));
-    } else {
-        combo_backward<false>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, c.yoff, fe_inv(prod));
-    }
-    // ---- the rest: identity operands, x_a = x_b
-    if (__ballot(pending)) {
-        for (int bi = c.b0; bi < c.b1; ++bi) {
-            const plan_cblock blk = c.blocks[bi];
-            for (int ri = blk.run_begin; ri < blk.run_end; ++ri) {
-                const plan_crun run = c.runs[ri];
-                for (int r = 0; r < CB; ++r) {
-                    if (run.dst[r] < 0) continue;
-                    uint32_t *slot = c.tab + run.dst[r] * c.estride;
-                    if (pending && (slot[NL - 1] & ENTRY_PENDING))
-                        combo_special(c.tab + blk.a[r] * c.estride, c.tab + run.b * c.estride, c.yoff,
-                                      (run.neg >> r) & 1, slot);
-                }
-            }
+            for (int w = 0; w < NL; ++w) prod.v[w] = cp[w * d.cb_lanes];
+            pending = cp[NL * d.cb_lanes] != 0;
         }
+        const bool safe = __ballot(live && fe_is_zero(prod)) != 0;
+        if (safe && live) {
+            pending = false;
+            prod = combo_forward<true>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, pending);
+        }
+        if (s == 0) {
+            pend0 = pending;
+            safe0 = safe;
+            prod0 = prod;
+        } else {
+            pend1 = pending;
+            safe1 = safe;
+            prod1 = prod;
+        }
+    }
+    const fe inv = fe_inv(fe_mul_lq(prod0, prod1));
+    const fe inv0 = fe_mul_lq(inv, prod1), inv1 = fe_mul_lq(inv, prod0);
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+        combo_lane c{};
+        const bool live = lane_of(s, c);
+        const bool pending = live && (s ? pend1 : pend0);
+        const fe iv = fe_select(s != 0, inv0, inv1);
+        if (s ? safe1 : safe0) {
+            if (live) combo_backward<true>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, c.yoff, iv);
+        } else if (live) {
+            combo_backward<false>(c.blocks, c.runs, c.b0, c.b1, c.tab, c.estride, c.yoff, iv);
+        }
+        if (__ballot(pending)) combo_rest(c, pending);
     }
 }
 

@@ -971,7 +971,7 @@ __device__ __forceinline__ void accumulate_tile(const run_args &a, const prob_de
     }
 }
 
-__global__ void __launch_bounds__(256) accumulate_kernel(run_args a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) accumulate_kernel(run_args a) {
     __shared__ int32_t s_tile;
     int32_t *ctr = at<int32_t>(a, a.ctr_off);
     for (;;) {

@@ -426,7 +426,7 @@ def paillier_leg(m, n, l, bits, reps, school_reps):
             "context": "the paper reports no Paillier timings; it expects speedups similar to EC-ElGamal's"}
 
 
-def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
+def serve_leg(n_requests, fractions, budget_gb, slots, max_batch, overlap_min=1):
     """Encrypted linear layers served by the continuous-batching scheduler:
     4 static layers W (256 x 1024, uniform signed 8-bit, resident plans),
     requests X (1024 x 8 ciphertexts of uniform 8-bit messages, a fresh
@@ -474,7 +474,7 @@ def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
         return [Request(rid=k, layer=int(which[k]), X=X[k], C=Cs[k]) for k in range(count)]
 
     def run(rate, count):
-        srv = Server(ex, budget=ws.numel(), slots=slots, max_batch=max_batch)
+        srv = Server(ex, budget=ws.numel(), slots=slots, max_batch=max_batch, overlap_min=overlap_min)
         reqs = fresh_requests(count)
         arr = poisson_arrivals(count, rate, seed=17) if rate else np.zeros(count)
         wall = run_arrivals(srv, reqs, arr)
@@ -527,7 +527,7 @@ def serve_leg(n_requests, fractions, budget_gb, slots, max_batch):
     return {"workload": f"4 layers W {m}x{n} uniform signed {base.bits}-bit (plans resident), requests X "
                         f"{n}x{l} ciphertexts of uniform {base.msg_bits}-bit messages, a fresh X per request, "
                         f"layer uniform; Poisson arrivals; Cussen N=4 g=1",
-            "requests_per_rate": n_requests, "slots": slots, "max_batch": max_batch,
+            "requests_per_rate": n_requests, "slots": slots, "max_batch": max_batch, "overlap_min": overlap_min,
             "budget_gb": budget_gb, "request_workspace_mb": plan.selected_workspace_bytes([0]) / 1e6,
             "host_plan_s": t_plan, "capacity_req_per_s": capacity, "burst": burst, "sweep": sweep,
             "alone_equals_mix": same, "decrypt": decrypt}
@@ -765,7 +765,7 @@ def main():
     if not args.no_serve:
         torch.cuda.empty_cache()
         out["serving"] = serve_leg(args.serve_requests, [float(x) for x in args.serve_fractions.split(",")],
-                                   args.serve_budget_gb, slots=2, max_batch=32)
+                                   args.serve_budget_gb, slots=2, max_batch=32, overlap_min=4)
     if not args.no_cpu_baseline:
         threads = max(1, min(os.cpu_count() or 1, 16))
         base, Corc, cols = cpu_baseline(sh, A, args.cpu_seconds, threads)

@@ -13,7 +13,11 @@ Scheduling (host side; the GPU work of a batch is one pcmm_plan_run_selected):
     workspace budget and the batch has fewer than `max_batch` requests.  A
     request that arrives while other batches run on the GPU therefore starts
     as soon as a slot and memory free up, and its batch overlaps on the device
-    with the batches still running (each slot has its own stream);
+    with the batches still running (each slot has its own stream).  With
+    `overlap_min` > 1 a batch is admitted while another is in flight only
+    when at least that many requests wait: a lone request then waits for the
+    running batch and runs alone (overlapping batches share the GPU and both
+    take longer), while a backlog still fills every slot;
   * a request whose footprint alone exceeds the whole budget is refused;
   * a request still queued after `timeout` seconds is cancelled;
   * a batch retires when its completion event has fired: its workspace range
@@ -97,11 +101,12 @@ class _Batch:
 
 class Server:
     def __init__(self, executor, budget: int, slots: int = 2, max_batch: int = 64, max_queue: int = 100000,
-                 timeout: float = None, clock=time.perf_counter):
+                 timeout: float = None, clock=time.perf_counter, overlap_min: int = 1):
         self.ex = executor
         self.arena = Arena(budget)
         self.slots = slots
         self.max_batch = max_batch
+        self.overlap_min = max(1, overlap_min)
         self.max_queue = max_queue
         self.timeout = timeout
         self.clock = clock
@@ -155,6 +160,8 @@ class Server:
         for slot in range(self.slots):
             if slot in self.inflight or not self.queue:
                 continue
+            if self.inflight and len(self.queue) < self.overlap_min:
+                break  # a short queue waits for the running batch instead of sharing the GPU
             take, offset = self._take()
             if not take:
                 break  # the head does not fit yet: wait for memory (FIFO, no overtaking)

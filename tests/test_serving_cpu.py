@@ -152,6 +152,34 @@ def test_arrivals_join_while_other_batches_run():
     assert late.latency == pytest.approx(1.0)
 
 
+def test_overlap_only_with_a_backlog():
+    """With overlap_min = 3 a lone request arriving during a batch waits for
+    it and then runs alone; three or more waiting requests fill the free slot
+    at once."""
+    clk = FakeClock()
+    ex = FakeExecutor(clk, {0: 1 << 20}, per_request=1.0)
+    srv = Server(ex, budget=1 << 30, slots=2, max_batch=8, clock=clk, overlap_min=3)
+    first = _reqs(2)
+    for r in first:
+        srv.submit(r)
+    srv.poll()                     # batch on slot 0 until t = 2 (the only batch: no wait)
+    assert all(r.state == RUNNING for r in first)
+    clk.t = 0.5
+    late = Request(rid=10, layer=0, arrival=0.5)
+    srv.submit(late)
+    srv.poll()
+    assert late.state == QUEUED and len(ex.launches) == 1
+    clk.t = 2.0
+    srv.poll()                     # the first batch retires, the lone request starts
+    assert all(r.state == DONE for r in first) and late.state == RUNNING and late.t_admit == 2.0
+    backlog = [Request(rid=20 + k, layer=0, arrival=2.0) for k in range(3)]
+    for r in backlog:
+        srv.submit(r)
+    srv.poll()                     # three waiting: the free slot takes them now
+    assert all(r.state == RUNNING for r in backlog) and len(ex.launches) == 3
+    assert ex.launches[-1][0] != ex.launches[-2][0]
+
+
 def test_poisson_driver_with_fake_clock():
     arr = poisson_arrivals(200, rate=50.0, seed=3)
     assert np.all(np.diff(arr) > 0)

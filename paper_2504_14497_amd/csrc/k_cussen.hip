@@ -1096,8 +1096,10 @@ acc_tiling acc_tiles(int m, int l) {
 // the 17th within 4 %.
 //   accumulation  persistent: a tile's time is its rows' chain of mixed
 //                 additions (nonzero codes per row and split) times tau;
-//                 tiles run W = 512 at a time (2 per CU), and a tile alone
-//                 still takes beta of its time under full load
+//                 tiles run W = 512 at a time (2 per CU, as when the model
+//                 was fitted; the kernel now keeps 3 per CU at about the
+//                 same throughput), and a tile alone still takes beta of
+//                 its time under full load
 //   combinations  throughput (all combinations) or, with few lanes, one
 //                 lane's chain: an inversion per level and its share of the
 //                 group's combinations; 2048 wavefronts resident

@@ -44,10 +44,15 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the kernels' code (fp.hpp, ec.hpp, common.hpp, k_cussen.hip)
+    with // comments and whitespace removed, so that edits of comments alone
+    keep counters taken on the same code valid."""
+    import re
     h = hashlib.sha256()
     for f in ("fp.hpp", "ec.hpp", "common.hpp", "k_cussen.hip"):
-        with open(os.path.join(ROOT, "paper_2504_14497_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2504_14497_amd", "csrc", f), encoding="utf-8") as fh:
+            code = re.sub(r"//[^\n]*", "", fh.read())
+        h.update("".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

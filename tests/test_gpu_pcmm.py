@@ -165,6 +165,29 @@ def test_exceptional_cases_vs_oracle(dev, orc):
     assert (want[8:11, 1] == 0).all()
 
 
+def test_combination_lanes_sharing_an_inversion(dev, orc):
+    """The combinations' backward pass gives a thread two (group, pair)
+    lanes, t and t + H (H = half the lanes in whole wavefronts), which share
+    one inversion.  With 2 groups of 80 pairs (160 lanes, H = 128) the lanes
+    of group 1's pairs 48..79 share threads with group 0's pairs 0..31.
+    Group 1's columns hold equal ciphertexts (B row 3 = row 2), so its equal
+    digits meet x_a = x_b: those lanes take the checked passes and the third
+    pass while their partners in group 0 take the fast path.  Equal to the
+    oracle everywhere."""
+    rng = np.random.default_rng(123)
+    A = rng.integers(0, 16, size=(20, 4)).astype(np.uint8)
+    A[:6, 2] = A[:6, 3]           # equal digits in group 1: chords with x_a = x_b
+    A[6, 2:] = [5, 5]
+    B = random_cts(orc, 4, 40, 456)
+    B[3] = B[2]
+    want = orc.pcmm_cussen(A, B)
+    Bd = _upload(dev, B)
+    log("combination lanes sharing an inversion")
+    C, st = dev.cussen(A, 4, Bd, cfg=dev.CussenCfg(4, 2, 1, 0))
+    assert st["group"] == 2 and st["combo_adds"] > 0
+    assert (C.to_host() == want).all()
+
+
 @pytest.mark.parametrize("m,n,l,bits,signed,g", [(50, 1, 5, 8, True, 1), (40, 2, 3, 4, False, 2),
                                                  (33, 3, 2, 2, False, 3), (20, 1, 4, 4, False, 1)])
 def test_direct_outputs_of_one_column_group(dev, orc, m, n, l, bits, signed, g):

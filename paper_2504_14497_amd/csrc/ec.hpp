@@ -3,7 +3,9 @@
 // Curve (Sec. 4.1): y^2 = x^3 - 3x + b over F_p, prime order q, cofactor 1.
 // Points are held in VGPRs in Montgomery form:
 //   jpt  Jacobian (X, Y, Z), x = X/Z^2, y = Y/Z^3; the identity has Z = 0;
-//   apt  affine (x, y); the identity is (0, 0) (not on the curve since b != 0).
+//   apt  affine (x, y); the identity is (0, 0) (not on the curve since b != 0);
+//   xpt  extended Jacobian (X, Y, ZZ, ZZZ), x = X/ZZ, y = Y/ZZZ, for the
+//        accumulator (mixed addition 8M + 2S).
 // Formulas are the standard Jacobian ones for a = -3 (doubling 3M + 5S,
 // mixed addition 7M + 4S, general addition 11M + 5S).  Every exceptional
 // case of the group law (Sec. 2.3) is handled:
@@ -123,9 +125,9 @@ __device__ __forceinline__ jpt fix_equal_operands(bool same, const jpt &R, const
 // carry-only (their products are below 32 p^2), X3 = r^2 - J - 2V and
 // Y3 = r (V - X3) - 2 Y1 J are each one limb pass plus one normalisation,
 // and Z3 = (Z1 + H)^2 - Z1Z1 - HH is computed as the equal 2 Z1 H.
-// LEAN (the accumulation) folds additions into the products and doubles in
-// an operand's limbs (fe_x2: below 2^30, valid for one operand of a
-// product): H = U2 - X1 and r' = S2 - Y1 (= r / 2) come out of the products
+// LEAN (the table builds' form) folds additions into the products and
+// doubles in an operand's limbs (fe_x2: below 2^30, valid for one operand of
+// a product): H = U2 - X1 and r' = S2 - Y1 (= r / 2) come out of the products
 // U2 and S2 with 2p - X1, 2p - Y1 added above R (carry-only, < 4p); r^2 =
 // 4 r'^2 enters the X3 limb pass; Y3 = (2 r') (V - X3) - 2 Y1 J is one
 // reduction of both products (fe_mul_sub2); Z3 = Z1 (2H) (below 16 p^2).
@@ -185,8 +187,8 @@ __device__ __forceinline__ jpt jpt_add_affine(const jpt &P, const apt &Q) {
     return R;
 }
 
-// P + Q with Q affine, complete, for an accumulation that knows which
-// operands are the identity: p_inf (Z1 = 0) and q_inf (Q is the affine
+// P + Q with Q affine, complete, for a caller that knows which operands
+// are the identity: p_inf (Z1 = 0) and q_inf (Q is the affine
 // identity) are given, and r_inf receives whether the result is the
 // identity (its Z is then 0), so the caller carries the flag instead of
 // testing Z1's limbs at every addition.  Exceptional cases: with neither

@@ -42,11 +42,14 @@ pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint32_t *b, ui
  * products that absorb an addition: 18 a*b + (2p - b) with the addend above
  * R (carry-only, in (0, 4p)), 20 (2a)*b - 2 b'*b' with one reduction, for a
  * and b carry-only (value < 4p) and b' the normal form of b (normal form);
- * 19 4a-3b (mod p, normal form, one limb pass adding 6p); products with
+ * 19 4a-3b (mod p, normal form, one limb pass adding 6p); the split
+ * (latency) forms 21 a*b and 22 a^2, 23 the inverse of a below 4p (0 -> 0,
+ * Montgomery form: x^-1 R for a = x R, by divsteps); products with
  * loose quotient digits, for operand bounds multiplying to at most
  * 31.99 p^2 (normal form): 24 a*b, 25 a^2, 26 a*b + (2p - b) as 18,
  * 27 a*(2b) with b carry-only (limbs of 2b below 2^30, no carry), 28 as 20,
- * 29 a*b - b'*b' with one reduction, a, b and b' as in 20 (normal form). */
+ * 29 a*b - b'*b' with one reduction, a, b and b' as in 20 (normal form),
+ * 30 the inverse of a by Fermat's little theorem (must agree with 23). */
 pcmm_status pcmm_diag_field_raw(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
                                 int64_t count, void *stream);
 

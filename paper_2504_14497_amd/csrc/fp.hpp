@@ -120,6 +120,8 @@ constexpr fe29 TWO_P29 = {{0x1ffffffeu, 0x1fffffffu, 0x1fffffffu, 0x3ffu, 0u, 0u
 constexpr fe29 ONE29 = c_to29(ONE_PLAIN);
 constexpr fe29 R29 = c_to29(R_MOD_P);
 constexpr fe29 R2_29 = c_to29(R2_MOD_P);
+constexpr fe_const R3_MOD_P = c_shift(R2_MOD_P, 261);    // R^3 mod p
+constexpr fe29 R3_29 = c_to29(R3_MOD_P);
 
 // 2p as limbs must be the radix-2^29 digits of 2p (checked at compile time)
 constexpr bool c_check_2p() {
@@ -692,13 +694,13 @@ __device__ __forceinline__ fe fe_to_mont(const fe &a) { return fe_mul_ilp(a, fe_
 // Montgomery limbs -> canonical integer limbs in [0, p)
 __device__ __forceinline__ fe fe_from_mont(const fe &a) { return fe_canon(fe_mul_ilp(a, fe_from29(ONE29))); }
 
-// a^(p-2) = a^-1 for a != 0 (0 maps to 0).  p - 2 in 32-bit words from the
-// top: ffffffff 00000001 00000000 00000000 00000000 ffffffff ffffffff fffffffd.
-// x_k below is a^(2^k - 1); the chain uses 255 squarings and 12 products,
-// all with loose quotient digits (for a below 4p every operand pair is below
-// 16 p^2; the chain is latency-bound, and the loose form is about a quarter
-// faster per dependent product on one wavefront).
-__device__ __noinline__ fe fe_inv(const fe &a) {
+// a^(p-2) = a^-1 for a != 0 (0 maps to 0), by Fermat's little theorem.
+// p - 2 in 32-bit words from the top: ffffffff 00000001 00000000 00000000
+// 00000000 ffffffff ffffffff fffffffd.  x_k below is a^(2^k - 1); the chain
+// uses 255 squarings and 12 products, all with loose quotient digits (for a
+// below 4p every operand pair is below 16 p^2).  Kept as the cross-check of
+// fe_inv.
+__device__ __noinline__ fe fe_inv_fermat(const fe &a) {
     fe x1 = a;
     fe x2 = fe_mul_t<false, true>(fe_sqr_t<false, true>(x1), x1);
     fe x3 = fe_mul_t<false, true>(fe_sqr_t<false, true>(x2), x1);
@@ -714,6 +716,182 @@ __device__ __noinline__ fe fe_inv(const fe &a) {
     r = fe_mul_t<false, true>(fe_sqr_n(r, 30), x30);         // word 0: 30 ones,
     r = fe_mul_t<false, true>(fe_sqr_n(r, 2), x1);           //         then bits 0 1
     return r;
+}
+
+// ---------------------------------------------------------------------------
+// Inversion by divsteps (Bernstein and Yang, "Fast constant-time gcd
+// computation and modular inversion", 2019).  A divstep maps (delta, f, g),
+// f odd, to (1 - delta, g, (g - f) / 2) if delta > 0 and g is odd, to
+// (1 + delta, f, (g + f) / 2) if g is odd otherwise, and to (1 + delta, f,
+// g / 2) if g is even.  From (1, p, x) with 0 <= x < p < 2^256, g reaches 0
+// (and f = +-1 when x != 0) within 742 divsteps (their bound
+// floor((49 d + 80) / 17) for d = 256 bits); this runs 25 batches of 30 =
+// 750.  The decisions of 30 divsteps depend only on the low 30 bits of f and
+// g, so a batch runs on the low 32 bits and records its effect as an integer
+// matrix (u v; q r): 2^30 (f', g') = (u f + v g, q f + r g), with |u| + |v|
+// and |q| + |r| at most 2^30; the matrix is then applied to the full f, g
+// and to d, e, which keep d x = f and e x = g (mod p): d' = (u d + v e) /
+// 2^30 (mod p), exact after adding the multiple md p (md < 2^30) that
+// clears the low 30 bits.  At the end d x = +-1, so x^-1 = +-d.
+// State: signed radix-2^30 values, limbs 0..7 in [0, 2^30), limb 8 signed.
+// |d|, |e| <= p throughout: |u d + v e| / 2^30 <= max(|d|, |e|) and md p /
+// 2^30 < p, and a step of p toward zero after each batch keeps the bound.
+// About 20 K VALU instructions per inversion against about 32 K for the
+// Fermat chain.
+// ---------------------------------------------------------------------------
+struct s30 {
+    int32_t v[NL];
+};
+constexpr int32_t M30 = (1 << 30) - 1;
+
+// 30 divsteps on the low 32 bits of f and g; d2 = 2 delta.
+__device__ __forceinline__ void divsteps30(int32_t &d2, uint32_t f, uint32_t g, int32_t &u, int32_t &v, int32_t &q,
+                                           int32_t &r) {
+    u = 1;
+    v = 0;
+    q = 0;
+    r = 1;
+#pragma unroll
+    for (int i = 0; i < 30; ++i) {
+        const bool odd = (g & 1u) != 0;
+        const bool swap = odd && d2 > 0;
+        // swap: (f, g, u, v, q, r, delta) <- (g, -f, q, r, -u, -v, -delta),
+        // after which every odd g is handled as g + f
+        const uint32_t f1 = swap ? g : f, g1 = swap ? 0u - f : g;
+        const int32_t u1 = swap ? q : u, v1 = swap ? r : v, q1 = swap ? -u : q, r1 = swap ? -v : r;
+        d2 = (swap ? -d2 : d2) + 2;
+        f = f1;
+        g = (g1 + (odd ? f1 : 0u)) >> 1;
+        q = q1 + (odd ? u1 : 0);
+        r = r1 + (odd ? v1 : 0);
+        u = (int32_t)((uint32_t)u1 << 1);
+        v = (int32_t)((uint32_t)v1 << 1);
+    }
+}
+
+// acc + x y for 32-bit signed x, y: one signed multiply-add (the empty
+// register constraint keeps the compiler from widening the product)
+__device__ __forceinline__ int64_t smad(int64_t acc, int32_t x, int32_t y) {
+    acc += (int64_t)x * (int64_t)y;
+    asm("" : "+v"(acc));
+    return acc;
+}
+
+// (u a + v b) / 2^30, exact (the caller's matrix makes the low 30 bits zero)
+__device__ __forceinline__ s30 s30_row(int32_t u, int32_t v, const s30 &a, const s30 &b) {
+    int64_t acc = smad(smad(0, u, a.v[0]), v, b.v[0]);
+    acc >>= 30;
+    s30 o;
+#pragma unroll
+    for (int i = 1; i < NL; ++i) {
+        acc = smad(smad(acc, u, a.v[i]), v, b.v[i]);
+        o.v[i - 1] = (int32_t)(acc & M30);
+        acc >>= 30;
+    }
+    o.v[NL - 1] = (int32_t)acc;
+    return o;
+}
+
+// limbs 0..7 back into [0, 2^30)
+__device__ __forceinline__ void s30_carry(s30 &x) {
+#pragma unroll
+    for (int i = 0; i < NL - 1; ++i) {
+        const int32_t c = x.v[i] >> 30;
+        x.v[i] &= M30;
+        x.v[i + 1] += c;
+    }
+}
+
+// (u d + v e) / 2^30 (mod p), then a step of p toward zero.  p in signed
+// radix-2^30 digits: -1 + 2^6 B^3 + 2^12 B^6 - 2^14 B^7 + 2^16 B^8 (B = 2^30),
+// so p = -1 (mod 2^30) and md = (u d + v e) mod 2^30 clears the low bits.
+__device__ __forceinline__ s30 s30_row_mod(int32_t u, int32_t v, const s30 &d, const s30 &e) {
+    int64_t acc = smad(smad(0, u, d.v[0]), v, e.v[0]);
+    const int64_t md = acc & M30;
+    acc = (acc - md) >> 30;
+    s30 o;
+#pragma unroll
+    for (int i = 1; i < NL; ++i) {
+        acc = smad(smad(acc, u, d.v[i]), v, e.v[i]);
+        if (i == 3) acc += md << 6;
+        if (i == 6) acc += md << 12;
+        if (i == 7) acc -= md << 14;
+        if (i == 8) acc += md << 16;
+        o.v[i - 1] = (int32_t)(acc & M30);
+        acc >>= 30;
+    }
+    o.v[NL - 1] = (int32_t)acc;
+    const int32_t sg = o.v[NL - 1] < 0 ? 1 : -1;  // + p below zero, - p from zero up
+    o.v[0] -= sg;
+    o.v[3] += sg * (1 << 6);
+    o.v[6] += sg * (1 << 12);
+    o.v[7] -= sg * (1 << 14);
+    o.v[8] += sg * (1 << 16);
+    s30_carry(o);
+    return o;
+}
+
+// limbs of a value in [0, 2^256) -> radix 2^30
+__device__ __forceinline__ s30 s30_from_fe(const fe &a) {
+    s30 o;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        const int bit = 30 * j, i = bit / LB, sh = bit % LB;
+        uint64_t x = (uint64_t)a.v[i] >> sh;
+        if (i + 1 < NL) x |= (uint64_t)a.v[i + 1] << (LB - sh);
+        if (i + 2 < NL) x |= (uint64_t)a.v[i + 2] << (2 * LB - sh);
+        o.v[j] = (int32_t)(x & M30);
+    }
+    return o;
+}
+
+// a value in [0, 2^261) in radix 2^30 (limbs 0..7 in [0, 2^30)) -> 29-bit limbs
+__device__ __forceinline__ fe fe_from_s30(const s30 &a) {
+    fe o;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int bit = LB * i, j = bit / 30, sh = bit % 30;
+        uint64_t x = (uint64_t)(uint32_t)a.v[j] >> sh;
+        if (j + 1 < NL) x |= (uint64_t)(uint32_t)a.v[j + 1] << (30 - sh);
+        o.v[i] = (uint32_t)(x & LMASK);
+    }
+    return o;
+}
+
+// x^-1 in Montgomery form for a = x R below 4p (0 maps to 0): the divsteps
+// invert the integer a, and one product with R^3 turns a^-1 = x^-1 R^-1 into
+// x^-1 R.
+__device__ __noinline__ fe fe_inv(const fe &a) {
+    s30 f = {{-1, 0, 0, 1 << 6, 0, 0, 1 << 12, -(1 << 14), 1 << 16}};
+    s30_carry(f);
+    s30 g = s30_from_fe(fe_canon(fe_norm(a)));
+    s30 d = {{0, 0, 0, 0, 0, 0, 0, 0, 0}}, e = {{1, 0, 0, 0, 0, 0, 0, 0, 0}};
+    int32_t d2 = 2;
+#pragma unroll 1
+    for (int b = 0; b < 25; ++b) {
+        int32_t u, v, q, r;
+        divsteps30(d2, (uint32_t)f.v[0] | ((uint32_t)f.v[1] << 30), (uint32_t)g.v[0] | ((uint32_t)g.v[1] << 30), u,
+                   v, q, r);
+        const s30 f1 = s30_row(u, v, f, g), g1 = s30_row(q, r, f, g);
+        const s30 d1 = s30_row_mod(u, v, d, e), e1 = s30_row_mod(q, r, d, e);
+        f = f1;
+        g = g1;
+        d = d1;
+        e = e1;
+    }
+    // f = +-1 (f = p, d = 0 for a = 0): x^-1 = sign(f) d, brought into [0, p]
+    const bool fneg = f.v[NL - 1] < 0;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) d.v[i] = fneg ? -d.v[i] : d.v[i];
+    s30_carry(d);
+    const bool dneg = d.v[NL - 1] < 0;
+    d.v[0] -= dneg ? 1 : 0;
+    d.v[3] += dneg ? 1 << 6 : 0;
+    d.v[6] += dneg ? 1 << 12 : 0;
+    d.v[7] -= dneg ? 1 << 14 : 0;
+    d.v[8] += dneg ? 1 << 16 : 0;
+    s30_carry(d);
+    return fe_mul_t<false, true>(fe_from_s30(d), fe_from29(R3_29));
 }
 
 }  // namespace pcmm

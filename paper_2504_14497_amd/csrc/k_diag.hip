@@ -56,12 +56,16 @@ __global__ void __launch_bounds__(256) field_raw_kernel(int op, const uint32_t *
         case 18: r = fe_mul_plus_t<true>(x, y, fe_2p_minus(y)); break;
         case 19: r = fe_4sub_sub2(x, y, y); break;
         case 20: r = fe_mul_sub2_t<true>(fe_x2(x), y, fe_norm(y), fe_norm(y)); break;
+        case 21: r = fe_mul_ilp(x, y); break;
+        case 22: r = fe_sqr_ilp(x); break;
+        case 23: r = fe_inv(x); break;
         case 24: r = fe_mul_t<true, true>(x, y); break;
         case 25: r = fe_sqr_t<true, true>(x); break;
         case 26: r = fe_mul_plus_t<true, true>(x, y, fe_2p_minus(y)); break;
         case 27: r = fe_mul_t<true, true>(x, fe_x2(y)); break;
         case 28: r = fe_mul_sub2_t<true, true>(fe_x2(x), y, fe_norm(y), fe_norm(y)); break;
-        default: r = fe_mul_sub_t<true, true>(x, y, fe_norm(y), fe_norm(y)); break;
+        case 29: r = fe_mul_sub_t<true, true>(x, y, fe_norm(y), fe_norm(y)); break;
+        default: r = fe_inv_fermat(x); break;
     }
     soa_store_m(out, n, 0, e, r);
 }
@@ -252,7 +256,7 @@ extern "C" pcmm_status pcmm_diag_field(int32_t op, const uint32_t *a, const uint
 
 extern "C" pcmm_status pcmm_diag_field_raw(int32_t op, const uint32_t *a, const uint32_t *b, uint32_t *out,
                                            int64_t count, void *stream) {
-    if (op < 0 || (op > 20 && op < 24) || op > 29 || count < 0) return PCMM_EINVAL;
+    if (op < 0 || op > 30 || count < 0) return PCMM_EINVAL;
     if (count == 0) return PCMM_OK;
     if (!a || !b || !out) return PCMM_EINVAL;
     int64_t blocks = (count + 255) / 256;

@@ -203,6 +203,32 @@ def check_loose_quotient_products(raw):
     assert not bad, bad[:5]
 
 
+def check_inversion(raw, n=20000):
+    """fe_inv (op 23, divsteps) on carry-only operands below 4p (its input
+    range): edge values (0, 1, p - 1, p, 2p - 1, 2^256 - 1, ...), carry-only
+    values at the largest limbs and random ones.  The result is x^-1 R for a
+    = x R (a^-1 R^2 mod p), 0 for a = 0 (mod p), in normal form, and equal
+    modulo p to the Fermat chain's (op 30) on every operand."""
+    rnd = random.Random(29)
+    edge, _ = _operands(0, 1)
+    vals = sorted(set(edge)) + [3 * P, 4 * P - 1, 3 * P + 1, 2**257, 2**257 + 2**256 - 1]
+    vals += [rnd.randrange(4 * P) for _ in range(n)]
+    vals += [rnd.randrange(2**k) for k in (1, 2, 3, 8, 31, 32, 33, 64, 128, 200, 255) for _ in range(20)]
+    rows = [limbs(v) for v in vals if v < 4 * P]
+    R4, v4 = _extreme_rows(4 * P, 2000, 30)
+    A = np.concatenate([np.array(rows, dtype=np.int64), R4])
+    vals = [v for v in vals if v < 4 * P] + list(v4)
+    out = raw(23, A, A)
+    _check_normal(out)
+    bad = [i for i, v in enumerate(vals)
+           if value(out[i]) % P != (0 if v % P == 0 else pow(v, -1, P) * R * R % P)]
+    assert not bad, [hex(vals[i]) for i in bad[:5]]
+    ref = raw(30, A, A)
+    _check_normal(ref)
+    bad = [i for i in range(len(vals)) if value(out[i]) % P != value(ref[i]) % P]
+    assert not bad, [hex(vals[i]) for i in bad[:5]]
+
+
 def check_signed_limb_normalisation(raw):
     rnd = random.Random(5)
     rows, vals = [], []

@@ -127,6 +127,7 @@ int hs_field_raw(int op, const uint32_t *a, const uint32_t *b, uint32_t *out) {
         case 27: r = fe_mul_t<true, true>(x, fe_x2(y)); break;
         case 28: r = fe_mul_sub2_t<true, true>(fe_x2(x), y, fe_norm(y), fe_norm(y)); break;
         case 29: r = fe_mul_sub_t<true, true>(x, y, fe_norm(y), fe_norm(y)); break;
+        case 30: r = fe_inv_fermat(x); break;
         default: return -1;
     }
     for (int i = 0; i < NL; ++i) out[i] = r.v[i];

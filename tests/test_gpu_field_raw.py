@@ -38,3 +38,10 @@ def test_loose_quotient_products(dev):
 
 def test_raw_normalisation_of_signed_limbs(dev):
     FC.check_signed_limb_normalisation(dev.diag_field_raw)
+
+
+def test_inversion_by_divsteps(dev):
+    """fe_inv (divsteps) on the GPU: the modular inverse in Montgomery form on
+    edge values, carry-only extremes and random operands below 4p, equal to
+    the Fermat chain's result."""
+    FC.check_inversion(dev.diag_field_raw)

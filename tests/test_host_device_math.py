@@ -64,6 +64,12 @@ def test_host_split_form_products_and_inverse(host):
         assert FC.value(out[i]) % P == want, i
 
 
+def test_host_inversion_by_divsteps(host):
+    """fe_inv (divsteps) equals the modular inverse and the Fermat chain on
+    edge values, carry-only extremes and 20,000 random operands below 4p."""
+    FC.check_inversion(host.field_raw)
+
+
 def _random_point(orc, rnd):
     p_, b_, gx, gy, q = orc.curve_params()
     return orc.ladder_big(rnd.randrange(1, q), orc.generator())

@@ -2,7 +2,7 @@
 //
 // Montgomery's simultaneous-inversion trick: one thread walks its batch of
 // points forward keeping the running product of the nonzero Z values (and
-// storing each prefix), inverts the total once (Fermat, 255 S + 12 M), then
+// storing each prefix), inverts the total once (fe_inv, by divsteps), then
 // walks backward: Z_j^-1 = inv * prefix_{j-1}, inv <- inv * Z_j.  Per point
 // that is 3 multiplications plus the affine conversion (x = X Z^-2,
 // y = Y Z^-3), with one inversion per batch.  Z = 0 (the identity) maps to

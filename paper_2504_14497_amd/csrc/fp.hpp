@@ -736,8 +736,9 @@ __device__ __noinline__ fe fe_inv_fermat(const fe &a) {
 // State: signed radix-2^30 values, limbs 0..7 in [0, 2^30), limb 8 signed.
 // |d|, |e| <= p throughout: |u d + v e| / 2^30 <= max(|d|, |e|) and md p /
 // 2^30 < p, and a step of p toward zero after each batch keeps the bound.
-// About 20 K VALU instructions per inversion against about 32 K for the
-// Fermat chain.
+// About 29 K VALU instructions per inversion against about 32 K for the
+// Fermat chain, with a shorter critical path (no 64-bit multiply-add
+// chains in the divsteps).
 // ---------------------------------------------------------------------------
 struct s30 {
     int32_t v[NL];

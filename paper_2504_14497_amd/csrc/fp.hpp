@@ -736,7 +736,7 @@ __device__ __noinline__ fe fe_inv_fermat(const fe &a) {
 // State: signed radix-2^30 values, limbs 0..7 in [0, 2^30), limb 8 signed.
 // |d|, |e| <= p throughout: |u d + v e| / 2^30 <= max(|d|, |e|) and md p /
 // 2^30 < p, and a step of p toward zero after each batch keeps the bound.
-// About 29 K VALU instructions per inversion against about 32 K for the
+// About 24 K VALU instructions per inversion against about 32 K for the
 // Fermat chain, with a shorter critical path (no 64-bit multiply-add
 // chains in the divsteps).
 // ---------------------------------------------------------------------------
@@ -770,9 +770,12 @@ __device__ __forceinline__ void divsteps30(int32_t &d2, uint32_t f, uint32_t g, 
     }
 }
 
-// acc + x y for 32-bit signed x, y: one signed multiply-add (the empty
-// register constraint keeps the compiler from widening the product)
+// acc + x y for 32-bit signed x, y: one signed multiply-add.  The empty
+// register constraints hide what the compiler knows of y (a masked limb is
+// non-negative, which would turn the signed product into a widened one)
+// and keep the sum one chain.
 __device__ __forceinline__ int64_t smad(int64_t acc, int32_t x, int32_t y) {
+    asm("" : "+v"(y));
     acc += (int64_t)x * (int64_t)y;
     asm("" : "+v"(acc));
     return acc;
